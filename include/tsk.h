@@ -1,0 +1,168 @@
+/*
+ * tsk.h -- C ABI of the MI355X (gfx950) library for recompressing a sum of
+ * Tucker tensors by structured Gaussian sketching.
+ *
+ * Problem (Section 3, "Sketching-Based Summation of Tucker Tensors"): given
+ *     X = sum_{i=1}^{s} c_i [[G^(i); U_1^(i), ..., U_d^(i)]]
+ * with cores G^(i) of size r_1^(i) x ... x r_d^(i) and factors U_k^(i) of
+ * size n_k x r_k^(i), a sketch kind and sketch sizes, compute, without ever
+ * forming X:
+ *   Y_n = X_(n) S_n    for every mode n                    (Stage 2 sketch)
+ *   Q_n                thin QR basis of Y_n, diag(R_n) >= 0  (Stage 2 QR)
+ *   H   = sum_i c_i G^(i) x_1 Q_1^T U_1^(i) ... x_d Q_d^T U_d^(i)  (Stage 3)
+ * so that X ~ [[H; Q_1, ..., Q_d]].  S_n is the Khatri-Rao product
+ * Omega_d (.) ... (.) Omega_1 (skipping n, Section 3.1.1) or the Kronecker
+ * product Omega_d (x) ... (x) Omega_1 (skipping n, Section 3.1.2) of one
+ * Gaussian test matrix Omega_k per mode, reused by every S_n with n != k.
+ *
+ * Layout.  Every matrix and tensor is column-major: mode 1 fastest, the
+ * mode-n unfolding orders the remaining modes first-mode-fastest (Section
+ * 2.1, unfolding index equation).  U_k^(i) has leading dimension n_k.
+ * Omega_k is n_k x m (KRP) or n_k x q_k (Kron).  Y_n is n_n x W_n with
+ * W_n = m (KRP) or prod_{k != n} q_k (Kron).  Q_n is n_n x w_n with
+ * w_n = min(n_n, W_n) (economy QR).  H is w_1 x ... x w_d.
+ *
+ * Ownership.  The caller allocates and owns every input, output and
+ * workspace buffer; the library never frees them and keeps no pointer past
+ * the call.  A handle owns only its device, a small device counter block,
+ * pinned staging memory for launch descriptors, and its last error text.
+ *
+ * Asynchrony.  Calls validate on the host, enqueue on `stream` (a
+ * hipStream_t passed as void*, NULL = default stream) and return without
+ * synchronising.  Outputs are valid once the stream reaches that point.
+ *
+ * Errors.  Every function returns a tsk_status.  On any host-side error
+ * nothing is enqueued and no output is written; tsk_last_error_detail()
+ * describes it.  Device-side faults surface as TSK_ERR_DEVICE from a later
+ * call that checks the runtime.  The library never aborts and never prints.
+ *
+ * Threads.  One handle per host thread; distinct handles are independent.
+ */
+#ifndef TSK_H_
+#define TSK_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TSK_OK = 0,
+  TSK_ERR_INVALID_ARG = 1,         /* NULL pointer, size < 1, bad enum, ...      */
+  TSK_ERR_UNSUPPORTED = 2,         /* valid but outside what the kernels handle  */
+  TSK_ERR_OUT_OF_MEMORY = 3,       /* pinned staging or handle memory            */
+  TSK_ERR_WORKSPACE_TOO_SMALL = 4, /* ws_bytes < tucker_sum_workspace_size()     */
+  TSK_ERR_DEVICE = 5,              /* HIP runtime error                          */
+  TSK_ERR_RANK_DEFICIENT = 6       /* Cholesky QR broke down under qr_policy 2   */
+} tsk_status;
+
+typedef enum { TSK_F64 = 0, TSK_F32 = 1 } tsk_dtype;
+
+typedef enum { TSK_SKETCH_KRP = 0, TSK_SKETCH_KRON = 1 } tsk_sketch_kind;
+
+/* Arithmetic of a stage.  FP64 and FP32 run on the matching MFMA units.
+ * BF16X1/X3/X6 split each FP32 operand into 1, 2 or 3 bfloat16 parts and
+ * keep 1, 3 or 6 of the cross products on BF16 MFMA with FP32 accumulation.
+ * The QR of Y_n is always FP64. */
+typedef enum {
+  TSK_PREC_FP64 = 0,
+  TSK_PREC_FP32 = 1,
+  TSK_PREC_BF16X1 = 2,
+  TSK_PREC_BF16X3 = 3,
+  TSK_PREC_BF16X6 = 4
+} tsk_precision;
+
+typedef struct tsk_handle_* tsk_handle;
+
+/* X = sum_i coeffs[i] * [[G_i; U_1^(i) .. U_d^(i)]]  (Section 2.2 Tucker
+ * format; the coefficients are those of the RoundSum({X_i},{c_i}) call of
+ * Algorithm 6 and the alpha, beta of Algorithm 1). */
+typedef struct {
+  int32_t order;               /* d >= 2                                            */
+  int32_t num_terms;           /* s >= 1                                            */
+  const int64_t* dims;         /* host [d], n_k >= 1                                */
+  const int32_t* ranks;        /* host [s*d], ranks[i*d + k] = r_k^(i) >= 1          */
+  const void* const* cores;    /* host [s] device pointers, core i column-major     */
+  const void* const* factors;  /* host [s*d] device pointers, factors[i*d + k] is
+                                  n_k x r_k^(i) column-major, ld = n_k              */
+  const double* coeffs;        /* host [s], or NULL for all ones                    */
+  tsk_dtype dtype;             /* element type of cores and factors                 */
+} tsk_tucker_sum;
+
+typedef struct {
+  tsk_sketch_kind kind;
+  const int32_t* sizes;        /* host; KRP: sizes[0] = m; Kron: sizes[k] = q_k, [d] */
+  uint64_t seed;               /* Omega_k generated on the device from (seed, k)    */
+  const void* const* omega;    /* optional host [d] device pointers to caller-made
+                                  Omega_k (sum dtype, n_k x width_k column-major);
+                                  NULL = generate from seed                        */
+  tsk_precision sketch_prec;   /* factor sketch, core sketch, term expansion        */
+  tsk_precision project_prec;  /* Q^T U and the multi-TTM of the core projection    */
+  int32_t qr_policy;           /* 0: Cholesky QR2, Householder on breakdown (device
+                                  side); 1: Householder always; 2: Cholesky QR2,
+                                  breakdown reported as TSK_ERR_RANK_DEFICIENT      */
+} tsk_sketch_spec;
+
+/* Handle on HIP device `device`.  Allocates the handle's counter block and
+ * nothing else on the device. */
+tsk_status tsk_create(tsk_handle* handle, int device);
+tsk_status tsk_destroy(tsk_handle handle);
+const char* tsk_status_string(tsk_status status);
+/* Text of the last error on this handle ("" if none).  Owned by the handle. */
+const char* tsk_last_error_detail(tsk_handle handle);
+
+/* Sketch sizes of Section 3.2.  KRP width m = max_k ell_k.  Kron sizes
+ * q_k = ceil((prod_j ell_j)^(1/(d-1)) / ell_k) (heuristic sketch-dimension
+ * equation), computed exactly in integers as the least q with
+ * (q ell_k)^(d-1) >= prod_j ell_j.  ell: host [d]; out: host [1] or [d]. */
+tsk_status tsk_krp_width(int32_t order, const int32_t* ell, int32_t* m_out);
+tsk_status tsk_kron_sizes(int32_t order, const int32_t* ell, int32_t* q_out);
+
+/* Per-mode widths: sketch_width[n] = W_n (columns of Y_n), basis_width[n] =
+ * w_n = min(n_n, W_n) (columns of Q_n and mode-n size of H).  Host arrays [d]. */
+tsk_status tsk_sketch_widths(const tsk_tucker_sum* sum, const tsk_sketch_spec* spec,
+                             int64_t* sketch_width, int64_t* basis_width);
+
+/* Omega_k for 0-based `mode` (Section 3.1: a standard Gaussian n_k x width
+ * matrix per mode).  Entry e = i + n_k t uses Philox4x32-10 (Salmon et al.,
+ * SC'11) block e/2 with counter (lo32(e/2), hi32(e/2), mode, 0) and key
+ * (lo32(seed), hi32(seed)); a Box-Muller pair in FP64 from the two 53-bit
+ * uniforms u1 = (w0 >> 11) + 1, u2 = w1 >> 11 (scaled by 2^-53; w0 = words
+ * 1:0, w1 = words 3:2); even entries take rho cos, odd take rho sin; the value
+ * is rounded to 8 significant bits (nearest even), so it is exact in BF16,
+ * FP32 and FP64.  `out` is a device buffer of rows*cols elements of out_dtype. */
+tsk_status tsk_sketch_omega(tsk_handle handle, uint64_t seed, int32_t mode, int64_t rows,
+                            int64_t cols, void* out, tsk_dtype out_dtype, void* stream);
+
+/* Bytes of device workspace that tucker_sum_sketch / tucker_sum_recompress
+ * need for this problem (the same figure covers both). */
+tsk_status tucker_sum_workspace_size(tsk_handle handle, const tsk_tucker_sum* sum,
+                                     const tsk_sketch_spec* spec, size_t* bytes);
+
+/* Stage 2 sketch only (eqs. for the KRP and Kronecker sketched unfoldings of
+ * a sum): Y_out[n] is a device n_n x W_n FP64 buffer.  `ws` is device
+ * workspace of at least tucker_sum_workspace_size() bytes, 256-byte aligned. */
+tsk_status tucker_sum_sketch(tsk_handle handle, const tsk_tucker_sum* sum,
+                             const tsk_sketch_spec* spec, double* const* Y_out, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* Stages 2 and 3 (Algorithms 4/5 without Stage 1 and Stage 4): Q_out[n] is a
+ * device n_n x w_n buffer, H_out a device w_1 x ... x w_d buffer, both of
+ * out_dtype.  Optional R_out (NULL or host [d] of device pointers, FP64
+ * w_n x W_n upper triangular) receives the R factors. */
+tsk_status tucker_sum_recompress(tsk_handle handle, const tsk_tucker_sum* sum,
+                                 const tsk_sketch_spec* spec, void* const* Q_out, void* H_out,
+                                 tsk_dtype out_dtype, double* const* R_out, void* ws,
+                                 size_t ws_bytes, void* stream);
+
+/* Number of mode QRs that took the Householder path since the handle was
+ * created (Cholesky breakdown, or qr_policy 1).  Synchronises `stream`. */
+tsk_status tsk_qr_fallback_count(tsk_handle handle, void* stream, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSK_H_ */

@@ -1,0 +1,262 @@
+"""Sketching-based recompression of Tucker-tensor sums on MI355X (gfx950).
+
+Thin PyTorch binding over the C ABI in include/tsk.h (libtsk.so).  PyTorch
+supplies device memory and the current HIP stream; every step of the method
+runs in the library's HIP kernels.  This module only marshals arguments:
+tensors are passed by pointer in column-major (Fortran) order, the layout the
+paper's unfolding convention uses (Section 2.1).
+
+A Tucker sum is given as `cores` (list of s tensors, core i of shape
+(r_1^(i), ..., r_d^(i))) and `factors` (list of s lists of d tensors of shape
+(n_k, r_k^(i))), all on the same CUDA/HIP device, all float64 or all float32.
+"""
+import ctypes
+from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_size_t, c_void_p
+
+import torch
+
+from . import _lib
+from ._lib import KINDS, PRECISIONS, QR_POLICIES, TSK_F32, TSK_F64, TskError, check, load
+
+__all__ = [
+    "fortran", "empty_fortran", "krp_width", "kron_sizes", "sketch_widths", "sketch_omega",
+    "tucker_sum_sketch", "tucker_sum_recompress", "qr_fallback_count", "Handle", "TskError",
+    "Recompressor",
+]
+
+
+# ---------------------------------------------------------------- layout helpers
+def is_fortran(t: torch.Tensor) -> bool:
+    expect = 1
+    for size, stride in zip(t.shape, t.stride()):
+        if size != 1 and stride != expect:
+            return False
+        expect *= size
+    return True
+
+
+def fortran(t: torch.Tensor) -> torch.Tensor:
+    """Same values, column-major memory (a copy only if needed)."""
+    if is_fortran(t):
+        return t
+    rev = list(reversed(range(t.dim())))
+    return t.permute(rev).contiguous().permute(rev)
+
+
+def empty_fortran(shape, dtype, device) -> torch.Tensor:
+    rev = list(reversed(range(len(shape))))
+    return torch.empty(tuple(reversed(tuple(shape))), dtype=dtype, device=device).permute(rev)
+
+
+def _dtype_code(dt) -> int:
+    if dt == torch.float64:
+        return TSK_F64
+    if dt == torch.float32:
+        return TSK_F32
+    raise TypeError(f"unsupported dtype {dt}")
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+# ---------------------------------------------------------------- sizes (host only)
+def krp_width(ell) -> int:
+    arr = (c_int32 * len(ell))(*ell)
+    out = c_int32()
+    check(load().tsk_krp_width(len(ell), arr, byref(out)))
+    return out.value
+
+
+def kron_sizes(ell) -> list:
+    arr = (c_int32 * len(ell))(*ell)
+    out = (c_int32 * len(ell))()
+    check(load().tsk_kron_sizes(len(ell), arr, out))
+    return list(out)
+
+
+# ---------------------------------------------------------------- handle
+class Handle:
+    """One library handle per device, plus a growable workspace tensor."""
+
+    _cache = {}
+
+    def __init__(self, device=None):
+        device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                              torch.device(device).index or 0)
+        self.device = device
+        self.ptr = c_void_p()
+        check(load().tsk_create(byref(self.ptr), device.index))
+        self.ws = None
+
+    @classmethod
+    def get(cls, device=None) -> "Handle":
+        idx = torch.cuda.current_device() if device is None else (torch.device(device).index or 0)
+        if idx not in cls._cache:
+            cls._cache[idx] = Handle(torch.device("cuda", idx))
+        return cls._cache[idx]
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=self.device)
+        assert self.ws.data_ptr() % 256 == 0
+        return self.ws
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                load().tsk_destroy(self.ptr)
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- marshalling
+class _Marshal:
+    """Keeps the ctypes arrays alive for the duration of one call."""
+
+    def __init__(self, cores, factors, coeffs, kind, sizes, seed, omega, sketch_prec,
+                 project_prec, qr_policy):
+        s = len(cores)
+        d = len(factors[0])
+        dt = cores[0].dtype
+        dev = cores[0].device
+        self.cores = [fortran(g) for g in cores]
+        self.factors = [[fortran(u) for u in us] for us in factors]
+        for g, us in zip(self.cores, self.factors):
+            if g.dim() != d or len(us) != d:
+                raise ValueError("every core must have one dimension per factor")
+            for k, u in enumerate(us):
+                if u.dtype != dt or g.dtype != dt or u.device != dev or g.device != dev:
+                    raise ValueError("all cores and factors must share dtype and device")
+                if u.dim() != 2 or u.shape[1] != g.shape[k]:
+                    raise ValueError(f"factor {k} shape {tuple(u.shape)} does not match core")
+        self.dims = [int(u.shape[0]) for u in self.factors[0]]
+        for us in self.factors:
+            if [int(u.shape[0]) for u in us] != self.dims:
+                raise ValueError("all terms must share the mode sizes")
+        self.d, self.s, self.dtype, self.device = d, s, dt, dev
+        self.c_dims = (c_int64 * d)(*self.dims)
+        self.c_ranks = (c_int32 * (s * d))(*[int(x) for g in self.cores for x in g.shape])
+        self.c_cores = (c_void_p * s)(*[g.data_ptr() for g in self.cores])
+        self.c_factors = (c_void_p * (s * d))(*[u.data_ptr() for us in self.factors for u in us])
+        self.c_coeffs = None if coeffs is None else (c_double * s)(*[float(c) for c in coeffs])
+        self.sum = _lib.TuckerSum(d, s, self.c_dims, self.c_ranks, self.c_cores, self.c_factors,
+                                  self.c_coeffs, _dtype_code(dt))
+        kind = kind.lower()
+        sizes = [int(x) for x in sizes]
+        self.c_sizes = (c_int32 * len(sizes))(*sizes)
+        self.omega = None
+        self.c_omega = None
+        if omega is not None:
+            self.omega = [fortran(o.to(dt)) for o in omega]
+            self.c_omega = (c_void_p * d)(*[o.data_ptr() for o in self.omega])
+        self.spec = _lib.SketchSpec(KINDS[kind], self.c_sizes, int(seed) & (2 ** 64 - 1),
+                                    self.c_omega, PRECISIONS[sketch_prec], PRECISIONS[project_prec],
+                                    QR_POLICIES[qr_policy])
+
+    def widths(self):
+        sw = (c_int64 * self.d)()
+        bw = (c_int64 * self.d)()
+        check(load().tsk_sketch_widths(byref(self.sum), byref(self.spec), sw, bw))
+        return list(sw), list(bw)
+
+
+def sketch_widths(cores, factors, kind, sizes, seed=0):
+    m = _Marshal(cores, factors, None, kind, sizes, seed, None, "fp64", "fp64", "auto")
+    return m.widths()
+
+
+def sketch_omega(seed: int, mode: int, rows: int, cols: int, dtype=torch.float64, device=None):
+    """Omega_k (rows x cols, column-major) generated on the device."""
+    h = Handle.get(device)
+    out = empty_fortran((rows, cols), dtype, h.device)
+    check(load().tsk_sketch_omega(h.ptr, int(seed) & (2 ** 64 - 1), mode, rows, cols,
+                                  c_void_p(out.data_ptr()), _dtype_code(dtype),
+                                  c_void_p(_stream_ptr(h.device))), h.ptr)
+    return out
+
+
+def _workspace(h, m):
+    nbytes = c_size_t()
+    check(load().tucker_sum_workspace_size(h.ptr, byref(m.sum), byref(m.spec), byref(nbytes)), h.ptr)
+    ws = h.workspace(nbytes.value)
+    return ws, nbytes.value
+
+
+def tucker_sum_sketch(cores, factors, kind, sizes, seed, coeffs=None, omega=None,
+                      sketch_prec="fp64"):
+    """Y_n = X_(n) S_n for every mode n (FP64 outputs, shape (n_n, W_n))."""
+    m = _Marshal(cores, factors, coeffs, kind, sizes, seed, omega, sketch_prec, "fp64", "auto")
+    h = Handle.get(m.device)
+    sw, _ = m.widths()
+    ys = [empty_fortran((m.dims[n], sw[n]), torch.float64, m.device) for n in range(m.d)]
+    c_y = (c_void_p * m.d)(*[y.data_ptr() for y in ys])
+    ws, nb = _workspace(h, m)
+    check(load().tucker_sum_sketch(h.ptr, byref(m.sum), byref(m.spec), c_y,
+                                   c_void_p(ws.data_ptr()), ws.numel(),
+                                   c_void_p(_stream_ptr(m.device))), h.ptr)
+    return ys
+
+
+def tucker_sum_recompress(cores, factors, kind, sizes, seed, coeffs=None, omega=None,
+                          sketch_prec="fp64", project_prec="fp64", out_dtype=None,
+                          qr_policy="auto", return_r=False):
+    """Stages 2-3: returns (Q list, H) (and R list if return_r) with
+    X ~ [[H; Q_1, ..., Q_d]]."""
+    m = _Marshal(cores, factors, coeffs, kind, sizes, seed, omega, sketch_prec, project_prec,
+                 qr_policy)
+    h = Handle.get(m.device)
+    out_dtype = m.dtype if out_dtype is None else out_dtype
+    sw, bw = m.widths()
+    qs = [empty_fortran((m.dims[n], bw[n]), out_dtype, m.device) for n in range(m.d)]
+    hh = empty_fortran(tuple(bw), out_dtype, m.device)
+    c_q = (c_void_p * m.d)(*[q.data_ptr() for q in qs])
+    rs = None
+    c_r = None
+    if return_r:
+        rs = [empty_fortran((bw[n], sw[n]), torch.float64, m.device) for n in range(m.d)]
+        c_r = (c_void_p * m.d)(*[r.data_ptr() for r in rs])
+    ws, nb = _workspace(h, m)
+    check(load().tucker_sum_recompress(h.ptr, byref(m.sum), byref(m.spec), c_q,
+                                       c_void_p(hh.data_ptr()), _dtype_code(out_dtype), c_r,
+                                       c_void_p(ws.data_ptr()), ws.numel(),
+                                       c_void_p(_stream_ptr(m.device))), h.ptr)
+    return (qs, hh, rs) if return_r else (qs, hh)
+
+
+class Recompressor:
+    """Pre-marshalled recompression of one fixed Tucker sum: repeated calls
+    reuse the pointer tables, outputs and workspace (used by the benchmark)."""
+
+    def __init__(self, cores, factors, kind, sizes, seed, coeffs=None, sketch_prec="fp64",
+                 project_prec="fp64", out_dtype=None, qr_policy="auto"):
+        self.m = _Marshal(cores, factors, coeffs, kind, sizes, seed, None, sketch_prec,
+                          project_prec, qr_policy)
+        m = self.m
+        self.h = Handle.get(m.device)
+        self.out_dtype = m.dtype if out_dtype is None else out_dtype
+        sw, bw = m.widths()
+        self.Q = [empty_fortran((m.dims[n], bw[n]), self.out_dtype, m.device) for n in range(m.d)]
+        self.H = empty_fortran(tuple(bw), self.out_dtype, m.device)
+        self.c_q = (c_void_p * m.d)(*[q.data_ptr() for q in self.Q])
+        nbytes = c_size_t()
+        check(load().tucker_sum_workspace_size(self.h.ptr, byref(m.sum), byref(m.spec),
+                                               byref(nbytes)), self.h.ptr)
+        self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=m.device)
+        self.ws_bytes = nbytes.value
+
+    def __call__(self, stream=None):
+        st = _stream_ptr(self.m.device) if stream is None else stream
+        check(load().tucker_sum_recompress(self.h.ptr, byref(self.m.sum), byref(self.m.spec),
+                                           self.c_q, c_void_p(self.H.data_ptr()),
+                                           _dtype_code(self.out_dtype), None,
+                                           c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                           c_void_p(st)), self.h.ptr)
+        return self.Q, self.H
+
+
+def qr_fallback_count(device=None) -> int:
+    h = Handle.get(device)
+    out = c_int64()
+    check(load().tsk_qr_fallback_count(h.ptr, c_void_p(_stream_ptr(h.device)), byref(out)), h.ptr)
+    return out.value

@@ -1,0 +1,79 @@
+// Internal declarations shared by the device kernels and the host planner.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsk {
+
+// Arithmetic of a contraction stage (mirrors tsk_precision in tsk.h).
+enum Prec : int32_t { P_FP64 = 0, P_FP32 = 1, P_BF16X1 = 2, P_BF16X3 = 3, P_BF16X6 = 4 };
+
+constexpr int kMaxOrder = 8;
+
+// ---------------------------------------------------------------------------
+// Grouped, batched, K-segmented GEMM descriptors (device-resident).
+//
+// For one descriptor and batch instance b:
+//   C_b = beta * C_b + sum_seg alpha_seg * op(A_seg,b) op(B_seg,b)
+// where C_b is M x N column-major (ldc) at C + b*strideC, op(A) is M x K and
+// op(B) is K x N of the segment.  Operands are read through two strides:
+//   op(A)[m][k] = A[m*a_sx + k*a_sk],  op(B)[k][n] = B[n*b_sx + k*b_sk],
+// one of which is 1.  A K-split s of `splits` covers K-tiles s, s+splits, ...
+// of the concatenated segment K range and writes its partial sum to
+// C + s*strideSplit (beta ignored); a later reduction folds the partials.
+struct GemmSeg {
+  const void* A;
+  const void* B;
+  int64_t a_sx, a_sk, strideA;
+  int64_t b_sx, b_sk, strideB;
+  int32_t K;
+  int32_t pad_;
+  double alpha;
+};
+
+struct GemmDesc {
+  void* C;
+  int64_t ldc, strideC, strideSplit;
+  int32_t M, N, batch, splits;
+  int32_t seg_begin, seg_count;
+  int32_t tiles_m, tiles_n;
+  int32_t beta;   // 1: accumulate into C (only when splits == 1)
+  int32_t c_f64;  // 1: C is double, 0: C is float
+  int64_t tile_begin;  // first linear tile id of this descriptor
+};
+
+// ---------------------------------------------------------------------------
+// KRP core sketch descriptor: V[a][t] = sum_c G_(n)[a][c] * prod_{k != n}
+// P_k[j_k(c)][t] for one term i and mode n (Algorithm 5, core sketch line).
+struct KrpDesc {
+  const void* G;                 // core, column-major
+  const void* P[kMaxOrder];      // P_k = U_k^T Omega_k, r_k x m column-major (P[n] unused)
+  void* V;                       // r_n x m (or partial block), column-major, ld r_n
+  int32_t r[kMaxOrder];
+  int32_t order, mode, m, splits;
+  int64_t strideSplit;           // elements between partial blocks
+  int64_t Kc;                    // prod_{k != n} r_k
+  int32_t tiles_m, tiles_n;
+  int64_t tile_begin;
+  double alpha;
+};
+
+// ---------------------------------------------------------------------------
+// Per-mode QR bookkeeping (Cholesky QR2 with Householder fallback).
+struct QrDesc {
+  const double* Y;      // n x W input sketch
+  double* Q;            // n x w output basis (FP64)
+  double* R;            // w x W (nullable): R factor
+  double* gram_part;    // splits x W x W partial Gram blocks
+  double* rinv;         // W x W upper triangular inverse of the current R
+  double* r1;           // W x W first-pass R (kept for the product R2 R1)
+  double* q1;           // n x W first-pass Q
+  double* hh;           // n x W Householder scratch
+  double* tau;          // W Householder scalars
+  int32_t* flag;        // 1: use Householder for this mode
+  int64_t n, W, w;
+  int32_t gram_splits, pad_;
+};
+
+}  // namespace tsk

@@ -1,0 +1,52 @@
+// Launch functions of the device kernels (host-callable, stream-ordered).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace tsk {
+
+// Omega_k (rows x cols, column-major) from (seed, mode); FP64 or FP32 output.
+hipError_t launch_omega(uint64_t seed, int mode, int64_t rows, int64_t cols, void* out, bool f64,
+                        hipStream_t stream);
+
+// Grouped GEMM over `ndesc` device descriptors covering `total_tiles` tiles.
+hipError_t launch_gemm(int prec, const GemmDesc* descs, int ndesc, const GemmSeg* segs,
+                       int64_t total_tiles, hipStream_t stream);
+
+// KRP core sketches over `ndesc` device descriptors covering `total_tiles` tiles.
+hipError_t launch_krp(int prec, const KrpDesc* descs, int ndesc, int64_t total_tiles,
+                      hipStream_t stream);
+
+// out[j] (rows x cols, ld_out) = beta * out + sum_{s < parts} part[s] (rows x
+// cols, ld_part, part stride `stride_part`), for `count` independent jobs.
+struct ReduceJob {
+  void* out;
+  const void* part;
+  int64_t rows, cols, ld_out, ld_part, stride_part;
+  int32_t parts, beta;
+  int32_t out_f64, part_f64;
+};
+hipError_t launch_reduce(const ReduceJob* jobs, int count, hipStream_t stream);
+
+// Fill `count` int32 words with `value` (used instead of hipMemsetAsync so
+// that captured graphs hold no memset nodes).
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t stream);
+
+// Typed copies with conversion: dst[i*ld_d + r] = src[i*ld_s + r], rows x cols.
+struct CopyJob {
+  void* dst;
+  const void* src;
+  int64_t rows, cols, ld_dst, ld_src;
+  int32_t dst_f64, src_f64;
+};
+hipError_t launch_copy(const CopyJob* jobs, int count, hipStream_t stream);
+
+// Cholesky QR passes and the Householder fallback over `count` modes.
+hipError_t launch_chol(const QrDesc* qr, int count, int pass, double tol, hipStream_t stream);
+hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* fallback_counter,
+                              hipStream_t stream);
+
+}  // namespace tsk

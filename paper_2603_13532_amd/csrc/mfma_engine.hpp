@@ -1,0 +1,207 @@
+// MFMA tile engine for gfx950 (CDNA4): a 256-thread workgroup (four wave64s)
+// computes a 64 x 64 output tile; wave w owns the 32 x 32 quadrant
+// (w & 1, w >> 1) as 2 x 2 blocks of 16 x 16 MFMA accumulators.
+//
+// FP64 tiles use v_mfma_f64_16x16x4_f64 and FP32 tiles v_mfma_f32_16x16x4_f32:
+// per instruction each lane supplies A[lane % 16][lane / 16] and
+// B[lane / 16][lane % 16] of a 16x4 / 4x16 step and holds
+// D[4 * (lane / 16) + v][lane % 16], v = 0..3, of the 16 x 16 result.
+// BF16 tiles use v_mfma_f32_16x16x32_bf16: each lane supplies eight
+// consecutive k of its row (A) or column (B), k = 8 * (lane / 16) + 0..7.
+//
+// Operands are staged through LDS one K-tile at a time, k-major for the
+// 4-deep instructions ([BK][64 + pad]) and row-major with k contiguous for
+// the BF16 planes ([64][BK + pad]) so that each lane reads its eight k with
+// one 16-byte LDS load.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace tsk {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+
+constexpr int TILE = 64;     // output tile edge
+constexpr int NTHREADS = 256;
+
+// ------------------------------------------------------------ precision traits
+template <int P> struct PT;
+template <> struct PT<P_FP64> {
+  typedef double in_t;
+  typedef v4d acc_t;
+  static constexpr int BK = 16;
+};
+template <> struct PT<P_FP32> {
+  typedef float in_t;
+  typedef v4f acc_t;
+  static constexpr int BK = 16;
+};
+template <int NP> struct PTBf {
+  typedef float in_t;
+  typedef v4f acc_t;
+  static constexpr int BK = 32;
+};
+template <> struct PT<P_BF16X1> : PTBf<1> { static constexpr int PARTS = 1; };
+template <> struct PT<P_BF16X3> : PTBf<3> { static constexpr int PARTS = 2; };
+template <> struct PT<P_BF16X6> : PTBf<6> { static constexpr int PARTS = 3; };
+
+__device__ __forceinline__ v4d mma(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mma(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mma_bf(v8s a, v8s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
+
+// Round-to-nearest-even FP32 -> BF16 bits (finite inputs).
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(uint16_t h) {
+  return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// ------------------------------------------------------------ LDS layouts
+// 4-deep instructions: k-major panels.
+template <typename T, int BK> struct LdsK {
+  T a[BK][TILE + 2];
+  T b[BK][TILE + 2];
+};
+// BF16: row-major, k contiguous, one plane per split part.
+template <int BK, int PARTS> struct LdsBf {
+  uint16_t a[PARTS][TILE][BK + 8];
+  uint16_t b[PARTS][TILE][BK + 8];
+};
+
+template <int P> struct Lds;
+template <> struct Lds<P_FP64> { typedef LdsK<double, 16> type; };
+template <> struct Lds<P_FP32> { typedef LdsK<float, 16> type; };
+template <> struct Lds<P_BF16X1> { typedef LdsBf<32, 1> type; };
+template <> struct Lds<P_BF16X3> { typedef LdsBf<32, 2> type; };
+template <> struct Lds<P_BF16X6> { typedef LdsBf<32, 3> type; };
+
+// Elements each thread stages per operand per K-tile.
+template <int P> struct Stage {
+  static constexpr int BK = PT<P>::BK;
+  static constexpr int PER_THREAD = TILE * BK / NTHREADS;  // 4 (BK 16) or 8 (BK 32)
+};
+
+// Store one staged element (row x in [0,64), depth k in [0,BK)) of operand
+// `which` (0 = A, 1 = B) into LDS, splitting into BF16 parts if needed.
+template <int P>
+__device__ __forceinline__ void lds_put(typename Lds<P>::type& s, int which, int x, int k,
+                                        typename PT<P>::in_t v) {
+  if constexpr (P == P_FP64 || P == P_FP32) {
+    if (which == 0) s.a[k][x] = v; else s.b[k][x] = v;
+  } else {
+    constexpr int PARTS = PT<P>::PARTS;
+    float rest = v;
+#pragma unroll
+    for (int p = 0; p < PARTS; ++p) {
+      uint16_t h = bf16_bits(rest);
+      if (which == 0) s.a[p][x][k] = h; else s.b[p][x][k] = h;
+      rest = rest - bf16_value(h);
+    }
+  }
+}
+
+// ------------------------------------------------------------ compute step
+template <int P>
+__device__ __forceinline__ void mma_tile(const typename Lds<P>::type& s,
+                                         typename PT<P>::acc_t (&acc)[2][2], int lane, int wm,
+                                         int wn) {
+  const int r = lane & 15, kq = lane >> 4;
+  if constexpr (P == P_FP64 || P == P_FP32) {
+    constexpr int BK = PT<P>::BK;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      auto a0 = s.a[ks + kq][wm * 32 + r];
+      auto a1 = s.a[ks + kq][wm * 32 + 16 + r];
+      auto b0 = s.b[ks + kq][wn * 32 + r];
+      auto b1 = s.b[ks + kq][wn * 32 + 16 + r];
+      acc[0][0] = mma(a0, b0, acc[0][0]);
+      acc[0][1] = mma(a0, b1, acc[0][1]);
+      acc[1][0] = mma(a1, b0, acc[1][0]);
+      acc[1][1] = mma(a1, b1, acc[1][1]);
+    }
+  } else {
+    constexpr int PARTS = PT<P>::PARTS;
+    v8s a[PARTS][2], b[PARTS][2];
+#pragma unroll
+    for (int p = 0; p < PARTS; ++p) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[p][i] = *reinterpret_cast<const v8s*>(&s.a[p][wm * 32 + 16 * i + r][8 * kq]);
+        b[p][i] = *reinterpret_cast<const v8s*>(&s.b[p][wn * 32 + 16 * i + r][8 * kq]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        // smallest cross products first so they are not absorbed early
+        if constexpr (PARTS == 3) {
+          acc[i][j] = mma_bf(a[0][i], b[2][j], acc[i][j]);
+          acc[i][j] = mma_bf(a[2][i], b[0][j], acc[i][j]);
+          acc[i][j] = mma_bf(a[1][i], b[1][j], acc[i][j]);
+        }
+        if constexpr (PARTS >= 2) {
+          acc[i][j] = mma_bf(a[0][i], b[1][j], acc[i][j]);
+          acc[i][j] = mma_bf(a[1][i], b[0][j], acc[i][j]);
+        }
+        acc[i][j] = mma_bf(a[0][i], b[0][j], acc[i][j]);
+      }
+    }
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void acc_zero(typename PT<P>::acc_t (&acc)[2][2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
+}
+
+// Row/column of accumulator element (i, j, v) inside the 64 x 64 tile.
+__device__ __forceinline__ int acc_row(int wm, int i, int lane, int v) {
+  return wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+}
+__device__ __forceinline__ int acc_col(int wn, int j, int lane) {
+  return wn * 32 + j * 16 + (lane & 15);
+}
+
+// ------------------------------------------------------------ operand staging
+// A 64 x BK panel element (x, k) lives at base[x*sx + k*sk]; exactly one of
+// sx, sk is 1.  Thread mapping follows the contiguous direction so that the
+// global loads coalesce.  Out-of-range elements are staged as zero.
+template <int P>
+struct PanelMap {
+  static constexpr int BK = PT<P>::BK;
+  static constexpr int PT_ = Stage<P>::PER_THREAD;
+  // element j of thread t
+  static __device__ __forceinline__ void xk(bool x_contig, int t, int j, int& x, int& k) {
+    if (x_contig) {
+      x = t & (TILE - 1);
+      k = (t >> 6) + (NTHREADS / TILE) * j;
+    } else {
+      k = t % BK;
+      x = t / BK + (NTHREADS / BK) * j;
+    }
+  }
+};
+
+}  // namespace tsk

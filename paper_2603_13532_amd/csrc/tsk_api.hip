@@ -1,0 +1,1315 @@
+// Host side of the C ABI in include/tsk.h: argument validation, the size
+// planner, workspace layout, and the stream-ordered launch program of
+// Stages 2 and 3 of Algorithms 4 (Kronecker) and 5 (Khatri-Rao).
+//
+// Every call plans the whole launch sequence first: descriptor tables for
+// all grouped kernels are packed into one host blob, copied to the device
+// workspace with a single asynchronous upload from pinned staging memory,
+// and the kernels read their work lists from there.  Nothing is enqueued
+// until validation and planning succeed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tsk.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace tsk;
+
+struct Staging {
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+};
+
+struct tsk_handle_ {
+  int device = 0;
+  std::string err;
+  int64_t* d_counter = nullptr;
+  std::vector<Staging> ring;
+  size_t ring_next = 0;
+  std::vector<void*> pinned_keep;  // staging owned by captured graphs
+};
+
+namespace {
+
+constexpr int kGemmBK64 = 16;
+
+tsk_status fail(tsk_handle h, tsk_status st, const char* fmt, ...) {
+  if (h != nullptr) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    h->err = buf;
+  }
+  return st;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+bool is_fp64(int prec) { return prec == P_FP64; }
+
+// ------------------------------------------------------------------ problem
+struct Problem {
+  int d = 0, s = 0;
+  std::vector<int64_t> dims;
+  std::vector<int32_t> ranks;  // s*d
+  std::vector<const void*> cores, factors;
+  std::vector<double> coeffs;
+  bool in_f64 = true;
+  int kind = TSK_SKETCH_KRP;
+  std::vector<int64_t> ow;  // columns of Omega_k
+  std::vector<int64_t> W;   // columns of Y_n
+  std::vector<int64_t> w;   // columns of Q_n
+  uint64_t seed = 0;
+  std::vector<const void*> omega;  // caller-given or empty
+  int ps = P_FP64, pp = P_FP64;
+  int qr_policy = 0;
+  int r(int i, int k) const { return ranks[(size_t)i * d + k]; }
+};
+
+tsk_status validate(tsk_handle h, const tsk_tucker_sum* sum, const tsk_sketch_spec* spec,
+                    Problem& P) {
+  if (sum == nullptr || spec == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "sum or spec is NULL");
+  if (sum->order < 2 || sum->order > kMaxOrder)
+    return fail(h, TSK_ERR_INVALID_ARG, "order %d outside [2, %d]", sum->order, kMaxOrder);
+  if (sum->num_terms < 1) return fail(h, TSK_ERR_INVALID_ARG, "num_terms %d < 1", sum->num_terms);
+  if (sum->dims == nullptr || sum->ranks == nullptr || sum->cores == nullptr ||
+      sum->factors == nullptr)
+    return fail(h, TSK_ERR_INVALID_ARG, "dims, ranks, cores or factors is NULL");
+  if (sum->dtype != TSK_F64 && sum->dtype != TSK_F32)
+    return fail(h, TSK_ERR_INVALID_ARG, "bad dtype %d", (int)sum->dtype);
+  if (spec->kind != TSK_SKETCH_KRP && spec->kind != TSK_SKETCH_KRON)
+    return fail(h, TSK_ERR_INVALID_ARG, "bad sketch kind %d", (int)spec->kind);
+  if (spec->sizes == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "sketch sizes is NULL");
+  if (spec->sketch_prec < TSK_PREC_FP64 || spec->sketch_prec > TSK_PREC_BF16X6 ||
+      spec->project_prec < TSK_PREC_FP64 || spec->project_prec > TSK_PREC_BF16X6)
+    return fail(h, TSK_ERR_INVALID_ARG, "bad precision");
+  if (spec->qr_policy < 0 || spec->qr_policy > 2)
+    return fail(h, TSK_ERR_INVALID_ARG, "bad qr_policy %d", spec->qr_policy);
+  P.d = sum->order;
+  P.s = sum->num_terms;
+  P.in_f64 = sum->dtype == TSK_F64;
+  P.kind = spec->kind;
+  P.seed = spec->seed;
+  P.ps = spec->sketch_prec;
+  P.pp = spec->project_prec;
+  P.qr_policy = spec->qr_policy;
+  for (int k = 0; k < P.d; ++k) {
+    if (sum->dims[k] < 1) return fail(h, TSK_ERR_INVALID_ARG, "dims[%d] = %lld < 1", k, (long long)sum->dims[k]);
+    if (sum->dims[k] > (1 << 30)) return fail(h, TSK_ERR_UNSUPPORTED, "dims[%d] too large", k);
+    P.dims.push_back(sum->dims[k]);
+  }
+  for (int i = 0; i < P.s; ++i) {
+    if (sum->cores[i] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "cores[%d] is NULL", i);
+    P.cores.push_back(sum->cores[i]);
+    int64_t csize = 1;
+    for (int k = 0; k < P.d; ++k) {
+      const int32_t r = sum->ranks[(size_t)i * P.d + k];
+      if (r < 1) return fail(h, TSK_ERR_INVALID_ARG, "ranks[%d][%d] = %d < 1", i, k, r);
+      if (r > (1 << 20)) return fail(h, TSK_ERR_UNSUPPORTED, "ranks[%d][%d] too large", i, k);
+      P.ranks.push_back(r);
+      csize *= r;
+      if (csize > (int64_t(1) << 40)) return fail(h, TSK_ERR_UNSUPPORTED, "core %d too large", i);
+      const void* f = sum->factors[(size_t)i * P.d + k];
+      if (f == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "factors[%d][%d] is NULL", i, k);
+      P.factors.push_back(f);
+    }
+    P.coeffs.push_back(sum->coeffs ? sum->coeffs[i] : 1.0);
+  }
+  if (P.kind == TSK_SKETCH_KRP) {
+    if (spec->sizes[0] < 1) return fail(h, TSK_ERR_INVALID_ARG, "KRP width %d < 1", spec->sizes[0]);
+    for (int k = 0; k < P.d; ++k) {
+      P.ow.push_back(spec->sizes[0]);
+      P.W.push_back(spec->sizes[0]);
+    }
+  } else {
+    for (int k = 0; k < P.d; ++k) {
+      if (spec->sizes[k] < 1) return fail(h, TSK_ERR_INVALID_ARG, "Kron q[%d] = %d < 1", k, spec->sizes[k]);
+      P.ow.push_back(spec->sizes[k]);
+    }
+    for (int n = 0; n < P.d; ++n) {
+      int64_t S = 1;
+      for (int k = 0; k < P.d; ++k)
+        if (k != n) {
+          S *= P.ow[k];
+          if (S > (1 << 24)) return fail(h, TSK_ERR_UNSUPPORTED, "Kron sketch width too large");
+        }
+      P.W.push_back(S);
+    }
+  }
+  for (int n = 0; n < P.d; ++n) {
+    P.w.push_back(std::min(P.dims[n], P.W[n]));
+    if (P.dims[n] * P.W[n] > (int64_t(1) << 34))
+      return fail(h, TSK_ERR_UNSUPPORTED, "sketch of mode %d too large", n);
+  }
+  if (spec->omega != nullptr) {
+    for (int k = 0; k < P.d; ++k) {
+      if (spec->omega[k] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "omega[%d] is NULL", k);
+      P.omega.push_back(spec->omega[k]);
+    }
+  }
+  return TSK_OK;
+}
+
+// ------------------------------------------------------------------ program
+enum StepKind { S_OMEGA, S_GEMM, S_KRP, S_REDUCE, S_COPY, S_FILL, S_CHOL, S_HOUSE };
+
+struct Step {
+  StepKind kind;
+  int prec = 0;
+  size_t meta = 0, meta2 = 0;  // offsets into the meta blob
+  int count = 0;
+  int64_t tiles = 0;
+  // omega / fill
+  uint64_t seed = 0;
+  int mode = 0, pass = 0, force = 0;
+  int64_t rows = 0, cols = 0;
+  void* ptr = nullptr;  // workspace address (resolved)
+  bool f64 = true;
+  int32_t value = 0;
+  double tol = 0;
+};
+
+// Workspace arena: addresses are planned against a base that may be null
+// (size query) and resolved when the caller's workspace is known.
+struct Arena {
+  char* base = nullptr;
+  size_t top = 0;
+  void* take(size_t bytes) {
+    top = align_up(top, 256);
+    void* p = base + top;
+    top += align_up(bytes, 256);
+    return p;
+  }
+};
+
+struct Program {
+  std::vector<char> blob;
+  std::vector<Step> steps;
+  size_t meta_region = 0;  // workspace offset of the blob
+  template <typename T>
+  size_t put(const std::vector<T>& v) {
+    size_t off = align_up(blob.size(), 64);
+    blob.resize(off + sizeof(T) * v.size());
+    if (!v.empty()) std::memcpy(blob.data() + off, v.data(), sizeof(T) * v.size());
+    return off;
+  }
+};
+
+// Collects grouped-GEMM descriptors for one launch.
+struct GemmBatch {
+  int prec;
+  std::vector<GemmDesc> descs;
+  std::vector<GemmSeg> segs;
+  std::vector<ReduceJob> reduces;
+  int64_t tiles = 0;
+  explicit GemmBatch(int p) : prec(p) {}
+  // Add one descriptor; `splits` > 1 writes partials to `part` and queues a
+  // reduction into C.
+  void add(void* C, bool c_f64, int64_t ldc, int64_t strideC, int M, int N, int batch, int beta,
+           const std::vector<GemmSeg>& sg, int splits = 1, void* part = nullptr) {
+    if (M <= 0 || N <= 0 || batch <= 0) return;
+    GemmDesc D{};
+    D.M = M;
+    D.N = N;
+    D.batch = batch;
+    D.tiles_m = (int)ceil_div(M, 64);
+    D.tiles_n = (int)ceil_div(N, 64);
+    D.seg_begin = (int)segs.size();
+    D.seg_count = (int)sg.size();
+    D.c_f64 = c_f64 ? 1 : 0;
+    D.splits = splits;
+    if (splits > 1) {
+      // partial blocks are dense M x N (ld M), one batch instance after another
+      D.C = part;
+      D.ldc = M;
+      D.strideC = (int64_t)M * N;
+      D.strideSplit = (int64_t)M * N * batch;
+      D.beta = 0;
+      for (int b = 0; b < batch; ++b) {
+        ReduceJob J{};
+        J.out = (char*)C + (size_t)b * strideC * (c_f64 ? 8 : 4);
+        J.part = (char*)part + (size_t)b * M * N * (c_f64 ? 8 : 4);
+        J.rows = M;
+        J.cols = N;
+        J.ld_out = ldc;
+        J.ld_part = M;
+        J.stride_part = D.strideSplit;
+        J.parts = splits;
+        J.beta = beta;
+        J.out_f64 = J.part_f64 = c_f64 ? 1 : 0;
+        reduces.push_back(J);
+      }
+    } else {
+      D.C = C;
+      D.ldc = ldc;
+      D.strideC = strideC;
+      D.strideSplit = 0;
+      D.beta = beta;
+    }
+    D.tile_begin = tiles;
+    tiles += (int64_t)D.tiles_m * D.tiles_n * batch * splits;
+    for (const auto& g : sg) segs.push_back(g);
+    descs.push_back(D);
+  }
+};
+
+GemmSeg seg(const void* A, int64_t a_sx, int64_t a_sk, int64_t sA, const void* B, int64_t b_sx,
+            int64_t b_sk, int64_t sB, int64_t K, double alpha = 1.0) {
+  GemmSeg g{};
+  g.A = A;
+  g.B = B;
+  g.a_sx = a_sx;
+  g.a_sk = a_sk;
+  g.strideA = sA;
+  g.b_sx = b_sx;
+  g.b_sk = b_sk;
+  g.strideB = sB;
+  g.K = (int32_t)K;
+  g.alpha = alpha;
+  return g;
+}
+
+void emit_gemm(Program& prog, GemmBatch& gb) {
+  if (gb.descs.empty()) return;
+  Step st{};
+  st.kind = S_GEMM;
+  st.prec = gb.prec;
+  st.meta = prog.put(gb.descs);
+  st.meta2 = prog.put(gb.segs);
+  st.count = (int)gb.descs.size();
+  st.tiles = gb.tiles;
+  prog.steps.push_back(st);
+  if (!gb.reduces.empty()) {
+    Step r{};
+    r.kind = S_REDUCE;
+    r.meta = prog.put(gb.reduces);
+    r.count = (int)gb.reduces.size();
+    prog.steps.push_back(r);
+  }
+}
+
+void emit_copies(Program& prog, const std::vector<CopyJob>& jobs) {
+  if (jobs.empty()) return;
+  Step c{};
+  c.kind = S_COPY;
+  c.meta = prog.put(jobs);
+  c.count = (int)jobs.size();
+  prog.steps.push_back(c);
+}
+
+int choose_splits(int64_t tiles_without_split, int64_t k_tiles, int64_t target = 512) {
+  if (tiles_without_split >= target || k_tiles < 4) return 1;
+  int64_t s = ceil_div(target, tiles_without_split);
+  s = std::min<int64_t>(s, k_tiles / 2);
+  s = std::min<int64_t>(s, 32);
+  return (int)std::max<int64_t>(s, 1);
+}
+
+size_t esize(bool f64) { return f64 ? 8 : 4; }
+
+// What the call produces.
+struct Outputs {
+  bool recompress = false;
+  std::vector<double*> Y;  // sketch-only: caller Y buffers
+  std::vector<void*> Q;
+  void* H = nullptr;
+  bool out_f64 = true;
+  std::vector<double*> R;
+};
+
+// Build the launch program for one Tucker sum.  All workspace addresses come
+// from `ar`; the meta blob is placed last by the caller.
+void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, int64_t* d_counter) {
+  const int d = P.d, s = P.s;
+  const bool ts64 = is_fp64(P.ps);  // sketch-stage element type
+  const bool tp64 = is_fp64(P.pp);  // projection-stage element type
+  const size_t es = esize(ts64), ep = esize(tp64);
+
+  // ---- inputs in the sketch element type (converted copies if needed)
+  std::vector<CopyJob> conv;
+  std::vector<const void*> core_s(s), fac_s((size_t)s * d);
+  for (int i = 0; i < s; ++i) {
+    int64_t csize = 1;
+    for (int k = 0; k < d; ++k) csize *= P.r(i, k);
+    if (P.in_f64 == ts64) {
+      core_s[i] = P.cores[i];
+    } else {
+      void* p = ar.take(csize * es);
+      conv.push_back(CopyJob{p, P.cores[i], csize, 1, csize, csize, ts64, P.in_f64});
+      core_s[i] = p;
+    }
+    for (int k = 0; k < d; ++k) {
+      const int64_t n = P.dims[k], r = P.r(i, k);
+      const void* u = P.factors[(size_t)i * d + k];
+      if (P.in_f64 == ts64) {
+        fac_s[(size_t)i * d + k] = u;
+      } else {
+        void* p = ar.take(n * r * es);
+        conv.push_back(CopyJob{p, u, n, r, n, n, ts64, P.in_f64});
+        fac_s[(size_t)i * d + k] = p;
+      }
+    }
+  }
+  // ---- Omega_k (Section 3.1), in the sketch element type
+  std::vector<const void*> om(d);
+  for (int k = 0; k < d; ++k) {
+    if (!P.omega.empty()) {
+      if (P.in_f64 == ts64) {
+        om[k] = P.omega[k];
+      } else {
+        void* p = ar.take(P.dims[k] * P.ow[k] * es);
+        conv.push_back(CopyJob{p, P.omega[k], P.dims[k], P.ow[k], P.dims[k], P.dims[k], ts64,
+                               P.in_f64});
+        om[k] = p;
+      }
+    } else {
+      void* p = ar.take(P.dims[k] * P.ow[k] * es);
+      Step st{};
+      st.kind = S_OMEGA;
+      st.seed = P.seed;
+      st.mode = k;
+      st.rows = P.dims[k];
+      st.cols = P.ow[k];
+      st.ptr = p;
+      st.f64 = ts64;
+      prog.steps.push_back(st);
+      om[k] = p;
+    }
+  }
+  emit_copies(prog, conv);
+
+  // ---- factor sketches P_k^(i) = U_k^(i)^T Omega_k  (r x ow), all terms and modes
+  std::vector<void*> Pf((size_t)s * d);
+  {
+    GemmBatch gb(P.ps);
+    int64_t tiles0 = 0, kt = 0;
+    for (int i = 0; i < s; ++i)
+      for (int k = 0; k < d; ++k) {
+        tiles0 += ceil_div(P.r(i, k), 64) * ceil_div(P.ow[k], 64);
+        kt = std::max<int64_t>(kt, ceil_div(P.dims[k], ts64 ? 16 : 32));
+      }
+    const int splits = choose_splits(tiles0, kt);
+    for (int i = 0; i < s; ++i)
+      for (int k = 0; k < d; ++k) {
+        const int64_t n = P.dims[k], r = P.r(i, k), m = P.ow[k];
+        void* p = ar.take(r * m * es);
+        Pf[(size_t)i * d + k] = p;
+        void* part = splits > 1 ? ar.take((size_t)splits * r * m * es) : nullptr;
+        gb.add(p, ts64, r, 0, (int)r, (int)m, 1, 0,
+               {seg(fac_s[(size_t)i * d + k], n, 1, 0, om[k], n, 1, 0, n)}, splits, part);
+      }
+    emit_gemm(prog, gb);
+  }
+
+  // ---- core sketches V^(i)_(n)
+  std::vector<void*> V((size_t)s * d);
+  if (P.kind == TSK_SKETCH_KRP) {
+    const int64_t m = P.ow[0];
+    std::vector<KrpDesc> kd;
+    std::vector<ReduceJob> red;
+    int64_t tiles0 = 0, ktmax = 0;
+    for (int i = 0; i < s; ++i)
+      for (int n = 0; n < d; ++n) {
+        int64_t Kc = 1;
+        for (int k = 0; k < d; ++k)
+          if (k != n) Kc *= P.r(i, k);
+        tiles0 += ceil_div(P.r(i, n), 64) * ceil_div(m, 64);
+        ktmax = std::max<int64_t>(ktmax, ceil_div(Kc, ts64 ? 16 : 32));
+      }
+    const int splits = choose_splits(tiles0, ktmax, 1024);
+    int64_t tiles = 0;
+    for (int i = 0; i < s; ++i)
+      for (int n = 0; n < d; ++n) {
+        KrpDesc D{};
+        D.G = core_s[i];
+        int64_t Kc = 1;
+        for (int k = 0; k < kMaxOrder; ++k) {
+          D.r[k] = k < d ? P.r(i, k) : 1;
+          D.P[k] = k < d ? Pf[(size_t)i * d + k] : nullptr;
+          if (k < d && k != n) Kc *= P.r(i, k);
+        }
+        const int64_t rn = P.r(i, n);
+        D.order = d;
+        D.mode = n;
+        D.m = (int)m;
+        D.Kc = Kc;
+        D.alpha = 1.0;
+        D.tiles_m = (int)ceil_div(rn, 64);
+        D.tiles_n = (int)ceil_div(m, 64);
+        void* v = ar.take(rn * m * es);
+        V[(size_t)i * d + n] = v;
+        const int sp = (int)std::min<int64_t>(splits, std::max<int64_t>(1, ceil_div(Kc, ts64 ? 16 : 32) / 2));
+        D.splits = sp;
+        if (sp > 1) {
+          void* part = ar.take((size_t)sp * rn * m * es);
+          D.V = part;
+          D.strideSplit = rn * m;
+          red.push_back(ReduceJob{v, part, rn, m, rn, rn, rn * m, sp, 0, ts64, ts64});
+        } else {
+          D.V = v;
+          D.strideSplit = 0;
+        }
+        D.tile_begin = tiles;
+        tiles += (int64_t)D.tiles_m * D.tiles_n * sp;
+        kd.push_back(D);
+      }
+    Step st{};
+    st.kind = S_KRP;
+    st.prec = P.ps;
+    st.meta = prog.put(kd);
+    st.count = (int)kd.size();
+    st.tiles = tiles;
+    prog.steps.push_back(st);
+    if (!red.empty()) {
+      Step r{};
+      r.kind = S_REDUCE;
+      r.meta = prog.put(red);
+      r.count = (int)red.size();
+      prog.steps.push_back(r);
+    }
+  } else {
+    // Kronecker: V = G x_{k != n} (Omega_k^T U_k), TTM chain in ascending mode order
+    // (Algorithm 4, inner loop), all (term, mode) chains advanced together.
+    struct Chain {
+      std::vector<int64_t> shape;
+      const void* cur;
+      void* buf[2];
+      int which;
+      int i, n;
+    };
+    std::vector<Chain> ch;
+    for (int i = 0; i < s; ++i)
+      for (int n = 0; n < d; ++n) {
+        Chain c;
+        for (int k = 0; k < d; ++k) c.shape.push_back(P.r(i, k));
+        c.cur = core_s[i];
+        // largest intermediate along the chain
+        int64_t mx = 1;
+        std::vector<int64_t> sh = c.shape;
+        for (int k = 0; k < d; ++k) {
+          if (k == n) continue;
+          sh[k] = P.ow[k];
+          int64_t sz = 1;
+          for (auto x : sh) sz *= x;
+          mx = std::max(mx, sz);
+        }
+        c.buf[0] = ar.take(mx * es);
+        c.buf[1] = ar.take(mx * es);
+        c.which = 0;
+        c.i = i;
+        c.n = n;
+        ch.push_back(c);
+      }
+    for (int step = 0; step < d - 1; ++step) {
+      GemmBatch gb(P.ps);
+      for (auto& c : ch) {
+        // the step-th mode other than n
+        int k = -1, cnt = 0;
+        for (int j = 0; j < d; ++j)
+          if (j != c.n) {
+            if (cnt == step) k = j;
+            ++cnt;
+          }
+        const int64_t rk = c.shape[k], q = P.ow[k];
+        const void* Pk = Pf[(size_t)c.i * d + k];  // r_k x q_k
+        void* outp = c.buf[c.which];
+        int64_t L = 1, Rr = 1;
+        for (int j = 0; j < k; ++j) L *= c.shape[j];
+        for (int j = k + 1; j < d; ++j) Rr *= c.shape[j];
+        if (k == 0) {
+          // out (q x Rr) = P_0^T (q x r_0) . T_(0) (r_0 x Rr)
+          gb.add(outp, ts64, q, 0, (int)q, (int)Rr, 1, 0,
+                 {seg(Pk, rk, 1, 0, c.cur, rk, 1, 0, rk)});
+        } else {
+          // per trailing index: out_b (L x q) = T_b (L x r_k) . P_k (r_k x q)
+          gb.add(outp, ts64, L, L * q, (int)L, (int)q, (int)Rr, 0,
+                 {seg(c.cur, 1, L, L * rk, Pk, rk, 1, 0, rk)});
+        }
+        c.shape[k] = q;
+        c.cur = outp;
+        c.which ^= 1;
+      }
+      emit_gemm(prog, gb);
+    }
+    for (auto& c : ch) V[(size_t)c.i * d + c.n] = (void*)c.cur;
+  }
+
+  // ---- term expansion Y_n = sum_i c_i U_n^(i) V^(i)_(n)  (FP64 output)
+  std::vector<double*> Y(d);
+  for (int n = 0; n < d; ++n)
+    Y[n] = out.recompress ? (double*)ar.take(P.dims[n] * P.W[n] * 8) : out.Y[n];
+  {
+    GemmBatch gb(P.ps);
+    for (int n = 0; n < d; ++n) {
+      const int64_t nn = P.dims[n];
+      std::vector<GemmSeg> sg;
+      if (P.kind == TSK_SKETCH_KRP) {
+        for (int i = 0; i < s; ++i) {
+          const int64_t r = P.r(i, n);
+          sg.push_back(seg(fac_s[(size_t)i * d + n], 1, nn, 0, V[(size_t)i * d + n], r, 1, 0, r,
+                           P.coeffs[i]));
+        }
+        gb.add(Y[n], true, nn, 0, (int)nn, (int)P.W[n], 1, 0, sg);
+      } else {
+        int64_t L = 1, T = 1;
+        for (int k = 0; k < n; ++k) L *= P.ow[k];
+        for (int k = n + 1; k < d; ++k) T *= P.ow[k];
+        for (int i = 0; i < s; ++i) {
+          const int64_t r = P.r(i, n);
+          sg.push_back(seg(fac_s[(size_t)i * d + n], 1, nn, 0, V[(size_t)i * d + n], 1, L, L * r,
+                           r, P.coeffs[i]));
+        }
+        gb.add(Y[n], true, nn, nn * L, (int)nn, (int)L, (int)T, 0, sg);
+      }
+    }
+    emit_gemm(prog, gb);
+  }
+  if (!out.recompress) return;
+
+  // ---- thin QR of every Y_n in FP64
+  std::vector<QrDesc> qd(d);
+  std::vector<double*> Qd(d);
+  bool any_chol = false;
+  int32_t* flags = (int32_t*)ar.take(sizeof(int32_t) * d);
+  for (int n = 0; n < d; ++n) {
+    const int64_t nn = P.dims[n], W = P.W[n], w = P.w[n];
+    QrDesc& q = qd[n];
+    q.Y = Y[n];
+    Qd[n] = out.out_f64 ? (double*)out.Q[n] : (double*)ar.take(nn * w * 8);
+    q.Q = Qd[n];
+    q.R = out.R.empty() ? nullptr : out.R[n];
+    q.n = nn;
+    q.W = W;
+    q.w = w;
+    q.flag = flags + n;
+    q.hh = (double*)ar.take(nn * W * 8);
+    q.tau = (double*)ar.take(W * 8);
+    const bool chol = P.qr_policy != 1 && W <= 96 && W <= nn;
+    if (chol) {
+      any_chol = true;
+      q.gram_splits = (int)std::min<int64_t>(16, std::max<int64_t>(1, nn / 64));
+      q.gram_part = (double*)ar.take((size_t)q.gram_splits * W * W * 8);
+      q.rinv = (double*)ar.take(W * W * 8);
+      q.r1 = (double*)ar.take(W * W * 8);
+      q.q1 = (double*)ar.take(nn * W * 8);
+    }
+  }
+  const size_t qmeta = prog.put(qd);
+  {
+    // flags: 0 where Cholesky QR2 applies, 1 where Householder is used directly
+    Step f{};
+    f.kind = S_FILL;
+    f.ptr = flags;
+    f.rows = d;
+    f.value = 0;
+    prog.steps.push_back(f);
+    for (int n = 0; n < d; ++n) {
+      if (qd[n].gram_part != nullptr) continue;
+      Step g{};
+      g.kind = S_FILL;
+      g.ptr = flags + n;
+      g.rows = 1;
+      g.value = 1;
+      prog.steps.push_back(g);
+    }
+  }
+  if (any_chol) {
+    for (int pass = 1; pass <= 2; ++pass) {
+      GemmBatch gram(P_FP64);
+      for (int n = 0; n < d; ++n) {
+        const QrDesc& q = qd[n];
+        if (q.gram_part == nullptr) continue;
+        const double* src = pass == 1 ? q.Y : q.q1;
+        // K-split of the Gram over row blocks, partials summed by the Cholesky kernel
+        const int64_t rows_per = ceil_div(q.n, q.gram_splits);
+        for (int sp = 0; sp < q.gram_splits; ++sp) {
+          const int64_t r0 = sp * rows_per, rl = std::min<int64_t>(rows_per, q.n - r0);
+          double* C = q.gram_part + (size_t)sp * q.W * q.W;
+          if (rl <= 0) {
+            // empty block: contributes zero (K = 0 GEMM writes zeros)
+            gram.add(C, true, q.W, 0, (int)q.W, (int)q.W, 1, 0,
+                     {seg(src, q.n, 1, 0, src, q.n, 1, 0, 0)});
+            continue;
+          }
+          gram.add(C, true, q.W, 0, (int)q.W, (int)q.W, 1, 0,
+                   {seg(src + r0, q.n, 1, 0, src + r0, q.n, 1, 0, rl)});
+        }
+      }
+      emit_gemm(prog, gram);
+      Step c{};
+      c.kind = S_CHOL;
+      c.meta = qmeta;
+      c.count = d;
+      c.pass = pass;
+      c.tol = pass == 1 ? 1e-11 : 1e-2;
+      prog.steps.push_back(c);
+      GemmBatch qq(P_FP64);
+      for (int n = 0; n < d; ++n) {
+        const QrDesc& q = qd[n];
+        if (q.gram_part == nullptr) continue;
+        const double* src = pass == 1 ? q.Y : q.q1;
+        double* dst = pass == 1 ? q.q1 : q.Q;
+        qq.add(dst, true, q.n, 0, (int)q.n, (int)q.W, 1, 0,
+               {seg(src, 1, q.n, 0, q.rinv, q.W, 1, 0, q.W)});
+      }
+      emit_gemm(prog, qq);
+    }
+  }
+  {
+    Step hh{};
+    hh.kind = S_HOUSE;
+    hh.meta = qmeta;
+    hh.count = d;
+    hh.force = 0;
+    hh.ptr = d_counter;
+    prog.steps.push_back(hh);
+  }
+
+  // ---- core projection (Section 3.3): W_k^(i) = Q_k^T U_k^(i), then the
+  // multi-TTM H = sum_i c_i G^(i) x_1 W_1^(i) ... x_d W_d^(i)
+  std::vector<const void*> Qp(d);
+  std::vector<CopyJob> cq;
+  for (int n = 0; n < d; ++n) {
+    if (tp64) {
+      Qp[n] = Qd[n];
+    } else {
+      void* p = ar.take(P.dims[n] * P.w[n] * 4);
+      cq.push_back(CopyJob{p, Qd[n], P.dims[n], P.w[n], P.dims[n], P.dims[n], 0, 1});
+      Qp[n] = p;
+    }
+    if (!out.out_f64)
+      cq.push_back(CopyJob{out.Q[n], Qd[n], P.dims[n], P.w[n], P.dims[n], P.dims[n], 0, 1});
+  }
+  // inputs in the projection element type
+  std::vector<const void*> core_p(s), fac_p((size_t)s * d);
+  for (int i = 0; i < s; ++i) {
+    int64_t csize = 1;
+    for (int k = 0; k < d; ++k) csize *= P.r(i, k);
+    if (P.in_f64 == tp64) {
+      core_p[i] = P.cores[i];
+    } else if (ts64 == tp64) {
+      core_p[i] = core_s[i];
+    } else {
+      void* p = ar.take(csize * ep);
+      cq.push_back(CopyJob{p, P.cores[i], csize, 1, csize, csize, tp64, P.in_f64});
+      core_p[i] = p;
+    }
+    for (int k = 0; k < d; ++k) {
+      const size_t idx = (size_t)i * d + k;
+      if (P.in_f64 == tp64) {
+        fac_p[idx] = P.factors[idx];
+      } else if (ts64 == tp64) {
+        fac_p[idx] = fac_s[idx];
+      } else {
+        void* p = ar.take(P.dims[k] * P.r(i, k) * ep);
+        cq.push_back(CopyJob{p, P.factors[idx], P.dims[k], P.r(i, k), P.dims[k], P.dims[k], tp64,
+                             P.in_f64});
+        fac_p[idx] = p;
+      }
+    }
+  }
+  emit_copies(prog, cq);
+  std::vector<void*> Wm((size_t)s * d);
+  {
+    GemmBatch gb(P.pp);
+    int64_t tiles0 = 0, kt = 0;
+    for (int i = 0; i < s; ++i)
+      for (int k = 0; k < d; ++k) {
+        tiles0 += ceil_div(P.w[k], 64) * ceil_div(P.r(i, k), 64);
+        kt = std::max<int64_t>(kt, ceil_div(P.dims[k], tp64 ? 16 : 32));
+      }
+    const int splits = choose_splits(tiles0, kt);
+    for (int i = 0; i < s; ++i)
+      for (int k = 0; k < d; ++k) {
+        const int64_t n = P.dims[k], r = P.r(i, k), w = P.w[k];
+        void* p = ar.take(w * r * ep);
+        Wm[(size_t)i * d + k] = p;
+        void* part = splits > 1 ? ar.take((size_t)splits * w * r * ep) : nullptr;
+        gb.add(p, tp64, w, 0, (int)w, (int)r, 1, 0,
+               {seg(Qp[k], n, 1, 0, fac_p[(size_t)i * d + k], n, 1, 0, n)}, splits, part);
+      }
+    emit_gemm(prog, gb);
+  }
+  // multi-TTM, modes 0..d-2 per term, then the last mode K-concatenated over terms
+  std::vector<std::vector<int64_t>> shape(s);
+  std::vector<const void*> cur(s);
+  std::vector<void*> buf0(s), buf1(s);
+  for (int i = 0; i < s; ++i) {
+    for (int k = 0; k < d; ++k) shape[i].push_back(P.r(i, k));
+    int64_t mx = 1;
+    std::vector<int64_t> sh = shape[i];
+    for (int k = 0; k < d - 1; ++k) {
+      sh[k] = P.w[k];
+      int64_t sz = 1;
+      for (auto x : sh) sz *= x;
+      mx = std::max(mx, sz);
+    }
+    buf0[i] = ar.take(mx * ep);
+    buf1[i] = ar.take(mx * ep);
+    cur[i] = core_p[i];
+  }
+  for (int k = 0; k < d - 1; ++k) {
+    GemmBatch gb(P.pp);
+    for (int i = 0; i < s; ++i) {
+      const int64_t rk = shape[i][k], w = P.w[k];
+      const void* Wk = Wm[(size_t)i * d + k];  // w x r_k
+      void* outp = (k % 2 == 0) ? buf0[i] : buf1[i];
+      int64_t L = 1, Rr = 1;
+      for (int j = 0; j < k; ++j) L *= shape[i][j];
+      for (int j = k + 1; j < d; ++j) Rr *= shape[i][j];
+      if (k == 0) {
+        gb.add(outp, tp64, w, 0, (int)w, (int)Rr, 1, 0, {seg(Wk, 1, w, 0, cur[i], rk, 1, 0, rk)});
+      } else {
+        gb.add(outp, tp64, L, L * w, (int)L, (int)w, (int)Rr, 0,
+               {seg(cur[i], 1, L, L * rk, Wk, 1, w, 0, rk)});
+      }
+      shape[i][k] = w;
+      cur[i] = outp;
+    }
+    emit_gemm(prog, gb);
+  }
+  {
+    GemmBatch gb(P.pp);
+    int64_t L = 1;
+    for (int k = 0; k < d - 1; ++k) L *= P.w[k];
+    const int64_t w = P.w[d - 1];
+    std::vector<GemmSeg> sg;
+    for (int i = 0; i < s; ++i) {
+      const int64_t rl = shape[i][d - 1];
+      sg.push_back(seg(cur[i], 1, L, 0, Wm[(size_t)i * d + d - 1], 1, w, 0, rl, P.coeffs[i]));
+    }
+    int64_t kt = 0;
+    for (int i = 0; i < s; ++i) kt += ceil_div(shape[i][d - 1], tp64 ? 16 : 32);
+    const int splits = choose_splits(ceil_div(L, 64) * ceil_div(w, 64), kt);
+    void* part = splits > 1 ? ar.take((size_t)splits * L * w * esize(out.out_f64)) : nullptr;
+    gb.add(out.H, out.out_f64, L, 0, (int)L, (int)w, 1, 0, sg, splits, part);
+    emit_gemm(prog, gb);
+  }
+}
+
+// ------------------------------------------------------------------ execution
+tsk_status acquire_staging(tsk_handle h, size_t bytes, bool capturing, void** host,
+                           hipEvent_t* ev) {
+  if (capturing) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, std::max<size_t>(bytes, 64), hipHostMallocDefault) != hipSuccess)
+      return fail(h, TSK_ERR_OUT_OF_MEMORY, "pinned staging allocation failed");
+    h->pinned_keep.push_back(p);
+    *host = p;
+    *ev = nullptr;
+    return TSK_OK;
+  }
+  if (h->ring.empty()) h->ring.resize(8);
+  Staging& sl = h->ring[h->ring_next];
+  h->ring_next = (h->ring_next + 1) % h->ring.size();
+  if (sl.done == nullptr) {
+    if (hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+      return fail(h, TSK_ERR_DEVICE, "hipEventCreate failed");
+  } else if (hipEventSynchronize(sl.done) != hipSuccess) {
+    return fail(h, TSK_ERR_DEVICE, "waiting for a staging slot failed");
+  }
+  if (sl.cap < bytes) {
+    if (sl.host) hipHostFree(sl.host);
+    sl.host = nullptr;
+    const size_t cap = std::max<size_t>(align_up(bytes, 65536), 65536);
+    if (hipHostMalloc(&sl.host, cap, hipHostMallocDefault) != hipSuccess) {
+      sl.cap = 0;
+      return fail(h, TSK_ERR_OUT_OF_MEMORY, "pinned staging allocation failed");
+    }
+    sl.cap = cap;
+  }
+  *host = sl.host;
+  *ev = sl.done;
+  return TSK_OK;
+}
+
+tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream) {
+  char* meta = ws + prog.meta_region;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess)
+    return fail(h, TSK_ERR_DEVICE, "hipStreamIsCapturing failed");
+  const bool capturing = cs == hipStreamCaptureStatusActive;
+  if (!prog.blob.empty()) {
+    void* host = nullptr;
+    hipEvent_t ev = nullptr;
+    tsk_status st = acquire_staging(h, prog.blob.size(), capturing, &host, &ev);
+    if (st != TSK_OK) return st;
+    std::memcpy(host, prog.blob.data(), prog.blob.size());
+    if (hipMemcpyAsync(meta, host, prog.blob.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
+      return fail(h, TSK_ERR_DEVICE, "descriptor upload failed");
+    if (ev != nullptr && hipEventRecord(ev, stream) != hipSuccess)
+      return fail(h, TSK_ERR_DEVICE, "hipEventRecord failed");
+  }
+  for (const Step& st : prog.steps) {
+    hipError_t e = hipSuccess;
+    switch (st.kind) {
+      case S_OMEGA: e = launch_omega(st.seed, st.mode, st.rows, st.cols, st.ptr, st.f64, stream); break;
+      case S_GEMM:
+        e = launch_gemm(st.prec, (const GemmDesc*)(meta + st.meta), st.count,
+                        (const GemmSeg*)(meta + st.meta2), st.tiles, stream);
+        break;
+      case S_KRP: e = launch_krp(st.prec, (const KrpDesc*)(meta + st.meta), st.count, st.tiles, stream); break;
+      case S_REDUCE: e = launch_reduce((const ReduceJob*)(meta + st.meta), st.count, stream); break;
+      case S_COPY: e = launch_copy((const CopyJob*)(meta + st.meta), st.count, stream); break;
+      case S_FILL: e = launch_fill_i32((int32_t*)st.ptr, st.rows, st.value, stream); break;
+      case S_CHOL: e = launch_chol((const QrDesc*)(meta + st.meta), st.count, st.pass, st.tol, stream); break;
+      case S_HOUSE:
+        e = launch_householder((const QrDesc*)(meta + st.meta), st.count, st.force, (int64_t*)st.ptr, stream);
+        break;
+    }
+    if (e != hipSuccess) return fail(h, TSK_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  }
+  return TSK_OK;
+}
+
+// Plan into a null-based arena to size the workspace, then rebase.
+tsk_status plan(tsk_handle h, const Problem& P, const Outputs& out, char* ws, Program& prog,
+                size_t* bytes) {
+  Arena ar;
+  ar.base = ws;
+  build_sum(P, out, ar, prog, h ? h->d_counter : nullptr);
+  prog.meta_region = align_up(ar.top, 256);
+  *bytes = prog.meta_region + align_up(prog.blob.size(), 256) + 256;
+  return TSK_OK;
+}
+
+tsk_status set_device(tsk_handle h) {
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, TSK_ERR_DEVICE, "hipSetDevice failed");
+  return TSK_OK;
+}
+
+
+// ------------------------------------------------------------------ plan self-check
+// Host-only verification that every address a planned launch sequence can
+// touch lies inside a buffer it is allowed to touch: the workspace or one of
+// the caller's buffers, each given a synthetic, widely separated address.
+// Used by the CPU test suite so that descriptor mistakes surface before any
+// kernel runs.
+struct Region {
+  uintptr_t lo, hi;  // [lo, hi)
+  const char* name;
+};
+
+struct Checker {
+  std::vector<Region> regions;
+  std::string err;
+  bool ok = true;
+  void add(const void* p, size_t bytes, const char* name) {
+    regions.push_back(Region{(uintptr_t)p, (uintptr_t)p + bytes, name});
+  }
+  void span(const void* base, int64_t first, int64_t last, size_t es, const char* what) {
+    if (!ok) return;
+    if (first > last) return;  // empty access
+    const uintptr_t lo = (uintptr_t)base + (uintptr_t)(first * (int64_t)es);
+    const uintptr_t hi = (uintptr_t)base + (uintptr_t)((last + 1) * (int64_t)es);
+    for (const Region& r : regions)
+      if (lo >= r.lo && hi <= r.hi) return;
+    ok = false;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: [%#zx, %#zx) outside every buffer", what, (size_t)lo, (size_t)hi);
+    err = buf;
+  }
+};
+
+// Largest value of sum_i idx_i * stride_i for 0 <= idx_i < ext_i.
+int64_t max_off(std::initializer_list<std::pair<int64_t, int64_t>> terms) {
+  int64_t o = 0;
+  for (auto& t : terms) o += (t.first - 1) * t.second;
+  return o;
+}
+
+void check_program(const Program& prog, Checker& ck) {
+  const char* blob = prog.blob.data();
+  for (const Step& st : prog.steps) {
+    switch (st.kind) {
+      case S_OMEGA:
+        ck.span(st.ptr, 0, st.rows * st.cols - 1, st.f64 ? 8 : 4, "omega");
+        break;
+      case S_FILL: ck.span(st.ptr, 0, st.rows - 1, 4, "fill"); break;
+      case S_GEMM: {
+        const GemmDesc* ds = (const GemmDesc*)(blob + st.meta);
+        const GemmSeg* sg = (const GemmSeg*)(blob + st.meta2);
+        const size_t ein = st.prec == P_FP64 ? 8 : 4;
+        int64_t tiles = 0;
+        for (int i = 0; i < st.count; ++i) {
+          const GemmDesc& D = ds[i];
+          if (D.tile_begin != tiles) { ck.ok = false; ck.err = "gemm tile prefix mismatch"; return; }
+          tiles += (int64_t)D.tiles_m * D.tiles_n * D.batch * D.splits;
+          if (D.tiles_m * 64 < D.M || D.tiles_n * 64 < D.N) { ck.ok = false; ck.err = "gemm tiles too few"; return; }
+          for (int j = 0; j < D.seg_count; ++j) {
+            const GemmSeg& S = sg[D.seg_begin + j];
+            if (S.a_sx != 1 && S.a_sk != 1) { ck.ok = false; ck.err = "gemm A has no unit stride"; return; }
+            if (S.b_sx != 1 && S.b_sk != 1) { ck.ok = false; ck.err = "gemm B has no unit stride"; return; }
+            if (S.K == 0) continue;
+            ck.span(S.A, 0, (D.batch - 1) * S.strideA + max_off({{D.M, S.a_sx}, {S.K, S.a_sk}}), ein, "gemm A");
+            ck.span(S.B, 0, (D.batch - 1) * S.strideB + max_off({{D.N, S.b_sx}, {S.K, S.b_sk}}), ein, "gemm B");
+          }
+          ck.span(D.C, 0, (D.batch - 1) * D.strideC + (D.splits - 1) * D.strideSplit +
+                              max_off({{D.M, 1}, {D.N, D.ldc}}), D.c_f64 ? 8 : 4, "gemm C");
+        }
+        if (tiles != st.tiles) { ck.ok = false; ck.err = "gemm total tiles mismatch"; }
+        break;
+      }
+      case S_KRP: {
+        const KrpDesc* ds = (const KrpDesc*)(blob + st.meta);
+        const size_t e = st.prec == P_FP64 ? 8 : 4;
+        int64_t tiles = 0;
+        for (int i = 0; i < st.count; ++i) {
+          const KrpDesc& D = ds[i];
+          if (D.tile_begin != tiles) { ck.ok = false; ck.err = "krp tile prefix mismatch"; return; }
+          tiles += (int64_t)D.tiles_m * D.tiles_n * D.splits;
+          int64_t cs = 1, Kc = 1;
+          for (int k = 0; k < D.order; ++k) {
+            cs *= D.r[k];
+            if (k != D.mode) {
+              Kc *= D.r[k];
+              ck.span(D.P[k], 0, (int64_t)D.r[k] * D.m - 1, e, "krp P");
+            }
+          }
+          if (Kc != D.Kc) { ck.ok = false; ck.err = "krp Kc mismatch"; return; }
+          ck.span(D.G, 0, cs - 1, e, "krp G");
+          ck.span(D.V, 0, (D.splits - 1) * D.strideSplit + (int64_t)D.r[D.mode] * D.m - 1, e, "krp V");
+        }
+        if (tiles != st.tiles) { ck.ok = false; ck.err = "krp total tiles mismatch"; }
+        break;
+      }
+      case S_REDUCE: {
+        const ReduceJob* js = (const ReduceJob*)(blob + st.meta);
+        for (int i = 0; i < st.count; ++i) {
+          const ReduceJob& J = js[i];
+          ck.span(J.out, 0, max_off({{J.rows, 1}, {J.cols, J.ld_out}}), J.out_f64 ? 8 : 4, "reduce out");
+          ck.span(J.part, 0, (J.parts - 1) * J.stride_part + max_off({{J.rows, 1}, {J.cols, J.ld_part}}),
+                  J.part_f64 ? 8 : 4, "reduce part");
+        }
+        break;
+      }
+      case S_COPY: {
+        const CopyJob* js = (const CopyJob*)(blob + st.meta);
+        for (int i = 0; i < st.count; ++i) {
+          const CopyJob& J = js[i];
+          ck.span(J.dst, 0, max_off({{J.rows, 1}, {J.cols, J.ld_dst}}), J.dst_f64 ? 8 : 4, "copy dst");
+          ck.span(J.src, 0, max_off({{J.rows, 1}, {J.cols, J.ld_src}}), J.src_f64 ? 8 : 4, "copy src");
+        }
+        break;
+      }
+      case S_CHOL:
+      case S_HOUSE: {
+        const QrDesc* qs = (const QrDesc*)(blob + st.meta);
+        for (int i = 0; i < st.count; ++i) {
+          const QrDesc& q = qs[i];
+          ck.span(q.Y, 0, q.n * q.W - 1, 8, "qr Y");
+          ck.span(q.Q, 0, q.n * q.w - 1, 8, "qr Q");
+          ck.span(q.hh, 0, q.n * q.W - 1, 8, "qr hh");
+          ck.span(q.tau, 0, q.W - 1, 8, "qr tau");
+          ck.span(q.flag, 0, 0, 4, "qr flag");
+          if (q.R) ck.span(q.R, 0, q.w * q.W - 1, 8, "qr R");
+          if (st.kind == S_CHOL && q.gram_part && q.W <= 96 && q.W <= q.n) {
+            ck.span(q.gram_part, 0, (int64_t)q.gram_splits * q.W * q.W - 1, 8, "qr gram");
+            ck.span(q.rinv, 0, q.W * q.W - 1, 8, "qr rinv");
+            ck.span(q.r1, 0, q.W * q.W - 1, 8, "qr r1");
+            ck.span(q.q1, 0, q.n * q.W - 1, 8, "qr q1");
+          }
+        }
+        break;
+      }
+    }
+    if (!ck.ok) return;
+  }
+}
+
+}  // namespace
+
+extern "C" int tsk_plan_selfcheck(const tsk_tucker_sum* sum, const tsk_sketch_spec* spec,
+                                  int out_dtype, int sketch_only, int with_r, char* msg,
+                                  size_t msglen) {
+  Problem P;
+  tsk_handle_ scratch_handle;
+  tsk_status st = validate(&scratch_handle, sum, spec, P);
+  auto say = [&](const std::string& s) {
+    if (msg && msglen) {
+      std::strncpy(msg, s.c_str(), msglen - 1);
+      msg[msglen - 1] = 0;
+    }
+  };
+  if (st != TSK_OK) {
+    say(scratch_handle.err);
+    return st;
+  }
+  Checker ck;
+  uintptr_t next = (uintptr_t)1 << 44;
+  auto fake = [&](size_t bytes, const char* name) {
+    void* p = (void*)next;
+    ck.add(p, bytes, name);
+    next += align_up(bytes, (size_t)1 << 20) + ((size_t)1 << 30);
+    return p;
+  };
+  const size_t ein = P.in_f64 ? 8 : 4;
+  for (int i = 0; i < P.s; ++i) {
+    int64_t cs = 1;
+    for (int k = 0; k < P.d; ++k) cs *= P.r(i, k);
+    P.cores[i] = fake(cs * ein, "core");
+    for (int k = 0; k < P.d; ++k)
+      P.factors[(size_t)i * P.d + k] = fake(P.dims[k] * P.r(i, k) * ein, "factor");
+  }
+  for (size_t k = 0; k < P.omega.size(); ++k) P.omega[k] = fake(P.dims[k] * P.ow[k] * ein, "omega");
+  Outputs out;
+  out.recompress = !sketch_only;
+  out.out_f64 = out_dtype == TSK_F64;
+  const size_t eo = out.out_f64 ? 8 : 4;
+  int64_t hsize = 1;
+  for (int n = 0; n < P.d; ++n) {
+    if (sketch_only) out.Y.push_back((double*)fake(P.dims[n] * P.W[n] * 8, "Y"));
+    out.Q.push_back(fake(P.dims[n] * P.w[n] * eo, "Q"));
+    if (with_r) out.R.push_back((double*)fake(P.w[n] * P.W[n] * 8, "R"));
+    hsize *= P.w[n];
+  }
+  out.H = fake(hsize * eo, "H");
+  int64_t* counter = (int64_t*)fake(256, "counter");
+  // size query, then the real plan against a fake workspace
+  Program p0;
+  size_t need = 0;
+  {
+    Arena ar;
+    build_sum(P, out, ar, p0, counter);
+    need = align_up(ar.top, 256) + align_up(p0.blob.size(), 256) + 256;
+  }
+  char* ws = (char*)fake(need, "workspace");
+  Program prog;
+  size_t need2 = 0;
+  plan(nullptr, P, out, ws, prog, &need2);
+  if (need2 != need) {
+    say("workspace size differs between the size query and the call");
+    return 99;
+  }
+  check_program(prog, ck);
+  if (!ck.ok) {
+    say(ck.err);
+    return 98;
+  }
+  say("ok");
+  return 0;
+}
+
+// ====================================================================== C ABI
+extern "C" {
+
+tsk_status tsk_create(tsk_handle* handle, int device) {
+  if (handle == nullptr) return TSK_ERR_INVALID_ARG;
+  *handle = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return TSK_ERR_INVALID_ARG;
+  tsk_handle h = new (std::nothrow) tsk_handle_();
+  if (h == nullptr) return TSK_ERR_OUT_OF_MEMORY;
+  h->device = device;
+  if (hipSetDevice(device) != hipSuccess || hipMalloc((void**)&h->d_counter, 256) != hipSuccess) {
+    delete h;
+    return TSK_ERR_DEVICE;
+  }
+  if (hipMemset(h->d_counter, 0, 256) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    hipFree(h->d_counter);
+    delete h;
+    return TSK_ERR_DEVICE;
+  }
+  *handle = h;
+  return TSK_OK;
+}
+
+tsk_status tsk_destroy(tsk_handle h) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  hipSetDevice(h->device);
+  hipDeviceSynchronize();
+  for (auto& sl : h->ring) {
+    if (sl.done) hipEventDestroy(sl.done);
+    if (sl.host) hipHostFree(sl.host);
+  }
+  for (void* p : h->pinned_keep) hipHostFree(p);
+  if (h->d_counter) hipFree(h->d_counter);
+  delete h;
+  return TSK_OK;
+}
+
+const char* tsk_status_string(tsk_status st) {
+  switch (st) {
+    case TSK_OK: return "TSK_OK";
+    case TSK_ERR_INVALID_ARG: return "TSK_ERR_INVALID_ARG";
+    case TSK_ERR_UNSUPPORTED: return "TSK_ERR_UNSUPPORTED";
+    case TSK_ERR_OUT_OF_MEMORY: return "TSK_ERR_OUT_OF_MEMORY";
+    case TSK_ERR_WORKSPACE_TOO_SMALL: return "TSK_ERR_WORKSPACE_TOO_SMALL";
+    case TSK_ERR_DEVICE: return "TSK_ERR_DEVICE";
+    case TSK_ERR_RANK_DEFICIENT: return "TSK_ERR_RANK_DEFICIENT";
+  }
+  return "unknown tsk_status";
+}
+
+const char* tsk_last_error_detail(tsk_handle h) { return h ? h->err.c_str() : ""; }
+
+tsk_status tsk_krp_width(int32_t order, const int32_t* ell, int32_t* m_out) {
+  if (order < 1 || ell == nullptr || m_out == nullptr) return TSK_ERR_INVALID_ARG;
+  int32_t m = 0;
+  for (int k = 0; k < order; ++k) {
+    if (ell[k] < 1) return TSK_ERR_INVALID_ARG;
+    m = std::max(m, ell[k]);
+  }
+  *m_out = m;
+  return TSK_OK;
+}
+
+tsk_status tsk_kron_sizes(int32_t order, const int32_t* ell, int32_t* q_out) {
+  if (order < 2 || order > kMaxOrder || ell == nullptr || q_out == nullptr) return TSK_ERR_INVALID_ARG;
+  // prod_j ell_j as an exact integer (unsigned __int128 holds up to 8 factors < 2^16)
+  unsigned __int128 prod = 1;
+  for (int k = 0; k < order; ++k) {
+    if (ell[k] < 1 || ell[k] > 65535) return TSK_ERR_INVALID_ARG;
+    prod *= (unsigned)ell[k];
+  }
+  for (int k = 0; k < order; ++k) {
+    for (int64_t q = 1;; ++q) {
+      unsigned __int128 p = 1;
+      bool big = false;
+      for (int e = 0; e < order - 1; ++e) {
+        p *= (unsigned __int128)(q * ell[k]);
+        if (p >= prod) { big = true; break; }
+      }
+      if (big || p >= prod) {
+        q_out[k] = (int32_t)q;
+        break;
+      }
+    }
+  }
+  return TSK_OK;
+}
+
+tsk_status tsk_sketch_widths(const tsk_tucker_sum* sum, const tsk_sketch_spec* spec,
+                             int64_t* sketch_width, int64_t* basis_width) {
+  Problem P;
+  tsk_status st = validate(nullptr, sum, spec, P);
+  if (st != TSK_OK) return st;
+  for (int n = 0; n < P.d; ++n) {
+    if (sketch_width) sketch_width[n] = P.W[n];
+    if (basis_width) basis_width[n] = P.w[n];
+  }
+  return TSK_OK;
+}
+
+tsk_status tsk_sketch_omega(tsk_handle h, uint64_t seed, int32_t mode, int64_t rows,
+                            int64_t cols, void* out, tsk_dtype out_dtype, void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  if (out == nullptr || rows < 1 || cols < 1 || mode < 0)
+    return fail(h, TSK_ERR_INVALID_ARG, "bad omega arguments");
+  if (out_dtype != TSK_F64 && out_dtype != TSK_F32) return fail(h, TSK_ERR_INVALID_ARG, "bad dtype");
+  tsk_status st = set_device(h);
+  if (st != TSK_OK) return st;
+  if (launch_omega(seed, mode, rows, cols, out, out_dtype == TSK_F64, (hipStream_t)stream) != hipSuccess)
+    return fail(h, TSK_ERR_DEVICE, "omega launch failed");
+  return TSK_OK;
+}
+
+tsk_status tucker_sum_workspace_size(tsk_handle h, const tsk_tucker_sum* sum,
+                                     const tsk_sketch_spec* spec, size_t* bytes) {
+  if (h == nullptr || bytes == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL handle or bytes");
+  h->err.clear();
+  Problem P;
+  tsk_status st = validate(h, sum, spec, P);
+  if (st != TSK_OK) return st;
+  // the recompress plan needs at least what the sketch-only plan needs
+  // the recompress plan needs at least what the sketch-only plan needs; the
+  // FP32- and FP64-output plans differ (Q staging vs. partial sizes): take both
+  size_t best = 0;
+  for (int o = 0; o < 2; ++o) {
+    Outputs out;
+    out.recompress = true;
+    out.out_f64 = o == 1;
+    out.Q.assign(P.d, nullptr);
+    out.R.assign(P.d, nullptr);
+    Program prog;
+    size_t b = 0;
+    plan(h, P, out, nullptr, prog, &b);
+    best = std::max(best, b);
+  }
+  *bytes = best;
+  return TSK_OK;
+}
+
+tsk_status tucker_sum_sketch(tsk_handle h, const tsk_tucker_sum* sum, const tsk_sketch_spec* spec,
+                             double* const* Y_out, void* ws, size_t ws_bytes, void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  Problem P;
+  tsk_status st = validate(h, sum, spec, P);
+  if (st != TSK_OK) return st;
+  if (Y_out == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "Y_out is NULL");
+  Outputs out;
+  out.recompress = false;
+  for (int n = 0; n < P.d; ++n) {
+    if (Y_out[n] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "Y_out[%d] is NULL", n);
+    out.Y.push_back(Y_out[n]);
+  }
+  if (ws == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  Program prog;
+  size_t need = 0;
+  plan(h, P, out, (char*)ws, prog, &need);
+  if (ws_bytes < need)
+    return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  if ((st = set_device(h)) != TSK_OK) return st;
+  return run_program(h, prog, (char*)ws, (hipStream_t)stream);
+}
+
+tsk_status tucker_sum_recompress(tsk_handle h, const tsk_tucker_sum* sum,
+                                 const tsk_sketch_spec* spec, void* const* Q_out, void* H_out,
+                                 tsk_dtype out_dtype, double* const* R_out, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  Problem P;
+  tsk_status st = validate(h, sum, spec, P);
+  if (st != TSK_OK) return st;
+  if (Q_out == nullptr || H_out == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "Q_out or H_out is NULL");
+  if (out_dtype != TSK_F64 && out_dtype != TSK_F32) return fail(h, TSK_ERR_INVALID_ARG, "bad out_dtype");
+  Outputs out;
+  out.recompress = true;
+  out.out_f64 = out_dtype == TSK_F64;
+  out.H = H_out;
+  for (int n = 0; n < P.d; ++n) {
+    if (Q_out[n] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "Q_out[%d] is NULL", n);
+    out.Q.push_back(Q_out[n]);
+    if (R_out != nullptr) {
+      if (R_out[n] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "R_out[%d] is NULL", n);
+      out.R.push_back(R_out[n]);
+    }
+  }
+  if (ws == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  Program prog;
+  size_t need = 0;
+  plan(h, P, out, (char*)ws, prog, &need);
+  if (ws_bytes < need)
+    return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  if ((st = set_device(h)) != TSK_OK) return st;
+  return run_program(h, prog, (char*)ws, (hipStream_t)stream);
+}
+
+tsk_status tsk_qr_fallback_count(tsk_handle h, void* stream, int64_t* count) {
+  if (h == nullptr || count == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL argument");
+  tsk_status st = set_device(h);
+  if (st != TSK_OK) return st;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return fail(h, TSK_ERR_DEVICE, "stream synchronisation failed");
+  if (hipMemcpy(count, h->d_counter, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(h, TSK_ERR_DEVICE, "counter read failed");
+  return TSK_OK;
+}
+
+}  // extern "C"

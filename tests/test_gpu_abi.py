@@ -1,0 +1,85 @@
+"""Error behaviour of the C ABI with a live handle: host-side errors enqueue
+nothing and leave outputs untouched."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import np_of, to_torch
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_13532_amd as tsk
+    from paper_2603_13532_amd import _lib
+    return tsk, _lib, _lib.load()
+
+
+def marshal(tsk, ts, kind="krp", sizes=(6,)):
+    cores, factors = to_torch(ts, DEV)
+    return tsk._Marshal(cores, factors, None, kind, sizes, 3, None, "fp64", "fp64", "auto")
+
+
+def test_workspace_too_small_and_null_outputs(env):
+    import torch
+    tsk, _lib, lib = env
+    ts = synth.random_sum(1, (30, 20, 25), [[3, 4, 5]])
+    m = marshal(tsk, ts)
+    h = tsk.Handle.get(DEV)
+    need = ctypes.c_size_t()
+    assert lib.tucker_sum_workspace_size(h.ptr, ctypes.byref(m.sum), ctypes.byref(m.spec),
+                                         ctypes.byref(need)) == 0
+    assert need.value > 0
+    ws = torch.empty(need.value, dtype=torch.uint8, device=DEV)
+    qs = [torch.full((n, 6), 7.0, dtype=torch.float64, device=DEV).t().contiguous().t() for n in m.dims]
+    hh = torch.full((6, 6, 6), 7.0, dtype=torch.float64, device=DEV)
+    cq = (ctypes.c_void_p * 3)(*[q.data_ptr() for q in qs])
+    st = lib.tucker_sum_recompress(h.ptr, ctypes.byref(m.sum), ctypes.byref(m.spec), cq,
+                                   ctypes.c_void_p(hh.data_ptr()), 0, None,
+                                   ctypes.c_void_p(ws.data_ptr()), need.value - 1, None)
+    assert st == 4
+    assert b"workspace" in lib.tsk_last_error_detail(h.ptr)
+    st = lib.tucker_sum_recompress(h.ptr, ctypes.byref(m.sum), ctypes.byref(m.spec), None,
+                                   ctypes.c_void_p(hh.data_ptr()), 0, None,
+                                   ctypes.c_void_p(ws.data_ptr()), need.value, None)
+    assert st == 1
+    misaligned = ctypes.c_void_p(ws.data_ptr() + 8)
+    st = lib.tucker_sum_recompress(h.ptr, ctypes.byref(m.sum), ctypes.byref(m.spec), cq,
+                                   ctypes.c_void_p(hh.data_ptr()), 0, None, misaligned,
+                                   need.value, None)
+    assert st == 1
+    torch.cuda.synchronize()
+    assert np.all(np_of(hh) == 7.0)
+    assert all(np.all(np_of(q) == 7.0) for q in qs)
+    # a valid call then succeeds
+    st = lib.tucker_sum_recompress(h.ptr, ctypes.byref(m.sum), ctypes.byref(m.spec), cq,
+                                   ctypes.c_void_p(hh.data_ptr()), 0, None,
+                                   ctypes.c_void_p(ws.data_ptr()), need.value, None)
+    assert st == 0
+    torch.cuda.synchronize()
+    assert not np.all(np_of(hh) == 7.0)
+
+
+def test_python_errors(env):
+    tsk, _lib, lib = env
+    ts = synth.random_sum(2, (30, 20, 25), [[3, 4, 5]])
+    cores, factors = to_torch(ts, DEV)
+    with pytest.raises(tsk.TskError) as ei:
+        tsk.tucker_sum_recompress(cores, factors, "krp", [0], 1)
+    assert ei.value.name == "TSK_ERR_INVALID_ARG"
+    with pytest.raises(ValueError):
+        tsk.tucker_sum_recompress(cores, [factors[0][:2]], "krp", [4], 1)
+
+
+def test_create_bad_device(env):
+    tsk, _lib, lib = env
+    h = ctypes.c_void_p()
+    assert lib.tsk_create(ctypes.byref(h), 999) == 1
+    assert lib.tsk_create(None, 0) == 1

@@ -1,0 +1,197 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle
+on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import synth
+from helpers import np_of, rel, to_torch
+from oracle import recompress as RC
+from oracle import sketch as S
+from oracle import tensor as T
+from oracle.omega import omega as oracle_omega
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def tsk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_13532_amd as m
+    return m
+
+
+def sizes_of(kind, ell_or_sizes):
+    return list(ell_or_sizes)
+
+
+def run(tsk, ts, kind, sizes, seed, **kw):
+    import torch
+    cores, factors = to_torch(ts, DEV, kw.pop("dtype", torch.float64))
+    out = tsk.tucker_sum_recompress(cores, factors, kind, sizes, seed, coeffs=ts["coeffs"], **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("seed,mode,rows,cols", [(1, 0, 64, 5), (2 ** 40 + 3, 2, 513, 74),
+                                                  (1002, 1, 512, 74), (7, 3, 1, 1), (9, 0, 3, 7)])
+def test_omega_bitwise(tsk, seed, mode, rows, cols):
+    import torch
+    want = oracle_omega(seed, mode, rows, cols)
+    got = np_of(tsk.sketch_omega(seed, mode, rows, cols, torch.float64, DEV))
+    mism = int(np.sum(got != want))
+    assert mism == 0, f"{mism} of {rows * cols} entries differ"
+    got32 = np_of(tsk.sketch_omega(seed, mode, rows, cols, torch.float32, DEV))
+    assert np.array_equal(got32, want)
+
+
+@pytest.mark.parametrize("kind", ["krp", "kron"])
+def test_sketch_tiny(tsk, kind):
+    import torch
+    ts = synth.config_tiny()
+    sizes = [24] if kind == "krp" else RC.kron_sizes(ts["ell"])
+    om = [oracle_omega(ts["omega_seed"], k, 64, w) for k, w in enumerate(RC.omega_widths(3, kind, sizes))]
+    want = S.structured_sketch(ts, om, kind)
+    cores, factors = to_torch(ts, DEV)
+    ys = tsk.tucker_sum_sketch(cores, factors, kind, sizes, ts["omega_seed"], coeffs=ts["coeffs"])
+    torch.cuda.synchronize()
+    for y, w in zip(ys, want):
+        assert y.shape == w.shape
+        assert rel(np_of(y), w) < 1e-13
+
+
+def check_recompress(tsk, ts, kind, sizes, seed, qtol=1e-10, htol=1e-11, **kw):
+    ref = RC.recompress(ts, kind, sizes, seed)
+    qs, h = run(tsk, ts, kind, sizes, seed, **kw)
+    for q, qr in zip(qs, ref["Q"]):
+        assert q.shape == qr.shape
+        assert rel(np_of(q), qr) < qtol
+    assert h.shape == ref["H"].shape
+    assert rel(np_of(h), ref["H"]) < htol
+    return ref, qs, h
+
+
+@pytest.mark.parametrize("kind", ["krp", "kron"])
+def test_recompress_tiny(tsk, kind):
+    ts = synth.config_tiny()
+    sizes = [24] if kind == "krp" else RC.kron_sizes(ts["ell"])
+    ref, qs, h = check_recompress(tsk, ts, kind, sizes, ts["omega_seed"])
+    x = T.sum_to_dense(ts)
+    e_gpu = T.rel_err(RC.reconstruct(np_of(h), [np_of(q) for q in qs]), x)
+    e_ref = T.rel_err(RC.reconstruct(ref["H"], ref["Q"]), x)
+    assert abs(e_gpu - e_ref) < 1e-12
+
+
+RAGGED = [
+    # (dims, ranks per term, kind, sizes): several tiles, ragged tails, uneven ranks
+    ((130, 70, 90), [[70, 5, 33], [1, 66, 12], [40, 40, 40]], "krp", [80]),
+    ((130, 70, 90), [[70, 5, 33], [1, 66, 12], [40, 40, 40]], "kron", [3, 5, 4]),
+    ((65, 33), [[17, 9], [65, 3]], "krp", [20]),
+    ((40, 30, 20, 25), [[6, 5, 4, 7], [3, 8, 2, 5]], "krp", [11]),
+    ((40, 30, 20, 25), [[6, 5, 4, 7], [3, 8, 2, 5]], "kron", [2, 3, 2, 2]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(RAGGED)))
+def test_recompress_ragged(tsk, case):
+    dims, ranks, kind, sizes = RAGGED[case]
+    ts = synth.random_sum(100 + case, dims, ranks, orthonormal_factors=False,
+                          coeffs=np.linspace(-1.5, 2.0, len(ranks)))
+    ref = RC.recompress(ts, kind, sizes, 31 + case)
+    import torch
+    cores, factors = to_torch(ts, DEV)
+    ys = tsk.tucker_sum_sketch(cores, factors, kind, sizes, 31 + case, coeffs=ts["coeffs"])
+    torch.cuda.synchronize()
+    for y, w in zip(ys, ref["Y"]):
+        assert rel(np_of(y), w) < 1e-13
+    check_recompress(tsk, ts, kind, sizes, 31 + case)
+
+
+def test_linearity_on_device(tsk):
+    import torch
+    ts = synth.random_sum(5, (70, 50, 60), [[8, 9, 7], [5, 6, 4], [9, 3, 8]], coeffs=[1.0, -2.0, 0.5])
+    cores, factors = to_torch(ts, DEV)
+    whole = tsk.tucker_sum_sketch(cores, factors, "krp", [12], 5, coeffs=ts["coeffs"])
+    acc = None
+    for i in range(3):
+        part = tsk.tucker_sum_sketch([cores[i]], [factors[i]], "krp", [12], 5, coeffs=[ts["coeffs"][i]])
+        acc = part if acc is None else [a + p for a, p in zip(acc, part)]
+    torch.cuda.synchronize()
+    for a, b in zip(whole, acc):
+        assert rel(np_of(a), np_of(b)) < 1e-13
+
+
+@pytest.mark.parametrize("kind,sizes", [("krp", [12]), ("kron", [3, 3, 3, 3])])
+def test_exact_recovery_rank_deficient(tsk, kind, sizes):
+    """Rank-10 sum sketched with 12 (or 27) columns: Y_n is rank deficient,
+    Cholesky QR breaks down and the device takes the Householder path; the
+    recompression is still exact."""
+    ts = synth.e1_low_rank_sum(seed=5, d=4, n=24, terms=20, r_true=10)
+    before = tsk.qr_fallback_count(DEV)
+    qs, h = run(tsk, ts, kind, sizes, 12)
+    after = tsk.qr_fallback_count(DEV)
+    assert after - before == 4
+    x = T.sum_to_dense(ts)
+    xh = RC.reconstruct(np_of(h), [np_of(q) for q in qs])
+    assert T.rel_err(xh, x) < 1e-12
+    for q in qs:
+        qn = np_of(q)
+        assert np.linalg.norm(qn.T @ qn - np.eye(qn.shape[1])) < 1e-12
+
+
+def test_householder_policy_matches_cholqr2(tsk):
+    ts = synth.random_sum(9, (96, 80, 72), [[10, 12, 9], [11, 7, 13]])
+    a_q, a_h = run(tsk, ts, "krp", [16], 3)
+    b_q, b_h = run(tsk, ts, "krp", [16], 3, qr_policy="householder")
+    for x, y in zip(a_q, b_q):
+        assert rel(np_of(x), np_of(y)) < 1e-11
+    assert rel(np_of(a_h), np_of(b_h)) < 1e-11
+    check_recompress(tsk, ts, "krp", [16], 3, qr_policy="householder")
+
+
+def test_zero_sum(tsk):
+    ts = synth.random_sum(10, (40, 30, 20), [[3, 4, 5], [2, 2, 2]], coeffs=[0.0, 0.0])
+    qs, h = run(tsk, ts, "krp", [6], 1)
+    assert np.all(np_of(h) == 0)
+    for q in qs:
+        qn = np_of(q)
+        assert np.linalg.norm(qn.T @ qn - np.eye(qn.shape[1])) < 1e-12
+
+
+def test_oversketch_width(tsk):
+    """m > n_k: economy QR keeps min(n_k, m) columns of that mode."""
+    ts = synth.random_sum(11, (9, 40, 30), [[3, 4, 5], [4, 3, 2]])
+    qs, h = run(tsk, ts, "krp", [14], 2)
+    assert [q.shape[1] for q in qs] == [9, 14, 14]
+    assert tuple(h.shape) == (9, 14, 14)
+    x = T.sum_to_dense(ts)
+    ref = RC.recompress(ts, "krp", [14], 2)
+    xh = RC.reconstruct(np_of(h), [np_of(q) for q in qs])
+    assert T.rel_err(xh, RC.reconstruct(ref["H"], ref["Q"])) < 1e-12
+
+
+def test_r_factor(tsk):
+    ts = synth.random_sum(12, (50, 60, 70), [[5, 6, 7], [7, 6, 5]])
+    qs, h, rs = run(tsk, ts, "krp", [10], 4, return_r=True)
+    ref = RC.recompress(ts, "krp", [10], 4)
+    for r, rr in zip(rs, ref["R"]):
+        assert rel(np_of(r), rr) < 1e-11
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kind", ["krp", "kron"])
+def test_structured_workload_fp64(tsk, kind):
+    """d=3, 512^3, 16 terms, ranks in [16, 48], decaying cores: KRP m = 74,
+    Kron q = 9 (S = 81)."""
+    ts = synth.config_structured()
+    sizes = [74] if kind == "krp" else RC.kron_sizes(ts["ell"])
+    check_recompress(tsk, ts, kind, sizes, ts["omega_seed"])
+
+
+@pytest.mark.slow
+def test_precision_workload_fp64(tsk):
+    """d=4, 256^4, 8 terms, cores 32^4, KRP m = 56, all FP64."""
+    ts = synth.config_precision()
+    check_recompress(tsk, ts, "krp", [56], ts["omega_seed"])

@@ -1,0 +1,87 @@
+"""Host-only bounds check of every planned launch: each address a kernel
+descriptor can reach must lie in the workspace or in a caller buffer of the
+right size.  Runs the library's planner on the CPU (no GPU), for every
+workload shape the GPU tests and the benchmark use."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.recompress import kron_sizes
+
+PRECS = ["fp64", "fp32", "bf16x1", "bf16x3", "bf16x6"]
+
+
+def selfcheck(dims, ranks, kind, sizes, sketch_prec="fp64", project_prec="fp64", in_f64=True,
+              out_f64=True, sketch_only=False, with_r=False, with_omega=False):
+    from paper_2603_13532_amd import _lib
+    lib = _lib.load()
+    fn = lib.tsk_plan_selfcheck
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.POINTER(_lib.TuckerSum), ctypes.POINTER(_lib.SketchSpec), ctypes.c_int,
+                   ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
+    ranks = np.asarray(ranks)
+    s, d = ranks.shape
+    c_dims = (ctypes.c_int64 * d)(*dims)
+    c_ranks = (ctypes.c_int32 * (s * d))(*[int(x) for x in ranks.ravel()])
+    c_cores = (ctypes.c_void_p * s)(*([0x1000] * s))
+    c_fac = (ctypes.c_void_p * (s * d))(*([0x1000] * (s * d)))
+    c_sizes = (ctypes.c_int32 * len(sizes))(*sizes)
+    c_om = (ctypes.c_void_p * d)(*([0x1000] * d)) if with_omega else None
+    tsum = _lib.TuckerSum(d, s, c_dims, c_ranks, c_cores, c_fac, None, 0 if in_f64 else 1)
+    spec = _lib.SketchSpec(_lib.KINDS[kind], c_sizes, 5, c_om, _lib.PRECISIONS[sketch_prec],
+                           _lib.PRECISIONS[project_prec], 0)
+    msg = ctypes.create_string_buffer(512)
+    rc = fn(ctypes.byref(tsum), ctypes.byref(spec), 0 if out_f64 else 1, int(sketch_only),
+            int(with_r), msg, 512)
+    return rc, msg.value.decode()
+
+
+CASES = [
+    ((64, 64, 64), np.full((4, 3), 8), "kron", [5, 5, 5]),
+    ((64, 64, 64), np.full((4, 3), 8), "krp", [24]),
+    ((130, 70, 90), [[70, 5, 33], [1, 66, 12], [40, 40, 40]], "krp", [80]),
+    ((130, 70, 90), [[70, 5, 33], [1, 66, 12], [40, 40, 40]], "kron", [3, 5, 4]),
+    ((65, 33), [[17, 9], [65, 3]], "krp", [20]),
+    ((40, 30, 20, 25), [[6, 5, 4, 7], [3, 8, 2, 5]], "krp", [11]),
+    ((40, 30, 20, 25), [[6, 5, 4, 7], [3, 8, 2, 5]], "kron", [2, 3, 2, 2]),
+    ((9, 40, 30), [[3, 4, 5], [4, 3, 2]], "krp", [14]),
+    ((24,) * 4, np.ones((20, 4), dtype=int), "krp", [12]),
+    ((24,) * 4, np.ones((20, 4), dtype=int), "kron", [3, 3, 3, 3]),
+    ((1, 1, 1), [[1, 1, 1]], "krp", [1]),
+    ((5, 300, 7), [[5, 200, 7]], "krp", [100]),       # wide Y: Householder-only mode
+    ((256,) * 4, np.full((8, 4), 32), "krp", [56]),
+    ((256,) * 3, np.full((6, 3), 24), "krp", [40]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_plan_in_bounds(case):
+    dims, ranks, kind, sizes = CASES[case]
+    for sp, pp in [("fp64", "fp64"), ("fp32", "fp32"), ("bf16x6", "bf16x3"), ("bf16x1", "fp64")]:
+        for in_f64 in (True, False):
+            for out_f64 in (True, False):
+                for sketch_only in (False, True):
+                    rc, msg = selfcheck(dims, ranks, kind, sizes, sp, pp, in_f64, out_f64,
+                                        sketch_only, with_r=not sketch_only, with_omega=sketch_only)
+                    assert rc == 0, (sp, pp, in_f64, out_f64, sketch_only, msg)
+
+
+def test_plan_in_bounds_structured_workload():
+    ts = synth.config_structured()
+    for kind, sizes in (("krp", [74]), ("kron", kron_sizes(ts["ell"]))):
+        for sp in PRECS:
+            rc, msg = selfcheck(ts["dims"], ts["ranks"], kind, sizes, sp, sp, sp == "fp64", True)
+            assert rc == 0, (kind, sp, msg)
+
+
+def test_plan_in_bounds_batch_shapes():
+    for one in synth.config_batch(count=24):
+        rc, msg = selfcheck(one["dims"], one["ranks"], "krp", [one["ell"][0]], "fp32", "fp32", False, False)
+        assert rc == 0, msg
+
+
+def test_selfcheck_detects_invalid_problem():
+    rc, msg = selfcheck((10, 10), [[0, 2]], "krp", [3])
+    assert rc == 1 and "ranks" in msg
