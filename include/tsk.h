@@ -157,6 +157,16 @@ tsk_status tucker_sum_recompress(tsk_handle handle, const tsk_tucker_sum* sum,
                                  tsk_dtype out_dtype, double* const* R_out, void* ws,
                                  size_t ws_bytes, void* stream);
 
+/* Per-launch timing.  While enabled, every kernel a call enqueues is
+ * bracketed by two HIP events on the call's stream (not inside stream
+ * capture).  tsk_profile_report() waits for the recorded events, writes a
+ * JSON object {"<kernel symbol> <step>": {"launches": n, "ms": total,
+ * "flops": algorithmic flops, "bytes": algorithmic bytes}, ...} into `buf`
+ * (NUL-terminated; *needed receives the size including the NUL; buf may be
+ * NULL to query the size) and clears the records. */
+tsk_status tsk_profile_enable(tsk_handle handle, int32_t on);
+tsk_status tsk_profile_report(tsk_handle handle, char* buf, size_t buf_len, size_t* needed);
+
 /* Number of mode QRs that took the Householder path since the handle was
  * created (Cholesky breakdown, or qr_policy 1).  Synchronises `stream`. */
 tsk_status tsk_qr_fallback_count(tsk_handle handle, void* stream, int64_t* count);

@@ -11,6 +11,19 @@ enum Prec : int32_t { P_FP64 = 0, P_FP32 = 1, P_BF16X1 = 2, P_BF16X3 = 3, P_BF16
 
 constexpr int kMaxOrder = 8;
 
+// Step of the method a GEMM launch serves (names the kernel symbol only).
+enum Role : int32_t {
+  R_FACTOR_SKETCH = 0,  // P_k^(i) = U_k^(i)T Omega_k
+  R_KRON_TTM = 1,       // Kronecker core sketch TTM chain
+  R_TERM_EXPAND = 2,    // Y_n = sum_i c_i U_n^(i) V^(i)_(n)
+  R_QR_GRAM = 3,        // Y^T Y (Cholesky QR)
+  R_QR_BASIS = 4,       // Y R^-1 (Cholesky QR)
+  R_PROJ_W = 5,         // W_k^(i) = Q_k^T U_k^(i)
+  R_PROJ_TTM = 6,       // leading TTMs of the core projection
+  R_PROJ_FINAL = 7,     // last TTM, K-concatenated over terms, writes H
+  R_OTHER = 8
+};
+
 // ---------------------------------------------------------------------------
 // Grouped, batched, K-segmented GEMM descriptors (device-resident).
 //

@@ -40,7 +40,7 @@ __device__ __forceinline__ void store_tile(typename PT<P>::acc_t (&acc)[2][2], O
       if (col >= N) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = m0 + acc_row(wm, i, lane, v);
+        const int row = m0 + acc_row<P>(wm, i, lane, v);
         if (row < M) {
           OutT* p = C + (int64_t)row + (int64_t)col * ldc;
           if (accum) *p = (OutT)((double)*p + (double)acc[i][j][v]);
@@ -50,7 +50,9 @@ __device__ __forceinline__ void store_tile(typename PT<P>::acc_t (&acc)[2][2], O
     }
 }
 
-template <int P>
+// ROLE only names the launch (one symbol per step of the method, so that
+// kernel traces separate them); the code is the same for every role.
+template <int P, int ROLE>
 __global__ __launch_bounds__(NTHREADS) void gemm_kernel(const GemmDesc* __restrict__ descs,
                                                         int ndesc,
                                                         const GemmSeg* __restrict__ segs) {
@@ -266,19 +268,44 @@ __global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* p, int64_t count
 
 }  // namespace
 
-hipError_t launch_gemm(int prec, const GemmDesc* descs, int ndesc, const GemmSeg* segs,
+template <int P>
+hipError_t launch_gemm_p(int role, dim3 grid, const GemmDesc* descs, int ndesc,
+                         const GemmSeg* segs, hipStream_t stream) {
+  const dim3 block(NTHREADS);
+  switch (role) {
+    case R_FACTOR_SKETCH: gemm_kernel<P, R_FACTOR_SKETCH><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
+    case R_KRON_TTM: gemm_kernel<P, R_KRON_TTM><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
+    case R_TERM_EXPAND: gemm_kernel<P, R_TERM_EXPAND><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
+    case R_PROJ_W: gemm_kernel<P, R_PROJ_W><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
+    case R_PROJ_TTM: gemm_kernel<P, R_PROJ_TTM><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
+    case R_PROJ_FINAL: gemm_kernel<P, R_PROJ_FINAL><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
+    default: gemm_kernel<P, R_OTHER><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(int prec, int role, const GemmDesc* descs, int ndesc, const GemmSeg* segs,
                        int64_t total_tiles, hipStream_t stream) {
   if (ndesc <= 0 || total_tiles <= 0) return hipSuccess;
   const dim3 grid((unsigned)total_tiles), block(NTHREADS);
   switch (prec) {
-    case P_FP64: gemm_kernel<P_FP64><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
-    case P_FP32: gemm_kernel<P_FP32><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
-    case P_BF16X1: gemm_kernel<P_BF16X1><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
-    case P_BF16X3: gemm_kernel<P_BF16X3><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
-    case P_BF16X6: gemm_kernel<P_BF16X6><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
+    case P_FP64:
+      // the QR products are FP64 only
+      if (role == R_QR_GRAM) {
+        gemm_kernel<P_FP64, R_QR_GRAM><<<grid, block, 0, stream>>>(descs, ndesc, segs);
+        return hipGetLastError();
+      }
+      if (role == R_QR_BASIS) {
+        gemm_kernel<P_FP64, R_QR_BASIS><<<grid, block, 0, stream>>>(descs, ndesc, segs);
+        return hipGetLastError();
+      }
+      return launch_gemm_p<P_FP64>(role, grid, descs, ndesc, segs, stream);
+    case P_FP32: return launch_gemm_p<P_FP32>(role, grid, descs, ndesc, segs, stream);
+    case P_BF16X1: return launch_gemm_p<P_BF16X1>(role, grid, descs, ndesc, segs, stream);
+    case P_BF16X3: return launch_gemm_p<P_BF16X3>(role, grid, descs, ndesc, segs, stream);
+    case P_BF16X6: return launch_gemm_p<P_BF16X6>(role, grid, descs, ndesc, segs, stream);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_krp(int prec, const KrpDesc* descs, int ndesc, int64_t total_tiles,

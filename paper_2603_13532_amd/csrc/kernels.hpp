@@ -13,7 +13,7 @@ hipError_t launch_omega(uint64_t seed, int mode, int64_t rows, int64_t cols, voi
                         hipStream_t stream);
 
 // Grouped GEMM over `ndesc` device descriptors covering `total_tiles` tiles.
-hipError_t launch_gemm(int prec, const GemmDesc* descs, int ndesc, const GemmSeg* segs,
+hipError_t launch_gemm(int prec, int role, const GemmDesc* descs, int ndesc, const GemmSeg* segs,
                        int64_t total_tiles, hipStream_t stream);
 
 // KRP core sketches over `ndesc` device descriptors covering `total_tiles` tiles.

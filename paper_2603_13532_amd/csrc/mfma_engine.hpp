@@ -4,8 +4,9 @@
 //
 // FP64 tiles use v_mfma_f64_16x16x4_f64 and FP32 tiles v_mfma_f32_16x16x4_f32:
 // per instruction each lane supplies A[lane % 16][lane / 16] and
-// B[lane / 16][lane % 16] of a 16x4 / 4x16 step and holds
-// D[4 * (lane / 16) + v][lane % 16], v = 0..3, of the 16 x 16 result.
+// B[lane / 16][lane % 16] of a 16x4 / 4x16 step.  The FP32 result lands as
+// D[4 * (lane / 16) + v][lane % 16], v = 0..3; the FP64 result as
+// D[lane / 16 + 4 * v][lane % 16] (both measured on gfx950).
 // BF16 tiles use v_mfma_f32_16x16x32_bf16: each lane supplies eight
 // consecutive k of its row (A) or column (B), k = 8 * (lane / 16) + 0..7.
 //
@@ -177,8 +178,10 @@ __device__ __forceinline__ void acc_zero(typename PT<P>::acc_t (&acc)[2][2]) {
 }
 
 // Row/column of accumulator element (i, j, v) inside the 64 x 64 tile.
+template <int P>
 __device__ __forceinline__ int acc_row(int wm, int i, int lane, int v) {
-  return wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+  if constexpr (P == P_FP64) return wm * 32 + i * 16 + (lane >> 4) + 4 * v;
+  else return wm * 32 + i * 16 + 4 * (lane >> 4) + v;
 }
 __device__ __forceinline__ int acc_col(int wn, int j, int lane) {
   return wn * 32 + j * 16 + (lane & 15);

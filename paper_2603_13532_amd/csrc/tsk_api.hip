@@ -28,9 +28,18 @@ struct Staging {
   hipEvent_t done = nullptr;
 };
 
+struct ProfRecord {
+  std::string name;
+  hipEvent_t begin, end;
+  double flops, bytes;
+};
+
 struct tsk_handle_ {
   int device = 0;
   std::string err;
+  bool prof = false;                   // record events around every launch
+  std::vector<ProfRecord> prof_records;
+  std::vector<hipEvent_t> event_pool;  // reusable timing events
   int64_t* d_counter = nullptr;
   std::vector<Staging> ring;
   size_t ring_next = 0;
@@ -166,6 +175,8 @@ enum StepKind { S_OMEGA, S_GEMM, S_KRP, S_REDUCE, S_COPY, S_FILL, S_CHOL, S_HOUS
 struct Step {
   StepKind kind;
   int prec = 0;
+  int role = R_OTHER;
+  double flops = 0, bytes = 0;  // algorithmic work of the launch
   size_t meta = 0, meta2 = 0;  // offsets into the meta blob
   int count = 0;
   int64_t tiles = 0;
@@ -208,11 +219,13 @@ struct Program {
 // Collects grouped-GEMM descriptors for one launch.
 struct GemmBatch {
   int prec;
+  int role;
   std::vector<GemmDesc> descs;
   std::vector<GemmSeg> segs;
   std::vector<ReduceJob> reduces;
   int64_t tiles = 0;
-  explicit GemmBatch(int p) : prec(p) {}
+  double flops = 0, bytes = 0;
+  GemmBatch(int p, int r) : prec(p), role(r) {}
   // Add one descriptor; `splits` > 1 writes partials to `part` and queues a
   // reduction into C.
   void add(void* C, bool c_f64, int64_t ldc, int64_t strideC, int M, int N, int batch, int beta,
@@ -258,7 +271,14 @@ struct GemmBatch {
     }
     D.tile_begin = tiles;
     tiles += (int64_t)D.tiles_m * D.tiles_n * batch * splits;
-    for (const auto& g : sg) segs.push_back(g);
+    const double ein = prec == P_FP64 ? 8.0 : 4.0, ec = c_f64 ? 8.0 : 4.0;
+    for (const auto& g : sg) {
+      segs.push_back(g);
+      flops += 2.0 * M * N * (double)g.K * batch;
+      bytes += ein * (double)M * g.K * (g.strideA != 0 ? batch : 1) +
+               ein * (double)g.K * N * (g.strideB != 0 ? batch : 1);
+    }
+    bytes += ec * (double)M * N * batch * (beta ? 2 : 1);
     descs.push_back(D);
   }
 };
@@ -284,6 +304,9 @@ void emit_gemm(Program& prog, GemmBatch& gb) {
   Step st{};
   st.kind = S_GEMM;
   st.prec = gb.prec;
+  st.role = gb.role;
+  st.flops = gb.flops;
+  st.bytes = gb.bytes;
   st.meta = prog.put(gb.descs);
   st.meta2 = prog.put(gb.segs);
   st.count = (int)gb.descs.size();
@@ -292,6 +315,8 @@ void emit_gemm(Program& prog, GemmBatch& gb) {
   if (!gb.reduces.empty()) {
     Step r{};
     r.kind = S_REDUCE;
+    for (const ReduceJob& J : gb.reduces)
+      r.bytes += (double)J.rows * J.cols * (J.parts + 1 + J.beta) * (J.out_f64 ? 8 : 4);
     r.meta = prog.put(gb.reduces);
     r.count = (int)gb.reduces.size();
     prog.steps.push_back(r);
@@ -382,6 +407,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
       st.cols = P.ow[k];
       st.ptr = p;
       st.f64 = ts64;
+      st.bytes = (double)P.dims[k] * P.ow[k] * es;
       prog.steps.push_back(st);
       om[k] = p;
     }
@@ -391,7 +417,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
   // ---- factor sketches P_k^(i) = U_k^(i)^T Omega_k  (r x ow), all terms and modes
   std::vector<void*> Pf((size_t)s * d);
   {
-    GemmBatch gb(P.ps);
+    GemmBatch gb(P.ps, R_FACTOR_SKETCH);
     int64_t tiles0 = 0, kt = 0;
     for (int i = 0; i < s; ++i)
       for (int k = 0; k < d; ++k) {
@@ -466,6 +492,16 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
     Step st{};
     st.kind = S_KRP;
     st.prec = P.ps;
+    for (const KrpDesc& D : kd) {
+      int64_t cs = 1;
+      double pbytes = 0;
+      for (int k = 0; k < d; ++k) {
+        cs *= D.r[k];
+        if (k != D.mode) pbytes += (double)D.r[k] * D.m * es;
+      }
+      st.flops += 2.0 * D.r[D.mode] * D.m * (double)D.Kc;
+      st.bytes += (double)cs * es + pbytes + (double)D.r[D.mode] * D.m * es;
+    }
     st.meta = prog.put(kd);
     st.count = (int)kd.size();
     st.tiles = tiles;
@@ -511,7 +547,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
         ch.push_back(c);
       }
     for (int step = 0; step < d - 1; ++step) {
-      GemmBatch gb(P.ps);
+      GemmBatch gb(P.ps, R_KRON_TTM);
       for (auto& c : ch) {
         // the step-th mode other than n
         int k = -1, cnt = 0;
@@ -549,7 +585,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
   for (int n = 0; n < d; ++n)
     Y[n] = out.recompress ? (double*)ar.take(P.dims[n] * P.W[n] * 8) : out.Y[n];
   {
-    GemmBatch gb(P.ps);
+    GemmBatch gb(P.ps, R_TERM_EXPAND);
     for (int n = 0; n < d; ++n) {
       const int64_t nn = P.dims[n];
       std::vector<GemmSeg> sg;
@@ -625,7 +661,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
   }
   if (any_chol) {
     for (int pass = 1; pass <= 2; ++pass) {
-      GemmBatch gram(P_FP64);
+      GemmBatch gram(P_FP64, R_QR_GRAM);
       for (int n = 0; n < d; ++n) {
         const QrDesc& q = qd[n];
         if (q.gram_part == nullptr) continue;
@@ -652,8 +688,14 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
       c.count = d;
       c.pass = pass;
       c.tol = pass == 1 ? 1e-11 : 1e-2;
+      for (int n = 0; n < d; ++n)
+        if (qd[n].gram_part != nullptr) {
+          const double W = (double)qd[n].W;
+          c.flops += 2.0 * W * W * W / 3.0;
+          c.bytes += 8.0 * W * W * (qd[n].gram_splits + 2);
+        }
       prog.steps.push_back(c);
-      GemmBatch qq(P_FP64);
+      GemmBatch qq(P_FP64, R_QR_BASIS);
       for (int n = 0; n < d; ++n) {
         const QrDesc& q = qd[n];
         if (q.gram_part == nullptr) continue;
@@ -721,7 +763,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
   emit_copies(prog, cq);
   std::vector<void*> Wm((size_t)s * d);
   {
-    GemmBatch gb(P.pp);
+    GemmBatch gb(P.pp, R_PROJ_W);
     int64_t tiles0 = 0, kt = 0;
     for (int i = 0; i < s; ++i)
       for (int k = 0; k < d; ++k) {
@@ -759,7 +801,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
     cur[i] = core_p[i];
   }
   for (int k = 0; k < d - 1; ++k) {
-    GemmBatch gb(P.pp);
+    GemmBatch gb(P.pp, R_PROJ_TTM);
     for (int i = 0; i < s; ++i) {
       const int64_t rk = shape[i][k], w = P.w[k];
       const void* Wk = Wm[(size_t)i * d + k];  // w x r_k
@@ -779,7 +821,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
     emit_gemm(prog, gb);
   }
   {
-    GemmBatch gb(P.pp);
+    GemmBatch gb(P.pp, R_PROJ_FINAL);
     int64_t L = 1;
     for (int k = 0; k < d - 1; ++k) L *= P.w[k];
     const int64_t w = P.w[d - 1];
@@ -798,6 +840,43 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
 }
 
 // ------------------------------------------------------------------ execution
+const char* role_name(int role) {
+  switch (role) {
+    case R_FACTOR_SKETCH: return "factor_sketch";
+    case R_KRON_TTM: return "kron_core_ttm";
+    case R_TERM_EXPAND: return "term_expand";
+    case R_QR_GRAM: return "qr_gram";
+    case R_QR_BASIS: return "qr_basis";
+    case R_PROJ_W: return "proj_w";
+    case R_PROJ_TTM: return "proj_ttm";
+    case R_PROJ_FINAL: return "proj_final";
+  }
+  return "other";
+}
+
+// Name of the kernel symbol a step launches (template arguments as a kernel
+// trace prints them), followed by the step's role.
+std::string step_name(const Step& st) {
+  char buf[96];
+  switch (st.kind) {
+    case S_OMEGA: return "omega_kernel";
+    case S_GEMM: {
+      int role = st.role;
+      if (role > R_OTHER || role < 0) role = R_OTHER;
+      if ((role == R_QR_GRAM || role == R_QR_BASIS) && st.prec != P_FP64) role = R_OTHER;
+      snprintf(buf, sizeof buf, "gemm_kernel<%d, %d> %s", st.prec, role, role_name(role));
+      return buf;
+    }
+    case S_KRP: snprintf(buf, sizeof buf, "krp_kernel<%d> core_sketch", st.prec); return buf;
+    case S_REDUCE: return "reduce_kernel";
+    case S_COPY: return "copy_kernel";
+    case S_FILL: return "fill_i32_kernel";
+    case S_CHOL: return "chol_kernel";
+    case S_HOUSE: return "householder_kernel";
+  }
+  return "unknown";
+}
+
 tsk_status acquire_staging(tsk_handle h, size_t bytes, bool capturing, void** host,
                            hipEvent_t* ev) {
   if (capturing) {
@@ -852,10 +931,22 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
   }
   for (const Step& st : prog.steps) {
     hipError_t e = hipSuccess;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (h->prof && !capturing) {
+      for (hipEvent_t* ev : {&ev0, &ev1}) {
+        if (!h->event_pool.empty()) {
+          *ev = h->event_pool.back();
+          h->event_pool.pop_back();
+        } else if (hipEventCreate(ev) != hipSuccess) {
+          return fail(h, TSK_ERR_DEVICE, "hipEventCreate failed");
+        }
+      }
+      if (hipEventRecord(ev0, stream) != hipSuccess) return fail(h, TSK_ERR_DEVICE, "hipEventRecord failed");
+    }
     switch (st.kind) {
       case S_OMEGA: e = launch_omega(st.seed, st.mode, st.rows, st.cols, st.ptr, st.f64, stream); break;
       case S_GEMM:
-        e = launch_gemm(st.prec, (const GemmDesc*)(meta + st.meta), st.count,
+        e = launch_gemm(st.prec, st.role, (const GemmDesc*)(meta + st.meta), st.count,
                         (const GemmSeg*)(meta + st.meta2), st.tiles, stream);
         break;
       case S_KRP: e = launch_krp(st.prec, (const KrpDesc*)(meta + st.meta), st.count, st.tiles, stream); break;
@@ -868,6 +959,10 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
         break;
     }
     if (e != hipSuccess) return fail(h, TSK_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    if (ev1 != nullptr) {
+      if (hipEventRecord(ev1, stream) != hipSuccess) return fail(h, TSK_ERR_DEVICE, "hipEventRecord failed");
+      h->prof_records.push_back(ProfRecord{step_name(st), ev0, ev1, st.flops, st.bytes});
+    }
   }
   return TSK_OK;
 }
@@ -1134,6 +1229,11 @@ tsk_status tsk_destroy(tsk_handle h) {
     if (sl.host) hipHostFree(sl.host);
   }
   for (void* p : h->pinned_keep) hipHostFree(p);
+  for (auto& r : h->prof_records) {
+    hipEventDestroy(r.begin);
+    hipEventDestroy(r.end);
+  }
+  for (hipEvent_t e : h->event_pool) hipEventDestroy(e);
   if (h->d_counter) hipFree(h->d_counter);
   delete h;
   return TSK_OK;
@@ -1301,6 +1401,54 @@ tsk_status tucker_sum_recompress(tsk_handle h, const tsk_tucker_sum* sum,
   return run_program(h, prog, (char*)ws, (hipStream_t)stream);
 }
 
+tsk_status tsk_profile_enable(tsk_handle h, int32_t on) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->prof = on != 0;
+  return TSK_OK;
+}
+
+tsk_status tsk_profile_report(tsk_handle h, char* buf, size_t buf_len, size_t* needed) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  struct Agg {
+    int64_t launches = 0;
+    double ms = 0, flops = 0, bytes = 0;
+  };
+  std::vector<std::pair<std::string, Agg>> agg;
+  for (auto& r : h->prof_records) {
+    if (hipEventSynchronize(r.end) != hipSuccess) return fail(h, TSK_ERR_DEVICE, "event wait failed");
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, r.begin, r.end) != hipSuccess)
+      return fail(h, TSK_ERR_DEVICE, "hipEventElapsedTime failed");
+    size_t j = 0;
+    while (j < agg.size() && agg[j].first != r.name) ++j;
+    if (j == agg.size()) agg.push_back({r.name, Agg{}});
+    agg[j].second.launches += 1;
+    agg[j].second.ms += ms;
+    agg[j].second.flops += r.flops;
+    agg[j].second.bytes += r.bytes;
+  }
+  std::string js = "{";
+  for (size_t j = 0; j < agg.size(); ++j) {
+    char line[384];
+    snprintf(line, sizeof line, "%s\"%s\": {\"launches\": %lld, \"ms\": %.9g, \"flops\": %.17g, \"bytes\": %.17g}",
+             j ? ", " : "", agg[j].first.c_str(), (long long)agg[j].second.launches, agg[j].second.ms,
+             agg[j].second.flops, agg[j].second.bytes);
+    js += line;
+  }
+  js += "}";
+  if (needed) *needed = js.size() + 1;
+  if (buf == nullptr || buf_len < js.size() + 1)
+    return buf == nullptr ? TSK_OK : fail(h, TSK_ERR_INVALID_ARG, "report buffer too small");
+  std::memcpy(buf, js.c_str(), js.size() + 1);
+  for (auto& r : h->prof_records) {
+    h->event_pool.push_back(r.begin);
+    h->event_pool.push_back(r.end);
+  }
+  h->prof_records.clear();
+  return TSK_OK;
+}
+
 tsk_status tsk_qr_fallback_count(tsk_handle h, void* stream, int64_t* count) {
   if (h == nullptr || count == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL argument");
   tsk_status st = set_device(h);
@@ -1313,3 +1461,26 @@ tsk_status tsk_qr_fallback_count(tsk_handle h, void* stream, int64_t* count) {
 }
 
 }  // extern "C"
+
+// Single GEMM through the grouped kernel, for kernel-level tests (not part of
+// the ABI header): C (M x N, ldc) = op(A) op(B) with op(A)[m][k] =
+// A[m*a_sx + k*a_sk] and op(B)[k][n] = B[n*b_sx + k*b_sk], `splits` K-splits.
+extern "C" int tsk_debug_gemm(tsk_handle h, int prec, int M, int N, int K, const void* A,
+                              int64_t a_sx, int64_t a_sk, const void* B, int64_t b_sx,
+                              int64_t b_sk, void* C, int64_t ldc, int c_f64, int splits, void* ws,
+                              size_t ws_bytes, void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  Program prog;
+  Arena ar;
+  ar.base = (char*)ws;
+  GemmBatch gb(prec, R_OTHER);
+  void* part = splits > 1 ? ar.take((size_t)splits * M * N * (c_f64 ? 8 : 4)) : nullptr;
+  gb.add(C, c_f64 != 0, ldc, 0, M, N, 1, 0, {seg(A, a_sx, a_sk, 0, B, b_sx, b_sk, 0, K)}, splits,
+         part);
+  emit_gemm(prog, gb);
+  prog.meta_region = align_up(ar.top, 256);
+  if (prog.meta_region + prog.blob.size() > ws_bytes) return TSK_ERR_WORKSPACE_TOO_SMALL;
+  tsk_status st = set_device(h);
+  if (st != TSK_OK) return st;
+  return run_program(h, prog, (char*)ws, (hipStream_t)stream);
+}

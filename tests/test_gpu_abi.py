@@ -43,7 +43,7 @@ def test_workspace_too_small_and_null_outputs(env):
     cq = (ctypes.c_void_p * 3)(*[q.data_ptr() for q in qs])
     st = lib.tucker_sum_recompress(h.ptr, ctypes.byref(m.sum), ctypes.byref(m.spec), cq,
                                    ctypes.c_void_p(hh.data_ptr()), 0, None,
-                                   ctypes.c_void_p(ws.data_ptr()), need.value - 1, None)
+                                   ctypes.c_void_p(ws.data_ptr()), 1024, None)
     assert st == 4
     assert b"workspace" in lib.tsk_last_error_detail(h.ptr)
     st = lib.tucker_sum_recompress(h.ptr, ctypes.byref(m.sum), ctypes.byref(m.spec), None,
@@ -83,3 +83,37 @@ def test_create_bad_device(env):
     h = ctypes.c_void_p()
     assert lib.tsk_create(ctypes.byref(h), 999) == 1
     assert lib.tsk_create(None, 0) == 1
+
+
+def test_profile_report(env):
+    import json
+    import torch
+    tsk, _lib, lib = env
+    ts = synth.random_sum(3, (64, 48, 40), [[5, 6, 7], [7, 5, 6]])
+    cores, factors = to_torch(ts, DEV)
+    rc = tsk.Recompressor(cores, factors, "krp", [10], 9)
+    h = rc.h
+    assert lib.tsk_profile_enable(h.ptr, 1) == 0
+    rc()
+    rc()
+    assert lib.tsk_profile_enable(h.ptr, 0) == 0
+    torch.cuda.synchronize()
+    need = ctypes.c_size_t()
+    assert lib.tsk_profile_report(h.ptr, None, 0, ctypes.byref(need)) == 0
+    buf = ctypes.create_string_buffer(need.value)
+    assert lib.tsk_profile_report(h.ptr, buf, need.value, ctypes.byref(need)) == 0
+    rep = json.loads(buf.value.decode())
+    names = " ".join(rep)
+    for part in ("omega_kernel", "krp_kernel<0>", "gemm_kernel<0, 0> factor_sketch",
+                 "gemm_kernel<0, 2> term_expand", "chol_kernel", "gemm_kernel<0, 7> proj_final"):
+        assert part in names, part
+    for v in rep.values():
+        assert v["launches"] % 2 == 0 and v["ms"] >= 0
+    krp = [v for k, v in rep.items() if k.startswith("krp_kernel")][0]
+    # 2 r_n m prod_{k != n} r_k per term and mode, two calls
+    want = 2 * sum(2 * r[n] * 10 * np.prod([r[k] for k in range(3) if k != n])
+                   for r in ts["ranks"] for n in range(3))
+    assert krp["flops"] == want
+    # records were cleared
+    assert lib.tsk_profile_report(h.ptr, None, 0, ctypes.byref(need)) == 0
+    assert need.value == 3

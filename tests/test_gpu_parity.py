@@ -62,14 +62,31 @@ def test_sketch_tiny(tsk, kind):
         assert rel(np_of(y), w) < 1e-13
 
 
+def full_rank(y, tol=1e-9):
+    s = np.linalg.svd(y, compute_uv=False)
+    return s.size > 0 and s[-1] > tol * s[0] and y.shape[0] >= y.shape[1]
+
+
 def check_recompress(tsk, ts, kind, sizes, seed, qtol=1e-10, htol=1e-11, **kw):
+    """Q_n and H are unique when every Y_n has full column rank (diag R >= 0);
+    otherwise the trailing columns of Q_n are arbitrary and only the
+    recompressed tensor [[H; Q]] (and orthonormality) can be compared."""
     ref = RC.recompress(ts, kind, sizes, seed)
     qs, h = run(tsk, ts, kind, sizes, seed, **kw)
-    for q, qr in zip(qs, ref["Q"]):
-        assert q.shape == qr.shape
-        assert rel(np_of(q), qr) < qtol
     assert h.shape == ref["H"].shape
-    assert rel(np_of(h), ref["H"]) < htol
+    for q in qs:
+        qn = np_of(q)
+        assert np.linalg.norm(qn.T @ qn - np.eye(qn.shape[1])) < 1e-11
+    if all(full_rank(y) for y in ref["Y"]):
+        for q, qr in zip(qs, ref["Q"]):
+            assert q.shape == qr.shape
+            assert rel(np_of(q), qr) < qtol
+        assert rel(np_of(h), ref["H"]) < htol
+    else:
+        assert int(np.prod(ts["dims"])) <= 4_000_000, "rank-deficient check needs a dense reconstruction"
+        xh_ref = RC.reconstruct(ref["H"], ref["Q"])
+        xh = RC.reconstruct(np_of(h), [np_of(q) for q in qs])
+        assert rel(xh, xh_ref) < htol
     return ref, qs, h
 
 
