@@ -162,6 +162,7 @@ def main():
         factors = [[tsk.fortran(torch.from_numpy(u).to(dev, tdt)) for u in us] for us in ts["factors"]]
         rc = tsk.Recompressor(cores, factors, "krp", [m], seed, sketch_prec=sp, project_prec=pp,
                               out_dtype=odt)
+        # eager launches (one library call per step)
         for _ in range(args.warmup):
             rc()
         torch.cuda.synchronize()
@@ -172,8 +173,19 @@ def main():
             rc()
         ev1.record(stream)
         torch.cuda.synchronize()
+        ms_eager = ev0.elapsed_time(ev1) / args.steps
+        # the same step captured once in a HIP graph and replayed
+        rc.capture()
+        for _ in range(args.warmup):
+            rc.replay()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            rc.replay()
+        ev1.record(stream)
+        torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / args.steps
-        qs, h = rc()
+        qs, h = rc.replay()
         torch.cuda.synchronize()
         x = dense(h, qs)
         err = (torch.linalg.vector_norm(x - x_ref).item()) / x_ref_norm
@@ -185,9 +197,11 @@ def main():
         err_y = max(float(np.linalg.norm(y.cpu().numpy() - yr) / np.linalg.norm(yr))
                     for y, yr in zip(ys, ref["Y"]))
         results[form] = {"ms_per_step": ms, "recompressions_per_s": 1e3 / ms,
+                         "ms_per_step_eager": ms_eager,
                          "rel_err_end_to_end": err, "rel_err_H": err_h, "rel_err_Y": err_y,
                          "sketch_prec": sp, "project_prec": pp, "_rc": rc}
-        log(f"{form}: {ms:.4f} ms/step, err {err:.2e} (H {err_h:.2e}, Y {err_y:.2e})")
+        log(f"{form}: {ms:.4f} ms/step graph, {ms_eager:.4f} eager, err {err:.2e} "
+            f"(H {err_h:.2e}, Y {err_y:.2e})")
 
     ok = {f: r for f, r in results.items() if r["rel_err_end_to_end"] <= 1e-6}
     best = min(ok, key=lambda f: ok[f]["ms_per_step"]) if ok else "fp64"

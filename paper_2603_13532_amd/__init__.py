@@ -245,6 +245,23 @@ class Recompressor:
         self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=m.device)
         self.ws_bytes = nbytes.value
 
+    def capture(self):
+        """Record one recompression into a HIP graph (replayed by replay()).
+        The library enqueues only kernels and one descriptor upload, no
+        memset, so the graph replays the whole step."""
+        self.graph_stream = torch.cuda.Stream(self.m.device)
+        self.graph = torch.cuda.CUDAGraph()
+        cur = torch.cuda.current_stream(self.m.device)
+        self.graph_stream.wait_stream(cur)
+        with torch.cuda.graph(self.graph, stream=self.graph_stream, capture_error_mode="relaxed"):
+            self(self.graph_stream.cuda_stream)
+        cur.wait_stream(self.graph_stream)
+        return self
+
+    def replay(self):
+        self.graph.replay()
+        return self.Q, self.H
+
     def __call__(self, stream=None):
         st = _stream_ptr(self.m.device) if stream is None else stream
         check(load().tucker_sum_recompress(self.h.ptr, byref(self.m.sum), byref(self.m.spec),

@@ -33,8 +33,10 @@ enum Role : int32_t {
 // op(B) is K x N of the segment.  Operands are read through two strides:
 //   op(A)[m][k] = A[m*a_sx + k*a_sk],  op(B)[k][n] = B[n*b_sx + k*b_sk],
 // one of which is 1.  A K-split s of `splits` covers K-tiles s, s+splits, ...
-// of the concatenated segment K range and writes its partial sum to
-// C + s*strideSplit (beta ignored); a later reduction folds the partials.
+// of the concatenated segment K range and writes its 64 x 64 partial tile to
+// `part`; the last split to arrive at a tile (arrival counter) adds the
+// partials in split order, applies beta and writes C, then re-arms the
+// counter, so the result does not depend on arrival order.
 struct GemmSeg {
   const void* A;
   const void* B;
@@ -47,6 +49,8 @@ struct GemmSeg {
 
 struct GemmDesc {
   void* C;
+  void* part;          // splits > 1: per-tile partial blocks (64 x 64, accumulator type)
+  int32_t* counters;   // splits > 1: one arrival counter per output tile, zero on entry
   int64_t ldc, strideC, strideSplit;
   int32_t M, N, batch, splits;
   int32_t seg_begin, seg_count;
@@ -62,10 +66,12 @@ struct GemmDesc {
 struct KrpDesc {
   const void* G;                 // core, column-major
   const void* P[kMaxOrder];      // P_k = U_k^T Omega_k, r_k x m column-major (P[n] unused)
-  void* V;                       // r_n x m (or partial block), column-major, ld r_n
+  void* V;                       // r_n x m, column-major, ld r_n
+  void* part;                    // splits > 1: per-tile partial blocks
+  int32_t* counters;             // splits > 1: arrival counters, zero on entry
   int32_t r[kMaxOrder];
   int32_t order, mode, m, splits;
-  int64_t strideSplit;           // elements between partial blocks
+  int64_t strideSplit;           // unused (kept for layout stability)
   int64_t Kc;                    // prod_{k != n} r_k
   int32_t tiles_m, tiles_n;
   int64_t tile_begin;

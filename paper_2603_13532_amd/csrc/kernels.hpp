@@ -30,6 +30,8 @@ struct ReduceJob {
   int32_t out_f64, part_f64;
 };
 hipError_t launch_reduce(const ReduceJob* jobs, int count, hipStream_t stream);
+// Same jobs, each a <= 64 x 64 tile whose parts are 64 x 64 blocks (ld 64).
+hipError_t launch_tile_reduce(const ReduceJob* jobs, int count, hipStream_t stream);
 
 // Fill `count` int32 words with `value` (used instead of hipMemsetAsync so
 // that captured graphs hold no memset nodes).

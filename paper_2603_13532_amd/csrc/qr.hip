@@ -23,75 +23,133 @@ namespace {
 
 constexpr int kCholMax = 96;  // widest Gram handled in LDS
 
+// One workgroup per mode, 256 threads as a 16 x 16 grid.  Thread (ty, tx)
+// keeps in registers the Gram entries G(i, k) and the entries X(i, k) of
+// X = L^-1 = R^-T for i = ty (mod 16), k = tx (mod 16): at most 6 x 6 of
+// each for W <= 96.  Elimination step j needs only row j of G and of X:
+// its owners publish it to an LDS buffer (double-buffered by the parity of
+// j), one barrier, then every thread updates its own entries.  X is built
+// by applying each elimination step to the identity.
+constexpr int kOwn = kCholMax / 16;
+
 __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qrs, int pass,
                                                    double tol) {
   const QrDesc& D = qrs[blockIdx.x];
   const int W = (int)D.W;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   if (*D.flag != 0 || W > kCholMax || D.W > D.n) return;
 
-  __shared__ double sG[kCholMax * kCholMax];
-  __shared__ double sX[kCholMax * kCholMax];
+  __shared__ double rowG[2][kCholMax];
+  __shared__ double rowX[2][kCholMax];
   __shared__ double diag0[kCholMax];
+  __shared__ double sR2[kCholMax * kCholMax];  // pass 2: R2 for the product R2 R1
 
+  double g[kOwn][kOwn], x[kOwn][kOwn];
   const int WW = W * W;
-  for (int e = tid; e < WW; e += 256) {
-    double acc = 0.0;
-    for (int s = 0; s < D.gram_splits; ++s) acc += D.gram_part[(int64_t)s * WW + e];
-    sG[e] = acc;
-    const int r = e % W, c = e / W;
-    sX[e] = (r == c) ? 1.0 : 0.0;
+  const double* part = D.gram_part;
+  const int ns = D.gram_splits;
+#pragma unroll
+  for (int a = 0; a < kOwn; ++a)
+#pragma unroll
+    for (int b = 0; b < kOwn; ++b) g[a][b] = 0.0;
+  // split loop outside, owned entries inside: 36 independent loads per split
+  for (int s = 0; s < ns; ++s) {
+    const double* ps = part + (int64_t)s * WW;
+#pragma unroll
+    for (int a = 0; a < kOwn; ++a)
+#pragma unroll
+      for (int b = 0; b < kOwn; ++b) {
+        const int i = ty + 16 * a, k = tx + 16 * b;
+        if (i < W && k < W) g[a][b] += ps[i + k * W];
+      }
   }
+#pragma unroll
+  for (int a = 0; a < kOwn; ++a)
+#pragma unroll
+    for (int b = 0; b < kOwn; ++b) {
+      const int i = ty + 16 * a, k = tx + 16 * b;
+      x[a][b] = (i == k && i < W) ? 1.0 : 0.0;
+      if (i == k && i < W) diag0[i] = g[a][b];
+    }
   __syncthreads();
-  for (int i = tid; i < W; i += 256) diag0[i] = sG[i + i * W];
-  __syncthreads();
-
   bool broke = false;
   for (int j = 0; j < W; ++j) {
-    const double piv = sG[j + j * W];
+    const int buf = j & 1;
+    const int aj = j >> 4;  // slot of row j among its owners' rows
+    if (ty == (j & 15)) {
+#pragma unroll
+      for (int a = 0; a < kOwn; ++a)
+        if (a == aj) {
+#pragma unroll
+          for (int b = 0; b < kOwn; ++b) {
+            const int k = tx + 16 * b;
+            if (k < W) {
+              rowG[buf][k] = g[a][b];
+              rowX[buf][k] = x[a][b];
+            }
+          }
+        }
+    }
+    __syncthreads();
+    const double piv = rowG[buf][j];
     if (!(piv > tol * diag0[j]) || !(diag0[j] > 0.0)) {
       broke = true;
       break;
     }
-    const double rjj = sqrt(piv);
-    const double inv = 1.0 / rjj;
-    __syncthreads();
-    // row j of R (upper storage) and row j of X = L^-1
-    for (int k = j + tid; k < W; k += 256) sG[j + k * W] = (k == j) ? rjj : sG[j + k * W] * inv;
-    for (int c = tid; c <= j; c += 256) sX[j + c * W] *= inv;
-    __syncthreads();
-    const int L = W - 1 - j;
-    // trailing update of the Gram (upper triangle) and of X's rows below j
-    for (int e = tid; e < L * L; e += 256) {
-      const int i = j + 1 + e % L, k = j + 1 + e / L;
-      if (i <= k) sG[i + k * W] -= sG[j + i * W] * sG[j + k * W];
+    const double inv = 1.0 / sqrt(piv);
+    const double ipiv = inv * inv;
+    double gi[kOwn], gk[kOwn], xk[kOwn];
+#pragma unroll
+    for (int a = 0; a < kOwn; ++a) {
+      const int i = ty + 16 * a;
+      gi[a] = (i < W) ? rowG[buf][i] : 0.0;
     }
-    for (int e = tid; e < L * (j + 1); e += 256) {
-      const int i = j + 1 + e % L, c = e / L;
-      sX[i + c * W] -= sG[j + i * W] * sX[j + c * W];
+#pragma unroll
+    for (int b = 0; b < kOwn; ++b) {
+      const int k = tx + 16 * b;
+      gk[b] = (k < W) ? rowG[buf][k] : 0.0;
+      // X(j, c) for c = k: Z(j, c) * inv for c < j, inv for c == j, 0 beyond
+      xk[b] = (k < j) ? rowX[buf][k] * inv : ((k == j) ? inv : 0.0);
     }
-    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < kOwn; ++a) {
+      const int i = ty + 16 * a;
+#pragma unroll
+      for (int b = 0; b < kOwn; ++b) {
+        const int k = tx + 16 * b;
+        if (i > j && k >= i) g[a][b] -= gi[a] * gk[b] * ipiv;   // trailing update, upper part
+        if (i > j && k <= j) x[a][b] -= gi[a] * inv * xk[b];     // X rows below j
+        if (i == j) {
+          if (k >= j) g[a][b] *= inv;                           // row j of R
+          if (k <= j) x[a][b] = xk[b];                          // row j of X final
+        }
+      }
+    }
   }
   if (broke) {
     if (tid == 0) *D.flag = 1;
     return;
   }
-  // R^-1 = X^T (upper triangular), zeros below the diagonal.
-  for (int e = tid; e < WW; e += 256) {
-    const int i = e % W, k = e / W;
-    D.rinv[e] = (i <= k) ? sX[k + i * W] : 0.0;
-  }
-  if (pass == 1) {
-    for (int e = tid; e < WW; e += 256) {
-      const int i = e % W, k = e / W;
-      D.r1[e] = (i <= k) ? sG[e] : 0.0;
+  // R^-1 = X^T (upper triangular); R in the upper triangle of g
+#pragma unroll
+  for (int a = 0; a < kOwn; ++a)
+#pragma unroll
+    for (int b = 0; b < kOwn; ++b) {
+      const int i = ty + 16 * a, k = tx + 16 * b;
+      if (i < W && k < W) {
+        D.rinv[k + (int64_t)i * W] = (k <= i) ? x[a][b] : 0.0;
+        const double r = (i <= k) ? g[a][b] : 0.0;
+        if (pass == 1) D.r1[i + (int64_t)k * W] = r;
+        else sR2[i + k * W] = r;
+      }
     }
-  } else if (D.R != nullptr) {
-    // R = R2 R1, both upper triangular; R is w x W with w == W on this path.
+  if (pass == 2 && D.R != nullptr) {
+    __syncthreads();
+    // R = R2 R1 (w == W on this path)
     for (int e = tid; e < WW; e += 256) {
       const int i = e % W, k = e / W;
       double acc = 0.0;
-      for (int l = i; l <= k; ++l) acc += sG[i + l * W] * D.r1[l + (int64_t)k * W];
+      for (int l = i; l <= k; ++l) acc += sR2[i + l * W] * D.r1[l + (int64_t)k * W];
       D.R[e] = (i <= k) ? acc : 0.0;
     }
   }

@@ -170,7 +170,7 @@ tsk_status validate(tsk_handle h, const tsk_tucker_sum* sum, const tsk_sketch_sp
 }
 
 // ------------------------------------------------------------------ program
-enum StepKind { S_OMEGA, S_GEMM, S_KRP, S_REDUCE, S_COPY, S_FILL, S_CHOL, S_HOUSE };
+enum StepKind { S_OMEGA, S_GEMM, S_KRP, S_REDUCE, S_TILE_REDUCE, S_COPY, S_FILL, S_CHOL, S_HOUSE };
 
 struct Step {
   StepKind kind;
@@ -195,10 +195,19 @@ struct Step {
 struct Arena {
   char* base = nullptr;
   size_t top = 0;
+  // int32 words that must be zero when the program starts (split-K arrival
+  // counters, QR flags): one block, cleared by a single fill at the start
+  int32_t* ctr_base = nullptr;
+  int64_t ctr_used = 0;
   void* take(size_t bytes) {
     top = align_up(top, 256);
     void* p = base + top;
     top += align_up(bytes, 256);
+    return p;
+  }
+  int32_t* counters(int64_t n) {
+    int32_t* p = ctr_base + ctr_used;
+    ctr_used += n;
     return p;
   }
 };
@@ -225,11 +234,13 @@ struct GemmBatch {
   std::vector<ReduceJob> reduces;
   int64_t tiles = 0;
   double flops = 0, bytes = 0;
-  GemmBatch(int p, int r) : prec(p), role(r) {}
+  GemmBatch(int p, int r, Arena* a) : prec(p), role(r), ar(a) {}
   // Add one descriptor; `splits` > 1 writes partials to `part` and queues a
   // reduction into C.
+  Arena* ar = nullptr;
   void add(void* C, bool c_f64, int64_t ldc, int64_t strideC, int M, int N, int batch, int beta,
-           const std::vector<GemmSeg>& sg, int splits = 1, void* part = nullptr) {
+           const std::vector<GemmSeg>& sg, int splits = 1, void* part_unused = nullptr) {
+    (void)part_unused;
     if (M <= 0 || N <= 0 || batch <= 0) return;
     GemmDesc D{};
     D.M = M;
@@ -241,33 +252,36 @@ struct GemmBatch {
     D.seg_count = (int)sg.size();
     D.c_f64 = c_f64 ? 1 : 0;
     D.splits = splits;
+    D.C = C;
+    D.ldc = ldc;
+    D.strideC = strideC;
+    D.strideSplit = 0;
+    D.beta = beta;
+    D.part = nullptr;
+    D.counters = nullptr;
     if (splits > 1) {
-      // partial blocks are dense M x N (ld M), one batch instance after another
-      D.C = part;
-      D.ldc = M;
-      D.strideC = (int64_t)M * N;
-      D.strideSplit = (int64_t)M * N * batch;
-      D.beta = 0;
-      for (int b = 0; b < batch; ++b) {
+      const int64_t ntiles = (int64_t)D.tiles_m * D.tiles_n * batch;
+      const size_t pe = prec == P_FP64 ? 8 : 4;
+      D.part = ar->take((size_t)ntiles * splits * 64 * 64 * pe);
+      // one reduce job per output tile, in the kernel's tile order
+      for (int64_t tl = 0; tl < ntiles; ++tl) {
+        const int tm = (int)(tl % D.tiles_m);
+        const int tn = (int)((tl / D.tiles_m) % D.tiles_n);
+        const int64_t bb = tl / ((int64_t)D.tiles_m * D.tiles_n);
         ReduceJob J{};
-        J.out = (char*)C + (size_t)b * strideC * (c_f64 ? 8 : 4);
-        J.part = (char*)part + (size_t)b * M * N * (c_f64 ? 8 : 4);
-        J.rows = M;
-        J.cols = N;
+        J.out = (char*)C + ((size_t)bb * strideC + (size_t)tm * 64 + (size_t)tn * 64 * ldc) * (c_f64 ? 8 : 4);
+        J.part = (char*)D.part + (size_t)tl * splits * 64 * 64 * pe;
+        J.rows = std::min<int64_t>(64, M - tm * 64);
+        J.cols = std::min<int64_t>(64, N - tn * 64);
         J.ld_out = ldc;
-        J.ld_part = M;
-        J.stride_part = D.strideSplit;
+        J.ld_part = 64;
+        J.stride_part = 64 * 64;
         J.parts = splits;
         J.beta = beta;
-        J.out_f64 = J.part_f64 = c_f64 ? 1 : 0;
+        J.out_f64 = c_f64 ? 1 : 0;
+        J.part_f64 = prec == P_FP64 ? 1 : 0;
         reduces.push_back(J);
       }
-    } else {
-      D.C = C;
-      D.ldc = ldc;
-      D.strideC = strideC;
-      D.strideSplit = 0;
-      D.beta = beta;
     }
     D.tile_begin = tiles;
     tiles += (int64_t)D.tiles_m * D.tiles_n * batch * splits;
@@ -314,7 +328,7 @@ void emit_gemm(Program& prog, GemmBatch& gb) {
   prog.steps.push_back(st);
   if (!gb.reduces.empty()) {
     Step r{};
-    r.kind = S_REDUCE;
+    r.kind = S_TILE_REDUCE;
     for (const ReduceJob& J : gb.reduces)
       r.bytes += (double)J.rows * J.cols * (J.parts + 1 + J.beta) * (J.out_f64 ? 8 : 4);
     r.meta = prog.put(gb.reduces);
@@ -417,7 +431,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
   // ---- factor sketches P_k^(i) = U_k^(i)^T Omega_k  (r x ow), all terms and modes
   std::vector<void*> Pf((size_t)s * d);
   {
-    GemmBatch gb(P.ps, R_FACTOR_SKETCH);
+    GemmBatch gb(P.ps, R_FACTOR_SKETCH, &ar);
     int64_t tiles0 = 0, kt = 0;
     for (int i = 0; i < s; ++i)
       for (int k = 0; k < d; ++k) {
@@ -430,9 +444,8 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
         const int64_t n = P.dims[k], r = P.r(i, k), m = P.ow[k];
         void* p = ar.take(r * m * es);
         Pf[(size_t)i * d + k] = p;
-        void* part = splits > 1 ? ar.take((size_t)splits * r * m * es) : nullptr;
         gb.add(p, ts64, r, 0, (int)r, (int)m, 1, 0,
-               {seg(fac_s[(size_t)i * d + k], n, 1, 0, om[k], n, 1, 0, n)}, splits, part);
+               {seg(fac_s[(size_t)i * d + k], n, 1, 0, om[k], n, 1, 0, n)}, splits);
       }
     emit_gemm(prog, gb);
   }
@@ -476,14 +489,28 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
         V[(size_t)i * d + n] = v;
         const int sp = (int)std::min<int64_t>(splits, std::max<int64_t>(1, ceil_div(Kc, ts64 ? 16 : 32) / 2));
         D.splits = sp;
+        D.V = v;
+        D.strideSplit = 0;
+        D.part = nullptr;
+        D.counters = nullptr;
         if (sp > 1) {
-          void* part = ar.take((size_t)sp * rn * m * es);
-          D.V = part;
-          D.strideSplit = rn * m;
-          red.push_back(ReduceJob{v, part, rn, m, rn, rn, rn * m, sp, 0, ts64, ts64});
-        } else {
-          D.V = v;
-          D.strideSplit = 0;
+          const int64_t ntiles = (int64_t)D.tiles_m * D.tiles_n;
+          D.part = ar.take((size_t)ntiles * sp * 64 * 64 * es);
+          for (int64_t tl = 0; tl < ntiles; ++tl) {
+            const int tm = (int)(tl % D.tiles_m), tn = (int)(tl / D.tiles_m);
+            ReduceJob J{};
+            J.out = (char*)v + ((size_t)tm * 64 + (size_t)tn * 64 * rn) * es;
+            J.part = (char*)D.part + (size_t)tl * sp * 64 * 64 * es;
+            J.rows = std::min<int64_t>(64, rn - tm * 64);
+            J.cols = std::min<int64_t>(64, m - tn * 64);
+            J.ld_out = rn;
+            J.ld_part = 64;
+            J.stride_part = 64 * 64;
+            J.parts = sp;
+            J.beta = 0;
+            J.out_f64 = J.part_f64 = ts64 ? 1 : 0;
+            red.push_back(J);
+          }
         }
         D.tile_begin = tiles;
         tiles += (int64_t)D.tiles_m * D.tiles_n * sp;
@@ -508,7 +535,8 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
     prog.steps.push_back(st);
     if (!red.empty()) {
       Step r{};
-      r.kind = S_REDUCE;
+      r.kind = S_TILE_REDUCE;
+      for (const ReduceJob& J : red) r.bytes += (double)J.rows * J.cols * (J.parts + 1) * es;
       r.meta = prog.put(red);
       r.count = (int)red.size();
       prog.steps.push_back(r);
@@ -547,7 +575,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
         ch.push_back(c);
       }
     for (int step = 0; step < d - 1; ++step) {
-      GemmBatch gb(P.ps, R_KRON_TTM);
+      GemmBatch gb(P.ps, R_KRON_TTM, &ar);
       for (auto& c : ch) {
         // the step-th mode other than n
         int k = -1, cnt = 0;
@@ -585,7 +613,24 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
   for (int n = 0; n < d; ++n)
     Y[n] = out.recompress ? (double*)ar.take(P.dims[n] * P.W[n] * 8) : out.Y[n];
   {
-    GemmBatch gb(P.ps, R_TERM_EXPAND);
+    GemmBatch gb(P.ps, R_TERM_EXPAND, &ar);
+    // K-split over the term concatenation when the output tiles alone cannot fill the GPU
+    int64_t tiles0 = 0, kt = 0;
+    const int bk = ts64 ? 16 : 32;
+    for (int n = 0; n < d; ++n) {
+      int64_t L = 1, T = 1;
+      if (P.kind == TSK_SKETCH_KRON) {
+        for (int k = 0; k < n; ++k) L *= P.ow[k];
+        for (int k = n + 1; k < d; ++k) T *= P.ow[k];
+      } else {
+        L = P.W[n];
+      }
+      tiles0 += ceil_div(P.dims[n], 64) * ceil_div(L, 64) * T;
+      int64_t ktn = 0;
+      for (int i = 0; i < s; ++i) ktn += ceil_div(P.r(i, n), bk);
+      kt = std::max(kt, ktn);
+    }
+    const int splits = choose_splits(tiles0, kt);
     for (int n = 0; n < d; ++n) {
       const int64_t nn = P.dims[n];
       std::vector<GemmSeg> sg;
@@ -595,7 +640,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
           sg.push_back(seg(fac_s[(size_t)i * d + n], 1, nn, 0, V[(size_t)i * d + n], r, 1, 0, r,
                            P.coeffs[i]));
         }
-        gb.add(Y[n], true, nn, 0, (int)nn, (int)P.W[n], 1, 0, sg);
+        gb.add(Y[n], true, nn, 0, (int)nn, (int)P.W[n], 1, 0, sg, splits);
       } else {
         int64_t L = 1, T = 1;
         for (int k = 0; k < n; ++k) L *= P.ow[k];
@@ -605,7 +650,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
           sg.push_back(seg(fac_s[(size_t)i * d + n], 1, nn, 0, V[(size_t)i * d + n], 1, L, L * r,
                            r, P.coeffs[i]));
         }
-        gb.add(Y[n], true, nn, nn * L, (int)nn, (int)L, (int)T, 0, sg);
+        gb.add(Y[n], true, nn, nn * L, (int)nn, (int)L, (int)T, 0, sg, splits);
       }
     }
     emit_gemm(prog, gb);
@@ -616,7 +661,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
   std::vector<QrDesc> qd(d);
   std::vector<double*> Qd(d);
   bool any_chol = false;
-  int32_t* flags = (int32_t*)ar.take(sizeof(int32_t) * d);
+  int32_t* flags = ar.counters(d);
   for (int n = 0; n < d; ++n) {
     const int64_t nn = P.dims[n], W = P.W[n], w = P.w[n];
     QrDesc& q = qd[n];
@@ -642,13 +687,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
   }
   const size_t qmeta = prog.put(qd);
   {
-    // flags: 0 where Cholesky QR2 applies, 1 where Householder is used directly
-    Step f{};
-    f.kind = S_FILL;
-    f.ptr = flags;
-    f.rows = d;
-    f.value = 0;
-    prog.steps.push_back(f);
+    // flags start at 0 (counter block); 1 where Householder is used directly
     for (int n = 0; n < d; ++n) {
       if (qd[n].gram_part != nullptr) continue;
       Step g{};
@@ -661,7 +700,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
   }
   if (any_chol) {
     for (int pass = 1; pass <= 2; ++pass) {
-      GemmBatch gram(P_FP64, R_QR_GRAM);
+      GemmBatch gram(P_FP64, R_QR_GRAM, &ar);
       for (int n = 0; n < d; ++n) {
         const QrDesc& q = qd[n];
         if (q.gram_part == nullptr) continue;
@@ -695,7 +734,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
           c.bytes += 8.0 * W * W * (qd[n].gram_splits + 2);
         }
       prog.steps.push_back(c);
-      GemmBatch qq(P_FP64, R_QR_BASIS);
+      GemmBatch qq(P_FP64, R_QR_BASIS, &ar);
       for (int n = 0; n < d; ++n) {
         const QrDesc& q = qd[n];
         if (q.gram_part == nullptr) continue;
@@ -763,7 +802,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
   emit_copies(prog, cq);
   std::vector<void*> Wm((size_t)s * d);
   {
-    GemmBatch gb(P.pp, R_PROJ_W);
+    GemmBatch gb(P.pp, R_PROJ_W, &ar);
     int64_t tiles0 = 0, kt = 0;
     for (int i = 0; i < s; ++i)
       for (int k = 0; k < d; ++k) {
@@ -776,9 +815,8 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
         const int64_t n = P.dims[k], r = P.r(i, k), w = P.w[k];
         void* p = ar.take(w * r * ep);
         Wm[(size_t)i * d + k] = p;
-        void* part = splits > 1 ? ar.take((size_t)splits * w * r * ep) : nullptr;
         gb.add(p, tp64, w, 0, (int)w, (int)r, 1, 0,
-               {seg(Qp[k], n, 1, 0, fac_p[(size_t)i * d + k], n, 1, 0, n)}, splits, part);
+               {seg(Qp[k], n, 1, 0, fac_p[(size_t)i * d + k], n, 1, 0, n)}, splits);
       }
     emit_gemm(prog, gb);
   }
@@ -801,7 +839,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
     cur[i] = core_p[i];
   }
   for (int k = 0; k < d - 1; ++k) {
-    GemmBatch gb(P.pp, R_PROJ_TTM);
+    GemmBatch gb(P.pp, R_PROJ_TTM, &ar);
     for (int i = 0; i < s; ++i) {
       const int64_t rk = shape[i][k], w = P.w[k];
       const void* Wk = Wm[(size_t)i * d + k];  // w x r_k
@@ -821,7 +859,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
     emit_gemm(prog, gb);
   }
   {
-    GemmBatch gb(P.pp, R_PROJ_FINAL);
+    GemmBatch gb(P.pp, R_PROJ_FINAL, &ar);
     int64_t L = 1;
     for (int k = 0; k < d - 1; ++k) L *= P.w[k];
     const int64_t w = P.w[d - 1];
@@ -833,8 +871,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
     int64_t kt = 0;
     for (int i = 0; i < s; ++i) kt += ceil_div(shape[i][d - 1], tp64 ? 16 : 32);
     const int splits = choose_splits(ceil_div(L, 64) * ceil_div(w, 64), kt);
-    void* part = splits > 1 ? ar.take((size_t)splits * L * w * esize(out.out_f64)) : nullptr;
-    gb.add(out.H, out.out_f64, L, 0, (int)L, (int)w, 1, 0, sg, splits, part);
+    gb.add(out.H, out.out_f64, L, 0, (int)L, (int)w, 1, 0, sg, splits);
     emit_gemm(prog, gb);
   }
 }
@@ -869,6 +906,7 @@ std::string step_name(const Step& st) {
     }
     case S_KRP: snprintf(buf, sizeof buf, "krp_kernel<%d> core_sketch", st.prec); return buf;
     case S_REDUCE: return "reduce_kernel";
+    case S_TILE_REDUCE: return "tile_reduce_kernel";
     case S_COPY: return "copy_kernel";
     case S_FILL: return "fill_i32_kernel";
     case S_CHOL: return "chol_kernel";
@@ -951,6 +989,7 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
         break;
       case S_KRP: e = launch_krp(st.prec, (const KrpDesc*)(meta + st.meta), st.count, st.tiles, stream); break;
       case S_REDUCE: e = launch_reduce((const ReduceJob*)(meta + st.meta), st.count, stream); break;
+      case S_TILE_REDUCE: e = launch_tile_reduce((const ReduceJob*)(meta + st.meta), st.count, stream); break;
       case S_COPY: e = launch_copy((const CopyJob*)(meta + st.meta), st.count, stream); break;
       case S_FILL: e = launch_fill_i32((int32_t*)st.ptr, st.rows, st.value, stream); break;
       case S_CHOL: e = launch_chol((const QrDesc*)(meta + st.meta), st.count, st.pass, st.tol, stream); break;
@@ -970,9 +1009,27 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
 // Plan into a null-based arena to size the workspace, then rebase.
 tsk_status plan(tsk_handle h, const Problem& P, const Outputs& out, char* ws, Program& prog,
                 size_t* bytes) {
+  // first pass counts the zero-initialised words, the second places them first
+  int64_t nctr = 0;
+  {
+    Arena a0;
+    Program p0;
+    build_sum(P, out, a0, p0, nullptr);
+    nctr = a0.ctr_used;
+  }
   Arena ar;
   ar.base = ws;
+  ar.ctr_base = (int32_t*)ar.take(sizeof(int32_t) * std::max<int64_t>(nctr, 1));
   build_sum(P, out, ar, prog, h ? h->d_counter : nullptr);
+  if (nctr > 0) {
+    Step f{};
+    f.kind = S_FILL;
+    f.ptr = ar.ctr_base;
+    f.rows = nctr;
+    f.value = 0;
+    f.bytes = 4.0 * nctr;
+    prog.steps.insert(prog.steps.begin(), f);
+  }
   prog.meta_region = align_up(ar.top, 256);
   *bytes = prog.meta_region + align_up(prog.blob.size(), 256) + 256;
   return TSK_OK;
@@ -1049,8 +1106,12 @@ void check_program(const Program& prog, Checker& ck) {
             ck.span(S.A, 0, (D.batch - 1) * S.strideA + max_off({{D.M, S.a_sx}, {S.K, S.a_sk}}), ein, "gemm A");
             ck.span(S.B, 0, (D.batch - 1) * S.strideB + max_off({{D.N, S.b_sx}, {S.K, S.b_sk}}), ein, "gemm B");
           }
-          ck.span(D.C, 0, (D.batch - 1) * D.strideC + (D.splits - 1) * D.strideSplit +
-                              max_off({{D.M, 1}, {D.N, D.ldc}}), D.c_f64 ? 8 : 4, "gemm C");
+          ck.span(D.C, 0, (D.batch - 1) * D.strideC + max_off({{D.M, 1}, {D.N, D.ldc}}),
+                  D.c_f64 ? 8 : 4, "gemm C");
+          if (D.splits > 1) {
+            const int64_t nt = (int64_t)D.tiles_m * D.tiles_n * D.batch;
+            ck.span(D.part, 0, nt * D.splits * 4096 - 1, ein, "gemm partials");
+          }
         }
         if (tiles != st.tiles) { ck.ok = false; ck.err = "gemm total tiles mismatch"; }
         break;
@@ -1073,11 +1134,16 @@ void check_program(const Program& prog, Checker& ck) {
           }
           if (Kc != D.Kc) { ck.ok = false; ck.err = "krp Kc mismatch"; return; }
           ck.span(D.G, 0, cs - 1, e, "krp G");
-          ck.span(D.V, 0, (D.splits - 1) * D.strideSplit + (int64_t)D.r[D.mode] * D.m - 1, e, "krp V");
+          ck.span(D.V, 0, (int64_t)D.r[D.mode] * D.m - 1, e, "krp V");
+          if (D.splits > 1) {
+            const int64_t nt = (int64_t)D.tiles_m * D.tiles_n;
+            ck.span(D.part, 0, nt * D.splits * 4096 - 1, e, "krp partials");
+          }
         }
         if (tiles != st.tiles) { ck.ok = false; ck.err = "krp total tiles mismatch"; }
         break;
       }
+      case S_TILE_REDUCE:
       case S_REDUCE: {
         const ReduceJob* js = (const ReduceJob*)(blob + st.meta);
         for (int i = 0; i < st.count; ++i) {
@@ -1173,11 +1239,7 @@ extern "C" int tsk_plan_selfcheck(const tsk_tucker_sum* sum, const tsk_sketch_sp
   // size query, then the real plan against a fake workspace
   Program p0;
   size_t need = 0;
-  {
-    Arena ar;
-    build_sum(P, out, ar, p0, counter);
-    need = align_up(ar.top, 256) + align_up(p0.blob.size(), 256) + 256;
-  }
+  plan(nullptr, P, out, nullptr, p0, &need);
   char* ws = (char*)fake(need, "workspace");
   Program prog;
   size_t need2 = 0;
@@ -1473,11 +1535,16 @@ extern "C" int tsk_debug_gemm(tsk_handle h, int prec, int M, int N, int K, const
   Program prog;
   Arena ar;
   ar.base = (char*)ws;
-  GemmBatch gb(prec, R_OTHER);
-  void* part = splits > 1 ? ar.take((size_t)splits * M * N * (c_f64 ? 8 : 4)) : nullptr;
-  gb.add(C, c_f64 != 0, ldc, 0, M, N, 1, 0, {seg(A, a_sx, a_sk, 0, B, b_sx, b_sk, 0, K)}, splits,
-         part);
+  ar.ctr_base = (int32_t*)ar.take(sizeof(int32_t) * 65536);
+  GemmBatch gb(prec, R_OTHER, &ar);
+  gb.add(C, c_f64 != 0, ldc, 0, M, N, 1, 0, {seg(A, a_sx, a_sk, 0, B, b_sx, b_sk, 0, K)}, splits);
   emit_gemm(prog, gb);
+  if (ar.ctr_used > 65536) return TSK_ERR_UNSUPPORTED;
+  Step f{};
+  f.kind = S_FILL;
+  f.ptr = ar.ctr_base;
+  f.rows = std::max<int64_t>(ar.ctr_used, 1);
+  prog.steps.insert(prog.steps.begin(), f);
   prog.meta_region = align_up(ar.top, 256);
   if (prog.meta_region + prog.blob.size() > ws_bytes) return TSK_ERR_WORKSPACE_TOO_SMALL;
   tsk_status st = set_device(h);

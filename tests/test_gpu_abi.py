@@ -117,3 +117,35 @@ def test_profile_report(env):
     # records were cleared
     assert lib.tsk_profile_report(h.ptr, None, 0, ctypes.byref(need)) == 0
     assert need.value == 3
+
+
+def test_graph_replay_matches_eager(env):
+    """A captured recompression replays correctly several times, with eager
+    work and synchronisations in between, and follows new input values."""
+    import torch
+    tsk, _lib, lib = env
+    ts = synth.random_sum(4, (96, 80, 72), [[10, 12, 9], [11, 7, 13], [5, 5, 5]])
+    cores, factors = to_torch(ts, DEV)
+    eager = tsk.Recompressor(cores, factors, "krp", [16], 21)
+    q0, h0 = eager()
+    torch.cuda.synchronize()
+    want_h = h0.clone()
+    want_q = [q.clone() for q in q0]
+    rc = tsk.Recompressor(cores, factors, "krp", [16], 21).capture()
+    for rep in range(4):
+        rc.H.fill_(float("nan"))
+        for q in rc.Q:
+            q.fill_(float("nan"))
+        q, h = rc.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(h, want_h), rep
+        for a, b in zip(q, want_q):
+            assert torch.equal(a, b)
+        _ = (torch.randn(1000, device=DEV) * 2).sum().item()   # eager work between replays
+    # new values in the same buffers are picked up by the replay
+    with torch.no_grad():
+        cores[0].mul_(2.0)
+    q, h = rc.replay()
+    q2, h2 = eager()
+    torch.cuda.synchronize()
+    assert torch.equal(h, h2)
