@@ -23,14 +23,16 @@ namespace {
 
 constexpr int kCholMax = 96;  // widest Gram handled in LDS
 
-// One workgroup per mode, 256 threads as a 16 x 16 grid.  Thread (ty, tx)
-// keeps in registers the Gram entries G(i, k) and the entries X(i, k) of
-// X = L^-1 = R^-T for i = ty (mod 16), k = tx (mod 16): at most 6 x 6 of
-// each for W <= 96.  Elimination step j needs only row j of G and of X:
-// its owners publish it to an LDS buffer (double-buffered by the parity of
-// j), one barrier, then every thread updates its own entries.  X is built
-// by applying each elimination step to the identity.
-constexpr int kOwn = kCholMax / 16;
+// Blocked Cholesky G = L L^T (L = R^T) and L^-1, one workgroup per mode,
+// both W x W matrices in LDS (leading dimension kLd).  Block size 16:
+//   1. wave 0 factors the 16 x 16 diagonal block in registers, exchanging
+//      columns with lane shuffles (no barrier inside the block);
+//   2. each row below the block solves its 16 unknowns by substitution;
+//   3. the trailing lower triangle is updated by 16-term dot products.
+// L^-1 follows blockwise: diagonal blocks inverted by substitution, then
+// block row I from X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ.  About 5
+// barriers per block instead of one per column.
+constexpr int kLd = kCholMax + 1;
 
 __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qrs, int pass,
                                                    double tol) {
@@ -39,117 +41,187 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   if (*D.flag != 0 || W > kCholMax || D.W > D.n) return;
 
-  __shared__ double rowG[2][kCholMax];
-  __shared__ double rowX[2][kCholMax];
+  __shared__ double sA[kCholMax * kLd];  // Gram, then L in the lower triangle
+  __shared__ double sX[kCholMax * kLd];  // L^-1 (lower triangle)
   __shared__ double diag0[kCholMax];
-  __shared__ double sR2[kCholMax * kCholMax];  // pass 2: R2 for the product R2 R1
+  __shared__ int s_broke;
 
-  double g[kOwn][kOwn], x[kOwn][kOwn];
+  // ---- Gram = sum of the K-split partial blocks (split loop outside so that
+  // each thread has many independent loads in flight)
   const int WW = W * W;
-  const double* part = D.gram_part;
-  const int ns = D.gram_splits;
+  constexpr int kPer = (kCholMax * kCholMax + 255) / 256;
+  {
+    double acc[kPer];
 #pragma unroll
-  for (int a = 0; a < kOwn; ++a)
+    for (int q = 0; q < kPer; ++q) acc[q] = 0.0;
+    for (int s = 0; s < D.gram_splits; ++s) {
+      const double* ps = D.gram_part + (int64_t)s * WW;
 #pragma unroll
-    for (int b = 0; b < kOwn; ++b) g[a][b] = 0.0;
-  // split loop outside, owned entries inside: 36 independent loads per split
-  for (int s = 0; s < ns; ++s) {
-    const double* ps = part + (int64_t)s * WW;
-#pragma unroll
-    for (int a = 0; a < kOwn; ++a)
-#pragma unroll
-      for (int b = 0; b < kOwn; ++b) {
-        const int i = ty + 16 * a, k = tx + 16 * b;
-        if (i < W && k < W) g[a][b] += ps[i + k * W];
+      for (int q = 0; q < kPer; ++q) {
+        const int e = tid + 256 * q;
+        if (e < WW) acc[q] += ps[e];
       }
-  }
-#pragma unroll
-  for (int a = 0; a < kOwn; ++a)
-#pragma unroll
-    for (int b = 0; b < kOwn; ++b) {
-      const int i = ty + 16 * a, k = tx + 16 * b;
-      x[a][b] = (i == k && i < W) ? 1.0 : 0.0;
-      if (i == k && i < W) diag0[i] = g[a][b];
     }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + 256 * q;
+      if (e < WW) {
+        const int i = e % W, k = e / W;
+        sA[i + k * kLd] = acc[q];
+        sX[i + k * kLd] = 0.0;
+        if (i == k) diag0[i] = acc[q];
+      }
+    }
+  }
+  if (tid == 0) s_broke = 0;
   __syncthreads();
-  bool broke = false;
-  for (int j = 0; j < W; ++j) {
-    const int buf = j & 1;
-    const int aj = j >> 4;  // slot of row j among its owners' rows
-    if (ty == (j & 15)) {
+
+  const int nb = (W + 15) >> 4;
+  for (int K = 0; K < nb; ++K) {
+    const int k0 = K * 16;
+    const int bs = min(16, W - k0);
+    // ---- 1. diagonal block, wave 0: lane = r + 16 qq holds A(k0+r, k0+qq+4e)
+    if (tid < 64) {
+      const int r = tid & 15, qq = tid >> 4;
+      double a[4];
 #pragma unroll
-      for (int a = 0; a < kOwn; ++a)
-        if (a == aj) {
+      for (int e = 0; e < 4; ++e) {
+        const int q = qq + 4 * e;
+        a[e] = (r < bs && q < bs) ? sA[(k0 + r) + (k0 + q) * kLd] : 0.0;
+      }
+      bool broke = false;
 #pragma unroll
-          for (int b = 0; b < kOwn; ++b) {
-            const int k = tx + 16 * b;
-            if (k < W) {
-              rowG[buf][k] = g[a][b];
-              rowX[buf][k] = x[a][b];
+      for (int c = 0; c < 16; ++c) {
+        if (c < bs && !broke) {
+          const int ec = c >> 2, src = 16 * (c & 3);
+          const double piv = __shfl(a[ec], c + src, 64);
+          if (!(piv > tol * diag0[k0 + c]) || !(diag0[k0 + c] > 0.0)) {
+            broke = true;
+          } else {
+            const double lcc = sqrt(piv);
+            const double inv = 1.0 / lcc;
+            if (qq == (c & 3)) {
+              if (r == c) a[ec] = lcc;
+              else if (r > c) a[ec] *= inv;
+            }
+            const double lrc = __shfl(a[ec], r + src, 64);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int q = qq + 4 * e;
+              const double lqc = __shfl(a[ec], q + src, 64);
+              if (q > c && q <= r) a[e] -= lrc * lqc;
             }
           }
         }
-    }
-    __syncthreads();
-    const double piv = rowG[buf][j];
-    if (!(piv > tol * diag0[j]) || !(diag0[j] > 0.0)) {
-      broke = true;
-      break;
-    }
-    const double inv = 1.0 / sqrt(piv);
-    const double ipiv = inv * inv;
-    double gi[kOwn], gk[kOwn], xk[kOwn];
+      }
+      if (broke) {
+        if (tid == 0) s_broke = 1;
+      } else {
 #pragma unroll
-    for (int a = 0; a < kOwn; ++a) {
-      const int i = ty + 16 * a;
-      gi[a] = (i < W) ? rowG[buf][i] : 0.0;
-    }
-#pragma unroll
-    for (int b = 0; b < kOwn; ++b) {
-      const int k = tx + 16 * b;
-      gk[b] = (k < W) ? rowG[buf][k] : 0.0;
-      // X(j, c) for c = k: Z(j, c) * inv for c < j, inv for c == j, 0 beyond
-      xk[b] = (k < j) ? rowX[buf][k] * inv : ((k == j) ? inv : 0.0);
-    }
-#pragma unroll
-    for (int a = 0; a < kOwn; ++a) {
-      const int i = ty + 16 * a;
-#pragma unroll
-      for (int b = 0; b < kOwn; ++b) {
-        const int k = tx + 16 * b;
-        if (i > j && k >= i) g[a][b] -= gi[a] * gk[b] * ipiv;   // trailing update, upper part
-        if (i > j && k <= j) x[a][b] -= gi[a] * inv * xk[b];     // X rows below j
-        if (i == j) {
-          if (k >= j) g[a][b] *= inv;                           // row j of R
-          if (k <= j) x[a][b] = xk[b];                          // row j of X final
+        for (int e = 0; e < 4; ++e) {
+          const int q = qq + 4 * e;
+          if (r < bs && q < bs && q <= r) sA[(k0 + r) + (k0 + q) * kLd] = a[e];
         }
       }
     }
-  }
-  if (broke) {
-    if (tid == 0) *D.flag = 1;
-    return;
-  }
-  // R^-1 = X^T (upper triangular); R in the upper triangle of g
+    __syncthreads();
+    if (s_broke) {
+      if (tid == 0) *D.flag = 1;
+      return;
+    }
+    // ---- 2. panel: rows below the block, x L_KK^T = a by substitution
+    const int i0 = k0 + bs;
+    for (int i = i0 + tid; i < W; i += 256) {
+      double x[16];
 #pragma unroll
-  for (int a = 0; a < kOwn; ++a)
+      for (int c = 0; c < 16; ++c) {
+        if (c < bs) {
+          double v = sA[i + (k0 + c) * kLd];
 #pragma unroll
-    for (int b = 0; b < kOwn; ++b) {
-      const int i = ty + 16 * a, k = tx + 16 * b;
-      if (i < W && k < W) {
-        D.rinv[k + (int64_t)i * W] = (k <= i) ? x[a][b] : 0.0;
-        const double r = (i <= k) ? g[a][b] : 0.0;
-        if (pass == 1) D.r1[i + (int64_t)k * W] = r;
-        else sR2[i + k * W] = r;
+          for (int q = 0; q < 16; ++q)
+            if (q < c) v -= x[q] * sA[(k0 + c) + (k0 + q) * kLd];
+          x[c] = v / sA[(k0 + c) + (k0 + c) * kLd];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < bs) sA[i + (k0 + c) * kLd] = x[c];
+    }
+    __syncthreads();
+    // ---- 3. trailing lower triangle: A(i,j) -= sum_c L(i,k0+c) L(j,k0+c), i >= j >= i0
+    for (int j = i0 + ty; j < W; j += 16)
+      for (int i = j + tx; i < W; i += 16) {
+        double v = sA[i + j * kLd];
+        for (int c = 0; c < bs; ++c) v -= sA[i + (k0 + c) * kLd] * sA[j + (k0 + c) * kLd];
+        sA[i + j * kLd] = v;
+      }
+    __syncthreads();
+  }
+
+  // ---- L^-1: diagonal blocks by substitution, thread per (block, column)
+  if (tid < nb * 16) {
+    const int I = tid >> 4, c = tid & 15;
+    const int k0 = I * 16, bs = min(16, W - k0);
+    if (c < bs) {
+      double x[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        double v = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (q >= c && q < r) v -= sA[(k0 + r) + (k0 + q) * kLd] * x[q];
+        x[r] = (r >= c && r < bs) ? v / sA[(k0 + r) + (k0 + r) * kLd] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (r < bs) sX[(k0 + r) + (k0 + c) * kLd] = x[r];
+    }
+  }
+  __syncthreads();
+  // ---- off-diagonal blocks, block row by block row
+  for (int I = 1; I < nb; ++I) {
+    const int r0 = I * 16, bsI = min(16, W - r0);
+    // T_IJ = sum_{K=J}^{I-1} L_IK X_KJ for every J < I, stored in X_IJ's place
+    for (int e = tid; e < I * 256; e += 256) {
+      const int J = e >> 8, rc = e & 255, r = rc & 15, c = rc >> 4;
+      if (r >= bsI) continue;
+      const int col = J * 16 + c;
+      double v = 0.0;
+      for (int q = J * 16; q < r0; ++q) v += sA[(r0 + r) + q * kLd] * sX[q + col * kLd];
+      sX[(r0 + r) + col * kLd] = v;
+    }
+    __syncthreads();
+    // X_IJ = -X_II T_IJ, thread per column of the block row
+    for (int col = tid; col < r0; col += 256) {
+      double tcol[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) tcol[q] = (q < bsI) ? sX[(r0 + q) + col * kLd] : 0.0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        if (r < bsI) {
+          double v = 0.0;
+#pragma unroll
+          for (int q = 0; q < 16; ++q)
+            if (q <= r) v += sX[(r0 + r) + (r0 + q) * kLd] * tcol[q];
+          sX[(r0 + r) + col * kLd] = -v;
+        }
       }
     }
-  if (pass == 2 && D.R != nullptr) {
     __syncthreads();
-    // R = R2 R1 (w == W on this path)
+  }
+
+  // ---- outputs: R^-1 = X^T, R = L^T (upper triangular, zeros below)
+  for (int e = tid; e < WW; e += 256) {
+    const int i = e % W, k = e / W;
+    D.rinv[e] = (i <= k) ? sX[k + i * kLd] : 0.0;
+    if (pass == 1) D.r1[e] = (i <= k) ? sA[k + i * kLd] : 0.0;
+  }
+  if (pass == 2 && D.R != nullptr) {
+    // R = R2 R1 with R2(i,l) = L2(l,i); w == W on this path
     for (int e = tid; e < WW; e += 256) {
       const int i = e % W, k = e / W;
       double acc = 0.0;
-      for (int l = i; l <= k; ++l) acc += sR2[i + l * W] * D.r1[l + (int64_t)k * W];
+      for (int l = i; l <= k; ++l) acc += sA[l + i * kLd] * D.r1[l + (int64_t)k * W];
       D.R[e] = (i <= k) ? acc : 0.0;
     }
   }
