@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="bound on oracle CPU time for the baseline sample")
     ap.add_argument("--profile-json", default=None, help="also write the per-kernel profile here")
+    ap.add_argument("--batch-count", type=int, default=256,
+                    help="sums in the batched-form leg (0 skips it)")
     return ap.parse_args()
 
 
@@ -203,6 +205,49 @@ def main():
         log(f"{form}: {ms:.4f} ms/step graph, {ms_eager:.4f} eager, err {err:.2e} "
             f"(H {err_h:.2e}, Y {err_y:.2e})")
 
+    # ---- batched form: 256 independent sums (uneven shapes) in one launch sequence
+    batch = None
+    if args.batch_count > 0:
+        sums = synth.config_batch(count=args.batch_count)
+        batch = {"workload": f"{args.batch_count} independent sums, d=3, n in {{64..384}}, "
+                             "s in [2,10], ranks [4,40], KRP m=min(48,n/4)+8"}
+        check_ids = list(range(0, len(sums), max(1, len(sums) // 8)))[:8]
+        refs = {i: RC.recompress(sums[i], "krp", [sums[i]["ell"][0]], sums[i]["omega_seed"])
+                for i in check_ids}
+        for form in [f for f in args.forms.split(",") if f]:
+            in_dt, sp, pp, out_dt = FORMS[form]
+            tdt = torch.float64 if in_dt == "f64" else torch.float32
+            odt = torch.float64 if out_dt == "f64" else torch.float32
+            ins = []
+            for one in sums:
+                ins.append({"cores": [tsk.fortran(torch.from_numpy(g).to(dev, tdt)) for g in one["cores"]],
+                            "factors": [[tsk.fortran(torch.from_numpy(u).to(dev, tdt)) for u in us]
+                                        for us in one["factors"]],
+                            "kind": "krp", "sizes": [one["ell"][0]], "seed": one["omega_seed"]})
+            br = tsk.BatchRecompressor(ins, sp, pp, odt).capture()
+            for _ in range(args.warmup):
+                br.replay()
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            bsteps = max(3, args.steps // 5)
+            for _ in range(bsteps):
+                br.replay()
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms_b = ev0.elapsed_time(ev1) / bsteps
+            qs_b, hs_b = br.replay()
+            torch.cuda.synchronize()
+            errs = []
+            for i in check_ids:
+                xr = dense(torch.from_numpy(np.ascontiguousarray(refs[i]["H"])).to(dev),
+                           [torch.from_numpy(np.ascontiguousarray(q)).to(dev) for q in refs[i]["Q"]])
+                xg = dense(hs_b[i], qs_b[i])
+                errs.append((torch.linalg.vector_norm(xg - xr) / torch.linalg.vector_norm(xr)).item())
+            batch[form] = {"ms_per_batch": ms_b, "recompressions_per_s": len(sums) * 1e3 / ms_b,
+                           "max_rel_err_end_to_end_sampled": max(errs)}
+            log(f"batch {form}: {ms_b:.3f} ms per {len(sums)} sums, sampled err {max(errs):.2e}")
+            del br, ins
+
     ok = {f: r for f, r in results.items() if r["rel_err_end_to_end"] <= 1e-6}
     best = min(ok, key=lambda f: ok[f]["ms_per_step"]) if ok else "fp64"
     chosen = results[best]
@@ -250,6 +295,7 @@ def main():
                    "form": best, "seed": 2, "omega_seed": seed},
         "speedup_vs_plain_fp64": (chosen["recompressions_per_s"] / fp64_rate) if fp64_rate else None,
         "forms": forms_out,
+        "batch_form": batch,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

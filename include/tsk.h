@@ -167,8 +167,26 @@ tsk_status tucker_sum_recompress(tsk_handle handle, const tsk_tucker_sum* sum,
 tsk_status tsk_profile_enable(tsk_handle handle, int32_t on);
 tsk_status tsk_profile_report(tsk_handle handle, char* buf, size_t buf_len, size_t* needed);
 
+/* Batched form: `batch` independent sums (sums[b], specs[b]) recompressed by
+ * one launch sequence, every stage of every sum in the same grouped kernel
+ * launches (the many independent sums of Section 5.3's time step, or the
+ * repeated RoundSum calls of Algorithm 6).  All sums share order, sketch kind
+ * and precisions; mode sizes, term counts, ranks, widths and seeds may
+ * differ.  Q_out[b][n] and H_out[b] as in tucker_sum_recompress. */
+tsk_status tucker_sum_batched_workspace_size(tsk_handle handle, int32_t batch,
+                                             const tsk_tucker_sum* sums,
+                                             const tsk_sketch_spec* specs, size_t* bytes);
+tsk_status tucker_sum_recompress_batched(tsk_handle handle, int32_t batch,
+                                         const tsk_tucker_sum* sums, const tsk_sketch_spec* specs,
+                                         void* const* const* Q_out, void* const* H_out,
+                                         tsk_dtype out_dtype, void* ws, size_t ws_bytes,
+                                         void* stream);
+
 /* Number of mode QRs that took the Householder path since the handle was
- * created (Cholesky breakdown, or qr_policy 1).  Synchronises `stream`. */
+ * created (Cholesky breakdown, or qr_policy 1).  Synchronises `stream`.
+ * Returns TSK_ERR_RANK_DEFICIENT (count still written) if, since the last
+ * call, a Cholesky QR broke down under qr_policy 2; the outputs of that call
+ * are still the Householder result. */
 tsk_status tsk_qr_fallback_count(tsk_handle handle, void* stream, int64_t* count);
 
 #ifdef __cplusplus

@@ -21,7 +21,7 @@ from ._lib import KINDS, PRECISIONS, QR_POLICIES, TSK_F32, TSK_F64, TskError, ch
 __all__ = [
     "fortran", "empty_fortran", "krp_width", "kron_sizes", "sketch_widths", "sketch_omega",
     "tucker_sum_sketch", "tucker_sum_recompress", "qr_fallback_count", "Handle", "TskError",
-    "Recompressor",
+    "Recompressor", "BatchRecompressor", "tucker_sum_recompress_batched",
 ]
 
 
@@ -270,6 +270,70 @@ class Recompressor:
                                            c_void_p(self.ws.data_ptr()), self.ws.numel(),
                                            c_void_p(st)), self.h.ptr)
         return self.Q, self.H
+
+
+class BatchRecompressor:
+    """Many independent Tucker sums recompressed by one launch sequence
+    (tucker_sum_recompress_batched): each stage of every sum runs in the same
+    grouped kernel launches.  `sums` is a list of dicts with keys cores,
+    factors, kind, sizes, seed and optionally coeffs; all share order, sketch
+    kind and precisions."""
+
+    def __init__(self, sums, sketch_prec="fp64", project_prec="fp64", out_dtype=None,
+                 qr_policy="auto"):
+        self.ms = [_Marshal(x["cores"], x["factors"], x.get("coeffs"), x["kind"], x["sizes"],
+                            x["seed"], None, sketch_prec, project_prec, qr_policy) for x in sums]
+        m0 = self.ms[0]
+        self.h = Handle.get(m0.device)
+        self.out_dtype = m0.dtype if out_dtype is None else out_dtype
+        B = len(self.ms)
+        self.c_sums = (_lib.TuckerSum * B)(*[m.sum for m in self.ms])
+        self.c_specs = (_lib.SketchSpec * B)(*[m.spec for m in self.ms])
+        self.Q, self.H, self._cq = [], [], []
+        for m in self.ms:
+            _, bw = m.widths()
+            qs = [empty_fortran((m.dims[n], bw[n]), self.out_dtype, m.device) for n in range(m.d)]
+            self.Q.append(qs)
+            self.H.append(empty_fortran(tuple(bw), self.out_dtype, m.device))
+            self._cq.append((c_void_p * m.d)(*[q.data_ptr() for q in qs]))
+        self.c_q = (POINTER(c_void_p) * B)(*[ctypes.cast(a, POINTER(c_void_p)) for a in self._cq])
+        self.c_h = (c_void_p * B)(*[h.data_ptr() for h in self.H])
+        nbytes = c_size_t()
+        check(load().tucker_sum_batched_workspace_size(self.h.ptr, B, self.c_sums, self.c_specs,
+                                                       byref(nbytes)), self.h.ptr)
+        self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=m0.device)
+
+    def __call__(self, stream=None):
+        st = _stream_ptr(self.ms[0].device) if stream is None else stream
+        check(load().tucker_sum_recompress_batched(
+            self.h.ptr, len(self.ms), self.c_sums, self.c_specs, self.c_q, self.c_h,
+            _dtype_code(self.out_dtype), c_void_p(self.ws.data_ptr()), self.ws.numel(),
+            c_void_p(st)), self.h.ptr)
+        return self.Q, self.H
+
+    def capture(self):
+        dev = self.ms[0].device
+        self.graph_stream = torch.cuda.Stream(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        cur = torch.cuda.current_stream(dev)
+        self.graph_stream.wait_stream(cur)
+        with torch.cuda.graph(self.graph, stream=self.graph_stream, capture_error_mode="relaxed"):
+            self(self.graph_stream.cuda_stream)
+        cur.wait_stream(self.graph_stream)
+        return self
+
+    def replay(self):
+        self.graph.replay()
+        return self.Q, self.H
+
+
+def tucker_sum_recompress_batched(sums, sketch_prec="fp64", project_prec="fp64", out_dtype=None,
+                                  qr_policy="auto"):
+    """Recompress a list of independent sums in one launch sequence; returns
+    a list of (Q list, H)."""
+    br = BatchRecompressor(sums, sketch_prec, project_prec, out_dtype, qr_policy)
+    q, h = br()
+    return list(zip(q, h))
 
 
 def qr_fallback_count(device=None) -> int:

@@ -70,6 +70,12 @@ PROTOTYPES = {
                                       POINTER(c_void_p), c_void_p, c_int, POINTER(c_void_p),
                                       c_void_p, c_size_t, c_void_p]),
     "tsk_qr_fallback_count": (c_int, [c_void_p, c_void_p, POINTER(c_int64)]),
+    "tucker_sum_batched_workspace_size": (c_int, [c_void_p, c_int32, POINTER(TuckerSum),
+                                                  POINTER(SketchSpec), POINTER(c_size_t)]),
+    "tucker_sum_recompress_batched": (c_int, [c_void_p, c_int32, POINTER(TuckerSum),
+                                              POINTER(SketchSpec), POINTER(POINTER(c_void_p)),
+                                              POINTER(c_void_p), c_int, c_void_p, c_size_t,
+                                              c_void_p]),
     "tsk_profile_enable": (c_int, [c_void_p, c_int32]),
     "tsk_profile_report": (c_int, [c_void_p, c_char_p, c_size_t, POINTER(c_size_t)]),
 }

@@ -92,7 +92,10 @@ struct QrDesc {
   double* tau;          // W Householder scalars
   int32_t* flag;        // 1: use Householder for this mode
   int64_t n, W, w;
-  int32_t gram_splits, pad_;
+  int32_t gram_splits;
+  int32_t hh_direct;    // 1: Householder without trying Cholesky QR (W > n, W too wide, policy)
+  int32_t report_only;  // 1: a Cholesky breakdown is also counted as a rank-deficiency report
+  int32_t pad_;
 };
 
 }  // namespace tsk

@@ -12,6 +12,16 @@ namespace tsk {
 hipError_t launch_omega(uint64_t seed, int mode, int64_t rows, int64_t cols, void* out, bool f64,
                         hipStream_t stream);
 
+// Many Omega_k in one launch.
+struct OmegaJobDev {
+  void* out;
+  int64_t count;
+  uint64_t seed;
+  int32_t mode, f64;
+};
+hipError_t launch_omega_jobs(const OmegaJobDev* jobs, int count, int64_t max_count,
+                             hipStream_t stream);
+
 // Grouped GEMM over `ndesc` device descriptors covering `total_tiles` tiles.
 hipError_t launch_gemm(int prec, int role, const GemmDesc* descs, int ndesc, const GemmSeg* segs,
                        int64_t total_tiles, hipStream_t stream);

@@ -39,40 +39,67 @@ __device__ __forceinline__ double round_8bit_significand(double x) {
   return __longlong_as_double((long long)b);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void omega_kernel(uint64_t seed, uint32_t mode, int64_t count,
-                                                    T* __restrict__ out) {
-  const int64_t pairs = (count + 1) / 2;
-  const uint32_t key0 = (uint32_t)(seed & 0xFFFFFFFFull);
-  const uint32_t key1 = (uint32_t)(seed >> 32);
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pairs;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t c[4] = {(uint32_t)((uint64_t)p & 0xFFFFFFFFull), (uint32_t)((uint64_t)p >> 32), mode,
-                     0u};
-    uint32_t k0 = key0, k1 = key1;
+__device__ __forceinline__ void omega_pair(uint64_t seed, uint32_t mode, int64_t p, double& z0,
+                                           double& z1) {
+  uint32_t c[4] = {(uint32_t)((uint64_t)p & 0xFFFFFFFFull), (uint32_t)((uint64_t)p >> 32), mode, 0u};
+  uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFull), k1 = (uint32_t)(seed >> 32);
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
-      if (r > 0) {
-        k0 += kPhiloxW0;
-        k1 += kPhiloxW1;
-      }
-      philox_round(c, k0, k1);
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += kPhiloxW0;
+      k1 += kPhiloxW1;
     }
-    const uint64_t w0 = ((uint64_t)c[1] << 32) | c[0];
-    const uint64_t w1 = ((uint64_t)c[3] << 32) | c[2];
-    const double u1 = (double)((w0 >> 11) + 1ull) * 0x1.0p-53;
-    const double u2 = (double)(w1 >> 11) * 0x1.0p-53;
-    const double rho = sqrt(-2.0 * log(u1));
-    const double ang = (2.0 * 3.141592653589793) * u2;
-    const double z0 = round_8bit_significand(rho * cos(ang));
-    const double z1 = round_8bit_significand(rho * sin(ang));
+    philox_round(c, k0, k1);
+  }
+  const uint64_t w0 = ((uint64_t)c[1] << 32) | c[0];
+  const uint64_t w1 = ((uint64_t)c[3] << 32) | c[2];
+  const double u1 = (double)((w0 >> 11) + 1ull) * 0x1.0p-53;
+  const double u2 = (double)(w1 >> 11) * 0x1.0p-53;
+  const double rho = sqrt(-2.0 * log(u1));
+  const double ang = (2.0 * 3.141592653589793) * u2;
+  z0 = round_8bit_significand(rho * cos(ang));
+  z1 = round_8bit_significand(rho * sin(ang));
+}
+
+template <typename T>
+__device__ __forceinline__ void omega_fill(uint64_t seed, uint32_t mode, int64_t count, T* out,
+                                           int64_t first, int64_t stride) {
+  const int64_t pairs = (count + 1) / 2;
+  for (int64_t p = first; p < pairs; p += stride) {
+    double z0, z1;
+    omega_pair(seed, mode, p, z0, z1);
     const int64_t e = 2 * p;
     out[e] = (T)z0;
     if (e + 1 < count) out[e + 1] = (T)z1;
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void omega_kernel(uint64_t seed, uint32_t mode, int64_t count,
+                                                    T* __restrict__ out) {
+  omega_fill<T>(seed, mode, count, out, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                (int64_t)gridDim.x * blockDim.x);
+}
+
+// Many matrices in one launch: blockIdx.y selects the job.
+__global__ __launch_bounds__(256) void omega_jobs_kernel(const OmegaJobDev* __restrict__ jobs) {
+  const OmegaJobDev J = jobs[blockIdx.y];
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (J.f64) omega_fill<double>(J.seed, (uint32_t)J.mode, J.count, (double*)J.out, first, stride);
+  else omega_fill<float>(J.seed, (uint32_t)J.mode, J.count, (float*)J.out, first, stride);
+}
+
 }  // namespace
+
+hipError_t launch_omega_jobs(const OmegaJobDev* jobs, int count, int64_t max_count,
+                             hipStream_t stream) {
+  if (count <= 0 || max_count <= 0) return hipSuccess;
+  int64_t blocks = ((max_count + 1) / 2 + 255) / 256;
+  if (blocks > 64) blocks = 64;
+  omega_jobs_kernel<<<dim3((unsigned)blocks, (unsigned)count), dim3(256), 0, stream>>>(jobs);
+  return hipGetLastError();
+}
 
 hipError_t launch_omega(uint64_t seed, int mode, int64_t rows, int64_t cols, void* out, bool f64,
                         hipStream_t stream) {

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
   const QrDesc& D = qrs[blockIdx.x];
   const int W = (int)D.W;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  if (*D.flag != 0 || W > kCholMax || D.W > D.n) return;
+  if (D.hh_direct || *D.flag != 0 || W > kCholMax || D.W > D.n) return;
 
   __shared__ double sA[kCholMax * kLd];  // Gram, then L in the lower triangle
   __shared__ double sX[kCholMax * kLd];  // L^-1 (lower triangle)
@@ -237,11 +237,15 @@ __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restri
                                                           int force,
                                                           unsigned long long* counter) {
   const QrDesc& D = qrs[blockIdx.x];
-  if (!force && *D.flag == 0) return;
+  const bool broke = *D.flag != 0;
+  if (!force && !broke && !D.hh_direct) return;
   const int64_t n = D.n, W = D.W;
   const int64_t w = n < W ? n : W;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0 && counter != nullptr) atomicAdd(counter, 1ull);
+  if (tid == 0 && counter != nullptr) {
+    atomicAdd(counter, 1ull);                              // QRs done by Householder
+    if (broke && D.report_only) atomicAdd(counter + 1, 1ull);  // reported breakdowns
+  }
   double* A = D.hh;
   for (int64_t e = tid; e < n * W; e += 256) A[e] = D.Y[e];
   __shared__ double red[4];

@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -366,16 +367,56 @@ struct Outputs {
   std::vector<double*> R;
 };
 
+// Stages of the launch program, in execution order.  Every sum planned into
+// one Builder contributes descriptors to the same stage launches, so a batch
+// of independent sums costs the same number of launches as one sum.
+enum StageId {
+  ST_CONVERT = 0, ST_OMEGA = 1, ST_FACTOR = 2, ST_KRP = 3, ST_KRON = 4,  // ST_KRON + step
+  ST_EXPAND = 20, ST_GRAM1 = 21, ST_BASIS1 = 22, ST_GRAM2 = 23, ST_BASIS2 = 24,
+  ST_QCOPY = 30, ST_PROJW = 31, ST_TTM = 32,  // ST_TTM + k
+  ST_FINAL = 50
+};
+
+typedef OmegaJobDev OmegaJob;
+
+struct Builder {
+  Arena& ar;
+  int nsums = 1;  // sums sharing the launches (scales the split-K decision)
+  std::map<int, GemmBatch> gemm;
+  std::map<int, std::vector<CopyJob>> copies;
+  std::vector<OmegaJob> omega;
+  double omega_bytes = 0;
+  std::vector<KrpDesc> krp;
+  std::vector<ReduceJob> krp_red;
+  int krp_prec = 0;
+  int64_t krp_tiles = 0;
+  double krp_flops = 0, krp_bytes = 0;
+  std::vector<QrDesc> qr;
+  bool any_chol = false;
+  int64_t* d_counter = nullptr;
+  explicit Builder(Arena& a) : ar(a) {}
+  GemmBatch& g(int stage, int prec, int role) {
+    auto it = gemm.find(stage);
+    if (it == gemm.end()) it = gemm.emplace(stage, GemmBatch(prec, role, &ar)).first;
+    return it->second;
+  }
+  int splits(int64_t tiles_without_split, int64_t k_tiles, int64_t target = 512) const {
+    return choose_splits(tiles_without_split * nsums, k_tiles, target);
+  }
+  void emit(Program& prog);
+};
+
 // Build the launch program for one Tucker sum.  All workspace addresses come
 // from `ar`; the meta blob is placed last by the caller.
-void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, int64_t* d_counter) {
+void build_sum(const Problem& P, const Outputs& out, Builder& B) {
+  Arena& ar = B.ar;
   const int d = P.d, s = P.s;
   const bool ts64 = is_fp64(P.ps);  // sketch-stage element type
   const bool tp64 = is_fp64(P.pp);  // projection-stage element type
   const size_t es = esize(ts64), ep = esize(tp64);
 
   // ---- inputs in the sketch element type (converted copies if needed)
-  std::vector<CopyJob> conv;
+  std::vector<CopyJob>& conv = B.copies[ST_CONVERT];
   std::vector<const void*> core_s(s), fac_s((size_t)s * d);
   for (int i = 0; i < s; ++i) {
     int64_t csize = 1;
@@ -413,32 +454,22 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
       }
     } else {
       void* p = ar.take(P.dims[k] * P.ow[k] * es);
-      Step st{};
-      st.kind = S_OMEGA;
-      st.seed = P.seed;
-      st.mode = k;
-      st.rows = P.dims[k];
-      st.cols = P.ow[k];
-      st.ptr = p;
-      st.f64 = ts64;
-      st.bytes = (double)P.dims[k] * P.ow[k] * es;
-      prog.steps.push_back(st);
+      B.omega.push_back(OmegaJob{p, P.dims[k] * P.ow[k], P.seed, k, ts64 ? 1 : 0});
+      B.omega_bytes += (double)P.dims[k] * P.ow[k] * es;
       om[k] = p;
     }
   }
-  emit_copies(prog, conv);
-
   // ---- factor sketches P_k^(i) = U_k^(i)^T Omega_k  (r x ow), all terms and modes
   std::vector<void*> Pf((size_t)s * d);
   {
-    GemmBatch gb(P.ps, R_FACTOR_SKETCH, &ar);
+    GemmBatch& gb = B.g(ST_FACTOR, P.ps, R_FACTOR_SKETCH);
     int64_t tiles0 = 0, kt = 0;
     for (int i = 0; i < s; ++i)
       for (int k = 0; k < d; ++k) {
         tiles0 += ceil_div(P.r(i, k), 64) * ceil_div(P.ow[k], 64);
         kt = std::max<int64_t>(kt, ceil_div(P.dims[k], ts64 ? 16 : 32));
       }
-    const int splits = choose_splits(tiles0, kt);
+    const int splits = B.splits(tiles0, kt);
     for (int i = 0; i < s; ++i)
       for (int k = 0; k < d; ++k) {
         const int64_t n = P.dims[k], r = P.r(i, k), m = P.ow[k];
@@ -447,15 +478,14 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
         gb.add(p, ts64, r, 0, (int)r, (int)m, 1, 0,
                {seg(fac_s[(size_t)i * d + k], n, 1, 0, om[k], n, 1, 0, n)}, splits);
       }
-    emit_gemm(prog, gb);
   }
 
   // ---- core sketches V^(i)_(n)
   std::vector<void*> V((size_t)s * d);
   if (P.kind == TSK_SKETCH_KRP) {
     const int64_t m = P.ow[0];
-    std::vector<KrpDesc> kd;
-    std::vector<ReduceJob> red;
+    std::vector<KrpDesc>& kd = B.krp;
+    std::vector<ReduceJob>& red = B.krp_red;
     int64_t tiles0 = 0, ktmax = 0;
     for (int i = 0; i < s; ++i)
       for (int n = 0; n < d; ++n) {
@@ -465,8 +495,9 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
         tiles0 += ceil_div(P.r(i, n), 64) * ceil_div(m, 64);
         ktmax = std::max<int64_t>(ktmax, ceil_div(Kc, ts64 ? 16 : 32));
       }
-    const int splits = choose_splits(tiles0, ktmax, 1024);
-    int64_t tiles = 0;
+    const int splits = B.splits(tiles0, ktmax, 1024);
+    int64_t& tiles = B.krp_tiles;
+    const size_t kd_first = kd.size();
     for (int i = 0; i < s; ++i)
       for (int n = 0; n < d; ++n) {
         KrpDesc D{};
@@ -516,30 +547,17 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
         tiles += (int64_t)D.tiles_m * D.tiles_n * sp;
         kd.push_back(D);
       }
-    Step st{};
-    st.kind = S_KRP;
-    st.prec = P.ps;
-    for (const KrpDesc& D : kd) {
+    B.krp_prec = P.ps;
+    for (size_t j = kd_first; j < kd.size(); ++j) {
+      const KrpDesc& D = kd[j];
       int64_t cs = 1;
       double pbytes = 0;
       for (int k = 0; k < d; ++k) {
         cs *= D.r[k];
         if (k != D.mode) pbytes += (double)D.r[k] * D.m * es;
       }
-      st.flops += 2.0 * D.r[D.mode] * D.m * (double)D.Kc;
-      st.bytes += (double)cs * es + pbytes + (double)D.r[D.mode] * D.m * es;
-    }
-    st.meta = prog.put(kd);
-    st.count = (int)kd.size();
-    st.tiles = tiles;
-    prog.steps.push_back(st);
-    if (!red.empty()) {
-      Step r{};
-      r.kind = S_TILE_REDUCE;
-      for (const ReduceJob& J : red) r.bytes += (double)J.rows * J.cols * (J.parts + 1) * es;
-      r.meta = prog.put(red);
-      r.count = (int)red.size();
-      prog.steps.push_back(r);
+      B.krp_flops += 2.0 * D.r[D.mode] * D.m * (double)D.Kc;
+      B.krp_bytes += (double)cs * es + pbytes + (double)D.r[D.mode] * D.m * es;
     }
   } else {
     // Kronecker: V = G x_{k != n} (Omega_k^T U_k), TTM chain in ascending mode order
@@ -575,7 +593,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
         ch.push_back(c);
       }
     for (int step = 0; step < d - 1; ++step) {
-      GemmBatch gb(P.ps, R_KRON_TTM, &ar);
+      GemmBatch& gb = B.g(ST_KRON + step, P.ps, R_KRON_TTM);
       for (auto& c : ch) {
         // the step-th mode other than n
         int k = -1, cnt = 0;
@@ -603,7 +621,6 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
         c.cur = outp;
         c.which ^= 1;
       }
-      emit_gemm(prog, gb);
     }
     for (auto& c : ch) V[(size_t)c.i * d + c.n] = (void*)c.cur;
   }
@@ -613,7 +630,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
   for (int n = 0; n < d; ++n)
     Y[n] = out.recompress ? (double*)ar.take(P.dims[n] * P.W[n] * 8) : out.Y[n];
   {
-    GemmBatch gb(P.ps, R_TERM_EXPAND, &ar);
+    GemmBatch& gb = B.g(ST_EXPAND, P.ps, R_TERM_EXPAND);
     // K-split over the term concatenation when the output tiles alone cannot fill the GPU
     int64_t tiles0 = 0, kt = 0;
     const int bk = ts64 ? 16 : 32;
@@ -630,7 +647,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
       for (int i = 0; i < s; ++i) ktn += ceil_div(P.r(i, n), bk);
       kt = std::max(kt, ktn);
     }
-    const int splits = choose_splits(tiles0, kt);
+    const int splits = B.splits(tiles0, kt);
     for (int n = 0; n < d; ++n) {
       const int64_t nn = P.dims[n];
       std::vector<GemmSeg> sg;
@@ -653,14 +670,12 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
         gb.add(Y[n], true, nn, nn * L, (int)nn, (int)L, (int)T, 0, sg, splits);
       }
     }
-    emit_gemm(prog, gb);
   }
   if (!out.recompress) return;
 
   // ---- thin QR of every Y_n in FP64
   std::vector<QrDesc> qd(d);
   std::vector<double*> Qd(d);
-  bool any_chol = false;
   int32_t* flags = ar.counters(d);
   for (int n = 0; n < d; ++n) {
     const int64_t nn = P.dims[n], W = P.W[n], w = P.w[n];
@@ -676,8 +691,10 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
     q.hh = (double*)ar.take(nn * W * 8);
     q.tau = (double*)ar.take(W * 8);
     const bool chol = P.qr_policy != 1 && W <= 96 && W <= nn;
+    q.hh_direct = chol ? 0 : 1;
+    q.report_only = P.qr_policy == 2 ? 1 : 0;
     if (chol) {
-      any_chol = true;
+      B.any_chol = true;
       q.gram_splits = (int)std::min<int64_t>(16, std::max<int64_t>(1, nn / 64));
       q.gram_part = (double*)ar.take((size_t)q.gram_splits * W * W * 8);
       q.rinv = (double*)ar.take(W * W * 8);
@@ -685,81 +702,33 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
       q.q1 = (double*)ar.take(nn * W * 8);
     }
   }
-  const size_t qmeta = prog.put(qd);
-  {
-    // flags start at 0 (counter block); 1 where Householder is used directly
+  for (int pass = 1; pass <= 2; ++pass) {
+    GemmBatch& gram = B.g(pass == 1 ? ST_GRAM1 : ST_GRAM2, P_FP64, R_QR_GRAM);
+    GemmBatch& qq = B.g(pass == 1 ? ST_BASIS1 : ST_BASIS2, P_FP64, R_QR_BASIS);
     for (int n = 0; n < d; ++n) {
-      if (qd[n].gram_part != nullptr) continue;
-      Step g{};
-      g.kind = S_FILL;
-      g.ptr = flags + n;
-      g.rows = 1;
-      g.value = 1;
-      prog.steps.push_back(g);
+      const QrDesc& q = qd[n];
+      if (q.gram_part == nullptr) continue;
+      const double* src = pass == 1 ? q.Y : q.q1;
+      // K-split of the Gram over row blocks, partials summed by the Cholesky kernel
+      const int64_t rows_per = ceil_div(q.n, q.gram_splits);
+      for (int sp = 0; sp < q.gram_splits; ++sp) {
+        const int64_t r0 = sp * rows_per, rl = std::max<int64_t>(0, std::min<int64_t>(rows_per, q.n - r0));
+        double* C = q.gram_part + (size_t)sp * q.W * q.W;
+        // an empty block (K = 0) writes zeros
+        gram.add(C, true, q.W, 0, (int)q.W, (int)q.W, 1, 0,
+                 {seg(rl > 0 ? src + r0 : src, q.n, 1, 0, rl > 0 ? src + r0 : src, q.n, 1, 0, rl)});
+      }
+      double* dst = pass == 1 ? q.q1 : q.Q;
+      qq.add(dst, true, q.n, 0, (int)q.n, (int)q.W, 1, 0,
+             {seg(src, 1, q.n, 0, q.rinv, q.W, 1, 0, q.W)});
     }
   }
-  if (any_chol) {
-    for (int pass = 1; pass <= 2; ++pass) {
-      GemmBatch gram(P_FP64, R_QR_GRAM, &ar);
-      for (int n = 0; n < d; ++n) {
-        const QrDesc& q = qd[n];
-        if (q.gram_part == nullptr) continue;
-        const double* src = pass == 1 ? q.Y : q.q1;
-        // K-split of the Gram over row blocks, partials summed by the Cholesky kernel
-        const int64_t rows_per = ceil_div(q.n, q.gram_splits);
-        for (int sp = 0; sp < q.gram_splits; ++sp) {
-          const int64_t r0 = sp * rows_per, rl = std::min<int64_t>(rows_per, q.n - r0);
-          double* C = q.gram_part + (size_t)sp * q.W * q.W;
-          if (rl <= 0) {
-            // empty block: contributes zero (K = 0 GEMM writes zeros)
-            gram.add(C, true, q.W, 0, (int)q.W, (int)q.W, 1, 0,
-                     {seg(src, q.n, 1, 0, src, q.n, 1, 0, 0)});
-            continue;
-          }
-          gram.add(C, true, q.W, 0, (int)q.W, (int)q.W, 1, 0,
-                   {seg(src + r0, q.n, 1, 0, src + r0, q.n, 1, 0, rl)});
-        }
-      }
-      emit_gemm(prog, gram);
-      Step c{};
-      c.kind = S_CHOL;
-      c.meta = qmeta;
-      c.count = d;
-      c.pass = pass;
-      c.tol = pass == 1 ? 1e-11 : 1e-2;
-      for (int n = 0; n < d; ++n)
-        if (qd[n].gram_part != nullptr) {
-          const double W = (double)qd[n].W;
-          c.flops += 2.0 * W * W * W / 3.0;
-          c.bytes += 8.0 * W * W * (qd[n].gram_splits + 2);
-        }
-      prog.steps.push_back(c);
-      GemmBatch qq(P_FP64, R_QR_BASIS, &ar);
-      for (int n = 0; n < d; ++n) {
-        const QrDesc& q = qd[n];
-        if (q.gram_part == nullptr) continue;
-        const double* src = pass == 1 ? q.Y : q.q1;
-        double* dst = pass == 1 ? q.q1 : q.Q;
-        qq.add(dst, true, q.n, 0, (int)q.n, (int)q.W, 1, 0,
-               {seg(src, 1, q.n, 0, q.rinv, q.W, 1, 0, q.W)});
-      }
-      emit_gemm(prog, qq);
-    }
-  }
-  {
-    Step hh{};
-    hh.kind = S_HOUSE;
-    hh.meta = qmeta;
-    hh.count = d;
-    hh.force = 0;
-    hh.ptr = d_counter;
-    prog.steps.push_back(hh);
-  }
+  for (auto& q : qd) B.qr.push_back(q);
 
   // ---- core projection (Section 3.3): W_k^(i) = Q_k^T U_k^(i), then the
   // multi-TTM H = sum_i c_i G^(i) x_1 W_1^(i) ... x_d W_d^(i)
   std::vector<const void*> Qp(d);
-  std::vector<CopyJob> cq;
+  std::vector<CopyJob>& cq = B.copies[ST_QCOPY];
   for (int n = 0; n < d; ++n) {
     if (tp64) {
       Qp[n] = Qd[n];
@@ -799,17 +768,16 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
       }
     }
   }
-  emit_copies(prog, cq);
   std::vector<void*> Wm((size_t)s * d);
   {
-    GemmBatch gb(P.pp, R_PROJ_W, &ar);
+    GemmBatch& gb = B.g(ST_PROJW, P.pp, R_PROJ_W);
     int64_t tiles0 = 0, kt = 0;
     for (int i = 0; i < s; ++i)
       for (int k = 0; k < d; ++k) {
         tiles0 += ceil_div(P.w[k], 64) * ceil_div(P.r(i, k), 64);
         kt = std::max<int64_t>(kt, ceil_div(P.dims[k], tp64 ? 16 : 32));
       }
-    const int splits = choose_splits(tiles0, kt);
+    const int splits = B.splits(tiles0, kt);
     for (int i = 0; i < s; ++i)
       for (int k = 0; k < d; ++k) {
         const int64_t n = P.dims[k], r = P.r(i, k), w = P.w[k];
@@ -818,7 +786,6 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
         gb.add(p, tp64, w, 0, (int)w, (int)r, 1, 0,
                {seg(Qp[k], n, 1, 0, fac_p[(size_t)i * d + k], n, 1, 0, n)}, splits);
       }
-    emit_gemm(prog, gb);
   }
   // multi-TTM, modes 0..d-2 per term, then the last mode K-concatenated over terms
   std::vector<std::vector<int64_t>> shape(s);
@@ -839,7 +806,7 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
     cur[i] = core_p[i];
   }
   for (int k = 0; k < d - 1; ++k) {
-    GemmBatch gb(P.pp, R_PROJ_TTM, &ar);
+    GemmBatch& gb = B.g(ST_TTM + k, P.pp, R_PROJ_TTM);
     for (int i = 0; i < s; ++i) {
       const int64_t rk = shape[i][k], w = P.w[k];
       const void* Wk = Wm[(size_t)i * d + k];  // w x r_k
@@ -856,10 +823,9 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
       shape[i][k] = w;
       cur[i] = outp;
     }
-    emit_gemm(prog, gb);
   }
   {
-    GemmBatch gb(P.pp, R_PROJ_FINAL, &ar);
+    GemmBatch& gb = B.g(ST_FINAL, P.pp, R_PROJ_FINAL);
     int64_t L = 1;
     for (int k = 0; k < d - 1; ++k) L *= P.w[k];
     const int64_t w = P.w[d - 1];
@@ -870,10 +836,86 @@ void build_sum(const Problem& P, const Outputs& out, Arena& ar, Program& prog, i
     }
     int64_t kt = 0;
     for (int i = 0; i < s; ++i) kt += ceil_div(shape[i][d - 1], tp64 ? 16 : 32);
-    const int splits = choose_splits(ceil_div(L, 64) * ceil_div(w, 64), kt);
+    const int splits = B.splits(ceil_div(L, 64) * ceil_div(w, 64), kt);
     gb.add(out.H, out.out_f64, L, 0, (int)L, (int)w, 1, 0, sg, splits);
-    emit_gemm(prog, gb);
   }
+}
+
+
+void Builder::emit(Program& prog) {
+  auto emit_copy_stage = [&](int stage) {
+    auto it = copies.find(stage);
+    if (it != copies.end()) emit_copies(prog, it->second);
+  };
+  auto emit_gemm_stage = [&](int stage) {
+    auto it = gemm.find(stage);
+    if (it != gemm.end()) emit_gemm(prog, it->second);
+  };
+  emit_copy_stage(ST_CONVERT);
+  if (!omega.empty()) {
+    Step st{};
+    st.kind = S_OMEGA;
+    st.meta = prog.put(omega);
+    st.count = (int)omega.size();
+    st.bytes = omega_bytes;
+    for (const OmegaJob& j : omega) st.rows = std::max<int64_t>(st.rows, j.count);
+    prog.steps.push_back(st);
+  }
+  emit_gemm_stage(ST_FACTOR);
+  if (!krp.empty()) {
+    Step st{};
+    st.kind = S_KRP;
+    st.prec = krp_prec;
+    st.flops = krp_flops;
+    st.bytes = krp_bytes;
+    st.meta = prog.put(krp);
+    st.count = (int)krp.size();
+    st.tiles = krp_tiles;
+    prog.steps.push_back(st);
+    if (!krp_red.empty()) {
+      Step r{};
+      r.kind = S_TILE_REDUCE;
+      for (const ReduceJob& J : krp_red)
+        r.bytes += (double)J.rows * J.cols * (J.parts + 1) * (J.out_f64 ? 8 : 4);
+      r.meta = prog.put(krp_red);
+      r.count = (int)krp_red.size();
+      prog.steps.push_back(r);
+    }
+  }
+  for (int st = ST_KRON; st < ST_EXPAND; ++st) emit_gemm_stage(st);
+  emit_gemm_stage(ST_EXPAND);
+  if (!qr.empty()) {
+    const size_t qmeta = prog.put(qr);
+    if (any_chol) {
+      for (int pass = 1; pass <= 2; ++pass) {
+        emit_gemm_stage(pass == 1 ? ST_GRAM1 : ST_GRAM2);
+        Step c{};
+        c.kind = S_CHOL;
+        c.meta = qmeta;
+        c.count = (int)qr.size();
+        c.pass = pass;
+        c.tol = pass == 1 ? 1e-11 : 1e-2;
+        for (const QrDesc& q : qr)
+          if (q.gram_part != nullptr) {
+            const double W = (double)q.W;
+            c.flops += 2.0 * W * W * W / 3.0;
+            c.bytes += 8.0 * W * W * (q.gram_splits + 2);
+          }
+        prog.steps.push_back(c);
+        emit_gemm_stage(pass == 1 ? ST_BASIS1 : ST_BASIS2);
+      }
+    }
+    Step hh{};
+    hh.kind = S_HOUSE;
+    hh.meta = qmeta;
+    hh.count = (int)qr.size();
+    hh.ptr = d_counter;
+    prog.steps.push_back(hh);
+  }
+  emit_copy_stage(ST_QCOPY);
+  emit_gemm_stage(ST_PROJW);
+  for (int st = ST_TTM; st < ST_FINAL; ++st) emit_gemm_stage(st);
+  emit_gemm_stage(ST_FINAL);
 }
 
 // ------------------------------------------------------------------ execution
@@ -982,7 +1024,7 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
       if (hipEventRecord(ev0, stream) != hipSuccess) return fail(h, TSK_ERR_DEVICE, "hipEventRecord failed");
     }
     switch (st.kind) {
-      case S_OMEGA: e = launch_omega(st.seed, st.mode, st.rows, st.cols, st.ptr, st.f64, stream); break;
+      case S_OMEGA: e = launch_omega_jobs((const OmegaJobDev*)(meta + st.meta), st.count, st.rows, stream); break;
       case S_GEMM:
         e = launch_gemm(st.prec, st.role, (const GemmDesc*)(meta + st.meta), st.count,
                         (const GemmSeg*)(meta + st.meta2), st.tiles, stream);
@@ -1007,20 +1049,25 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
 }
 
 // Plan into a null-based arena to size the workspace, then rebase.
-tsk_status plan(tsk_handle h, const Problem& P, const Outputs& out, char* ws, Program& prog,
-                size_t* bytes) {
+tsk_status plan_many(tsk_handle h, const std::vector<Problem>& Ps, const std::vector<Outputs>& outs,
+                     char* ws, Program& prog, size_t* bytes) {
   // first pass counts the zero-initialised words, the second places them first
   int64_t nctr = 0;
   {
     Arena a0;
     Program p0;
-    build_sum(P, out, a0, p0, nullptr);
+    Builder B0(a0);
+    B0.nsums = (int)Ps.size();
+    for (size_t j = 0; j < Ps.size(); ++j) build_sum(Ps[j], outs[j], B0);
     nctr = a0.ctr_used;
   }
   Arena ar;
   ar.base = ws;
   ar.ctr_base = (int32_t*)ar.take(sizeof(int32_t) * std::max<int64_t>(nctr, 1));
-  build_sum(P, out, ar, prog, h ? h->d_counter : nullptr);
+  Builder B(ar);
+  B.nsums = (int)Ps.size();
+  B.d_counter = h ? h->d_counter : nullptr;
+  for (size_t j = 0; j < Ps.size(); ++j) build_sum(Ps[j], outs[j], B);
   if (nctr > 0) {
     Step f{};
     f.kind = S_FILL;
@@ -1028,11 +1075,17 @@ tsk_status plan(tsk_handle h, const Problem& P, const Outputs& out, char* ws, Pr
     f.rows = nctr;
     f.value = 0;
     f.bytes = 4.0 * nctr;
-    prog.steps.insert(prog.steps.begin(), f);
+    prog.steps.push_back(f);
   }
+  B.emit(prog);
   prog.meta_region = align_up(ar.top, 256);
   *bytes = prog.meta_region + align_up(prog.blob.size(), 256) + 256;
   return TSK_OK;
+}
+
+tsk_status plan(tsk_handle h, const Problem& P, const Outputs& out, char* ws, Program& prog,
+                size_t* bytes) {
+  return plan_many(h, std::vector<Problem>{P}, std::vector<Outputs>{out}, ws, prog, bytes);
 }
 
 tsk_status set_device(tsk_handle h) {
@@ -1084,9 +1137,11 @@ void check_program(const Program& prog, Checker& ck) {
   const char* blob = prog.blob.data();
   for (const Step& st : prog.steps) {
     switch (st.kind) {
-      case S_OMEGA:
-        ck.span(st.ptr, 0, st.rows * st.cols - 1, st.f64 ? 8 : 4, "omega");
+      case S_OMEGA: {
+        const OmegaJob* js = (const OmegaJob*)(blob + st.meta);
+        for (int i = 0; i < st.count; ++i) ck.span(js[i].out, 0, js[i].count - 1, js[i].f64 ? 8 : 4, "omega");
         break;
+      }
       case S_FILL: ck.span(st.ptr, 0, st.rows - 1, 4, "fill"); break;
       case S_GEMM: {
         const GemmDesc* ds = (const GemmDesc*)(blob + st.meta);
@@ -1188,23 +1243,22 @@ void check_program(const Program& prog, Checker& ck) {
   }
 }
 
-}  // namespace
-
-extern "C" int tsk_plan_selfcheck(const tsk_tucker_sum* sum, const tsk_sketch_spec* spec,
-                                  int out_dtype, int sketch_only, int with_r, char* msg,
-                                  size_t msglen) {
-  Problem P;
-  tsk_handle_ scratch_handle;
-  tsk_status st = validate(&scratch_handle, sum, spec, P);
+static int selfcheck_impl(int32_t batch, const tsk_tucker_sum* sums, const tsk_sketch_spec* specs,
+                          int out_dtype, int sketch_only, int with_r, char* msg, size_t msglen) {
   auto say = [&](const std::string& s) {
     if (msg && msglen) {
       std::strncpy(msg, s.c_str(), msglen - 1);
       msg[msglen - 1] = 0;
     }
   };
-  if (st != TSK_OK) {
-    say(scratch_handle.err);
-    return st;
+  tsk_handle_ scratch_handle;
+  std::vector<Problem> Ps(batch);
+  for (int b = 0; b < batch; ++b) {
+    tsk_status st = validate(&scratch_handle, &sums[b], &specs[b], Ps[b]);
+    if (st != TSK_OK) {
+      say(scratch_handle.err);
+      return st;
+    }
   }
   Checker ck;
   uintptr_t next = (uintptr_t)1 << 44;
@@ -1214,36 +1268,40 @@ extern "C" int tsk_plan_selfcheck(const tsk_tucker_sum* sum, const tsk_sketch_sp
     next += align_up(bytes, (size_t)1 << 20) + ((size_t)1 << 30);
     return p;
   };
-  const size_t ein = P.in_f64 ? 8 : 4;
-  for (int i = 0; i < P.s; ++i) {
-    int64_t cs = 1;
-    for (int k = 0; k < P.d; ++k) cs *= P.r(i, k);
-    P.cores[i] = fake(cs * ein, "core");
-    for (int k = 0; k < P.d; ++k)
-      P.factors[(size_t)i * P.d + k] = fake(P.dims[k] * P.r(i, k) * ein, "factor");
+  std::vector<Outputs> outs(batch);
+  for (int b = 0; b < batch; ++b) {
+    Problem& P = Ps[b];
+    const size_t ein = P.in_f64 ? 8 : 4;
+    for (int i = 0; i < P.s; ++i) {
+      int64_t cs = 1;
+      for (int k = 0; k < P.d; ++k) cs *= P.r(i, k);
+      P.cores[i] = fake(cs * ein, "core");
+      for (int k = 0; k < P.d; ++k)
+        P.factors[(size_t)i * P.d + k] = fake(P.dims[k] * P.r(i, k) * ein, "factor");
+    }
+    for (size_t k = 0; k < P.omega.size(); ++k) P.omega[k] = fake(P.dims[k] * P.ow[k] * ein, "omega");
+    Outputs& out = outs[b];
+    out.recompress = !sketch_only;
+    out.out_f64 = out_dtype == TSK_F64;
+    const size_t eo = out.out_f64 ? 8 : 4;
+    int64_t hsize = 1;
+    for (int n = 0; n < P.d; ++n) {
+      if (sketch_only) out.Y.push_back((double*)fake(P.dims[n] * P.W[n] * 8, "Y"));
+      out.Q.push_back(fake(P.dims[n] * P.w[n] * eo, "Q"));
+      if (with_r) out.R.push_back((double*)fake(P.w[n] * P.W[n] * 8, "R"));
+      hsize *= P.w[n];
+    }
+    out.H = fake(hsize * eo, "H");
   }
-  for (size_t k = 0; k < P.omega.size(); ++k) P.omega[k] = fake(P.dims[k] * P.ow[k] * ein, "omega");
-  Outputs out;
-  out.recompress = !sketch_only;
-  out.out_f64 = out_dtype == TSK_F64;
-  const size_t eo = out.out_f64 ? 8 : 4;
-  int64_t hsize = 1;
-  for (int n = 0; n < P.d; ++n) {
-    if (sketch_only) out.Y.push_back((double*)fake(P.dims[n] * P.W[n] * 8, "Y"));
-    out.Q.push_back(fake(P.dims[n] * P.w[n] * eo, "Q"));
-    if (with_r) out.R.push_back((double*)fake(P.w[n] * P.W[n] * 8, "R"));
-    hsize *= P.w[n];
-  }
-  out.H = fake(hsize * eo, "H");
-  int64_t* counter = (int64_t*)fake(256, "counter");
-  // size query, then the real plan against a fake workspace
+  tsk_handle_ fake_handle;
+  fake_handle.d_counter = (int64_t*)fake(256, "counter");
   Program p0;
   size_t need = 0;
-  plan(nullptr, P, out, nullptr, p0, &need);
+  plan_many(&fake_handle, Ps, outs, nullptr, p0, &need);
   char* ws = (char*)fake(need, "workspace");
   Program prog;
   size_t need2 = 0;
-  plan(nullptr, P, out, ws, prog, &need2);
+  plan_many(&fake_handle, Ps, outs, ws, prog, &need2);
   if (need2 != need) {
     say("workspace size differs between the size query and the call");
     return 99;
@@ -1255,6 +1313,21 @@ extern "C" int tsk_plan_selfcheck(const tsk_tucker_sum* sum, const tsk_sketch_sp
   }
   say("ok");
   return 0;
+}
+
+}  // namespace
+
+// Host-only bounds self-check of a planned call (tests; not part of the ABI header).
+extern "C" int tsk_plan_selfcheck(const tsk_tucker_sum* sum, const tsk_sketch_spec* spec,
+                                  int out_dtype, int sketch_only, int with_r, char* msg,
+                                  size_t msglen) {
+  return selfcheck_impl(1, sum, spec, out_dtype, sketch_only, with_r, msg, msglen);
+}
+
+extern "C" int tsk_plan_selfcheck_batched(int32_t batch, const tsk_tucker_sum* sums,
+                                          const tsk_sketch_spec* specs, int out_dtype, char* msg,
+                                          size_t msglen) {
+  return selfcheck_impl(batch, sums, specs, out_dtype, 0, 0, msg, msglen);
 }
 
 // ====================================================================== C ABI
@@ -1511,14 +1584,102 @@ tsk_status tsk_profile_report(tsk_handle h, char* buf, size_t buf_len, size_t* n
   return TSK_OK;
 }
 
+// ---- batched form: many independent sums in one launch sequence
+static tsk_status validate_batch(tsk_handle h, int32_t batch, const tsk_tucker_sum* sums,
+                                 const tsk_sketch_spec* specs, std::vector<Problem>& Ps) {
+  if (batch < 1 || sums == nullptr || specs == nullptr)
+    return fail(h, TSK_ERR_INVALID_ARG, "batch < 1 or NULL sums/specs");
+  Ps.resize(batch);
+  for (int b = 0; b < batch; ++b) {
+    tsk_status st = validate(h, &sums[b], &specs[b], Ps[b]);
+    if (st != TSK_OK) {
+      if (h) h->err = "sum " + std::to_string(b) + ": " + h->err;
+      return st;
+    }
+    if (Ps[b].d != Ps[0].d || Ps[b].kind != Ps[0].kind || Ps[b].ps != Ps[0].ps ||
+        Ps[b].pp != Ps[0].pp)
+      return fail(h, TSK_ERR_INVALID_ARG,
+                  "sum %d: order, sketch kind and precisions must match across the batch", b);
+  }
+  return TSK_OK;
+}
+
+tsk_status tucker_sum_batched_workspace_size(tsk_handle h, int32_t batch, const tsk_tucker_sum* sums,
+                                             const tsk_sketch_spec* specs, size_t* bytes) {
+  if (h == nullptr || bytes == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL handle or bytes");
+  h->err.clear();
+  std::vector<Problem> Ps;
+  tsk_status st = validate_batch(h, batch, sums, specs, Ps);
+  if (st != TSK_OK) return st;
+  size_t best = 0;
+  for (int o = 0; o < 2; ++o) {
+    std::vector<Outputs> outs(batch);
+    for (int b = 0; b < batch; ++b) {
+      outs[b].recompress = true;
+      outs[b].out_f64 = o == 1;
+      outs[b].Q.assign(Ps[b].d, nullptr);
+    }
+    Program prog;
+    size_t nb = 0;
+    plan_many(h, Ps, outs, nullptr, prog, &nb);
+    best = std::max(best, nb);
+  }
+  *bytes = best;
+  return TSK_OK;
+}
+
+tsk_status tucker_sum_recompress_batched(tsk_handle h, int32_t batch, const tsk_tucker_sum* sums,
+                                         const tsk_sketch_spec* specs, void* const* const* Q_out,
+                                         void* const* H_out, tsk_dtype out_dtype, void* ws,
+                                         size_t ws_bytes, void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  std::vector<Problem> Ps;
+  tsk_status st = validate_batch(h, batch, sums, specs, Ps);
+  if (st != TSK_OK) return st;
+  if (Q_out == nullptr || H_out == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "Q_out or H_out is NULL");
+  if (out_dtype != TSK_F64 && out_dtype != TSK_F32) return fail(h, TSK_ERR_INVALID_ARG, "bad out_dtype");
+  std::vector<Outputs> outs(batch);
+  for (int b = 0; b < batch; ++b) {
+    outs[b].recompress = true;
+    outs[b].out_f64 = out_dtype == TSK_F64;
+    if (Q_out[b] == nullptr || H_out[b] == nullptr)
+      return fail(h, TSK_ERR_INVALID_ARG, "Q_out[%d] or H_out[%d] is NULL", b, b);
+    outs[b].H = H_out[b];
+    for (int n = 0; n < Ps[b].d; ++n) {
+      if (Q_out[b][n] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "Q_out[%d][%d] is NULL", b, n);
+      outs[b].Q.push_back(Q_out[b][n]);
+    }
+  }
+  if (ws == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  Program prog;
+  size_t need = 0;
+  plan_many(h, Ps, outs, (char*)ws, prog, &need);
+  if (ws_bytes < need)
+    return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  if ((st = set_device(h)) != TSK_OK) return st;
+  return run_program(h, prog, (char*)ws, (hipStream_t)stream);
+}
+
 tsk_status tsk_qr_fallback_count(tsk_handle h, void* stream, int64_t* count) {
   if (h == nullptr || count == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL argument");
   tsk_status st = set_device(h);
   if (st != TSK_OK) return st;
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
     return fail(h, TSK_ERR_DEVICE, "stream synchronisation failed");
-  if (hipMemcpy(count, h->d_counter, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+  int64_t c[2] = {0, 0};
+  if (hipMemcpy(c, h->d_counter, sizeof c, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(h, TSK_ERR_DEVICE, "counter read failed");
+  *count = c[0];
+  if (c[1] != 0) {
+    // breakdowns under qr_policy 2 are reported once, then cleared
+    if (hipMemset(h->d_counter + 1, 0, sizeof(int64_t)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
+      return fail(h, TSK_ERR_DEVICE, "counter reset failed");
+    return fail(h, TSK_ERR_RANK_DEFICIENT, "%lld Cholesky QR breakdown(s) under qr_policy 2",
+                (long long)c[1]);
+  }
   return TSK_OK;
 }
 

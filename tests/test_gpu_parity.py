@@ -212,3 +212,21 @@ def test_precision_workload_fp64(tsk):
     """d=4, 256^4, 8 terms, cores 32^4, KRP m = 56, all FP64."""
     ts = synth.config_precision()
     check_recompress(tsk, ts, "krp", [56], ts["omega_seed"])
+
+
+def test_cholqr2_policy_reports_rank_deficiency(tsk):
+    """qr_policy 'cholqr2': a breakdown is reported by the next
+    qr_fallback_count call as TSK_ERR_RANK_DEFICIENT; the outputs are the
+    Householder result and the recompression is still exact."""
+    ts = synth.e1_low_rank_sum(seed=9, d=3, n=40, terms=12, r_true=6)
+    try:
+        tsk.qr_fallback_count(DEV)
+    except tsk.TskError:
+        pass
+    qs, h = run(tsk, ts, "krp", [9], 3, qr_policy="cholqr2")
+    with pytest.raises(tsk.TskError) as ei:
+        tsk.qr_fallback_count(DEV)
+    assert ei.value.name == "TSK_ERR_RANK_DEFICIENT"
+    tsk.qr_fallback_count(DEV)  # cleared after one report
+    x = T.sum_to_dense(ts)
+    assert T.rel_err(RC.reconstruct(np_of(h), [np_of(q) for q in qs]), x) < 1e-12

@@ -85,3 +85,44 @@ def test_plan_in_bounds_batch_shapes():
 def test_selfcheck_detects_invalid_problem():
     rc, msg = selfcheck((10, 10), [[0, 2]], "krp", [3])
     assert rc == 1 and "ranks" in msg
+
+
+def selfcheck_batched(sums, kind_sizes, prec="fp32", in_f64=False, out_f64=False):
+    from paper_2603_13532_amd import _lib
+    lib = _lib.load()
+    fn = lib.tsk_plan_selfcheck_batched
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_int32, ctypes.POINTER(_lib.TuckerSum), ctypes.POINTER(_lib.SketchSpec),
+                   ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
+    keep = []
+    ts = (_lib.TuckerSum * len(sums))()
+    sp = (_lib.SketchSpec * len(sums))()
+    for b, (one, (kind, sizes)) in enumerate(zip(sums, kind_sizes)):
+        ranks = np.asarray(one["ranks"])
+        s, d = ranks.shape
+        c_dims = (ctypes.c_int64 * d)(*one["dims"])
+        c_ranks = (ctypes.c_int32 * (s * d))(*[int(x) for x in ranks.ravel()])
+        c_cores = (ctypes.c_void_p * s)(*([0x1000] * s))
+        c_fac = (ctypes.c_void_p * (s * d))(*([0x1000] * (s * d)))
+        c_sizes = (ctypes.c_int32 * len(sizes))(*sizes)
+        keep += [c_dims, c_ranks, c_cores, c_fac, c_sizes]
+        ts[b] = _lib.TuckerSum(d, s, c_dims, c_ranks, c_cores, c_fac, None, 0 if in_f64 else 1)
+        sp[b] = _lib.SketchSpec(_lib.KINDS[kind], c_sizes, 1004 + b, None, _lib.PRECISIONS[prec],
+                                _lib.PRECISIONS[prec], 0)
+    msg = ctypes.create_string_buffer(512)
+    rc = fn(len(sums), ts, sp, 0 if out_f64 else 1, msg, 512)
+    return rc, msg.value.decode()
+
+
+@pytest.mark.parametrize("prec,in_f64,out_f64", [("fp32", False, False), ("fp64", True, True),
+                                                 ("bf16x6", False, True)])
+def test_batched_plan_in_bounds(prec, in_f64, out_f64):
+    sums = synth.config_batch(count=40)
+    rc, msg = selfcheck_batched(sums, [("krp", [one["ell"][0]]) for one in sums], prec, in_f64, out_f64)
+    assert rc == 0, msg
+
+
+def test_batched_plan_kron_mixed_shapes():
+    sums = [synth.random_sum(i, (30 + i, 20, 25), [[3, 4, 5], [2, 2, 2]]) for i in range(5)]
+    rc, msg = selfcheck_batched(sums, [("kron", [2, 3, 2])] * 5, "fp64", True, True)
+    assert rc == 0, msg
