@@ -182,6 +182,29 @@ tsk_status tucker_sum_recompress_batched(tsk_handle handle, int32_t batch,
                                          tsk_dtype out_dtype, void* ws, size_t ws_bytes,
                                          void* stream);
 
+/* Reverse mode of tucker_sum_recompress for the Khatri-Rao sketch (the paper
+ * gives no gradients; the rules are derived from the Stage 2-3 definitions of
+ * Algorithm 5): given the forward outputs Q[n] (n_n x w_n) and R[n] (FP64,
+ * w_n x w_n, from R_out), and the gradients H_bar (w_1 x ... x w_d) and
+ * Q_bar[n] (NULL = zero) of a scalar loss, write the gradients with respect
+ * to every core (core_bar[i], core-shaped) and factor (factor_bar[i*d+k],
+ * n_k x r_k^(i)), in the sum's dtype.  Q, H_bar and Q_bar are of out_dtype.
+ * The thin-QR adjoint
+ *   Y_bar = (Q_bar + Q copyltu(-Q_bar^T Q)) R^-T
+ * runs in FP64 and needs full column rank (w_n = W_n <= n_n, R invertible);
+ * the contractions run in spec->sketch_prec.  Intermediates (P, V, W) are
+ * recomputed from the inputs and Omega (regenerated from the seed).
+ * Returns TSK_ERR_UNSUPPORTED for the Kronecker sketch, oversketched modes or
+ * widths above 96. */
+tsk_status tucker_sum_backward_workspace_size(tsk_handle handle, const tsk_tucker_sum* sum,
+                                              const tsk_sketch_spec* spec, size_t* bytes);
+tsk_status tucker_sum_recompress_backward(tsk_handle handle, const tsk_tucker_sum* sum,
+                                          const tsk_sketch_spec* spec, const void* const* Q,
+                                          const double* const* R, const void* H_bar,
+                                          const void* const* Q_bar, tsk_dtype out_dtype,
+                                          void* const* core_bar, void* const* factor_bar,
+                                          void* ws, size_t ws_bytes, void* stream);
+
 /* Number of mode QRs that took the Householder path since the handle was
  * created (Cholesky breakdown, or qr_policy 1).  Synchronises `stream`.
  * Returns TSK_ERR_RANK_DEFICIENT (count still written) if, since the last

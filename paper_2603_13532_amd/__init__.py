@@ -22,6 +22,7 @@ __all__ = [
     "fortran", "empty_fortran", "krp_width", "kron_sizes", "sketch_widths", "sketch_omega",
     "tucker_sum_sketch", "tucker_sum_recompress", "qr_fallback_count", "Handle", "TskError",
     "Recompressor", "BatchRecompressor", "tucker_sum_recompress_batched",
+    "tucker_sum_recompress_backward", "recompress",
 ]
 
 
@@ -334,6 +335,89 @@ def tucker_sum_recompress_batched(sums, sketch_prec="fp64", project_prec="fp64",
     br = BatchRecompressor(sums, sketch_prec, project_prec, out_dtype, qr_policy)
     q, h = br()
     return list(zip(q, h))
+
+
+def tucker_sum_recompress_backward(cores, factors, kind, sizes, seed, Q, R, H_bar, Q_bar=None,
+                                   coeffs=None, sketch_prec="fp64"):
+    """Gradients of a loss with respect to every core and factor, given the
+    forward outputs Q, R and the loss gradients H_bar (and Q_bar, or None).
+    Returns (core_bar list, factor_bar list of lists) in the input dtype."""
+    m = _Marshal(cores, factors, coeffs, kind, sizes, seed, None, sketch_prec, sketch_prec, "auto")
+    h = Handle.get(m.device)
+    out_dtype = H_bar.dtype
+    Qf = [fortran(q.to(out_dtype)) for q in Q]
+    Rf = [fortran(r.to(torch.float64)) for r in R]
+    Hf = fortran(H_bar.to(out_dtype))
+    Qbf = None if Q_bar is None else [fortran(q.to(out_dtype)) for q in Q_bar]
+    core_bar = [empty_fortran(tuple(g.shape), m.dtype, m.device) for g in m.cores]
+    factor_bar = [[empty_fortran(tuple(u.shape), m.dtype, m.device) for u in us] for us in m.factors]
+    c_q = (c_void_p * m.d)(*[q.data_ptr() for q in Qf])
+    c_r = (c_void_p * m.d)(*[r.data_ptr() for r in Rf])
+    c_qb = None if Qbf is None else (c_void_p * m.d)(*[q.data_ptr() for q in Qbf])
+    c_gb = (c_void_p * m.s)(*[g.data_ptr() for g in core_bar])
+    c_ub = (c_void_p * (m.s * m.d))(*[u.data_ptr() for us in factor_bar for u in us])
+    nbytes = c_size_t()
+    check(load().tucker_sum_backward_workspace_size(h.ptr, byref(m.sum), byref(m.spec),
+                                                    byref(nbytes)), h.ptr)
+    ws = h.workspace(nbytes.value)
+    check(load().tucker_sum_recompress_backward(
+        h.ptr, byref(m.sum), byref(m.spec), c_q, c_r, c_void_p(Hf.data_ptr()), c_qb,
+        _dtype_code(out_dtype), c_gb, c_ub, c_void_p(ws.data_ptr()), ws.numel(),
+        c_void_p(_stream_ptr(m.device))), h.ptr)
+    return core_bar, factor_bar
+
+
+class _RecompressFn(torch.autograd.Function):
+    """Differentiable Stages 2-3 (Khatri-Rao sketch): forward and backward are
+    both the library's HIP kernels (tucker_sum_recompress with R_out, and
+    tucker_sum_recompress_backward)."""
+
+    @staticmethod
+    def forward(ctx, meta, *flat):
+        s, d = meta["s"], meta["d"]
+        cores = list(flat[:s])
+        factors = [list(flat[s + i * d: s + (i + 1) * d]) for i in range(s)]
+        qs, h, rs = tucker_sum_recompress(cores, factors, meta["kind"], meta["sizes"], meta["seed"],
+                                          coeffs=meta["coeffs"], sketch_prec=meta["sketch_prec"],
+                                          project_prec=meta["project_prec"], return_r=True)
+        ctx.meta = meta
+        ctx.save_for_backward(*flat, *qs, *rs)
+        return (h, *qs)
+
+    @staticmethod
+    def backward(ctx, h_bar, *q_bars):
+        meta = ctx.meta
+        s, d = meta["s"], meta["d"]
+        saved = ctx.saved_tensors
+        nin = s + s * d
+        flat = saved[:nin]
+        qs = list(saved[nin:nin + d])
+        rs = list(saved[nin + d:nin + 2 * d])
+        cores = list(flat[:s])
+        factors = [list(flat[s + i * d: s + (i + 1) * d]) for i in range(s)]
+        if h_bar is None:
+            h_bar = torch.zeros(tuple(q.shape[1] for q in qs), dtype=qs[0].dtype, device=qs[0].device)
+        if all(q is None for q in q_bars):
+            q_bar = None
+        else:
+            q_bar = [torch.zeros_like(q) if g is None else g for q, g in zip(qs, q_bars)]
+        gb, ub = tucker_sum_recompress_backward(cores, factors, meta["kind"], meta["sizes"],
+                                                meta["seed"], qs, rs, h_bar, q_bar,
+                                                coeffs=meta["coeffs"],
+                                                sketch_prec=meta["sketch_prec"])
+        return (None, *gb, *[u for us in ub for u in us])
+
+
+def recompress(cores, factors, kind, sizes, seed, coeffs=None, sketch_prec="fp64",
+               project_prec=None):
+    """Differentiable recompression: returns (H, [Q_1..Q_d]) with gradients
+    flowing to every core and factor through the hand-written adjoint."""
+    meta = {"s": len(cores), "d": len(factors[0]), "kind": kind, "sizes": list(sizes),
+            "seed": seed, "coeffs": None if coeffs is None else [float(c) for c in coeffs],
+            "sketch_prec": sketch_prec, "project_prec": project_prec or sketch_prec}
+    flat = list(cores) + [u for us in factors for u in us]
+    out = _RecompressFn.apply(meta, *flat)
+    return out[0], list(out[1:])
 
 
 def qr_fallback_count(device=None) -> int:

@@ -76,6 +76,12 @@ PROTOTYPES = {
                                               POINTER(SketchSpec), POINTER(POINTER(c_void_p)),
                                               POINTER(c_void_p), c_int, c_void_p, c_size_t,
                                               c_void_p]),
+    "tucker_sum_backward_workspace_size": (c_int, [c_void_p, POINTER(TuckerSum),
+                                                   POINTER(SketchSpec), POINTER(c_size_t)]),
+    "tucker_sum_recompress_backward": (c_int, [c_void_p, POINTER(TuckerSum), POINTER(SketchSpec),
+                                               POINTER(c_void_p), POINTER(c_void_p), c_void_p,
+                                               POINTER(c_void_p), c_int, POINTER(c_void_p),
+                                               POINTER(c_void_p), c_void_p, c_size_t, c_void_p]),
     "tsk_profile_enable": (c_int, [c_void_p, c_int32]),
     "tsk_profile_report": (c_int, [c_void_p, c_char_p, c_size_t, POINTER(c_size_t)]),
 }

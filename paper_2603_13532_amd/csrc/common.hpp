@@ -79,6 +79,39 @@ struct KrpDesc {
 };
 
 // ---------------------------------------------------------------------------
+// Adjoint of the KRP core sketch with respect to the core, for one term and
+// mode n: G_bar_(n) += Vbar (r_n x m) * KR_n^T, written through the mode-n
+// unfolding into a core-shaped (column-major) output.
+struct KrpAdjDesc {
+  const void* Vbar;              // r_n x m, ld r_n
+  const void* P[kMaxOrder];      // r_k x m (P[n] unused)
+  void* Gout;                    // core-shaped output
+  int32_t r[kMaxOrder];
+  int32_t order, mode, m, pad_;
+  int64_t Nc;                    // prod_{k != n} r_k
+  int32_t tiles_m, tiles_n;
+  int64_t tile_begin;
+  double alpha;
+};
+
+// Y_bar = Z R^-T for one mode (rows of Z are independent back substitutions).
+struct TrsmJob {
+  const double* Z;      // n x w, ld n
+  const double* R;      // w x w upper triangular, ld w
+  double* X;            // n x w, ld n (may alias Z)
+  int64_t n, w;
+  int64_t row0;         // first row of this job's chunk
+  int32_t rows, pad_;
+};
+
+// S = copyltu(M): lower triangle of M mirrored to the upper one.
+struct SymJob {
+  const double* M;
+  double* S;
+  int64_t w;
+};
+
+// ---------------------------------------------------------------------------
 // Per-mode QR bookkeeping (Cholesky QR2 with Householder fallback).
 struct QrDesc {
   const double* Y;      // n x W input sketch

@@ -333,6 +333,129 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
   }
 }
 
+// Adjoint of the KRP core sketch with respect to the core: rows a (mode n
+// of the core) against columns c (the other modes, first remaining mode
+// fastest), K = t over the sketch width.  The Khatri-Rao row of column c is
+// generated from the P_k; its mixed-radix digits are computed once per
+// thread because a thread's columns do not change along K.  The result is
+// scattered through the mode-n unfolding into the core layout.
+template <int P>
+__global__ __launch_bounds__(NTHREADS) void krp_adj_kernel(const KrpAdjDesc* __restrict__ descs,
+                                                           int ndesc) {
+  typedef typename PT<P>::in_t in_t;
+  typedef typename PT<P>::acc_t acc_t;
+  constexpr int BK = PT<P>::BK;
+  constexpr int PER = Stage<P>::PER_THREAD;
+  __shared__ typename Lds<P>::type s[2];
+
+  const int64_t tile = blockIdx.x;
+  const KrpAdjDesc& D = descs[find_desc(descs, ndesc, tile)];
+  const int64_t local = tile - D.tile_begin;
+  const int tm = (int)(local % D.tiles_m);
+  const int64_t tn = local / D.tiles_m;
+  const int order = D.order, n = D.mode, m = D.m;
+  const int64_t Nc = D.Nc;
+  const int64_t m0 = (int64_t)tm * TILE, n0 = tn * TILE;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w & 1, wn = w >> 1;
+  const in_t* __restrict__ Vb = (const in_t*)D.Vbar;
+  const in_t alpha = (in_t)D.alpha;
+  int64_t st[kMaxOrder];
+  int rk[kMaxOrder];
+  const in_t* Pk[kMaxOrder];
+  {
+    int64_t acc_st = 1;
+#pragma unroll
+    for (int k = 0; k < kMaxOrder; ++k) {
+      rk[k] = (k < order) ? D.r[k] : 1;
+      st[k] = acc_st;
+      acc_st *= rk[k];
+      Pk[k] = (const in_t*)D.P[k];
+    }
+  }
+  const int rn = rk[n];
+  // this thread's B columns (k-contiguous mapping: depth kq, rows x_j)
+  const int kq = t % BK;
+  int dig[PER][kMaxOrder];
+  bool colok[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int64_t c = n0 + t / BK + (NTHREADS / BK) * j;
+    colok[j] = c < Nc;
+    int64_t rem = colok[j] ? c : 0;
+#pragma unroll
+    for (int k = 0; k < kMaxOrder; ++k) {
+      dig[j][k] = 0;
+      if (k < order && k != n) {
+        const int64_t q = rem / rk[k];
+        dig[j][k] = (int)(rem - q * rk[k]);
+        rem = q;
+      }
+    }
+  }
+  acc_t acc[2][2];
+  acc_zero<P>(acc);
+  in_t ra[PER], rb[PER];
+  const int nkt = (m + BK - 1) / BK;
+#define TSK_ADJ_FETCH(KT)                                                           \
+  {                                                                                 \
+    const int k0 = (KT) * BK;                                                       \
+    _Pragma("unroll") for (int j = 0; j < PER; ++j) {                               \
+      int x, k;                                                                     \
+      PanelMap<P>::xk(true, t, j, x, k);                                            \
+      const int64_t a = m0 + x;                                                     \
+      ra[j] = (a < rn && k0 + k < m) ? Vb[a + (int64_t)(k0 + k) * rn] * alpha : (in_t)0; \
+      const int tt = k0 + kq;                                                       \
+      in_t prod = (in_t)0;                                                          \
+      if (colok[j] && tt < m) {                                                     \
+        prod = (in_t)1;                                                             \
+        _Pragma("unroll") for (int q = 0; q < kMaxOrder; ++q) if (q < order &&      \
+                                                                 q != n) prod *=    \
+            Pk[q][dig[j][q] + (int64_t)tt * rk[q]];                                 \
+      }                                                                             \
+      rb[j] = prod;                                                                 \
+    }                                                                               \
+  }
+  int kt = 0, buf = 0;
+  if (kt < nkt) {
+    TSK_ADJ_FETCH(kt);
+    stage<P>(s[0], true, false, t, ra, rb);
+  }
+  __syncthreads();
+  while (kt < nkt) {
+    const int kn = kt + 1;
+    if (kn < nkt) TSK_ADJ_FETCH(kn);
+    mma_tile<P>(s[buf], acc, lane, wm, wn);
+    if (kn < nkt) stage<P>(s[buf ^ 1], true, false, t, ra, rb);
+    __syncthreads();
+    buf ^= 1;
+    kt = kn;
+  }
+#undef TSK_ADJ_FETCH
+  // scatter through the unfolding: (a, c) -> a*st_n + sum_k dig_k(c) st_k
+  typedef typename std::conditional<P == P_FP64, double, float>::type vt;
+  vt* __restrict__ Gout = (vt*)D.Gout;
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj) {
+    const int64_t c = n0 + acc_col(wn, jj, lane);
+    if (c >= Nc) continue;
+    int64_t rem = c, off = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxOrder; ++k)
+      if (k < order && k != n) {
+        const int64_t q = rem / rk[k];
+        off += (rem - q * rk[k]) * st[k];
+        rem = q;
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t a = m0 + acc_row<P>(wm, i, lane, v);
+        if (a < rn) Gout[a * st[n] + off] = (vt)acc[i][jj][v];
+      }
+  }
+}
+
 // One job per blockIdx.y; blocks stride over columns, threads over rows.
 // Parts are summed four at a time so that several loads are in flight.
 __global__ __launch_bounds__(256) void reduce_kernel(const ReduceJob* __restrict__ jobs) {
@@ -489,6 +612,21 @@ hipError_t launch_krp(int prec, const KrpDesc* descs, int ndesc, int64_t total_t
     case P_BF16X1: krp_kernel<P_BF16X1><<<grid, block, 0, stream>>>(descs, ndesc); break;
     case P_BF16X3: krp_kernel<P_BF16X3><<<grid, block, 0, stream>>>(descs, ndesc); break;
     case P_BF16X6: krp_kernel<P_BF16X6><<<grid, block, 0, stream>>>(descs, ndesc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_krp_adj(int prec, const KrpAdjDesc* descs, int ndesc, int64_t total_tiles,
+                          hipStream_t stream) {
+  if (ndesc <= 0 || total_tiles <= 0) return hipSuccess;
+  const dim3 grid((unsigned)total_tiles), block(NTHREADS);
+  switch (prec) {
+    case P_FP64: krp_adj_kernel<P_FP64><<<grid, block, 0, stream>>>(descs, ndesc); break;
+    case P_FP32: krp_adj_kernel<P_FP32><<<grid, block, 0, stream>>>(descs, ndesc); break;
+    case P_BF16X1: krp_adj_kernel<P_BF16X1><<<grid, block, 0, stream>>>(descs, ndesc); break;
+    case P_BF16X3: krp_adj_kernel<P_BF16X3><<<grid, block, 0, stream>>>(descs, ndesc); break;
+    case P_BF16X6: krp_adj_kernel<P_BF16X6><<<grid, block, 0, stream>>>(descs, ndesc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -30,6 +30,13 @@ hipError_t launch_gemm(int prec, int role, const GemmDesc* descs, int ndesc, con
 hipError_t launch_krp(int prec, const KrpDesc* descs, int ndesc, int64_t total_tiles,
                       hipStream_t stream);
 
+// Core adjoint of the KRP sketch (core-shaped outputs).
+hipError_t launch_krp_adj(int prec, const KrpAdjDesc* descs, int ndesc, int64_t total_tiles,
+                          hipStream_t stream);
+// Adjoint of the thin QR: copyltu and the R^-T substitution.
+hipError_t launch_sym(const SymJob* jobs, int count, hipStream_t stream);
+hipError_t launch_trsm_rt(const TrsmJob* jobs, int count, hipStream_t stream);
+
 // out[j] (rows x cols, ld_out) = beta * out + sum_{s < parts} part[s] (rows x
 // cols, ld_part, part stride `stride_part`), for `count` independent jobs.
 struct ReduceJob {

@@ -329,7 +329,51 @@ __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restri
   }
 }
 
+// copyltu(M): S(i, j) = M(max(i,j), min(i,j)).
+__global__ __launch_bounds__(256) void sym_kernel(const SymJob* __restrict__ jobs) {
+  const SymJob J = jobs[blockIdx.x];
+  const int64_t w = J.w;
+  for (int64_t e = threadIdx.x; e < w * w; e += 256) {
+    const int64_t i = e % w, j = e / w;
+    J.S[e] = (i >= j) ? J.M[i + j * w] : J.M[j + i * w];
+  }
+}
+
+// X = Z R^-T: thread per row, x R^T = z, i.e. back substitution with the
+// rows of R.  R and the running solutions live in LDS (one wave per job).
+constexpr int kTrsmMax = 96;
+__global__ __launch_bounds__(64) void trsm_rt_kernel(const TrsmJob* __restrict__ jobs) {
+  const TrsmJob J = jobs[blockIdx.x];
+  const int w = (int)J.w, t = threadIdx.x;
+  __shared__ double sR[kTrsmMax * kTrsmMax];
+  __shared__ double sx[kTrsmMax][64];
+  for (int e = t; e < w * w; e += 64) sR[e] = J.R[e];
+  __syncthreads();
+  const int64_t row = J.row0 + t;
+  const bool active = t < J.rows && row < J.n;
+  if (active) {
+    for (int j = w - 1; j >= 0; --j) {
+      double acc = J.Z[row + (int64_t)j * J.n];
+      for (int l = j + 1; l < w; ++l) acc -= sR[j + l * w] * sx[l][t];
+      sx[j][t] = acc / sR[j + j * w];
+    }
+    for (int j = 0; j < w; ++j) J.X[row + (int64_t)j * J.n] = sx[j][t];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_sym(const SymJob* jobs, int count, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  sym_kernel<<<dim3((unsigned)count), dim3(256), 0, stream>>>(jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_rt(const TrsmJob* jobs, int count, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  trsm_rt_kernel<<<dim3((unsigned)count), dim3(64), 0, stream>>>(jobs);
+  return hipGetLastError();
+}
 
 hipError_t launch_chol(const QrDesc* qr, int count, int pass, double tol, hipStream_t stream) {
   if (count <= 0) return hipSuccess;

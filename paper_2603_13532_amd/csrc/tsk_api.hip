@@ -171,7 +171,8 @@ tsk_status validate(tsk_handle h, const tsk_tucker_sum* sum, const tsk_sketch_sp
 }
 
 // ------------------------------------------------------------------ program
-enum StepKind { S_OMEGA, S_GEMM, S_KRP, S_REDUCE, S_TILE_REDUCE, S_COPY, S_FILL, S_CHOL, S_HOUSE };
+enum StepKind { S_OMEGA, S_GEMM, S_KRP, S_REDUCE, S_TILE_REDUCE, S_COPY, S_FILL, S_CHOL, S_HOUSE,
+                S_KRP_ADJ, S_SYM, S_TRSM };
 
 struct Step {
   StepKind kind;
@@ -918,6 +919,428 @@ void Builder::emit(Program& prog) {
   emit_gemm_stage(ST_FINAL);
 }
 
+// ------------------------------------------------------------------ backward
+// Buffers of one backward call (see tucker_sum_recompress_backward).
+struct BackwardIO {
+  std::vector<const void*> Q;       // forward Q_n (out dtype)
+  std::vector<const double*> R;     // forward R_n (FP64, w x w)
+  const void* Hbar = nullptr;       // out dtype
+  std::vector<const void*> Qbar;    // out dtype, or empty
+  bool out_f64 = true;              // dtype of Q, Hbar, Qbar
+  std::vector<void*> core_bar;      // sum dtype
+  std::vector<void*> factor_bar;    // sum dtype, [s*d]
+};
+
+// Reverse mode of the KRP recompression, in the order of the oracle's
+// derivation: recompute P, V, W; project H_bar back (G_bar, W_bar, Q_bar);
+// thin-QR adjoint in FP64; term expansion, core sketch and factor sketch
+// adjoints; sum the contributions.
+void build_backward(const Problem& P, const BackwardIO& io, Arena& ar, Program& prog) {
+  const int d = P.d, s = P.s;
+  const int pc = P.ps;                 // one arithmetic for every contraction
+  const bool tc64 = is_fp64(pc);
+  const size_t ec = esize(tc64);
+  std::vector<CopyJob> conv;
+  auto as_tc = [&](const void* src, bool src_f64, int64_t rows, int64_t cols) -> const void* {
+    if (src_f64 == tc64) return src;
+    void* p = ar.take(rows * cols * ec);
+    conv.push_back(CopyJob{p, src, rows, cols, rows, rows, tc64, src_f64});
+    return p;
+  };
+  std::vector<const void*> core(s), fac((size_t)s * d);
+  std::vector<int64_t> csize(s, 1);
+  for (int i = 0; i < s; ++i) {
+    for (int k = 0; k < d; ++k) csize[i] *= P.r(i, k);
+    core[i] = as_tc(P.cores[i], P.in_f64, csize[i], 1);
+    for (int k = 0; k < d; ++k)
+      fac[(size_t)i * d + k] = as_tc(P.factors[(size_t)i * d + k], P.in_f64, P.dims[k], P.r(i, k));
+  }
+  std::vector<const void*> Qc(d);
+  std::vector<const double*> Q64(d);
+  int64_t hsize = 1;
+  for (int n = 0; n < d; ++n) {
+    Qc[n] = as_tc(io.Q[n], io.out_f64, P.dims[n], P.w[n]);
+    Q64[n] = (const double*)(io.out_f64 ? io.Q[n] : as_tc(io.Q[n], false, P.dims[n], P.w[n]));
+    hsize *= P.w[n];
+  }
+  if (!io.out_f64 && !tc64) {
+    // as_tc above returned the float Q for Q64: make a real FP64 copy
+    for (int n = 0; n < d; ++n) {
+      void* p = ar.take(P.dims[n] * P.w[n] * 8);
+      conv.push_back(CopyJob{p, io.Q[n], P.dims[n], P.w[n], P.dims[n], P.dims[n], 1, 0});
+      Q64[n] = (const double*)p;
+    }
+  }
+  const void* Hb = as_tc(io.Hbar, io.out_f64, hsize, 1);
+  // Q_bar accumulators (FP64), seeded with the caller's Q_bar
+  std::vector<double*> Qb(d);
+  for (int n = 0; n < d; ++n) {
+    Qb[n] = (double*)ar.take(P.dims[n] * P.w[n] * 8);
+    if (!io.Qbar.empty())
+      conv.push_back(CopyJob{Qb[n], io.Qbar[n], P.dims[n], P.w[n], P.dims[n], P.dims[n], 1,
+                             io.out_f64 ? 1 : 0});
+  }
+  // Omega
+  std::vector<OmegaJob> om_jobs;
+  std::vector<const void*> om(d);
+  for (int k = 0; k < d; ++k) {
+    if (!P.omega.empty()) {
+      om[k] = as_tc(P.omega[k], P.in_f64, P.dims[k], P.ow[k]);
+    } else {
+      void* p = ar.take(P.dims[k] * P.ow[k] * ec);
+      om_jobs.push_back(OmegaJob{p, P.dims[k] * P.ow[k], P.seed, k, tc64 ? 1 : 0});
+      om[k] = p;
+    }
+  }
+  emit_copies(prog, conv);
+  if (!om_jobs.empty()) {
+    Step st{};
+    st.kind = S_OMEGA;
+    st.meta = prog.put(om_jobs);
+    st.count = (int)om_jobs.size();
+    for (const OmegaJob& j : om_jobs) st.rows = std::max<int64_t>(st.rows, j.count);
+    prog.steps.push_back(st);
+  }
+  const int64_t m = P.ow[0];
+  const int bk = tc64 ? 16 : 32;
+  // ---- recompute P_k = U_k^T Omega_k and W_k = Q_k^T U_k
+  std::vector<void*> Pf((size_t)s * d), Wm((size_t)s * d);
+  {
+    GemmBatch gb(pc, R_FACTOR_SKETCH, &ar);
+    GemmBatch gw(pc, R_PROJ_W, &ar);
+    for (int i = 0; i < s; ++i)
+      for (int k = 0; k < d; ++k) {
+        const int64_t n = P.dims[k], r = P.r(i, k), w = P.w[k];
+        Pf[(size_t)i * d + k] = ar.take(r * m * ec);
+        gb.add(Pf[(size_t)i * d + k], tc64, r, 0, (int)r, (int)m, 1, 0,
+               {seg(fac[(size_t)i * d + k], n, 1, 0, om[k], n, 1, 0, n)},
+               choose_splits((int64_t)s * d * ceil_div(r, 64) * ceil_div(m, 64), ceil_div(n, bk)));
+        Wm[(size_t)i * d + k] = ar.take(w * r * ec);
+        gw.add(Wm[(size_t)i * d + k], tc64, w, 0, (int)w, (int)r, 1, 0,
+               {seg(Qc[k], n, 1, 0, fac[(size_t)i * d + k], n, 1, 0, n)},
+               choose_splits((int64_t)s * d * ceil_div(w, 64) * ceil_div(r, 64), ceil_div(n, bk)));
+      }
+    emit_gemm(prog, gb);
+    emit_gemm(prog, gw);
+  }
+  // ---- recompute V_n = G_(n) KR_n (KRP kernel, no split)
+  std::vector<void*> V((size_t)s * d);
+  auto krp_step = [&](std::vector<KrpDesc>& kd, int64_t tiles) {
+    if (kd.empty()) return;
+    Step st{};
+    st.kind = S_KRP;
+    st.prec = pc;
+    st.meta = prog.put(kd);
+    st.count = (int)kd.size();
+    st.tiles = tiles;
+    prog.steps.push_back(st);
+  };
+  auto krp_desc = [&](int i, int mode, const std::vector<const void*>& fs, void* out,
+                      int64_t& tiles) {
+    KrpDesc D{};
+    D.G = core[i];
+    int64_t Kc = 1;
+    for (int k = 0; k < kMaxOrder; ++k) {
+      D.r[k] = k < d ? P.r(i, k) : 1;
+      D.P[k] = k < d ? fs[k] : nullptr;
+      if (k < d && k != mode) Kc *= P.r(i, k);
+    }
+    D.order = d;
+    D.mode = mode;
+    D.m = (int)m;
+    D.Kc = Kc;
+    D.alpha = 1.0;
+    D.tiles_m = (int)ceil_div(P.r(i, mode), 64);
+    D.tiles_n = (int)ceil_div(m, 64);
+    D.splits = 1;
+    D.V = out;
+    D.tile_begin = tiles;
+    tiles += (int64_t)D.tiles_m * D.tiles_n;
+    return D;
+  };
+  {
+    std::vector<KrpDesc> kd;
+    int64_t tiles = 0;
+    for (int i = 0; i < s; ++i) {
+      std::vector<const void*> fs(d);
+      for (int k = 0; k < d; ++k) fs[k] = Pf[(size_t)i * d + k];
+      for (int n = 0; n < d; ++n) {
+        V[(size_t)i * d + n] = ar.take(P.r(i, n) * m * ec);
+        kd.push_back(krp_desc(i, n, fs, V[(size_t)i * d + n], tiles));
+      }
+    }
+    krp_step(kd, tiles);
+  }
+  // ---- projection adjoint: Z_k = H_bar x_{j != k} W_j^T (chains), W_bar, G_bar
+  std::vector<void*> Zk((size_t)s * d);
+  {
+    struct Chain {
+      std::vector<int64_t> shape;
+      const void* cur;
+      void* buf[2];
+      int which, i, k;
+    };
+    std::vector<Chain> ch;
+    for (int i = 0; i < s; ++i)
+      for (int k = 0; k < d; ++k) {
+        Chain c;
+        for (int j = 0; j < d; ++j) c.shape.push_back(P.w[j]);
+        c.cur = Hb;
+        int64_t mx = 1;
+        std::vector<int64_t> sh = c.shape;
+        for (int j = 0; j < d; ++j) {
+          if (j == k) continue;
+          sh[j] = P.r(i, j);
+          int64_t sz = 1;
+          for (auto x : sh) sz *= x;
+          mx = std::max(mx, sz);
+        }
+        c.buf[0] = ar.take(mx * ec);
+        c.buf[1] = ar.take(mx * ec);
+        c.which = 0;
+        c.i = i;
+        c.k = k;
+        ch.push_back(c);
+      }
+    for (int step = 0; step < d - 1; ++step) {
+      GemmBatch gb(pc, R_PROJ_TTM, &ar);
+      for (auto& c : ch) {
+        int j = -1, cnt = 0;
+        for (int q = 0; q < d; ++q)
+          if (q != c.k) {
+            if (cnt == step) j = q;
+            ++cnt;
+          }
+        const int64_t wj = c.shape[j], rj = P.r(c.i, j);
+        const void* Wj = Wm[(size_t)c.i * d + j];  // w_j x r_j
+        void* outp = c.buf[c.which];
+        int64_t L = 1, Rr = 1;
+        for (int q = 0; q < j; ++q) L *= c.shape[q];
+        for (int q = j + 1; q < d; ++q) Rr *= c.shape[q];
+        if (j == 0) {
+          // out (r_0 x Rr) = W_0^T (r_0 x w_0) . T_(0) (w_0 x Rr)
+          gb.add(outp, tc64, rj, 0, (int)rj, (int)Rr, 1, 0, {seg(Wj, wj, 1, 0, c.cur, wj, 1, 0, wj)});
+        } else {
+          // out_b (L x r_j) = T_b (L x w_j) . W_j (w_j x r_j)
+          gb.add(outp, tc64, L, L * rj, (int)L, (int)rj, (int)Rr, 0,
+                 {seg(c.cur, 1, L, L * wj, Wj, wj, 1, 0, wj)});
+        }
+        c.shape[j] = rj;
+        c.cur = outp;
+        c.which ^= 1;
+      }
+      emit_gemm(prog, gb);
+    }
+    for (auto& c : ch) Zk[(size_t)c.i * d + c.k] = (void*)c.cur;
+  }
+  // W_bar_k = c_i Z_k,(k) G_(k)^T (w_k x r_k); G_bar_proj = c_i Z_{d-1} x_{d-1} W_{d-1}^T
+  std::vector<void*> Wb((size_t)s * d), gparts(s);
+  {
+    GemmBatch gb(pc, R_OTHER, &ar);
+    GemmBatch gg(pc, R_PROJ_FINAL, &ar);
+    for (int i = 0; i < s; ++i) {
+      gparts[i] = ar.take((size_t)(d + 1) * csize[i] * ec);  // slot 0: projection, 1..d: sketch
+      for (int k = 0; k < d; ++k) {
+        const int64_t w = P.w[k], r = P.r(i, k);
+        Wb[(size_t)i * d + k] = ar.take(w * r * ec);
+        const void* Z = Zk[(size_t)i * d + k];
+        int64_t L = 1, T = 1;
+        for (int q = 0; q < k; ++q) L *= P.r(i, q);
+        for (int q = k + 1; q < d; ++q) T *= P.r(i, q);
+        std::vector<GemmSeg> sg;
+        int64_t ktiles = 0;
+        if (k == 0) {
+          sg.push_back(seg(Z, 1, w, 0, core[i], 1, r, 0, csize[i] / r, P.coeffs[i]));
+          ktiles = ceil_div(csize[i] / r, bk);
+        } else {
+          for (int64_t t = 0; t < T; ++t) {
+            sg.push_back(seg((const char*)Z + (size_t)t * L * w * ec, L, 1, 0,
+                             (const char*)core[i] + (size_t)t * L * r * ec, L, 1, 0, L, P.coeffs[i]));
+            ktiles += ceil_div(L, bk);
+          }
+        }
+        gb.add(Wb[(size_t)i * d + k], tc64, w, 0, (int)w, (int)r, 1, 0, sg,
+               choose_splits((int64_t)s * d * ceil_div(w, 64) * ceil_div(r, 64), ktiles));
+      }
+      // slot 0 of G_bar: c_i Z_{d-1} (L x w) . W_{d-1} (w x r)
+      const int k = d - 1;
+      const int64_t w = P.w[k], r = P.r(i, k);
+      const int64_t L = csize[i] / r;
+      gg.add(gparts[i], tc64, L, 0, (int)L, (int)r, 1, 0,
+             {seg(Zk[(size_t)i * d + k], 1, L, 0, Wm[(size_t)i * d + k], w, 1, 0, w, P.coeffs[i])});
+    }
+    emit_gemm(prog, gb);
+    emit_gemm(prog, gg);
+  }
+  // ---- Q_bar_k += sum_i U_k^(i) W_bar_k^(i)T (FP64 accumulator)
+  {
+    GemmBatch gb(pc, R_OTHER, &ar);
+    for (int k = 0; k < d; ++k) {
+      const int64_t n = P.dims[k], w = P.w[k];
+      std::vector<GemmSeg> sg;
+      for (int i = 0; i < s; ++i)
+        sg.push_back(seg(fac[(size_t)i * d + k], 1, n, 0, Wb[(size_t)i * d + k], 1, w, 0, P.r(i, k)));
+      gb.add(Qb[k], true, n, 0, (int)n, (int)w, 1, io.Qbar.empty() ? 0 : 1, sg);
+    }
+    emit_gemm(prog, gb);
+  }
+  // ---- thin-QR adjoint (FP64): M = -Q_bar^T Q, S = copyltu(M), Z = Q_bar + Q S, Y_bar = Z R^-T
+  std::vector<double*> Mm(d), Sm(d);
+  {
+    GemmBatch gm(P_FP64, R_OTHER, &ar);
+    for (int k = 0; k < d; ++k) {
+      const int64_t n = P.dims[k], w = P.w[k];
+      Mm[k] = (double*)ar.take(w * w * 8);
+      Sm[k] = (double*)ar.take(w * w * 8);
+      gm.add(Mm[k], true, w, 0, (int)w, (int)w, 1, 0, {seg(Qb[k], n, 1, 0, Q64[k], n, 1, 0, n, -1.0)},
+             choose_splits(d * ceil_div(w, 64) * ceil_div(w, 64), ceil_div(n, 16)));
+    }
+    emit_gemm(prog, gm);
+    std::vector<SymJob> sj;
+    for (int k = 0; k < d; ++k) sj.push_back(SymJob{Mm[k], Sm[k], P.w[k]});
+    Step st{};
+    st.kind = S_SYM;
+    st.meta = prog.put(sj);
+    st.count = d;
+    prog.steps.push_back(st);
+    GemmBatch gz(P_FP64, R_OTHER, &ar);
+    for (int k = 0; k < d; ++k) {
+      const int64_t n = P.dims[k], w = P.w[k];
+      gz.add(Qb[k], true, n, 0, (int)n, (int)w, 1, 1, {seg(Q64[k], 1, n, 0, Sm[k], w, 1, 0, w)});
+    }
+    emit_gemm(prog, gz);
+    std::vector<TrsmJob> tj;
+    for (int k = 0; k < d; ++k)
+      for (int64_t r0 = 0; r0 < P.dims[k]; r0 += 64)
+        tj.push_back(TrsmJob{Qb[k], io.R[k], Qb[k], P.dims[k], P.w[k], r0,
+                             (int32_t)std::min<int64_t>(64, P.dims[k] - r0), 0});
+    Step tr{};
+    tr.kind = S_TRSM;
+    tr.meta = prog.put(tj);
+    tr.count = (int)tj.size();
+    prog.steps.push_back(tr);
+  }
+  // Y_bar in the contraction type
+  std::vector<const void*> Yb(d);
+  {
+    std::vector<CopyJob> cj;
+    for (int k = 0; k < d; ++k) {
+      if (tc64) {
+        Yb[k] = Qb[k];
+      } else {
+        void* p = ar.take(P.dims[k] * P.w[k] * 4);
+        cj.push_back(CopyJob{p, Qb[k], P.dims[k], P.w[k], P.dims[k], P.dims[k], 0, 1});
+        Yb[k] = p;
+      }
+    }
+    emit_copies(prog, cj);
+  }
+  // ---- V_bar_n^(i) = c_i U_n^(i)T Y_bar_n
+  std::vector<void*> Vb((size_t)s * d);
+  {
+    GemmBatch gb(pc, R_OTHER, &ar);
+    for (int i = 0; i < s; ++i)
+      for (int n = 0; n < d; ++n) {
+        const int64_t nn = P.dims[n], r = P.r(i, n);
+        Vb[(size_t)i * d + n] = ar.take(r * m * ec);
+        gb.add(Vb[(size_t)i * d + n], tc64, r, 0, (int)r, (int)m, 1, 0,
+               {seg(fac[(size_t)i * d + n], nn, 1, 0, Yb[n], nn, 1, 0, nn, P.coeffs[i])},
+               choose_splits((int64_t)s * d * ceil_div(r, 64) * ceil_div(m, 64), ceil_div(nn, bk)));
+      }
+    emit_gemm(prog, gb);
+  }
+  // ---- P_bar_k = sum_{n != k} G_(k) KR(P_j, j != k with V_bar_n at n): d-1 slots, then a sum
+  std::vector<void*> Pb((size_t)s * d), Pslots((size_t)s * d);
+  {
+    std::vector<KrpDesc> kd;
+    int64_t tiles = 0;
+    std::vector<ReduceJob> red;
+    for (int i = 0; i < s; ++i)
+      for (int k = 0; k < d; ++k) {
+        const int64_t r = P.r(i, k);
+        Pslots[(size_t)i * d + k] = ar.take((size_t)(d - 1) * r * m * ec);
+        Pb[(size_t)i * d + k] = ar.take(r * m * ec);
+        int slot = 0;
+        for (int n = 0; n < d; ++n) {
+          if (n == k) continue;
+          std::vector<const void*> fs(d);
+          for (int j = 0; j < d; ++j) fs[j] = (j == n) ? Vb[(size_t)i * d + n] : Pf[(size_t)i * d + j];
+          kd.push_back(krp_desc(i, k, fs, (char*)Pslots[(size_t)i * d + k] + (size_t)slot * r * m * ec,
+                                tiles));
+          ++slot;
+        }
+        red.push_back(ReduceJob{Pb[(size_t)i * d + k], Pslots[(size_t)i * d + k], r, m, r, r, r * m,
+                                d - 1, 0, tc64 ? 1 : 0, tc64 ? 1 : 0});
+      }
+    krp_step(kd, tiles);
+    Step st{};
+    st.kind = S_REDUCE;
+    st.meta = prog.put(red);
+    st.count = (int)red.size();
+    prog.steps.push_back(st);
+  }
+  // ---- G_bar slots 1..d: V_bar_n KR_n^T through the mode-n unfolding
+  {
+    std::vector<KrpAdjDesc> ad;
+    int64_t tiles = 0;
+    for (int i = 0; i < s; ++i)
+      for (int n = 0; n < d; ++n) {
+        KrpAdjDesc D{};
+        D.Vbar = Vb[(size_t)i * d + n];
+        int64_t Nc = 1;
+        for (int k = 0; k < kMaxOrder; ++k) {
+          D.r[k] = k < d ? P.r(i, k) : 1;
+          D.P[k] = k < d ? Pf[(size_t)i * d + k] : nullptr;
+          if (k < d && k != n) Nc *= P.r(i, k);
+        }
+        D.Gout = (char*)gparts[i] + (size_t)(1 + n) * csize[i] * ec;
+        D.order = d;
+        D.mode = n;
+        D.m = (int)m;
+        D.Nc = Nc;
+        D.alpha = 1.0;
+        D.tiles_m = (int)ceil_div(P.r(i, n), 64);
+        D.tiles_n = (int)ceil_div(Nc, 64);
+        D.tile_begin = tiles;
+        tiles += (int64_t)D.tiles_m * D.tiles_n;
+        ad.push_back(D);
+      }
+    Step st{};
+    st.kind = S_KRP_ADJ;
+    st.prec = pc;
+    st.meta = prog.put(ad);
+    st.count = (int)ad.size();
+    st.tiles = tiles;
+    prog.steps.push_back(st);
+  }
+  // ---- core_bar = sum of the d + 1 slots
+  {
+    std::vector<ReduceJob> red;
+    for (int i = 0; i < s; ++i)
+      red.push_back(ReduceJob{io.core_bar[i], gparts[i], P.r(i, 0), csize[i] / P.r(i, 0), P.r(i, 0),
+                              P.r(i, 0), csize[i], d + 1, 0, P.in_f64 ? 1 : 0, tc64 ? 1 : 0});
+    Step st{};
+    st.kind = S_REDUCE;
+    st.meta = prog.put(red);
+    st.count = (int)red.size();
+    prog.steps.push_back(st);
+  }
+  // ---- factor_bar = Q_k W_bar_k + c_i Y_bar_k V_k^T + Omega_k P_bar_k^T
+  {
+    GemmBatch gb(pc, R_OTHER, &ar);
+    for (int i = 0; i < s; ++i)
+      for (int k = 0; k < d; ++k) {
+        const int64_t n = P.dims[k], r = P.r(i, k), w = P.w[k];
+        const size_t ik = (size_t)i * d + k;
+        gb.add(io.factor_bar[ik], P.in_f64, n, 0, (int)n, (int)r, 1, 0,
+               {seg(Qc[k], 1, n, 0, Wb[ik], w, 1, 0, w),
+                seg(Yb[k], 1, n, 0, V[ik], 1, r, 0, m, P.coeffs[i]),
+                seg(om[k], 1, n, 0, Pb[ik], 1, r, 0, m)});
+      }
+    emit_gemm(prog, gb);
+  }
+}
+
 // ------------------------------------------------------------------ execution
 const char* role_name(int role) {
   switch (role) {
@@ -953,6 +1376,12 @@ std::string step_name(const Step& st) {
     case S_FILL: return "fill_i32_kernel";
     case S_CHOL: return "chol_kernel";
     case S_HOUSE: return "householder_kernel";
+    case S_KRP_ADJ: {
+      snprintf(buf, sizeof buf, "krp_adj_kernel<%d> core_sketch_adjoint", st.prec);
+      return buf;
+    }
+    case S_SYM: return "sym_kernel";
+    case S_TRSM: return "trsm_rt_kernel";
   }
   return "unknown";
 }
@@ -1035,6 +1464,11 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
       case S_COPY: e = launch_copy((const CopyJob*)(meta + st.meta), st.count, stream); break;
       case S_FILL: e = launch_fill_i32((int32_t*)st.ptr, st.rows, st.value, stream); break;
       case S_CHOL: e = launch_chol((const QrDesc*)(meta + st.meta), st.count, st.pass, st.tol, stream); break;
+      case S_KRP_ADJ:
+        e = launch_krp_adj(st.prec, (const KrpAdjDesc*)(meta + st.meta), st.count, st.tiles, stream);
+        break;
+      case S_SYM: e = launch_sym((const SymJob*)(meta + st.meta), st.count, stream); break;
+      case S_TRSM: e = launch_trsm_rt((const TrsmJob*)(meta + st.meta), st.count, stream); break;
       case S_HOUSE:
         e = launch_householder((const QrDesc*)(meta + st.meta), st.count, st.force, (int64_t*)st.ptr, stream);
         break;
@@ -1218,6 +1652,44 @@ void check_program(const Program& prog, Checker& ck) {
         }
         break;
       }
+      case S_KRP_ADJ: {
+        const KrpAdjDesc* ds = (const KrpAdjDesc*)(blob + st.meta);
+        const size_t e = st.prec == P_FP64 ? 8 : 4;
+        int64_t tiles = 0;
+        for (int i = 0; i < st.count; ++i) {
+          const KrpAdjDesc& D = ds[i];
+          if (D.tile_begin != tiles) { ck.ok = false; ck.err = "krp_adj tile prefix mismatch"; return; }
+          tiles += (int64_t)D.tiles_m * D.tiles_n;
+          int64_t cs = 1;
+          for (int k = 0; k < D.order; ++k) {
+            cs *= D.r[k];
+            if (k != D.mode) ck.span(D.P[k], 0, (int64_t)D.r[k] * D.m - 1, e, "krp_adj P");
+          }
+          ck.span(D.Vbar, 0, (int64_t)D.r[D.mode] * D.m - 1, e, "krp_adj Vbar");
+          ck.span(D.Gout, 0, cs - 1, e, "krp_adj out");
+        }
+        if (tiles != st.tiles) { ck.ok = false; ck.err = "krp_adj total tiles mismatch"; }
+        break;
+      }
+      case S_SYM: {
+        const SymJob* js = (const SymJob*)(blob + st.meta);
+        for (int i = 0; i < st.count; ++i) {
+          ck.span(js[i].M, 0, js[i].w * js[i].w - 1, 8, "sym M");
+          ck.span(js[i].S, 0, js[i].w * js[i].w - 1, 8, "sym S");
+        }
+        break;
+      }
+      case S_TRSM: {
+        const TrsmJob* js = (const TrsmJob*)(blob + st.meta);
+        for (int i = 0; i < st.count; ++i) {
+          const TrsmJob& J = js[i];
+          if (J.w > 96 || J.rows > 64) { ck.ok = false; ck.err = "trsm job too large"; return; }
+          ck.span(J.R, 0, J.w * J.w - 1, 8, "trsm R");
+          ck.span(J.Z, 0, J.n * J.w - 1, 8, "trsm Z");
+          ck.span(J.X, 0, J.n * J.w - 1, 8, "trsm X");
+        }
+        break;
+      }
       case S_CHOL:
       case S_HOUSE: {
         const QrDesc* qs = (const QrDesc*)(blob + st.meta);
@@ -1316,6 +1788,96 @@ static int selfcheck_impl(int32_t batch, const tsk_tucker_sum* sums, const tsk_s
 }
 
 }  // namespace
+
+static tsk_status plan_backward(const Problem& P, const BackwardIO& io, char* ws, Program& prog,
+                                size_t* bytes) {
+  Arena ar;
+  ar.base = ws;
+  ar.ctr_base = (int32_t*)ar.take(256);
+  build_backward(P, io, ar, prog);
+  prog.meta_region = align_up(ar.top, 256);
+  *bytes = prog.meta_region + align_up(prog.blob.size(), 256) + 256;
+  return TSK_OK;
+}
+
+static tsk_status validate_backward(tsk_handle h, const Problem& P) {
+  if (P.kind != TSK_SKETCH_KRP)
+    return fail(h, TSK_ERR_UNSUPPORTED, "backward is implemented for the Khatri-Rao sketch");
+  for (int n = 0; n < P.d; ++n) {
+    if (P.W[n] > P.dims[n])
+      return fail(h, TSK_ERR_UNSUPPORTED, "backward needs sketch width <= n_k (mode %d)", n);
+    if (P.w[n] > 96) return fail(h, TSK_ERR_UNSUPPORTED, "backward needs sketch width <= 96");
+  }
+  return TSK_OK;
+}
+
+
+// Host-only bounds self-check of a backward plan (tests; not part of the ABI header).
+extern "C" int tsk_plan_selfcheck_backward(const tsk_tucker_sum* sum, const tsk_sketch_spec* spec,
+                                           int out_dtype, int with_qbar, char* msg, size_t msglen) {
+  auto say = [&](const std::string& s) {
+    if (msg && msglen) {
+      std::strncpy(msg, s.c_str(), msglen - 1);
+      msg[msglen - 1] = 0;
+    }
+  };
+  tsk_handle_ hh;
+  Problem P;
+  tsk_status st = validate(&hh, sum, spec, P);
+  if (st == TSK_OK) st = validate_backward(&hh, P);
+  if (st != TSK_OK) {
+    say(hh.err);
+    return st;
+  }
+  Checker ck;
+  uintptr_t next = (uintptr_t)1 << 44;
+  auto fake = [&](size_t bytes, const char* name) {
+    void* p = (void*)next;
+    ck.add(p, bytes, name);
+    next += align_up(bytes, (size_t)1 << 20) + ((size_t)1 << 30);
+    return p;
+  };
+  const size_t ein = P.in_f64 ? 8 : 4, eo = out_dtype == TSK_F64 ? 8 : 4;
+  BackwardIO io;
+  io.out_f64 = out_dtype == TSK_F64;
+  int64_t hsize = 1;
+  for (int i = 0; i < P.s; ++i) {
+    int64_t cs = 1;
+    for (int k = 0; k < P.d; ++k) cs *= P.r(i, k);
+    P.cores[i] = fake(cs * ein, "core");
+    io.core_bar.push_back(fake(cs * ein, "core_bar"));
+    for (int k = 0; k < P.d; ++k) {
+      P.factors[(size_t)i * P.d + k] = fake(P.dims[k] * P.r(i, k) * ein, "factor");
+      io.factor_bar.push_back(fake(P.dims[k] * P.r(i, k) * ein, "factor_bar"));
+    }
+  }
+  for (int n = 0; n < P.d; ++n) {
+    io.Q.push_back(fake(P.dims[n] * P.w[n] * eo, "Q"));
+    io.R.push_back((const double*)fake(P.w[n] * P.w[n] * 8, "R"));
+    if (with_qbar) io.Qbar.push_back(fake(P.dims[n] * P.w[n] * eo, "Qbar"));
+    hsize *= P.w[n];
+  }
+  io.Hbar = fake(hsize * eo, "Hbar");
+  Program p0;
+  size_t need = 0;
+  plan_backward(P, io, nullptr, p0, &need);
+  char* ws = (char*)fake(need, "workspace");
+  Program prog;
+  size_t need2 = 0;
+  plan_backward(P, io, ws, prog, &need2);
+  if (need != need2) {
+    say("workspace size differs between the size query and the call");
+    return 99;
+  }
+  check_program(prog, ck);
+  if (!ck.ok) {
+    say(ck.err);
+    return 98;
+  }
+  say("ok");
+  return 0;
+}
+
 
 // Host-only bounds self-check of a planned call (tests; not part of the ABI header).
 extern "C" int tsk_plan_selfcheck(const tsk_tucker_sum* sum, const tsk_sketch_spec* spec,
@@ -1656,6 +2218,89 @@ tsk_status tucker_sum_recompress_batched(tsk_handle h, int32_t batch, const tsk_
   Program prog;
   size_t need = 0;
   plan_many(h, Ps, outs, (char*)ws, prog, &need);
+  if (ws_bytes < need)
+    return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  if ((st = set_device(h)) != TSK_OK) return st;
+  return run_program(h, prog, (char*)ws, (hipStream_t)stream);
+}
+
+static tsk_status backward_io(tsk_handle h, const Problem& P, const void* const* Q,
+                              const double* const* R, const void* H_bar, const void* const* Q_bar,
+                              tsk_dtype out_dtype, void* const* core_bar, void* const* factor_bar,
+                              BackwardIO& io) {
+  if (Q == nullptr || R == nullptr || H_bar == nullptr || core_bar == nullptr || factor_bar == nullptr)
+    return fail(h, TSK_ERR_INVALID_ARG, "NULL Q, R, H_bar, core_bar or factor_bar");
+  if (out_dtype != TSK_F64 && out_dtype != TSK_F32) return fail(h, TSK_ERR_INVALID_ARG, "bad out_dtype");
+  io.out_f64 = out_dtype == TSK_F64;
+  io.Hbar = H_bar;
+  for (int n = 0; n < P.d; ++n) {
+    if (Q[n] == nullptr || R[n] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "Q[%d] or R[%d] is NULL", n, n);
+    io.Q.push_back(Q[n]);
+    io.R.push_back(R[n]);
+    if (Q_bar != nullptr) {
+      if (Q_bar[n] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "Q_bar[%d] is NULL", n);
+      io.Qbar.push_back(Q_bar[n]);
+    }
+  }
+  for (int i = 0; i < P.s; ++i) {
+    if (core_bar[i] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "core_bar[%d] is NULL", i);
+    io.core_bar.push_back(core_bar[i]);
+    for (int k = 0; k < P.d; ++k) {
+      void* f = factor_bar[(size_t)i * P.d + k];
+      if (f == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "factor_bar[%d][%d] is NULL", i, k);
+      io.factor_bar.push_back(f);
+    }
+  }
+  return TSK_OK;
+}
+
+tsk_status tucker_sum_backward_workspace_size(tsk_handle h, const tsk_tucker_sum* sum,
+                                              const tsk_sketch_spec* spec, size_t* bytes) {
+  if (h == nullptr || bytes == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL handle or bytes");
+  h->err.clear();
+  Problem P;
+  tsk_status st = validate(h, sum, spec, P);
+  if (st == TSK_OK) st = validate_backward(h, P);
+  if (st != TSK_OK) return st;
+  size_t best = 0;
+  for (int o = 0; o < 2; ++o)
+    for (int qb = 0; qb < 2; ++qb) {
+      BackwardIO io;
+      io.out_f64 = o == 1;
+      io.Q.assign(P.d, nullptr);
+      io.R.assign(P.d, nullptr);
+      if (qb) io.Qbar.assign(P.d, nullptr);
+      io.core_bar.assign(P.s, nullptr);
+      io.factor_bar.assign((size_t)P.s * P.d, nullptr);
+      Program prog;
+      size_t nb = 0;
+      plan_backward(P, io, nullptr, prog, &nb);
+      best = std::max(best, nb);
+    }
+  *bytes = best;
+  return TSK_OK;
+}
+
+tsk_status tucker_sum_recompress_backward(tsk_handle h, const tsk_tucker_sum* sum,
+                                          const tsk_sketch_spec* spec, const void* const* Q,
+                                          const double* const* R, const void* H_bar,
+                                          const void* const* Q_bar, tsk_dtype out_dtype,
+                                          void* const* core_bar, void* const* factor_bar, void* ws,
+                                          size_t ws_bytes, void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  Problem P;
+  tsk_status st = validate(h, sum, spec, P);
+  if (st == TSK_OK) st = validate_backward(h, P);
+  if (st != TSK_OK) return st;
+  BackwardIO io;
+  if ((st = backward_io(h, P, Q, R, H_bar, Q_bar, out_dtype, core_bar, factor_bar, io)) != TSK_OK)
+    return st;
+  if (ws == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  Program prog;
+  size_t need = 0;
+  plan_backward(P, io, (char*)ws, prog, &need);
   if (ws_bytes < need)
     return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
   if ((st = set_device(h)) != TSK_OK) return st;

@@ -126,3 +126,41 @@ def test_batched_plan_kron_mixed_shapes():
     sums = [synth.random_sum(i, (30 + i, 20, 25), [[3, 4, 5], [2, 2, 2]]) for i in range(5)]
     rc, msg = selfcheck_batched(sums, [("kron", [2, 3, 2])] * 5, "fp64", True, True)
     assert rc == 0, msg
+
+
+def selfcheck_backward(dims, ranks, m, prec="fp32", in_f64=False, out_f64=False, with_qbar=True):
+    from paper_2603_13532_amd import _lib
+    lib = _lib.load()
+    fn = lib.tsk_plan_selfcheck_backward
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.POINTER(_lib.TuckerSum), ctypes.POINTER(_lib.SketchSpec), ctypes.c_int,
+                   ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
+    ranks = np.asarray(ranks)
+    s, d = ranks.shape
+    c_dims = (ctypes.c_int64 * d)(*dims)
+    c_ranks = (ctypes.c_int32 * (s * d))(*[int(x) for x in ranks.ravel()])
+    c_cores = (ctypes.c_void_p * s)(*([0x1000] * s))
+    c_fac = (ctypes.c_void_p * (s * d))(*([0x1000] * (s * d)))
+    c_sizes = (ctypes.c_int32 * 1)(m)
+    tsum = _lib.TuckerSum(d, s, c_dims, c_ranks, c_cores, c_fac, None, 0 if in_f64 else 1)
+    spec = _lib.SketchSpec(0, c_sizes, 5, None, _lib.PRECISIONS[prec], _lib.PRECISIONS[prec], 0)
+    msg = ctypes.create_string_buffer(512)
+    rc = fn(ctypes.byref(tsum), ctypes.byref(spec), 0 if out_f64 else 1, int(with_qbar), msg, 512)
+    return rc, msg.value.decode()
+
+
+@pytest.mark.parametrize("dims,ranks,m", [((256,) * 3, np.full((6, 3), 24), 40),
+                                          ((12, 10, 9), [[3, 2, 4], [2, 3, 2], [4, 4, 3]], 6),
+                                          ((8, 7, 6, 7), [[3, 3, 3, 3], [2, 3, 2, 3]], 5),
+                                          ((70, 65, 80), [[33, 5, 70], [2, 40, 9]], 64)])
+def test_backward_plan_in_bounds(dims, ranks, m):
+    for prec, in_f64, out_f64 in (("fp64", True, True), ("fp32", False, False), ("fp32", True, False),
+                                  ("bf16x6", False, True)):
+        for qb in (True, False):
+            rc, msg = selfcheck_backward(dims, ranks, m, prec, in_f64, out_f64, qb)
+            assert rc == 0, (prec, in_f64, out_f64, qb, msg)
+
+
+def test_backward_rejects_kron_and_oversketch():
+    rc, msg = selfcheck_backward((10, 40, 40), [[3, 3, 3]], 12)
+    assert rc == 2 and "sketch width" in msg
