@@ -47,6 +47,8 @@ struct GemmSeg {
   double alpha;
 };
 
+static_assert(sizeof(GemmSeg) % 8 == 0, "segments are copied as 8-byte words");
+
 struct GemmDesc {
   void* C;
   void* part;          // splits > 1: per-tile partial blocks (64 x 64, accumulator type)

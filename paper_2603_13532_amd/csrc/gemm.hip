@@ -20,8 +20,16 @@ namespace tsk {
 
 namespace {
 
+// Descriptor of a linear tile id: the last one whose tile_begin <= tile.
+// Up to 256 descriptors every thread tests one and the block counts (one
+// memory round trip); beyond that, a binary search.
 template <typename D>
 __device__ __forceinline__ int find_desc(const D* __restrict__ descs, int ndesc, int64_t tile) {
+  if (ndesc <= NTHREADS) {
+    const int t = threadIdx.x;
+    const bool le = t < ndesc && descs[t].tile_begin <= tile;
+    return uni(__syncthreads_count(le) - 1);
+  }
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -74,83 +82,206 @@ __device__ __forceinline__ void store_partial(typename PT<P>::acc_t (&acc)[2][2]
 }
 
 // Stage one K-tile held in registers into an LDS buffer.
+// LDS element offsets of a thread's staged elements for both thread maps
+// (x-contiguous and k-contiguous operands); fixed for the whole kernel.
 template <int P>
-__device__ __forceinline__ void stage(typename Lds<P>::type& s, bool a_xc, bool b_xc, int t,
-                                     const typename PT<P>::in_t (&ra)[Stage<P>::PER_THREAD],
-                                     const typename PT<P>::in_t (&rb)[Stage<P>::PER_THREAD]) {
+struct StageMap {
+  static constexpr int PER = Stage<P>::PER_THREAD;
+  int lx[PER], lk[PER];
+  __device__ __forceinline__ explicit StageMap(int t) {
 #pragma unroll
-  for (int j = 0; j < Stage<P>::PER_THREAD; ++j) {
-    int x, k;
-    PanelMap<P>::xk(a_xc, t, j, x, k);
-    lds_put<P>(s, 0, x, k, ra[j]);
-    PanelMap<P>::xk(b_xc, t, j, x, k);
-    lds_put<P>(s, 1, x, k, rb[j]);
+    for (int j = 0; j < PER; ++j) {
+      int x, k;
+      PanelMap<P>::xk(true, t, j, x, k);
+      lx[j] = k * (TILE + 2) + x;
+      PanelMap<P>::xk(false, t, j, x, k);
+      lk[j] = k * (TILE + 2) + x;
+    }
+  }
+};
+
+// Stage one K-tile held in registers into an LDS buffer; the A operand is
+// scaled by its segment coefficient here, after the loads have landed.
+template <int P>
+__device__ __forceinline__ void stage(typename Lds<P>::type& s, const StageMap<P>& map, bool a_xc,
+                                     bool b_xc, int t,
+                                     const typename PT<P>::in_t (&ra)[Stage<P>::PER_THREAD],
+                                     const typename PT<P>::in_t (&rb)[Stage<P>::PER_THREAD],
+                                     typename PT<P>::in_t alpha) {
+  if constexpr (P == P_FP64 || P == P_FP32) {
+    typedef typename PT<P>::in_t in_t;
+    in_t* sa = &s.a[0][0];
+    in_t* sb = &s.b[0][0];
+#pragma unroll
+    for (int j = 0; j < Stage<P>::PER_THREAD; ++j) {
+      sa[a_xc ? map.lx[j] : map.lk[j]] = ra[j] * alpha;
+      sb[b_xc ? map.lx[j] : map.lk[j]] = rb[j];
+    }
+  } else {
+    stage_bf<P>(s.a, t, ra, alpha);
+    stage_bf<P>(s.b, t, rb, 1.0f);
   }
 }
 
 // Position in the concatenated K range of a descriptor's segments, with the
-// per-thread element offsets of the current segment kept in registers.
+// per-thread byte offsets of the current segment kept in registers.  The
+// segment table is read through an LDS window of kSegCache entries, refilled
+// by the whole block when the cursor leaves it, so a segment change costs no
+// global round trip.
+constexpr int kSegCache = 64;
+typedef __attribute__((address_space(3))) GemmSeg lds_seg_t;
+typedef __attribute__((address_space(3))) uint64_t lds_u64_t;
+
 template <int P>
 struct SegCursor {
   typedef typename PT<P>::in_t in_t;
   static constexpr int BK = PT<P>::BK;
   static constexpr int PER = Stage<P>::PER_THREAD;
-  const GemmSeg* segs;
+  const GemmSeg* segs;  // global table, from the descriptor's first segment
+  lds_seg_t* cache;     // LDS window [c0, c0 + kSegCache)
+  int c0;
   int si, seg_end, kt, nkt, K;
-  const in_t* A;
-  const in_t* B;
-  int64_t a_step, b_step;  // element step of one K-tile
+  const char* A;  // byte address of the tile origin (row m0 / column n0, k = 0)
+  const char* B;
+  int64_t a_step, b_step;  // bytes per K-tile
   in_t alpha;
   bool a_xc, b_xc;
-  int64_t offA[PER], offB[PER];
+  uint32_t offA[PER], offB[PER];  // byte offsets from the origin (kOob outside M / N)
   int kA[PER], kB[PER];
-  bool okA[PER], okB[PER];
+  // launch context: batch index, tile origin, bounds, thread, K-tile stride
+  int64_t b;
+  int m0, n0, M, N, t, step;
 
-  __device__ __forceinline__ void load(int64_t b, int m0, int n0, int M, int N, int t) {
-    const GemmSeg S = segs[si];
-    A = (const in_t*)S.A + b * S.strideA;
-    B = (const in_t*)S.B + b * S.strideB;
-    a_step = (int64_t)BK * S.a_sk;
-    b_step = (int64_t)BK * S.b_sk;
-    K = S.K;
+  // Copy segments [first, first + kSegCache) into the window (block-wide,
+  // called in uniform control flow).
+  __device__ __forceinline__ void fill(int first) {
+    constexpr int kw = sizeof(GemmSeg) / 8;
+    const int n = min(kSegCache, seg_end - first);
+    const uint64_t* src = (const uint64_t*)(segs + first);
+    lds_u64_t* dst = (lds_u64_t*)cache;
+    __syncthreads();
+    for (int e = t; e < n * kw; e += NTHREADS) dst[e] = src[e];
+    __syncthreads();
+    c0 = first;
+  }
+  __device__ __forceinline__ void load() {
+    if (si - c0 >= kSegCache) fill(si);
+    lds_seg_t& S = cache[si - c0];
+    constexpr int64_t es = sizeof(in_t);
+    const char* sA = uni((const char*)S.A);
+    const char* sB = uni((const char*)S.B);
+    const int64_t a_sx = uni((int64_t)S.a_sx), a_sk = uni((int64_t)S.a_sk);
+    const int64_t b_sx = uni((int64_t)S.b_sx), b_sk = uni((int64_t)S.b_sk);
+    A = sA + (b * uni((int64_t)S.strideA) + (int64_t)m0 * a_sx) * es;
+    B = sB + (b * uni((int64_t)S.strideB) + (int64_t)n0 * b_sx) * es;
+    a_step = (int64_t)BK * a_sk * es;
+    b_step = (int64_t)BK * b_sk * es;
+    K = uni((int)S.K);
     nkt = (K + BK - 1) / BK;
-    alpha = (in_t)S.alpha;
-    a_xc = S.a_sx == 1;
-    b_xc = S.b_sx == 1;
+    alpha = (in_t)uni(S.alpha);
+    a_xc = a_sx == 1;
+    b_xc = b_sx == 1;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       int x, k;
       PanelMap<P>::xk(a_xc, t, j, x, k);
-      okA[j] = m0 + x < M;
-      offA[j] = (int64_t)(m0 + x) * S.a_sx + (int64_t)k * S.a_sk;
+      offA[j] = m0 + x < M ? (uint32_t)(((int64_t)x * a_sx + (int64_t)k * a_sk) * es) : kOob;
       kA[j] = k;
       PanelMap<P>::xk(b_xc, t, j, x, k);
-      okB[j] = n0 + x < N;
-      offB[j] = (int64_t)(n0 + x) * S.b_sx + (int64_t)k * S.b_sk;
+      offB[j] = n0 + x < N ? (uint32_t)(((int64_t)x * b_sx + (int64_t)k * b_sk) * es) : kOob;
       kB[j] = k;
     }
   }
-  // Move `step` K-tiles forward; false once past the last segment.
-  __device__ __forceinline__ bool advance(int step, int64_t b, int m0, int n0, int M, int N, int t) {
-    kt += step;
+  // Move `n` K-tiles forward; false once past the last segment.
+  __device__ __forceinline__ bool skip(int n) {
+    kt += n;
     while (kt >= nkt) {
       kt -= nkt;
       if (++si >= seg_end) return false;
-      load(b, m0, n0, M, N, t);
+      load();
     }
     return true;
   }
+  __device__ __forceinline__ bool advance() { return skip(step); }
   __device__ __forceinline__ void fetch(in_t (&ra)[PER], in_t (&rb)[PER]) const {
     const int k0 = kt * BK;
-    const in_t* Ak = A + (int64_t)kt * a_step;
-    const in_t* Bk = B + (int64_t)kt * b_step;
+    const rsrc_t rA = make_rsrc(A + (int64_t)kt * a_step);
+    const rsrc_t rB = make_rsrc(B + (int64_t)kt * b_step);
+    if (k0 + BK <= K) {  // full K-tile: offsets as precomputed
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      ra[j] = (okA[j] && k0 + kA[j] < K) ? Ak[offA[j]] * alpha : (in_t)0;
-      rb[j] = (okB[j] && k0 + kB[j] < K) ? Bk[offB[j]] : (in_t)0;
+      for (int j = 0; j < PER; ++j) {
+        ra[j] = bload<in_t>(rA, offA[j]);
+        rb[j] = bload<in_t>(rB, offB[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        ra[j] = bload<in_t>(rA, k0 + kA[j] < K ? offA[j] : kOob);
+        rb[j] = bload<in_t>(rB, k0 + kB[j] < K ? offB[j] : kOob);
+      }
     }
   }
 };
+
+// Register ring depth of the K-loop: K-tiles whose global loads are in
+// flight while one tile feeds the MFMAs.
+template <int P> struct Depth { static constexpr int value = 4; };
+template <> struct Depth<P_FP32> { static constexpr int value = 8; };
+
+// K-loop shared by the contraction kernels.  Most launches of the method put
+// one or two workgroups on a CU, so global latency (first touches after the
+// producing kernel, about a microsecond) is hidden by depth rather than by
+// occupancy: D K-tiles are fetched ahead into registers, and each iteration
+// stages the next one into the idle half of the double-buffered LDS while
+// the MFMAs consume the other half.  `Cur` supplies fetch(ra, rb) for its
+// current K-tile, advance() to its next one, and the operand orientations.
+template <int P, int D, class Cur>
+__device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type (&s)[2],
+                                      typename PT<P>::acc_t (&acc)[2][2], int t, int lane, int wm,
+                                      int wn) {
+  typedef typename PT<P>::in_t in_t;
+  constexpr int PER = Stage<P>::PER_THREAD;
+  const StageMap<P> map(t);
+  in_t ra[D][PER], rb[D][PER], al[D];
+  bool ax[D], bx[D];
+  int inflight = 0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    if (have) {
+      cur.fetch(ra[d], rb[d]);
+      ax[d] = cur.a_xc;
+      bx[d] = cur.b_xc;
+      al[d] = cur.alpha;
+      ++inflight;
+      have = cur.advance();
+    }
+  }
+  if (inflight == 0) return;
+  stage<P>(s[0], map, ax[0], bx[0], t, ra[0], rb[0], al[0]);
+  __syncthreads();
+  int buf = 0;
+  while (true) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      // s[buf] holds slot d's tile; its registers take the next fetch
+      if (have) {
+        cur.fetch(ra[d], rb[d]);
+        ax[d] = cur.a_xc;
+        bx[d] = cur.b_xc;
+        al[d] = cur.alpha;
+        ++inflight;
+        have = cur.advance();
+      }
+      mma_tile<P>(s[buf], acc, lane, wm, wn);
+      --inflight;
+      const int nx = (d + 1) % D;
+      if (inflight > 0) stage<P>(s[buf ^ 1], map, ax[nx], bx[nx], t, ra[nx], rb[nx], al[nx]);
+      __syncthreads();
+      buf ^= 1;
+      if (inflight == 0) return;
+    }
+  }
+}
 
 // ROLE only names the launch (one symbol per step of the method, so that
 // kernel traces separate them); the code is the same for every role.
@@ -160,7 +291,6 @@ __global__ __launch_bounds__(NTHREADS) void gemm_kernel(const GemmDesc* __restri
                                                         const GemmSeg* __restrict__ segs) {
   typedef typename PT<P>::in_t in_t;
   typedef typename PT<P>::acc_t acc_t;
-  constexpr int PER = Stage<P>::PER_THREAD;
   __shared__ typename Lds<P>::type s[2];
 
   const int64_t tile = blockIdx.x;
@@ -181,36 +311,30 @@ __global__ __launch_bounds__(NTHREADS) void gemm_kernel(const GemmDesc* __restri
 
   acc_t acc[2][2];
   acc_zero<P>(acc);
-  in_t ra[PER], rb[PER];
 
+  __shared__ GemmSeg sseg[kSegCache];
   SegCursor<P> cur;
-  cur.segs = segs;
-  cur.si = D.seg_begin;
-  cur.seg_end = D.seg_begin + D.seg_count;
+  cur.segs = segs + D.seg_begin;
+  cur.cache = (lds_seg_t*)sseg;
+  cur.c0 = 0;
+  cur.si = 0;
+  cur.seg_end = D.seg_count;
   cur.kt = 0;
   cur.nkt = 0;
+  cur.b = b;
+  cur.m0 = m0;
+  cur.n0 = n0;
+  cur.M = M;
+  cur.N = N;
+  cur.t = t;
+  cur.step = splits;
   bool have = false;
   if (D.seg_count > 0) {
-    cur.load(b, m0, n0, M, N, t);
-    have = cur.advance(split, b, m0, n0, M, N, t);
+    cur.fill(0);
+    cur.load();
+    have = cur.skip(split);
   }
-  // Double-buffered LDS: the next K-tile's global loads are in flight while
-  // the current one feeds the MFMAs; one barrier per K-tile.
-  int buf = 0;
-  if (have) {
-    cur.fetch(ra, rb);
-    stage<P>(s[0], cur.a_xc, cur.b_xc, t, ra, rb);
-  }
-  __syncthreads();
-  while (have) {
-    const bool next = cur.advance(splits, b, m0, n0, M, N, t);
-    if (next) cur.fetch(ra, rb);
-    mma_tile<P>(s[buf], acc, lane, wm, wn);
-    if (next) stage<P>(s[buf ^ 1], cur.a_xc, cur.b_xc, t, ra, rb);
-    __syncthreads();
-    buf ^= 1;
-    have = next;
-  }
+  kloop<P, Depth<P>::value>(cur, have, s, acc, t, lane, wm, wn);
 
   const int64_t off = b * D.strideC;
   if (splits == 1) {
@@ -224,6 +348,119 @@ __global__ __launch_bounds__(NTHREADS) void gemm_kernel(const GemmDesc* __restri
   }
 }
 
+// K-tiles of the KRP core sketch: row a of G_(n) and the Khatri-Rao entry
+// prod_{k != n} P_k[j_k(c)][t] for depth c.  FP64/FP32: one depth per thread
+// and four rows x_j (the k-contiguous staging map); BF16: one row x = t % 64
+// and eight consecutive depths, whose mixed-radix digits are stepped
+// incrementally (they wrap, so they stay inside their ranges past the end of
+// K).  With LDS_P the block's 64 columns of every P_k sit in LDS (slice k at
+// soff[k], column x at x * r_k), so the Khatri-Rao products wait only on LDS;
+// the core loads are buffer loads that nothing waits for before staging.
+constexpr int kKrpLds = 6144;  // elements of P slices kept in LDS
+typedef __attribute__((address_space(3))) const float lds_cf32;
+typedef __attribute__((address_space(3))) const double lds_cf64;
+
+template <int P, bool LDS_P>
+struct KrpCursor {
+  typedef typename PT<P>::in_t in_t;
+  typedef typename std::conditional<P == P_FP64, lds_cf64, lds_cf32>::type lds_in_t;
+  static constexpr int BK = PT<P>::BK;
+  static constexpr int PER = Stage<P>::PER_THREAD;
+  const in_t* G;
+  in_t alpha;
+  const in_t* Pk[kMaxOrder];
+  lds_in_t* sP;
+  int soff[kMaxOrder];
+  int rk[kMaxOrder];
+  int64_t st[kMaxOrder];
+  int order, n, m, m0, n0, t, rn;
+  int64_t stn, Kc, kt, nkt, step;
+  bool a_xc = false, b_xc = false;
+
+  __device__ __forceinline__ bool advance() {
+    kt += step;
+    return kt < nkt;
+  }
+  // P_k[dg][n0 + x]
+  __device__ __forceinline__ in_t pval(int k, int x, int dg) const {
+    if constexpr (LDS_P) return sP[soff[k] + x * rk[k] + dg];
+    else return Pk[k][dg + (int64_t)(n0 + x) * rk[k]];
+  }
+  __device__ __forceinline__ void fetch(in_t (&ra)[PER], in_t (&rb)[PER]) const {
+    constexpr int64_t es = sizeof(in_t);
+    const rsrc_t rG = make_rsrc(G);
+    if constexpr (P != P_FP64 && P != P_FP32) {
+      const int x = t & (TILE - 1);
+      const int a = m0 + x, tt = n0 + x;
+      const int64_t c0 = kt * BK + 8 * (t >> 6);
+      int dg[kMaxOrder];
+      int64_t offg = 0;
+      {
+        uint32_t rem = c0 < Kc ? (uint32_t)c0 : 0u;
+#pragma unroll
+        for (int k = 0; k < kMaxOrder; ++k) {
+          dg[k] = 0;
+          if (k < order && k != n) {
+            const uint32_t q = rem / (uint32_t)rk[k];
+            dg[k] = (int)(rem - q * (uint32_t)rk[k]);
+            rem = q;
+            offg += (int64_t)dg[k] * st[k];
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const bool valid = c0 + j < Kc;
+        ra[j] = bload<in_t>(rG, (valid && a < rn) ? (uint32_t)(((int64_t)a * stn + offg) * es) : kOob);
+        in_t prod = (in_t)1;
+#pragma unroll
+        for (int k = 0; k < kMaxOrder; ++k)
+          if (k < order && k != n) prod *= pval(k, x, dg[k]);
+        rb[j] = (valid && tt < m) ? prod : (in_t)0;
+        // next depth: add one to the mixed-radix digits, branch-free
+        bool carry = true;
+#pragma unroll
+        for (int k = 0; k < kMaxOrder; ++k) {
+          if (k < order && k != n) {
+            const int nd = dg[k] + (carry ? 1 : 0);
+            const bool wrap = nd == rk[k];
+            offg += carry ? (wrap ? (int64_t)(1 - rk[k]) * st[k] : st[k]) : 0;
+            dg[k] = wrap ? 0 : nd;
+            carry = carry && wrap;
+          }
+        }
+      }
+    } else {
+      const int64_t c = kt * BK + t % BK;
+      const bool valid = c < Kc;
+      int dig[kMaxOrder];
+      int64_t offg = 0;
+      uint32_t rem = valid ? (uint32_t)c : 0u;
+#pragma unroll
+      for (int k = 0; k < kMaxOrder; ++k) {
+        dig[k] = 0;
+        if (k < order && k != n) {
+          const uint32_t q = rem / (uint32_t)rk[k];
+          dig[k] = (int)(rem - q * (uint32_t)rk[k]);
+          rem = q;
+          offg += (int64_t)dig[k] * st[k];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int x = t / BK + (NTHREADS / BK) * j;
+        const int a = m0 + x, tt = n0 + x;
+        ra[j] = bload<in_t>(rG, (valid && a < rn) ? (uint32_t)(((int64_t)a * stn + offg) * es) : kOob);
+        in_t prod = (in_t)1;
+#pragma unroll
+        for (int k = 0; k < kMaxOrder; ++k)
+          if (k < order && k != n) prod *= pval(k, x, dig[k]);
+        rb[j] = (valid && tt < m) ? prod : (in_t)0;
+      }
+    }
+  }
+};
+
 // KRP core sketch: rows a of G_(n) against Khatri-Rao columns t, K = c over
 // the other modes, first remaining mode fastest (unfolding index equation).
 template <int P>
@@ -232,7 +469,6 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
   typedef typename PT<P>::in_t in_t;
   typedef typename PT<P>::acc_t acc_t;
   constexpr int BK = PT<P>::BK;
-  constexpr int PER = Stage<P>::PER_THREAD;
   __shared__ typename Lds<P>::type s[2];
 
   const int64_t tile = blockIdx.x;
@@ -271,59 +507,61 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
 
   acc_t acc[2][2];
   acc_zero<P>(acc);
-  in_t ra[PER], rb[PER];
-  const int64_t nkt = (Kc + BK - 1) / BK;
-  const int kq = t % BK;
-  // gather one K-tile: row a of G_(n) and the Khatri-Rao entry
-  // prod_{k != n} P_k[j_k(c)][t] for this thread's depth c = kt*BK + kq
-#define TSK_KRP_FETCH(KT)                                                          \
-  {                                                                                \
-    const int64_t c = (KT) * BK + kq;                                              \
-    const bool valid = c < Kc;                                                     \
-    int dig[kMaxOrder];                                                            \
-    int64_t offg = 0;                                                              \
-    int64_t rem = valid ? c : 0;                                                   \
-    _Pragma("unroll") for (int k = 0; k < kMaxOrder; ++k) {                        \
-      dig[k] = 0;                                                                  \
-      if (k < order && k != n) {                                                   \
-        const int64_t q = rem / rk[k];                                             \
-        dig[k] = (int)(rem - q * rk[k]);                                           \
-        rem = q;                                                                   \
-        offg += (int64_t)dig[k] * st[k];                                           \
-      }                                                                            \
-    }                                                                              \
-    _Pragma("unroll") for (int j = 0; j < PER; ++j) {                              \
-      const int x = t / BK + (NTHREADS / BK) * j;                                  \
-      const int a = m0 + x;                                                        \
-      ra[j] = (valid && a < rn) ? G[(int64_t)a * stn + offg] * alpha : (in_t)0;    \
-      const int tt = n0 + x;                                                       \
-      in_t prod = (in_t)0;                                                         \
-      if (valid && tt < m) {                                                       \
-        prod = (in_t)1;                                                            \
-        _Pragma("unroll") for (int k = 0; k < kMaxOrder; ++k) if (k < order &&     \
-                                                                  k != n) prod *=  \
-            Pk[k][dig[k] + (int64_t)tt * rk[k]];                                   \
-      }                                                                            \
-      rb[j] = prod;                                                                \
-    }                                                                              \
+  // the block's 64 columns of every P_k (k != n) into LDS when they fit
+  __shared__ in_t sP[kKrpLds];
+  int soff[kMaxOrder];
+  int total = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxOrder; ++k) {
+    soff[k] = total;
+    if (k < order && k != n) total += TILE * rk[k];
   }
-  int64_t kt = split;
-  int buf = 0;
-  if (kt < nkt) {
-    TSK_KRP_FETCH(kt);
-    stage<P>(s[0], false, false, t, ra, rb);
-  }
-  __syncthreads();
-  while (kt < nkt) {
-    const int64_t kn = kt + splits;
-    if (kn < nkt) TSK_KRP_FETCH(kn);
-    mma_tile<P>(s[buf], acc, lane, wm, wn);
-    if (kn < nkt) stage<P>(s[buf ^ 1], false, false, t, ra, rb);
+  const bool lds_p = total <= kKrpLds;
+  if (lds_p) {
+    const int cols = min(TILE, m - n0);
+#pragma unroll
+    for (int k = 0; k < kMaxOrder; ++k) {
+      if (k < order && k != n) {
+        const in_t* src = Pk[k] + (int64_t)n0 * rk[k];
+        const int cnt = cols * rk[k];
+        for (int e = t; e < cnt; e += NTHREADS) sP[soff[k] + e] = src[e];
+      }
+    }
     __syncthreads();
-    buf ^= 1;
-    kt = kn;
   }
-#undef TSK_KRP_FETCH
+#define TSK_KRP_CURSOR(CUR)          \
+  CUR.G = G;                         \
+  CUR.alpha = alpha;                 \
+  _Pragma("unroll") for (int k = 0; k < kMaxOrder; ++k) { \
+    CUR.Pk[k] = Pk[k];               \
+    CUR.soff[k] = soff[k];           \
+    CUR.rk[k] = rk[k];               \
+    CUR.st[k] = st[k];               \
+  }                                  \
+  CUR.order = order;                 \
+  CUR.n = n;                         \
+  CUR.m = m;                         \
+  CUR.m0 = m0;                       \
+  CUR.n0 = n0;                       \
+  CUR.t = t;                         \
+  CUR.rn = rn;                       \
+  CUR.stn = stn;                     \
+  CUR.Kc = Kc;                       \
+  CUR.kt = split;                    \
+  CUR.nkt = (Kc + BK - 1) / BK;      \
+  CUR.step = splits;
+  if (lds_p) {
+    KrpCursor<P, true> cur;
+    TSK_KRP_CURSOR(cur)
+    cur.sP = (typename KrpCursor<P, true>::lds_in_t*)sP;
+    kloop<P, Depth<P>::value>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn);
+  } else {
+    KrpCursor<P, false> cur;
+    TSK_KRP_CURSOR(cur)
+    cur.sP = nullptr;
+    kloop<P, Depth<P>::value>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn);
+  }
+#undef TSK_KRP_CURSOR
   typedef typename std::conditional<P == P_FP64, double, float>::type vt;
   if (splits == 1) {
     store_tile<P, vt>(acc, (vt*)Vout, rn, rn, m, m0, n0, false, lane, wm, wn);
@@ -373,13 +611,16 @@ __global__ __launch_bounds__(NTHREADS) void krp_adj_kernel(const KrpAdjDesc* __r
     }
   }
   const int rn = rk[n];
-  // this thread's B columns (k-contiguous mapping: depth kq, rows x_j)
+  // this thread's B columns: FP64/FP32 stage k-contiguous (depth kq, columns
+  // x_j); the BF16 forms give each thread one column and eight depths.
+  constexpr bool BF = P != P_FP64 && P != P_FP32;
+  constexpr int NCOL = BF ? 1 : PER;
   const int kq = t % BK;
-  int dig[PER][kMaxOrder];
-  bool colok[PER];
+  int dig[NCOL][kMaxOrder];
+  bool colok[NCOL];
 #pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int64_t c = n0 + t / BK + (NTHREADS / BK) * j;
+  for (int j = 0; j < NCOL; ++j) {
+    const int64_t c = BF ? n0 + (t & (TILE - 1)) : n0 + t / BK + (NTHREADS / BK) * j;
     colok[j] = c < Nc;
     int64_t rem = colok[j] ? c : 0;
 #pragma unroll
@@ -404,28 +645,30 @@ __global__ __launch_bounds__(NTHREADS) void krp_adj_kernel(const KrpAdjDesc* __r
       PanelMap<P>::xk(true, t, j, x, k);                                            \
       const int64_t a = m0 + x;                                                     \
       ra[j] = (a < rn && k0 + k < m) ? Vb[a + (int64_t)(k0 + k) * rn] * alpha : (in_t)0; \
-      const int tt = k0 + kq;                                                       \
+      const int jc = BF ? 0 : j;                                                    \
+      const int tt = k0 + (BF ? 8 * (t >> 6) + j : kq);                             \
       in_t prod = (in_t)0;                                                          \
-      if (colok[j] && tt < m) {                                                     \
+      if (colok[jc] && tt < m) {                                                    \
         prod = (in_t)1;                                                             \
         _Pragma("unroll") for (int q = 0; q < kMaxOrder; ++q) if (q < order &&      \
                                                                  q != n) prod *=    \
-            Pk[q][dig[j][q] + (int64_t)tt * rk[q]];                                 \
+            Pk[q][dig[jc][q] + (int64_t)tt * rk[q]];                                \
       }                                                                             \
       rb[j] = prod;                                                                 \
     }                                                                               \
   }
+  const StageMap<P> smap(t);
   int kt = 0, buf = 0;
   if (kt < nkt) {
     TSK_ADJ_FETCH(kt);
-    stage<P>(s[0], true, false, t, ra, rb);
+    stage<P>(s[0], smap, true, false, t, ra, rb, (in_t)1);
   }
   __syncthreads();
   while (kt < nkt) {
     const int kn = kt + 1;
     if (kn < nkt) TSK_ADJ_FETCH(kn);
     mma_tile<P>(s[buf], acc, lane, wm, wn);
-    if (kn < nkt) stage<P>(s[buf ^ 1], true, false, t, ra, rb);
+    if (kn < nkt) stage<P>(s[buf ^ 1], smap, true, false, t, ra, rb, (in_t)1);
     __syncthreads();
     buf ^= 1;
     kt = kn;

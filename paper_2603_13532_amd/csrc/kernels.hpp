@@ -64,7 +64,9 @@ struct CopyJob {
 hipError_t launch_copy(const CopyJob* jobs, int count, hipStream_t stream);
 
 // Cholesky QR passes and the Householder fallback over `count` modes.
-hipError_t launch_chol(const QrDesc* qr, int count, int pass, double tol, hipStream_t stream);
+// wmax: widest Gram (W) among the descriptors; sizes the dynamic LDS.
+hipError_t launch_chol(const QrDesc* qr, int count, int pass, double tol, int wmax,
+                       hipStream_t stream);
 hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* fallback_counter,
                               hipStream_t stream);
 

@@ -80,7 +80,7 @@ template <typename T, int BK> struct LdsK {
   T b[BK][TILE + 2];
 };
 // BF16: row-major, k contiguous, one plane per split part.
-template <int BK, int PARTS> struct LdsBf {
+template <int BK, int PARTS> struct alignas(16) LdsBf {
   uint16_t a[PARTS][TILE][BK + 8];
   uint16_t b[PARTS][TILE][BK + 8];
 };
@@ -189,22 +189,89 @@ __device__ __forceinline__ int acc_col(int wn, int j, int lane) {
 
 // ------------------------------------------------------------ operand staging
 // A 64 x BK panel element (x, k) lives at base[x*sx + k*sk]; exactly one of
-// sx, sk is 1.  Thread mapping follows the contiguous direction so that the
-// global loads coalesce.  Out-of-range elements are staged as zero.
+// sx, sk is 1.  For the 4-deep FP64/FP32 instructions the thread mapping
+// follows the contiguous direction so that the global loads coalesce.  For
+// the BF16 forms every thread holds eight consecutive k of one row x
+// (x = t % 64), so that each split part goes to LDS as one 16-byte store;
+// across a wave the 64 rows of one k are still one coalesced load when x is
+// the contiguous direction.  Out-of-range elements are staged as zero.
 template <int P>
 struct PanelMap {
   static constexpr int BK = PT<P>::BK;
-  static constexpr int PT_ = Stage<P>::PER_THREAD;
   // element j of thread t
   static __device__ __forceinline__ void xk(bool x_contig, int t, int j, int& x, int& k) {
-    if (x_contig) {
-      x = t & (TILE - 1);
-      k = (t >> 6) + (NTHREADS / TILE) * j;
+    if constexpr (P == P_FP64 || P == P_FP32) {
+      // both candidates, then a select (no branch between the outputs)
+      const int xa = t & (TILE - 1), ka = (t >> 6) + (NTHREADS / TILE) * j;
+      const int kb = t % BK, xb = t / BK + (NTHREADS / BK) * j;
+      x = x_contig ? xa : xb;
+      k = x_contig ? ka : kb;
     } else {
-      k = t % BK;
-      x = t / BK + (NTHREADS / BK) * j;
+      x = t & (TILE - 1);
+      k = 8 * (t >> 6) + j;
     }
   }
 };
+
+// BF16 forms: split a thread's eight consecutive k of row x into PARTS bf16
+// planes and write each plane with one 16-byte LDS store.
+template <int P>
+__device__ __forceinline__ void stage_bf(uint16_t (*plane)[TILE][PT<P>::BK + 8], int t,
+                                         const float (&v)[8], float scale) {
+  constexpr int PARTS = PT<P>::PARTS;
+  const int x = t & (TILE - 1), k0 = 8 * (t >> 6);
+  v8s out[PARTS];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    float rest = v[e] * scale;
+#pragma unroll
+    for (int p = 0; p < PARTS; ++p) {
+      const uint16_t h = bf16_bits(rest);
+      out[p][e] = (short)h;
+      rest = rest - bf16_value(h);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PARTS; ++p) *reinterpret_cast<v8s*>(&plane[p][x][k0]) = out[p];
+}
+
+// ------------------------------------------------------------ global loads
+// Operand loads go through buffer resources: a 32-bit byte offset from a
+// tile origin, and any offset past the resource's record count reads as
+// zero.  Out-of-range elements therefore cost no branch and no select on the
+// loaded value, so a load is never waited for before its K-tile is staged
+// (the memory counter completes in order: an early wait would drain every
+// K-tile in flight behind it).
+// Values that are the same in every lane but reach the compiler through a
+// vector register (LDS reads, block-wide counts) are moved to scalar
+// registers explicitly; a buffer resource must be scalar, and the compiler
+// would otherwise loop over the lanes to make it so.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double uni(double v) {
+  return __longlong_as_double((long long)uni((int64_t)__double_as_longlong(v)));
+}
+template <typename T> __device__ __forceinline__ T* uni(T* p) {
+  return (T*)(uintptr_t)uni((int64_t)(uintptr_t)p);
+}
+
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kRawWord3 = 0x00020000;       // raw 32-bit data format (CDNA buffer descriptor)
+constexpr uint32_t kOob = 0x80000000u;      // an offset that reads as zero
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7FFFFFFF,
+                                           kRawWord3);
+}
+template <typename T> __device__ __forceinline__ T bload(rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ float bload<float>(rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <> __device__ __forceinline__ double bload<double>(rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
 
 }  // namespace tsk

@@ -3,11 +3,11 @@
 //
 // Default path: Cholesky QR2.  The Gram matrix Y^T Y is formed by the MFMA
 // GEMM (K-split over rows, partial blocks summed here in a fixed order); one
-// workgroup per mode factors it in LDS, G = R^T R, while applying the same
-// row operations to the identity to get L^-1 = R^-T, so that Q1 = Y R^-1 is
-// one more GEMM.  The second pass repeats this on Q1 and multiplies
-// R = R2 R1.  A pivot that is not positive, or smaller than tol times the
-// original diagonal entry, marks the mode as breaking down.
+// workgroup per mode factors it in LDS, G = L L^T with R = L^T, and forms
+// L^-1 = R^-T, so that Q1 = Y R^-1 is one more GEMM.  The second pass
+// repeats this on Q1 and multiplies R = R2 R1.  A pivot that is not positive,
+// or smaller than tol times the original diagonal entry, marks the mode as
+// breaking down.
 //
 // Fallback: Householder QR by one workgroup per flagged mode, panel in
 // global memory, reflectors applied column by column; chosen on the device
@@ -22,208 +22,251 @@ namespace tsk {
 namespace {
 
 constexpr int kCholMax = 96;  // widest Gram handled in LDS
+constexpr int kCholBs = 16;   // column block of the factorization
 
-// Blocked Cholesky G = L L^T (L = R^T) and L^-1, one workgroup per mode,
-// both W x W matrices in LDS (leading dimension kLd).  Block size 16:
-//   1. wave 0 factors the 16 x 16 diagonal block in registers, exchanging
-//      columns with lane shuffles (no barrier inside the block);
-//   2. each row below the block solves its 16 unknowns by substitution;
-//   3. the trailing lower triangle is updated by 16-term dot products.
-// L^-1 follows blockwise: diagonal blocks inverted by substitution, then
-// block row I from X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ.  About 5
-// barriers per block instead of one per column.
-constexpr int kLd = kCholMax + 1;
+// The Gram is padded with an identity block to a multiple of 16 columns, so
+// every panel is full and no step needs a bounds test; the padding does not
+// change the leading W x W block of L or of L^-1.  Leading dimension: even
+// (16-byte aligned row pairs) and two rows past the padded width.
+__host__ __device__ constexpr int chol_pad(int W) { return (W + kCholBs - 1) & ~(kCholBs - 1); }
+__host__ __device__ constexpr int chol_ld(int W) { return chol_pad(W) + 2; }
 
+// Dynamic LDS of a launch whose widest Gram is Wmax: L, L^-1, 1/diag, diag
+// and the breakdown word.
+__host__ __device__ constexpr size_t chol_lds_bytes(int Wmax) {
+  return (2 * (size_t)chol_pad(Wmax) * chol_ld(Wmax) + 2 * kCholMax) * sizeof(double) + 16;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Cholesky G = L L^T and X = L^-1 of one W x W Gram (W <= 96), one
+// workgroup.  Latency bounds this kernel, not arithmetic, so the design
+// keeps the column-to-column chain short and free of branches:
+//   * the Gram's lower triangle is summed from the split partials with the
+//     loads of eight elements times eight splits in flight together;
+//   * a 16-column panel (diagonal block and all rows below it) is factored
+//     by one wave in registers, lane l holding rows k0 + l and k0 + 64 + l;
+//     the pivot and the multipliers of later panel columns come from their
+//     lanes by readlane, 1/sqrt of the pivot from the hardware reciprocal
+//     square root and one Newton step; a bad pivot is recorded and replaced
+//     by 1 so that the panel finishes without a branch;
+//   * L^-1 is formed alongside by block forward substitution on the
+//     identity: X_K = L_KK^-1 B_K (thread per column), then
+//     B_{>K} -= L_{>K,K} X_K, next to the trailing update of the Gram
+//     A_{>K} -= L_{>K,K} L_{>K,K}^T; both updates use 2 x 2 register blocks
+//     over the 16 panel columns.
+// LDS is sized by the widest Gram of the launch, so narrow Grams leave room
+// for several workgroups per CU.
 __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qrs, int pass,
                                                    double tol) {
+  extern __shared__ __align__(16) double smem[];
   const QrDesc& D = qrs[blockIdx.x];
   const int W = (int)D.W;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   if (D.hh_direct || *D.flag != 0 || W > kCholMax || D.W > D.n) return;
+  const int Wp = chol_pad(W), ld = chol_ld(W);
+  double* sA = smem;            // Gram, then L (lower triangle), column-major
+  double* sX = smem + Wp * ld;  // identity, then L^-1 (lower triangle)
+  double* dinv = sX + Wp * ld;  // 1 / L(c, c)
+  double* diag0 = dinv + kCholMax;
+  int& s_bad = *reinterpret_cast<int*>(diag0 + kCholMax);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  __shared__ double sA[kCholMax * kLd];  // Gram, then L in the lower triangle
-  __shared__ double sX[kCholMax * kLd];  // L^-1 (lower triangle)
-  __shared__ double diag0[kCholMax];
-  __shared__ int s_broke;
-
-  // ---- Gram = sum of the K-split partial blocks (split loop outside so that
-  // each thread has many independent loads in flight)
-  const int WW = W * W;
-  constexpr int kPer = (kCholMax * kCholMax + 255) / 256;
-  {
-    double acc[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) acc[q] = 0.0;
-    for (int s = 0; s < D.gram_splits; ++s) {
-      const double* ps = D.gram_part + (int64_t)s * WW;
-#pragma unroll
-      for (int q = 0; q < kPer; ++q) {
-        const int e = tid + 256 * q;
-        if (e < WW) acc[q] += ps[e];
-      }
+  // ---- identity in X, identity padding of the Gram
+  for (int j = wave; j < Wp; j += 4)
+    for (int i = lane; i < Wp; i += 64) {
+      const double id = (i == j) ? 1.0 : 0.0;
+      sX[i + j * ld] = id;
+      if (i >= W || j >= W) sA[i + j * ld] = id;
     }
+  for (int i = W + tid; i < Wp; i += 256) diag0[i] = 1.0;
+  if (tid == 0) s_bad = 0;
+
+  // ---- Gram lower triangle = partial blocks summed in split order
+  {
+    const int splits = max(1, (int)D.gram_splits);
+    const int64_t WW = (int64_t)W * W;
+    const double* part = D.gram_part;
+    for (int j0 = wave; j0 < W; j0 += 16) {
+      // elements u: column j0 + 4 (u >> 1), rows lane + 64 (u & 1)
+      int off[8];
+      bool ok[8];
+      double acc[8];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + 256 * q;
-      if (e < WW) {
-        const int i = e % W, k = e / W;
-        sA[i + k * kLd] = acc[q];
-        sX[i + k * kLd] = 0.0;
-        if (i == k) diag0[i] = acc[q];
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + 4 * (u >> 1), i = lane + 64 * (u & 1);
+        ok[u] = j < W && i < W && i >= j;
+        off[u] = ok[u] ? i + j * W : 0;
+        acc[u] = 0.0;
       }
+      for (int s0 = 0; s0 < splits; s0 += 8) {
+        double v[8][8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const double* p = part + (int64_t)min(s0 + s, splits - 1) * WW;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[s][u] = p[off[u]];
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+          if (s0 + s < splits)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += v[s][u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (ok[u]) {
+          const int j = j0 + 4 * (u >> 1), i = lane + 64 * (u & 1);
+          sA[i + j * ld] = acc[u];
+          if (i == j) diag0[i] = acc[u];
+        }
     }
   }
-  if (tid == 0) s_broke = 0;
   __syncthreads();
 
-  const int nb = (W + 15) >> 4;
+  const int nb = Wp / kCholBs;
   for (int K = 0; K < nb; ++K) {
-    const int k0 = K * 16;
-    const int bs = min(16, W - k0);
-    // ---- 1. diagonal block, wave 0: lane = r + 16 qq holds A(k0+r, k0+qq+4e)
-    if (tid < 64) {
-      const int r = tid & 15, qq = tid >> 4;
-      double a[4];
+    const int k0 = K * kCholBs, k1 = k0 + kCholBs;
+    // ---- panel factorization, wave 0
+    if (wave == 0) {
+      const int r0 = k0 + lane, r1 = k0 + 64 + lane;
+      const bool two = Wp - k0 > 64;
+      double p0[kCholBs], p1[kCholBs], g0[kCholBs];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int q = qq + 4 * e;
-        a[e] = (r < bs && q < bs) ? sA[(k0 + r) + (k0 + q) * kLd] : 0.0;
+      for (int c = 0; c < kCholBs; ++c) {
+        p0[c] = (c <= lane && r0 < Wp) ? sA[r0 + (k0 + c) * ld] : 0.0;
+        p1[c] = (two && r1 < Wp) ? sA[r1 + (k0 + c) * ld] : 0.0;
+        g0[c] = diag0[k0 + c];
       }
-      bool broke = false;
+      bool bad = false;
+      double yc = 0.0;  // lane c: 1 / L(k0 + c, k0 + c)
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        if (c < bs && !broke) {
-          const int ec = c >> 2, src = 16 * (c & 3);
-          const double piv = __shfl(a[ec], c + src, 64);
-          if (!(piv > tol * diag0[k0 + c]) || !(diag0[k0 + c] > 0.0)) {
-            broke = true;
-          } else {
-            const double lcc = sqrt(piv);
-            const double inv = 1.0 / lcc;
-            if (qq == (c & 3)) {
-              if (r == c) a[ec] = lcc;
-              else if (r > c) a[ec] *= inv;
-            }
-            const double lrc = __shfl(a[ec], r + src, 64);
+      for (int c = 0; c < kCholBs; ++c) {
+        const double piv = readlane_d(p0[c], c);
+        const bool badc = !(piv > tol * g0[c]) || !(g0[c] > 0.0);
+        bad = bad || badc;
+        const double x = badc ? 1.0 : piv;
+        double y = __builtin_amdgcn_rsq(x);
+        double t = x * y;
+        const double e = fma(-t, 0.5 * y, 0.5);
+        y = fma(y, e, y);  // 1 / sqrt(x)
+        t = fma(t, e, t);  // sqrt(x)
+        yc = (lane == c) ? y : yc;
+        p0[c] = (lane == c) ? t : p0[c] * y;
+        p1[c] *= y;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int q = qq + 4 * e;
-              const double lqc = __shfl(a[ec], q + src, 64);
-              if (q > c && q <= r) a[e] -= lrc * lqc;
-            }
-          }
+        for (int c2 = c + 1; c2 < kCholBs; ++c2) {
+          const double l = readlane_d(p0[c], c2);  // L(k0 + c2, k0 + c)
+          p0[c2] = fma(-p0[c], l, p0[c2]);
+          p1[c2] = fma(-p1[c], l, p1[c2]);
         }
       }
-      if (broke) {
-        if (tid == 0) s_broke = 1;
-      } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int q = qq + 4 * e;
-          if (r < bs && q < bs && q <= r) sA[(k0 + r) + (k0 + q) * kLd] = a[e];
-        }
+      for (int c = 0; c < kCholBs; ++c) {
+        if (c <= lane && r0 < Wp) sA[r0 + (k0 + c) * ld] = p0[c];
+        if (two && r1 < Wp) sA[r1 + (k0 + c) * ld] = p1[c];
       }
+      if (lane < kCholBs) dinv[k0 + lane] = yc;
+      if (bad && lane == 0) s_bad = 1;
     }
     __syncthreads();
-    if (s_broke) {
+    if (s_bad) {
       if (tid == 0) *D.flag = 1;
       return;
     }
-    // ---- 2. panel: rows below the block, x L_KK^T = a by substitution
-    const int i0 = k0 + bs;
-    for (int i = i0 + tid; i < W; i += 256) {
-      double x[16];
+    // ---- X_K = L_KK^-1 B_K for the columns col < k1 (thread per column)
+    if (tid < k1) {
+      const int col = tid;
+      double b[kCholBs];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        if (c < bs) {
-          double v = sA[i + (k0 + c) * kLd];
+      for (int r = 0; r < kCholBs; ++r) b[r] = sX[(k0 + r) + col * ld];
 #pragma unroll
-          for (int q = 0; q < 16; ++q)
-            if (q < c) v -= x[q] * sA[(k0 + c) + (k0 + q) * kLd];
-          x[c] = v / sA[(k0 + c) + (k0 + c) * kLd];
+      for (int r = 0; r < kCholBs; ++r) {
+        const double x = b[r] * dinv[k0 + r];
+        b[r] = x;
+#pragma unroll
+        for (int r2 = r + 1; r2 < kCholBs; ++r2)
+          b[r2] = fma(-sA[(k0 + r2) + (k0 + r) * ld], x, b[r2]);
+      }
+#pragma unroll
+      for (int r = 0; r < kCholBs; ++r) sX[(k0 + r) + col * ld] = b[r];
+    }
+    // ---- trailing Gram: A(i, j) -= sum_c L(i, k0 + c) L(j, k0 + c), i >= j >= k1
+    const int T = Wp - k1, nbk = T >> 1;
+    if (T > 0) {
+      const int nblk = nbk * (nbk + 1) / 2;
+      for (int e = tid; e < nblk; e += 256) {
+        // packed lower-triangle block index -> (bi, bj), bi >= bj
+        int bi = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+        if ((bi + 1) * (bi + 2) / 2 <= e) ++bi;
+        if (bi * (bi + 1) / 2 > e) --bi;
+        const int bj = e - bi * (bi + 1) / 2;
+        const int i0 = k1 + 2 * bi, j0 = k1 + 2 * bj;
+        double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
+#pragma unroll
+        for (int c = 0; c < kCholBs; ++c) {
+          const double2 li = *reinterpret_cast<const double2*>(&sA[i0 + (k0 + c) * ld]);
+          const double2 lj = *reinterpret_cast<const double2*>(&sA[j0 + (k0 + c) * ld]);
+          a00 = fma(li.x, lj.x, a00);
+          a01 = fma(li.x, lj.y, a01);
+          a10 = fma(li.y, lj.x, a10);
+          a11 = fma(li.y, lj.y, a11);
         }
+        sA[i0 + j0 * ld] -= a00;
+        sA[i0 + 1 + j0 * ld] -= a10;
+        if (i0 > j0) sA[i0 + (j0 + 1) * ld] -= a01;
+        sA[i0 + 1 + (j0 + 1) * ld] -= a11;
       }
-#pragma unroll
-      for (int c = 0; c < 16; ++c)
-        if (c < bs) sA[i + (k0 + c) * kLd] = x[c];
     }
     __syncthreads();
-    // ---- 3. trailing lower triangle: A(i,j) -= sum_c L(i,k0+c) L(j,k0+c), i >= j >= i0
-    for (int j = i0 + ty; j < W; j += 16)
-      for (int i = j + tx; i < W; i += 16) {
-        double v = sA[i + j * kLd];
-        for (int c = 0; c < bs; ++c) v -= sA[i + (k0 + c) * kLd] * sA[j + (k0 + c) * kLd];
-        sA[i + j * kLd] = v;
-      }
-    __syncthreads();
-  }
-
-  // ---- L^-1: diagonal blocks by substitution, thread per (block, column)
-  if (tid < nb * 16) {
-    const int I = tid >> 4, c = tid & 15;
-    const int k0 = I * 16, bs = min(16, W - k0);
-    if (c < bs) {
-      double x[16];
+    // ---- B(i, col) -= sum_c L(i, k0 + c) X(k0 + c, col), i >= k1 > col
+    if (T > 0) {
+      const int ncb = k1 >> 1, nblk = nbk * ncb;
+      for (int e = tid; e < nblk; e += 256) {
+        const int bi = e / ncb, bj = e - bi * ncb;
+        const int i0 = k1 + 2 * bi, j0 = 2 * bj;
+        double b00 = 0.0, b01 = 0.0, b10 = 0.0, b11 = 0.0;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        double v = (r == c) ? 1.0 : 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (q >= c && q < r) v -= sA[(k0 + r) + (k0 + q) * kLd] * x[q];
-        x[r] = (r >= c && r < bs) ? v / sA[(k0 + r) + (k0 + r) * kLd] : 0.0;
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        if (r < bs) sX[(k0 + r) + (k0 + c) * kLd] = x[r];
-    }
-  }
-  __syncthreads();
-  // ---- off-diagonal blocks, block row by block row
-  for (int I = 1; I < nb; ++I) {
-    const int r0 = I * 16, bsI = min(16, W - r0);
-    // T_IJ = sum_{K=J}^{I-1} L_IK X_KJ for every J < I, stored in X_IJ's place
-    for (int e = tid; e < I * 256; e += 256) {
-      const int J = e >> 8, rc = e & 255, r = rc & 15, c = rc >> 4;
-      if (r >= bsI) continue;
-      const int col = J * 16 + c;
-      double v = 0.0;
-      for (int q = J * 16; q < r0; ++q) v += sA[(r0 + r) + q * kLd] * sX[q + col * kLd];
-      sX[(r0 + r) + col * kLd] = v;
-    }
-    __syncthreads();
-    // X_IJ = -X_II T_IJ, thread per column of the block row
-    for (int col = tid; col < r0; col += 256) {
-      double tcol[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) tcol[q] = (q < bsI) ? sX[(r0 + q) + col * kLd] : 0.0;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        if (r < bsI) {
-          double v = 0.0;
-#pragma unroll
-          for (int q = 0; q < 16; ++q)
-            if (q <= r) v += sX[(r0 + r) + (r0 + q) * kLd] * tcol[q];
-          sX[(r0 + r) + col * kLd] = -v;
+        for (int c = 0; c < kCholBs; ++c) {
+          const double2 li = *reinterpret_cast<const double2*>(&sA[i0 + (k0 + c) * ld]);
+          const double x0 = sX[(k0 + c) + j0 * ld], x1 = sX[(k0 + c) + (j0 + 1) * ld];
+          b00 = fma(li.x, x0, b00);
+          b01 = fma(li.x, x1, b01);
+          b10 = fma(li.y, x0, b10);
+          b11 = fma(li.y, x1, b11);
         }
+        sX[i0 + j0 * ld] -= b00;
+        sX[i0 + 1 + j0 * ld] -= b10;
+        sX[i0 + (j0 + 1) * ld] -= b01;
+        sX[i0 + 1 + (j0 + 1) * ld] -= b11;
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   // ---- outputs: R^-1 = X^T, R = L^T (upper triangular, zeros below)
-  for (int e = tid; e < WW; e += 256) {
-    const int i = e % W, k = e / W;
-    D.rinv[e] = (i <= k) ? sX[k + i * kLd] : 0.0;
-    if (pass == 1) D.r1[e] = (i <= k) ? sA[k + i * kLd] : 0.0;
-  }
-  if (pass == 2 && D.R != nullptr) {
-    // R = R2 R1 with R2(i,l) = L2(l,i); w == W on this path
-    for (int e = tid; e < WW; e += 256) {
-      const int i = e % W, k = e / W;
-      double acc = 0.0;
-      for (int l = i; l <= k; ++l) acc += sA[l + i * kLd] * D.r1[l + (int64_t)k * W];
-      D.R[e] = (i <= k) ? acc : 0.0;
+  for (int k = wave; k < W; k += 4)
+    for (int i = lane; i < W; i += 64) {
+      D.rinv[i + (int64_t)k * W] = (i <= k) ? sX[k + i * ld] : 0.0;
+      if (pass == 1) D.r1[i + (int64_t)k * W] = (i <= k) ? sA[k + i * ld] : 0.0;
     }
+  if (pass == 2 && D.R != nullptr) {
+    // R = R2 R1 with R2(i, l) = L2(l, i); w == W on this path.  R1 is staged
+    // in LDS (X is no longer needed).
+    __syncthreads();
+    for (int k = wave; k < W; k += 4)
+      for (int i = lane; i < W; i += 64) sX[i + k * ld] = D.r1[i + (int64_t)k * W];
+    __syncthreads();
+    for (int k = wave; k < W; k += 4)
+      for (int i = lane; i < W; i += 64) {
+        double acc = 0.0;
+        for (int l = i; l <= k; ++l) acc = fma(sA[l + i * ld], sX[l + k * ld], acc);
+        D.R[i + (int64_t)k * W] = (i <= k) ? acc : 0.0;
+      }
   }
 }
 
@@ -375,9 +418,20 @@ hipError_t launch_trsm_rt(const TrsmJob* jobs, int count, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_chol(const QrDesc* qr, int count, int pass, double tol, hipStream_t stream) {
-  if (count <= 0) return hipSuccess;
-  chol_kernel<<<dim3((unsigned)count), dim3(256), 0, stream>>>(qr, pass, tol);
+hipError_t launch_chol(const QrDesc* qr, int count, int pass, double tol, int wmax,
+                       hipStream_t stream) {
+  if (count <= 0 || wmax <= 0) return hipSuccess;
+  if (wmax > kCholMax) wmax = kCholMax;  // wider Grams skip the kernel
+  const size_t lds = chol_lds_bytes(wmax);
+  static bool attr_set = false;
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute((const void*)chol_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)chol_lds_bytes(kCholMax));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  chol_kernel<<<dim3((unsigned)count), dim3(256), lds, stream>>>(qr, pass, tol);
   return hipGetLastError();
 }
 

@@ -190,6 +190,7 @@ struct Step {
   bool f64 = true;
   int32_t value = 0;
   double tol = 0;
+  int wmax = 0;  // chol: widest Gram of the launch
 };
 
 // Workspace arena: addresses are planned against a base that may be null
@@ -898,6 +899,7 @@ void Builder::emit(Program& prog) {
         c.tol = pass == 1 ? 1e-11 : 1e-2;
         for (const QrDesc& q : qr)
           if (q.gram_part != nullptr) {
+            c.wmax = std::max(c.wmax, (int)q.W);
             const double W = (double)q.W;
             c.flops += 2.0 * W * W * W / 3.0;
             c.bytes += 8.0 * W * W * (q.gram_splits + 2);
@@ -1463,7 +1465,9 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
       case S_TILE_REDUCE: e = launch_tile_reduce((const ReduceJob*)(meta + st.meta), st.count, stream); break;
       case S_COPY: e = launch_copy((const CopyJob*)(meta + st.meta), st.count, stream); break;
       case S_FILL: e = launch_fill_i32((int32_t*)st.ptr, st.rows, st.value, stream); break;
-      case S_CHOL: e = launch_chol((const QrDesc*)(meta + st.meta), st.count, st.pass, st.tol, stream); break;
+      case S_CHOL:
+        e = launch_chol((const QrDesc*)(meta + st.meta), st.count, st.pass, st.tol, st.wmax, stream);
+        break;
       case S_KRP_ADJ:
         e = launch_krp_adj(st.prec, (const KrpAdjDesc*)(meta + st.meta), st.count, st.tiles, stream);
         break;
@@ -1702,6 +1706,7 @@ void check_program(const Program& prog, Checker& ck) {
           ck.span(q.flag, 0, 0, 4, "qr flag");
           if (q.R) ck.span(q.R, 0, q.w * q.W - 1, 8, "qr R");
           if (st.kind == S_CHOL && q.gram_part && q.W <= 96 && q.W <= q.n) {
+            if (q.W > st.wmax) { ck.ok = false; ck.err = "chol LDS sized below a Gram width"; return; }
             ck.span(q.gram_part, 0, (int64_t)q.gram_splits * q.W * q.W - 1, 8, "qr gram");
             ck.span(q.rinv, 0, q.W * q.W - 1, 8, "qr rinv");
             ck.span(q.r1, 0, q.W * q.W - 1, 8, "qr r1");
@@ -1715,8 +1720,38 @@ void check_program(const Program& prog, Checker& ck) {
   }
 }
 
+// One line per launch of a checked plan: kernel, descriptors, workgroups,
+// largest K-split and segment count (a planning aid for the tests and for
+// tuning; not part of the ABI header).
+static std::string describe_program(const Program& prog) {
+  std::string out;
+  const char* blob = prog.blob.data();
+  char line[256];
+  for (const Step& st : prog.steps) {
+    int max_split = 1, max_seg = 0;
+    int64_t blocks = st.tiles;
+    if (st.kind == S_GEMM) {
+      const GemmDesc* ds = (const GemmDesc*)(blob + st.meta);
+      for (int i = 0; i < st.count; ++i) {
+        max_split = std::max(max_split, (int)ds[i].splits);
+        max_seg = std::max(max_seg, (int)ds[i].seg_count);
+      }
+    } else if (st.kind == S_KRP) {
+      const KrpDesc* ds = (const KrpDesc*)(blob + st.meta);
+      for (int i = 0; i < st.count; ++i) max_split = std::max(max_split, (int)ds[i].splits);
+    } else if (st.kind == S_CHOL || st.kind == S_HOUSE) {
+      blocks = st.count;
+    }
+    snprintf(line, sizeof line, "%-40s descs=%d blocks=%lld max_split=%d max_seg=%d flops=%.3g\n",
+             step_name(st).c_str(), st.count, (long long)blocks, max_split, max_seg, st.flops);
+    out += line;
+  }
+  return out;
+}
+
 static int selfcheck_impl(int32_t batch, const tsk_tucker_sum* sums, const tsk_sketch_spec* specs,
-                          int out_dtype, int sketch_only, int with_r, char* msg, size_t msglen) {
+                          int out_dtype, int sketch_only, int with_r, char* msg, size_t msglen,
+                          bool describe = false) {
   auto say = [&](const std::string& s) {
     if (msg && msglen) {
       std::strncpy(msg, s.c_str(), msglen - 1);
@@ -1783,7 +1818,7 @@ static int selfcheck_impl(int32_t batch, const tsk_tucker_sum* sums, const tsk_s
     say(ck.err);
     return 98;
   }
-  say("ok");
+  say(describe ? describe_program(prog) : std::string("ok"));
   return 0;
 }
 
@@ -1880,6 +1915,12 @@ extern "C" int tsk_plan_selfcheck_backward(const tsk_tucker_sum* sum, const tsk_
 
 
 // Host-only bounds self-check of a planned call (tests; not part of the ABI header).
+extern "C" int tsk_plan_describe(int32_t batch, const tsk_tucker_sum* sums,
+                                 const tsk_sketch_spec* specs, int out_dtype, char* msg,
+                                 size_t msglen) {
+  return selfcheck_impl(batch, sums, specs, out_dtype, 0, 0, msg, msglen, true);
+}
+
 extern "C" int tsk_plan_selfcheck(const tsk_tucker_sum* sum, const tsk_sketch_spec* spec,
                                   int out_dtype, int sketch_only, int with_r, char* msg,
                                   size_t msglen) {
