@@ -20,6 +20,35 @@ namespace tsk {
 
 namespace {
 
+// GEMM descriptor lookup that also returns the descriptor's segment range,
+// read in the same pass, so that the segment table can be fetched while the
+// descriptor itself is still in flight.
+__device__ __forceinline__ int find_gemm_desc(const GemmDesc* __restrict__ descs, int ndesc,
+                                              int64_t tile, int& seg_begin, int& seg_count) {
+  __shared__ int s_sb[NTHREADS], s_sc[NTHREADS];
+  if (ndesc <= NTHREADS) {
+    const int t = threadIdx.x;
+    bool le = false;
+    if (t < ndesc) {
+      le = descs[t].tile_begin <= tile;
+      s_sb[t] = descs[t].seg_begin;
+      s_sc[t] = descs[t].seg_count;
+    }
+    const int di = uni(__syncthreads_count(le) - 1);
+    seg_begin = uni(s_sb[di]);
+    seg_count = uni(s_sc[di]);
+    return di;
+  }
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  seg_begin = descs[lo].seg_begin;
+  seg_count = descs[lo].seg_count;
+  return lo;
+}
+
 // Descriptor of a linear tile id: the last one whose tile_begin <= tile.
 // Up to 256 descriptors every thread tests one and the block counts (one
 // memory round trip); beyond that, a binary search.
@@ -238,7 +267,7 @@ template <> struct Depth<P_FP32> { static constexpr int value = 8; };
 template <int P, int D, class Cur>
 __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type (&s)[2],
                                       typename PT<P>::acc_t (&acc)[2][2], int t, int lane, int wm,
-                                      int wn) {
+                                      int wn, int mv, int nv) {
   typedef typename PT<P>::in_t in_t;
   constexpr int PER = Stage<P>::PER_THREAD;
   const StageMap<P> map(t);
@@ -272,7 +301,7 @@ __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type
         ++inflight;
         have = cur.advance();
       }
-      mma_tile<P>(s[buf], acc, lane, wm, wn);
+      mma_tile<P>(s[buf], acc, lane, wm, wn, mv, nv);
       --inflight;
       const int nx = (d + 1) % D;
       if (inflight > 0) stage<P>(s[buf ^ 1], map, ax[nx], bx[nx], t, ra[nx], rb[nx], al[nx]);
@@ -294,8 +323,16 @@ __global__ __launch_bounds__(NTHREADS) void gemm_kernel(const GemmDesc* __restri
   __shared__ typename Lds<P>::type s[2];
 
   const int64_t tile = blockIdx.x;
-  const int di = find_desc(descs, ndesc, tile);
-  const GemmDesc D = descs[di];
+  int seg_begin, seg_count;
+  const int di = find_gemm_desc(descs, ndesc, tile, seg_begin, seg_count);
+  __shared__ GemmSeg sseg[kSegCache];
+  SegCursor<P> cur;
+  cur.segs = segs + seg_begin;
+  cur.cache = (lds_seg_t*)sseg;
+  cur.seg_end = seg_count;
+  cur.t = threadIdx.x;
+  const GemmDesc D = descs[di];  // scalar loads, in flight with the segment copy
+  if (seg_count > 0) cur.fill(0);
   int64_t local = tile - D.tile_begin;
   const int splits = D.splits;
   const int split = (int)(local % splits);
@@ -312,13 +349,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_kernel(const GemmDesc* __restri
   acc_t acc[2][2];
   acc_zero<P>(acc);
 
-  __shared__ GemmSeg sseg[kSegCache];
-  SegCursor<P> cur;
-  cur.segs = segs + D.seg_begin;
-  cur.cache = (lds_seg_t*)sseg;
-  cur.c0 = 0;
   cur.si = 0;
-  cur.seg_end = D.seg_count;
   cur.kt = 0;
   cur.nkt = 0;
   cur.b = b;
@@ -329,12 +360,11 @@ __global__ __launch_bounds__(NTHREADS) void gemm_kernel(const GemmDesc* __restri
   cur.t = t;
   cur.step = splits;
   bool have = false;
-  if (D.seg_count > 0) {
-    cur.fill(0);
+  if (seg_count > 0) {
     cur.load();
     have = cur.skip(split);
   }
-  kloop<P, Depth<P>::value>(cur, have, s, acc, t, lane, wm, wn);
+  kloop<P, Depth<P>::value>(cur, have, s, acc, t, lane, wm, wn, M - m0, N - n0);
 
   const int64_t off = b * D.strideC;
   if (splits == 1) {
@@ -554,12 +584,12 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
     KrpCursor<P, true> cur;
     TSK_KRP_CURSOR(cur)
     cur.sP = (typename KrpCursor<P, true>::lds_in_t*)sP;
-    kloop<P, Depth<P>::value>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn);
+    kloop<P, Depth<P>::value>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn, rn - m0, m - n0);
   } else {
     KrpCursor<P, false> cur;
     TSK_KRP_CURSOR(cur)
     cur.sP = nullptr;
-    kloop<P, Depth<P>::value>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn);
+    kloop<P, Depth<P>::value>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn, rn - m0, m - n0);
   }
 #undef TSK_KRP_CURSOR
   typedef typename std::conditional<P == P_FP64, double, float>::type vt;
@@ -667,7 +697,7 @@ __global__ __launch_bounds__(NTHREADS) void krp_adj_kernel(const KrpAdjDesc* __r
   while (kt < nkt) {
     const int kn = kt + 1;
     if (kn < nkt) TSK_ADJ_FETCH(kn);
-    mma_tile<P>(s[buf], acc, lane, wm, wn);
+    mma_tile<P>(s[buf], acc, lane, wm, wn, (int)(rn - m0), (int)min<int64_t>(Nc - n0, TILE));
     if (kn < nkt) stage<P>(s[buf ^ 1], smap, true, false, t, ra, rb, (in_t)1);
     __syncthreads();
     buf ^= 1;

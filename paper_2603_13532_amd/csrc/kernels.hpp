@@ -67,7 +67,8 @@ hipError_t launch_copy(const CopyJob* jobs, int count, hipStream_t stream);
 // wmax: widest Gram (W) among the descriptors; sizes the dynamic LDS.
 hipError_t launch_chol(const QrDesc* qr, int count, int pass, double tol, int wmax,
                        hipStream_t stream);
+// max_elems: largest (n+1)*W + 2W among the descriptors (sizes the in-LDS panel).
 hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* fallback_counter,
-                              hipStream_t stream);
+                              int64_t max_elems, hipStream_t stream);
 
 }  // namespace tsk

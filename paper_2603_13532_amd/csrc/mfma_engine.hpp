@@ -118,11 +118,17 @@ __device__ __forceinline__ void lds_put(typename Lds<P>::type& s, int which, int
 }
 
 // ------------------------------------------------------------ compute step
+// mv, nv: rows and columns of the tile inside the output; 16 x 16 blocks
+// wholly outside it are skipped (a wave-uniform test), which matters for the
+// small ranks and sketch widths that leave most of a 64 x 64 tile empty.
 template <int P>
 __device__ __forceinline__ void mma_tile(const typename Lds<P>::type& s,
                                          typename PT<P>::acc_t (&acc)[2][2], int lane, int wm,
-                                         int wn) {
+                                         int wn, int mv, int nv) {
   const int r = lane & 15, kq = lane >> 4;
+  const bool oi0 = wm * 32 < mv, oi1 = wm * 32 + 16 < mv;
+  const bool oj0 = wn * 32 < nv, oj1 = wn * 32 + 16 < nv;
+  if (!oi0 || !oj0) return;  // the wave's whole quadrant is outside
   if constexpr (P == P_FP64 || P == P_FP32) {
     constexpr int BK = PT<P>::BK;
 #pragma unroll
@@ -132,9 +138,9 @@ __device__ __forceinline__ void mma_tile(const typename Lds<P>::type& s,
       auto b0 = s.b[ks + kq][wn * 32 + r];
       auto b1 = s.b[ks + kq][wn * 32 + 16 + r];
       acc[0][0] = mma(a0, b0, acc[0][0]);
-      acc[0][1] = mma(a0, b1, acc[0][1]);
-      acc[1][0] = mma(a1, b0, acc[1][0]);
-      acc[1][1] = mma(a1, b1, acc[1][1]);
+      if (oj1) acc[0][1] = mma(a0, b1, acc[0][1]);
+      if (oi1) acc[1][0] = mma(a1, b0, acc[1][0]);
+      if (oi1 && oj1) acc[1][1] = mma(a1, b1, acc[1][1]);
     }
   } else {
     constexpr int PARTS = PT<P>::PARTS;
@@ -151,6 +157,7 @@ __device__ __forceinline__ void mma_tile(const typename Lds<P>::type& s,
     for (int i = 0; i < 2; ++i) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
+        if (!(i == 0 || oi1) || !(j == 0 || oj1)) continue;
         // smallest cross products first so they are not absorbed early
         if constexpr (PARTS == 3) {
           acc[i][j] = mma_bf(a[0][i], b[2][j], acc[i][j]);

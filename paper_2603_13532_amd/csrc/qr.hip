@@ -270,105 +270,401 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
   }
 }
 
+constexpr int64_t kHhLdsMax = 19456;  // doubles of LDS for an in-LDS Householder panel (152 KB)
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
+// Householder QR with the whole n x W panel in LDS (column-major, ld n),
+// used when it fits.  Reflector j: norm of the subdiagonal part by a block
+// reduction, then each wave applies it to every fourth trailing column, two
+// columns per pass so that their two reductions overlap.  Q is formed in
+// place from the stored reflectors, last to first (the LAPACK org2r order),
+// after R has been written out; signs then make diag(R) >= 0.
+typedef __attribute__((address_space(3))) double lds_f64;
+
+// Householder QR of the n x W matrix Ysrc (leading dimension ldy) in the
+// panel A (leading dimension lda).  Writes R (w x W, ld ldr; null to skip)
+// and Q (n x w, ld ldq); with fix_signs, rows of R and columns of Q are
+// negated where needed so that diag(R) >= 0.  A, tau, sgn: LDS or global
+// (the same algorithm for both); red, part: LDS.
+//
+// Reflector j: a block reduction gives the norm below the diagonal, and
+// every thread then derives tau, beta and the scale of the reflector.  The
+// trailing columns are updated with lane = column and wave = every fourth
+// row: partial dot products, one exchange through LDS, then the rank-one
+// update, so each reflector costs three barriers and no per-column
+// reductions.  The reflector's column is scaled one step later, while the
+// next norm is formed.  Q is then formed in place, last reflector first
+// (LAPACK org2r order), with the same column-parallel update.
+template <typename PA, typename PV>
+__device__ __forceinline__ void hh_core(const double* Ysrc, int64_t ldy, double* Qdst,
+                                        int64_t ldq, double* Rdst, int64_t ldr, bool fix_signs,
+                                        PA A, int64_t lda, PV tau, PV sgn, lds_f64* red,
+                                        lds_f64* part, int64_t n64, int64_t W64, int64_t w64) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = (int)n64, W = (int)W64, w = (int)w64;
+  // column k of the panel
+  auto col_of = [&](int k) { return A + (int64_t)k * lda; };
+  for (int k = wave; k < W; k += 4) {
+    auto ak = col_of(k);
+    const double* yk = Ysrc + (int64_t)k * ldy;
+    for (int i = lane; i < n; i += 64) ak[i] = yk[i];
+  }
+  __syncthreads();
+  double scal_prev = 1.0;
+  for (int j = 0; j < w; ++j) {
+    auto aj = col_of(j);
+    double pn = 0.0;
+#pragma unroll 4
+    for (int i = j + 1 + tid; i < n; i += 256) pn += aj[i] * aj[i];
+    if (j > 0) {
+      auto ap = col_of(j - 1);
+      for (int i = j + tid; i < n; i += 256) ap[i] *= scal_prev;
+    }
+    const double alpha = aj[j];
+    pn = wave_sum(pn);
+    if (lane == 0) red[wave] = pn;
+    __syncthreads();
+    const double sigma = red[0] + red[1] + red[2] + red[3];
+    double t = 0.0, scal = 1.0, beta = alpha;
+    if (sigma > 0.0) {
+      const double mu = sqrt(alpha * alpha + sigma);
+      beta = (alpha <= 0.0) ? mu : -mu;
+      t = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    if (tid == 0) {
+      aj[j] = beta;
+      tau[j] = t;
+    }
+    if (t != 0.0) {
+      for (int cb = j + 1; cb < W; cb += 64) {
+        const int col = cb + lane;
+        const bool ok = col < W;
+        auto ac = col_of(ok ? col : j);
+        double d = 0.0, arow = 0.0;
+        if (ok) {
+#pragma unroll 4
+          for (int i = j + 1 + wave; i < n; i += 4) d += aj[i] * ac[i];
+          arow = ac[j];
+        }
+        part[wave * 64 + lane] = d;
+        __syncthreads();
+        const double S = part[lane] + part[64 + lane] + part[128 + lane] + part[192 + lane];
+        const double f = t * (arow + scal * S), fs = f * scal;
+        if (ok) {
+#pragma unroll 4
+          for (int i = j + 1 + wave; i < n; i += 4) ac[i] -= fs * aj[i];
+          if (wave == 0) ac[j] = arow - f;
+        }
+        __syncthreads();
+      }
+    } else {
+      __syncthreads();
+    }
+    scal_prev = scal;
+  }
+  __syncthreads();
+  if (w > 0) {
+    auto al = col_of(w - 1);
+    for (int i = w + tid; i < n; i += 256) al[i] *= scal_prev;
+  }
+  for (int i = tid; i < w; i += 256) sgn[i] = (fix_signs && col_of(i)[i] < 0.0) ? -1.0 : 1.0;
+  __syncthreads();
+  if (Rdst != nullptr) {
+    for (int k = wave; k < W; k += 4) {
+      auto ak = col_of(k);
+      for (int i = lane; i < w; i += 64) Rdst[i + (int64_t)k * ldr] = (i <= k) ? sgn[i] * ak[i] : 0.0;
+    }
+  }
+  __syncthreads();
+  // Q = H_0 ... H_{w-1} [I_w; 0], formed in place in columns 0 .. w-1
+  for (int j = w - 1; j >= 0; --j) {
+    auto aj = col_of(j);
+    const double t = tau[j];
+    if (t != 0.0) {
+      for (int cb = j + 1; cb < w; cb += 64) {
+        const int col = cb + lane;
+        const bool ok = col < w;
+        auto ac = col_of(ok ? col : j);
+        double d = 0.0, arow = 0.0;
+        if (ok) {
+#pragma unroll 4
+          for (int i = j + 1 + wave; i < n; i += 4) d += aj[i] * ac[i];
+          arow = ac[j];
+        }
+        part[wave * 64 + lane] = d;
+        __syncthreads();
+        const double S = part[lane] + part[64 + lane] + part[128 + lane] + part[192 + lane];
+        const double f = t * (arow + S);
+        if (ok) {
+#pragma unroll 4
+          for (int i = j + 1 + wave; i < n; i += 4) ac[i] -= f * aj[i];
+          if (wave == 0) ac[j] = arow - f;
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = tid; i < n; i += 256) {
+      if (i > j) aj[i] *= -t;
+      else if (i == j) aj[i] = 1.0 - t;
+      else aj[i] = 0.0;
+    }
+    __syncthreads();
+  }
+  for (int k = wave; k < w; k += 4) {
+    auto ak = col_of(k);
+    double* qk = Qdst + (int64_t)k * ldq;
+    for (int i = lane; i < n; i += 64) qk[i] = sgn[k] * ak[i];
+  }
+  __syncthreads();
+}
+
+// Register-resident Householder QR for n <= 4 NR rows and W <= 64 columns:
+// lane c holds column c, wave w holds rows w, w + 4, ...  The reflector
+// column is broadcast from its lane with readlane (a scalar operand of the
+// FMAs, read where it is used so that it never stays live); the norm and
+// the partial dot products of all trailing columns come from one pass over
+// the registers, four partial sums per column are exchanged through LDS
+// (double-buffered by step parity), and one more pass applies the update:
+// one barrier per reflector and no LDS traffic proportional to the panel.
+// Registers are shifted by one row block every four reflectors, so that row
+// j always sits in register 0 of wave j % 4 (static register indexing);
+// rows leaving the window are parked in the LDS panel A (ld lda), which
+// also stages the coalesced input and output.  Q is formed backwards (org2r
+// order) with the window shifted back.  Same arithmetic as hh_core.
+template <int NR>
+__device__ __forceinline__ void hh_regs(const double* Ysrc, int64_t ldy, double* Qdst,
+                                        int64_t ldq, double* Rdst, int64_t ldr, bool fix_signs,
+                                        lds_f64* A, int lda, lds_f64* tau, lds_f64* sgn,
+                                        lds_f64* red, lds_f64* part, int n, int W, int w) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c = lane;
+  for (int k = wave; k < W; k += 4)
+    for (int i = lane; i < n; i += 64) A[i + k * lda] = Ysrc[i + (int64_t)k * ldy];
+  __syncthreads();
+  double a[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = wave + 4 * r;
+    a[r] = (i < n && c < W) ? A[i + c * lda] : 0.0;
+  }
+  __syncthreads();
+  const int nq = (w + 3) / 4;
+  for (int q = 0; q < nq; ++q) {
+#pragma unroll
+    for (int jw = 0; jw < 4; ++jw) {
+      const int j = 4 * q + jw;
+      if (j < w) {
+        const bool first_below = wave > jw;  // register 0 holds a row below j
+        lds_f64* rd = red + 8 * jw;           // step parity buffers (jw & 1 would do;
+        lds_f64* pt = part + 320 * (jw & 1);  // red is indexed by jw for clarity)
+        double p = 0.0, d = 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const double v = readlane_d(a[r], j);
+          if (r > 0 || first_below) {
+            p += v * v;
+            d += v * a[r];
+          }
+        }
+        const double a0j = readlane_d(a[0], j);
+        if (lane == 0) rd[wave] = p;
+        if (wave == jw && lane == 0) rd[4] = a0j;  // alpha = A(j, j)
+        pt[wave * 64 + lane] = d;
+        if (wave == jw) pt[256 + lane] = a[0];  // row j
+        __syncthreads();
+        const double sigma = rd[0] + rd[1] + rd[2] + rd[3], alpha = rd[4];
+        double t = 0.0, scal = 1.0, beta = alpha;
+        if (sigma > 0.0) {
+          const double mu = sqrt(alpha * alpha + sigma);
+          beta = (alpha <= 0.0) ? mu : -mu;
+          t = (beta - alpha) / beta;
+          scal = 1.0 / (alpha - beta);
+        }
+        const double S = pt[lane] + pt[64 + lane] + pt[128 + lane] + pt[192 + lane];
+        const double arow = pt[256 + lane];
+        const double f = t * (arow + scal * S), fs = f * scal;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const double v = readlane_d(a[r], j);
+          if (r > 0 || first_below)
+            a[r] = (c > j) ? a[r] - fs * v : ((c == j) ? a[r] * scal : a[r]);
+        }
+        if (wave == jw) a[0] = (c > j) ? arow - f : ((c == j) ? beta : a[0]);
+        if (tid == 0) tau[j] = t;
+      }
+    }
+    // park row 4q + wave and shift the window down by one row block
+    {
+      const int i = 4 * q + wave;
+      if (i < n && c < W) A[i + c * lda] = a[0];
+    }
+#pragma unroll
+    for (int r = 0; r < NR - 1; ++r) a[r] = a[r + 1];
+    a[NR - 1] = 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = 4 * nq + wave + 4 * r;
+    if (i < n && c < W) A[i + c * lda] = a[r];
+  }
+  __syncthreads();
+  for (int i = tid; i < w; i += 256) sgn[i] = (fix_signs && A[i + i * lda] < 0.0) ? -1.0 : 1.0;
+  __syncthreads();
+  if (Rdst != nullptr)
+    for (int k = wave; k < W; k += 4)
+      for (int i = lane; i < w; i += 64)
+        Rdst[i + (int64_t)k * ldr] = (i <= k) ? sgn[i] * A[i + k * lda] : 0.0;
+  // Q = H_0 ... H_{w-1} [I_w; 0]: window at the last row block, entries on
+  // or above the diagonal cleared (formed columns are zero above their index)
+  const int q0 = nq > 0 ? nq - 1 : 0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = 4 * q0 + wave + 4 * r;
+    a[r] = (i < n && c < w && c < i) ? A[i + c * lda] : 0.0;
+  }
+  for (int q = nq - 1; q >= 0; --q) {
+#pragma unroll
+    for (int jw = 3; jw >= 0; --jw) {
+      const int j = 4 * q + jw;
+      if (j < w) {
+        const bool first_below = wave > jw;
+        lds_f64* pt = part + 320 * (jw & 1);
+        const double t = tau[j];
+        double d = 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const double v = readlane_d(a[r], j);
+          if (r > 0 || first_below) d += v * a[r];
+        }
+        pt[wave * 64 + lane] = d;
+        if (wave == jw) pt[256 + lane] = a[0];
+        __syncthreads();
+        const double S = pt[lane] + pt[64 + lane] + pt[128 + lane] + pt[192 + lane];
+        const double arow = pt[256 + lane];
+        const double f = t * (arow + S);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const double v = readlane_d(a[r], j);
+          if (r > 0 || first_below)
+            a[r] = (c > j) ? a[r] - f * v : ((c == j) ? -t * a[r] : a[r]);
+        }
+        if (wave == jw) a[0] = (c > j) ? arow - f : ((c == j) ? 1.0 - t : a[0]);
+      }
+    }
+    if (q > 0) {
+#pragma unroll
+      for (int r = NR - 1; r > 0; --r) a[r] = a[r - 1];
+      const int i = 4 * (q - 1) + wave;
+      a[0] = (i < n && c < w && c < i) ? A[i + c * lda] : 0.0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = wave + 4 * r;
+    if (i < n && c < w) A[i + c * lda] = sgn[c] * a[r];
+  }
+  __syncthreads();
+  for (int k = wave; k < w; k += 4)
+    for (int i = lane; i < n; i += 64) Qdst[i + (int64_t)k * ldq] = A[i + k * lda];
+  __syncthreads();
+}
+
+// Register path when the panel fits it (n <= 256, W <= 64), else hh_core.
+__device__ __forceinline__ void hh_any(const double* Ysrc, int64_t ldy, double* Qdst, int64_t ldq,
+                                       double* Rdst, int64_t ldr, bool fix_signs, lds_f64* A,
+                                       int64_t lda, lds_f64* tau, lds_f64* sgn, lds_f64* red,
+                                       lds_f64* part, int64_t n, int64_t W, int64_t w) {
+  if (W <= 64 && n <= 256) {
+    const int ni = (int)n, Wi = (int)W, wi = (int)w, li = (int)lda;
+    if (n <= 64)
+      hh_regs<16>(Ysrc, ldy, Qdst, ldq, Rdst, ldr, fix_signs, A, li, tau, sgn, red, part, ni, Wi, wi);
+    else if (n <= 128)
+      hh_regs<32>(Ysrc, ldy, Qdst, ldq, Rdst, ldr, fix_signs, A, li, tau, sgn, red, part, ni, Wi, wi);
+    else if (n <= 192)
+      hh_regs<48>(Ysrc, ldy, Qdst, ldq, Rdst, ldr, fix_signs, A, li, tau, sgn, red, part, ni, Wi, wi);
+    else
+      hh_regs<64>(Ysrc, ldy, Qdst, ldq, Rdst, ldr, fix_signs, A, li, tau, sgn, red, part, ni, Wi, wi);
+  } else {
+    hh_core(Ysrc, ldy, Qdst, ldq, Rdst, ldr, fix_signs, A, lda, tau, sgn, red, part, n, W, w);
+  }
+}
+
+// Tall panels that do not fit LDS whole (n >= 4 W): one level of TSQR.
+// The two row halves are factored in LDS, their R factors stacked, the
+// stack factored (with the sign fix), and Q = diag(Q1, Q2) Q3 formed from
+// LDS copies of Q3 and of each half's Q.  Workspace: the stack S (m3 x W)
+// and Q3 (m3 x w) in the panel scratch, Q1 and Q2 in place in Q.
+__device__ __forceinline__ void hh_tsqr(const QrDesc& D, lds_f64* base, lds_f64* red,
+                                        lds_f64* part, int64_t n, int64_t W, int64_t w) {
+  const int tid = threadIdx.x;
+  const int64_t n1 = (n + 1) / 2, n2 = n - n1;
+  const int64_t w1 = n1 < W ? n1 : W, w2 = n2 < W ? n2 : W, m3 = w1 + w2;
+  double* S = D.hh;             // m3 x W, ld m3
+  double* Q3 = D.hh + m3 * W;   // m3 x w, ld m3
+  lds_f64* A = base;
+  const int64_t l1 = n1 + 1, l2 = n2 + 1, l3 = m3 + 1;  // odd leading dimensions
+  hh_any(D.Y, n, D.Q, n, S, m3, false, A, l1, A + l1 * W, A + l1 * W + W, red, part, n1, W, w1);
+  hh_any(D.Y + n1, n, D.Q + n1, n, S + w1, m3, false, A, l2, A + l2 * W, A + l2 * W + W, red, part,
+         n2, W, w2);
+  hh_any(S, m3, Q3, m3, D.R, w, true, A, l3, A + l3 * W, A + l3 * W + W, red, part, m3, W, w);
+  // Q rows of half h: Q_h (rows x wh, in place in D.Q) times Q3 rows [off, off + wh)
+  lds_f64* sQ3 = base;          // m3 x w
+  lds_f64* sQh = base + m3 * w; // rows x wh
+  for (int64_t e = tid; e < m3 * w; e += 256) sQ3[e] = Q3[e];
+  for (int h = 0; h < 2; ++h) {
+    const int64_t r0 = h ? n1 : 0, rows = h ? n2 : n1, wh = h ? w2 : w1, off = h ? w1 : 0;
+    __syncthreads();
+    for (int64_t e = tid; e < rows * wh; e += 256) {
+      const int64_t i = e % rows, k = e / rows;
+      sQh[e] = D.Q[r0 + i + k * n];
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < rows * w; e += 256) {
+      const int64_t i = e % rows, c = e / rows;
+      double acc = 0.0;
+      for (int64_t k = 0; k < wh; ++k) acc += sQh[i + k * rows] * sQ3[off + k + c * m3];
+      D.Q[r0 + i + c * n] = acc;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restrict__ qrs,
                                                           int force,
-                                                          unsigned long long* counter) {
+                                                          unsigned long long* counter,
+                                                          int64_t lds_elems) {
+  extern __shared__ __align__(16) double hsm[];
   const QrDesc& D = qrs[blockIdx.x];
   const bool broke = *D.flag != 0;
   if (!force && !broke && !D.hh_direct) return;
   const int64_t n = D.n, W = D.W;
   const int64_t w = n < W ? n : W;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   if (tid == 0 && counter != nullptr) {
     atomicAdd(counter, 1ull);                              // QRs done by Householder
     if (broke && D.report_only) atomicAdd(counter + 1, 1ull);  // reported breakdowns
   }
-  double* A = D.hh;
-  for (int64_t e = tid; e < n * W; e += 256) A[e] = D.Y[e];
-  __shared__ double red[4];
-  __shared__ double s_tau, s_scal;
-  __syncthreads();
-
-  for (int64_t j = 0; j < w; ++j) {
-    double part = 0.0;
-    for (int64_t i = j + 1 + tid; i < n; i += 256) {
-      const double x = A[i + j * n];
-      part += x * x;
-    }
-    part = wave_sum(part);
-    if (lane == 0) red[wave] = part;
-    __syncthreads();
-    if (tid == 0) {
-      const double sigma = red[0] + red[1] + red[2] + red[3];
-      const double alpha = A[j + j * n];
-      double tau = 0.0, scal = 0.0, beta = alpha;
-      if (sigma > 0.0) {
-        const double mu = sqrt(alpha * alpha + sigma);
-        beta = (alpha <= 0.0) ? mu : -mu;
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-      }
-      A[j + j * n] = beta;
-      D.tau[j] = tau;
-      s_tau = tau;
-      s_scal = scal;
-    }
-    __syncthreads();
-    const double tau = s_tau;
-    if (tau != 0.0) {
-      const double scal = s_scal;
-      for (int64_t i = j + 1 + tid; i < n; i += 256) A[i + j * n] *= scal;
-      __syncthreads();
-      for (int64_t c = j + 1 + wave; c < W; c += 4) {
-        double dot = 0.0;
-        for (int64_t i = j + 1 + lane; i < n; i += 64) dot += A[i + j * n] * A[i + c * n];
-        dot = wave_sum(dot) + A[j + c * n];
-        const double f = tau * dot;
-        for (int64_t i = j + 1 + lane; i < n; i += 64) A[i + c * n] -= f * A[i + j * n];
-        if (lane == 0) A[j + c * n] -= f;
-      }
-    }
-    __syncthreads();
-  }
-
-  // R (w x W, ld w) with signs making diag(R) >= 0
-  if (D.R != nullptr) {
-    for (int64_t e = tid; e < w * W; e += 256) {
-      const int64_t i = e % w, k = e / w;
-      const double sgn = (A[i + i * n] < 0.0) ? -1.0 : 1.0;
-      D.R[e] = (i <= k) ? sgn * A[i + k * n] : 0.0;
-    }
-  }
-  // Q = H_0 H_1 ... H_{w-1} [I_w; 0]
-  double* Q = D.Q;
-  for (int64_t e = tid; e < n * w; e += 256) {
-    const int64_t i = e % n, c = e / n;
-    Q[e] = (i == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int64_t j = w - 1; j >= 0; --j) {
-    const double tau = D.tau[j];
-    if (tau != 0.0) {
-      for (int64_t c = j + wave; c < w; c += 4) {
-        double dot = 0.0;
-        for (int64_t i = j + 1 + lane; i < n; i += 64) dot += A[i + j * n] * Q[i + c * n];
-        dot = wave_sum(dot) + Q[j + c * n];
-        const double f = tau * dot;
-        for (int64_t i = j + 1 + lane; i < n; i += 64) Q[i + c * n] -= f * A[i + j * n];
-        if (lane == 0) Q[j + c * n] -= f;
-      }
-    }
-    __syncthreads();
-  }
-  for (int64_t e = tid; e < n * w; e += 256) {
-    const int64_t c = e / n;
-    if (A[c + c * n] < 0.0) Q[e] = -Q[e];
+  __shared__ double red_s[32];
+  __shared__ double part_s[640];
+  lds_f64* red = (lds_f64*)red_s;
+  lds_f64* part = (lds_f64*)part_s;
+  lds_f64* base = (lds_f64*)hsm;
+  const int64_t n1 = (n + 1) / 2, w1 = n1 < W ? n1 : W;
+  if ((n + 1) * W + 2 * W <= lds_elems) {
+    const int64_t la = n + 1;  // odd: lanes on different columns hit different banks
+    hh_any(D.Y, n, D.Q, n, D.R, w, true, base, la, base + la * W, base + la * W + W, red, part, n,
+           W, w);
+  } else if (n >= 4 * W && (n1 + 1) * W + 2 * W <= lds_elems &&
+             (2 * w1 + 1) * W + 2 * W <= lds_elems && 2 * w1 * w + n1 * w1 <= lds_elems) {
+    hh_tsqr(D, base, red, part, n, W, w);
+  } else {
+    // panel in global memory (workspace: n x W panel, then W signs)
+    hh_core(D.Y, n, D.Q, n, D.R, w, true, D.hh, n, D.tau, D.hh + n * W, red, part, n, W, w);
   }
 }
 
@@ -436,10 +732,21 @@ hipError_t launch_chol(const QrDesc* qr, int count, int pass, double tol, int wm
 }
 
 hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* fallback_counter,
-                              hipStream_t stream) {
+                              int64_t max_elems, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
-  householder_kernel<<<dim3((unsigned)count), dim3(256), 0, stream>>>(
-      qr, force, (unsigned long long*)fallback_counter);
+  // LDS for the largest panel (plus tau, signs and reduction slots), capped
+  int64_t elems = max_elems < kHhLdsMax ? max_elems : kHhLdsMax;
+  if (elems < 0) elems = 0;
+  static bool attr_set = false;
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute((const void*)householder_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(kHhLdsMax * sizeof(double)));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  householder_kernel<<<dim3((unsigned)count), dim3(256), (size_t)elems * sizeof(double), stream>>>(
+      qr, force, (unsigned long long*)fallback_counter, elems);
   return hipGetLastError();
 }
 

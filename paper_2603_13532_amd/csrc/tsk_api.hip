@@ -349,9 +349,12 @@ void emit_copies(Program& prog, const std::vector<CopyJob>& jobs) {
   prog.steps.push_back(c);
 }
 
+// K-splits so that a launch stays within one round of resident workgroups
+// (target = CUs x workgroups per CU): a launch just past that size would run
+// a second, nearly empty round and take twice as long.
 int choose_splits(int64_t tiles_without_split, int64_t k_tiles, int64_t target = 512) {
   if (tiles_without_split >= target || k_tiles < 4) return 1;
-  int64_t s = ceil_div(target, tiles_without_split);
+  int64_t s = target / tiles_without_split;
   s = std::min<int64_t>(s, k_tiles / 2);
   s = std::min<int64_t>(s, 32);
   return (int)std::max<int64_t>(s, 1);
@@ -497,6 +500,8 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
         tiles0 += ceil_div(P.r(i, n), 64) * ceil_div(m, 64);
         ktmax = std::max<int64_t>(ktmax, ceil_div(Kc, ts64 ? 16 : 32));
       }
+    // the Khatri-Rao expansion makes a KRP K-tile costly, so several rounds
+    // of short workgroups beat one round of long ones
     const int splits = B.splits(tiles0, ktmax, 1024);
     int64_t& tiles = B.krp_tiles;
     const size_t kd_first = kd.size();
@@ -690,7 +695,7 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
     q.W = W;
     q.w = w;
     q.flag = flags + n;
-    q.hh = (double*)ar.take(nn * W * 8);
+    q.hh = (double*)ar.take((nn * W + W) * 8);  // panel, then the R-diagonal signs
     q.tau = (double*)ar.take(W * 8);
     const bool chol = P.qr_policy != 1 && W <= 96 && W <= nn;
     q.hh_direct = chol ? 0 : 1;
@@ -913,6 +918,7 @@ void Builder::emit(Program& prog) {
     hh.meta = qmeta;
     hh.count = (int)qr.size();
     hh.ptr = d_counter;
+    for (const QrDesc& q : qr) hh.rows = std::max<int64_t>(hh.rows, (q.n + 1) * q.W + 2 * q.W);
     prog.steps.push_back(hh);
   }
   emit_copy_stage(ST_QCOPY);
@@ -1474,7 +1480,8 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
       case S_SYM: e = launch_sym((const SymJob*)(meta + st.meta), st.count, stream); break;
       case S_TRSM: e = launch_trsm_rt((const TrsmJob*)(meta + st.meta), st.count, stream); break;
       case S_HOUSE:
-        e = launch_householder((const QrDesc*)(meta + st.meta), st.count, st.force, (int64_t*)st.ptr, stream);
+        e = launch_householder((const QrDesc*)(meta + st.meta), st.count, st.force, (int64_t*)st.ptr,
+                               st.rows, stream);
         break;
     }
     if (e != hipSuccess) return fail(h, TSK_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -1701,7 +1708,7 @@ void check_program(const Program& prog, Checker& ck) {
           const QrDesc& q = qs[i];
           ck.span(q.Y, 0, q.n * q.W - 1, 8, "qr Y");
           ck.span(q.Q, 0, q.n * q.w - 1, 8, "qr Q");
-          ck.span(q.hh, 0, q.n * q.W - 1, 8, "qr hh");
+          ck.span(q.hh, 0, q.n * q.W + q.W - 1, 8, "qr hh");
           ck.span(q.tau, 0, q.W - 1, 8, "qr tau");
           ck.span(q.flag, 0, 0, 4, "qr flag");
           if (q.R) ck.span(q.R, 0, q.w * q.W - 1, 8, "qr R");

@@ -168,6 +168,27 @@ def test_householder_policy_matches_cholqr2(tsk):
     check_recompress(tsk, ts, "krp", [16], 3, qr_policy="householder")
 
 
+@pytest.mark.parametrize("dims,ranks,m", [
+    # mode 0: 700 x 40 panel, too large for LDS whole -> two-level TSQR
+    # (full rank: compared with Cholesky QR2; rank-deficient: through [[H; Q]])
+    ((700, 60, 50), [[20, 20, 18], [15, 14, 15], [12, 12, 12]], 40),
+    ((700, 60, 50), [[12, 9, 8], [10, 11, 7], [9, 8, 10]], 40),
+    # mode 0: 200 x 100 panel (W > 96 and not tall) -> panel in global memory
+    ((200, 150, 120), [[40, 30, 35], [38, 36, 30], [30, 34, 33]], 100),
+])
+def test_householder_panel_paths(tsk, dims, ranks, m):
+    """Householder with the panel in LDS, in two stacked halves (TSQR) and
+    in global memory, each against the oracle."""
+    ts = synth.random_sum(13, dims, ranks)
+    check_recompress(tsk, ts, "krp", [m], 5, qr_policy="householder")
+    if m <= 96:
+        a_q, a_h = run(tsk, ts, "krp", [m], 5)
+        b_q, b_h = run(tsk, ts, "krp", [m], 5, qr_policy="householder")
+        for x, y in zip(a_q, b_q):
+            assert rel(np_of(x), np_of(y)) < 1e-11
+        assert rel(np_of(a_h), np_of(b_h)) < 1e-11
+
+
 def test_zero_sum(tsk):
     ts = synth.random_sum(10, (40, 30, 20), [[3, 4, 5], [2, 2, 2]], coeffs=[0.0, 0.0])
     qs, h = run(tsk, ts, "krp", [6], 1)
