@@ -68,6 +68,37 @@ def kernel_precision(name):
     return {0: "fp64", 1: "fp32", 2: "bf16x1", 3: "bf16x3", 4: "bf16x6"}.get(code, "fp64")
 
 
+def kernel_peak(name):
+    """(bound, peak TFLOP/s) of a contraction or QR kernel; None otherwise.
+    MFMA kernels take the dense matrix peak of their arithmetic (split BF16:
+    the BF16 peak over the number of products); the Cholesky and Householder
+    kernels are FP64 vector arithmetic (FP64 vector peak)."""
+    if "chol" in name or "householder" in name:
+        return "alu", PEAK_TFLOPS["fp64"]
+    if "gemm" in name or "krp" in name:
+        prec = kernel_precision(name)
+        if prec.startswith("bf16"):
+            parts = {"bf16x1": 1, "bf16x3": 3, "bf16x6": 6}[prec]
+            return "mfma", PEAK_TFLOPS["bf16"] / parts
+        return "mfma", PEAK_TFLOPS[prec]
+    return None
+
+
+def step_roofline(report, steps, step_bytes, ms_measured):
+    """Whole-step roofline: the time the step's algorithmic work needs at the
+    peaks of its stages' arithmetic, or to move its algorithmic bytes,
+    against the measured graph-replayed step time."""
+    t_flop = 0.0
+    for name, rec in report.items():
+        kp = kernel_peak(name)
+        if kp is not None and rec["flops"] > 0:
+            t_flop += rec["flops"] / steps / (kp[1] * 1e12)
+    t_bytes = step_bytes / (HBM_GBS * 1e9)
+    t_roof = max(t_flop, t_bytes)
+    return {"t_roof_us": t_roof * 1e6, "t_flop_us": t_flop * 1e6, "t_bytes_us": t_bytes * 1e6,
+            "t_measured_us": ms_measured * 1e3, "frac": t_roof / (ms_measured * 1e-3)}
+
+
 def roofline_of(report):
     """Dominant kernel (largest total time) of a profile report."""
     name, rec = max(report.items(), key=lambda kv: kv[1]["ms"])
@@ -75,7 +106,12 @@ def roofline_of(report):
     avg_s = rec["ms"] / launches * 1e-3
     flops = rec["flops"] / launches
     nbytes = rec["bytes"] / launches
-    prec = kernel_precision(name) if ("gemm" in name or "krp" in name or "chol" in name) else None
+    kp = kernel_peak(name)
+    if kp is not None and kp[0] == "alu" and flops > 0:
+        achieved = flops / avg_s / 1e12
+        return name, {"bound": "alu", "achieved": achieved, "peak": kp[1], "unit": "TFLOP/s",
+                      "frac": achieved / kp[1], "traffic": None}, avg_s
+    prec = kernel_precision(name) if ("gemm" in name or "krp" in name) else None
     if prec is None or flops == 0:
         achieved = nbytes / avg_s / 1e9
         return name, {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s",
@@ -268,6 +304,15 @@ def main():
     kname, roof, avg_s = roofline_of(report)
     roof["kernel"] = kname
     roof["avg_launch_us"] = avg_s * 1e6
+    # algorithmic bytes of one step: inputs and Omega read once, Q and H written once
+    in_es = 8 if FORMS[best][0] == "f64" else 4
+    out_es = 8 if FORMS[best][3] == "f64" else 4
+    n_in = sum(g.size for g in ts["cores"]) + sum(u.size for us in ts["factors"] for u in us)
+    n_om = sum(ts["dims"][k] * m for k in range(len(ts["dims"])))
+    w = min(m, min(ts["dims"]))
+    n_out = sum(ts["dims"][k] * w for k in range(len(ts["dims"]))) + w ** len(ts["dims"])
+    step_bytes = (n_in + n_om) * in_es + n_out * out_es
+    step_roof = step_roofline(report, args.steps, step_bytes, chosen["ms_per_step"])
     if args.profile_json:
         with open(args.profile_json, "w") as f:
             json.dump({"form": best, "steps": args.steps, "report": report}, f, indent=1)
@@ -297,6 +342,7 @@ def main():
         "forms": forms_out,
         "batch_form": batch,
         "roofline": roof,
+        "step_roofline": step_roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -62,6 +62,51 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 //     over the 16 panel columns.
 // LDS is sized by the widest Gram of the launch, so narrow Grams leave room
 // for several workgroups per CU.
+// One 16-column panel of the Cholesky factorization by one wave: lane l
+// holds row k0 + l (and k0 + 64 + l when TWO) of the panel in registers.
+template <bool TWO>
+__device__ __forceinline__ void chol_panel(double* sA, int ld, double* dinv, const double* diag0,
+                                           int* s_bad, int k0, int Wp, int lane, double tol) {
+  const int r0 = k0 + lane, r1 = k0 + 64 + lane;
+  double p0[kCholBs], p1[kCholBs], g0[kCholBs];
+#pragma unroll
+  for (int c = 0; c < kCholBs; ++c) {
+    p0[c] = (c <= lane && r0 < Wp) ? sA[r0 + (k0 + c) * ld] : 0.0;
+    if (TWO) p1[c] = (r1 < Wp) ? sA[r1 + (k0 + c) * ld] : 0.0;
+    g0[c] = diag0[k0 + c];
+  }
+  bool bad = false;
+  double yc = 0.0;  // lane c: 1 / L(k0 + c, k0 + c)
+#pragma unroll
+  for (int c = 0; c < kCholBs; ++c) {
+    const double piv = readlane_d(p0[c], c);
+    const bool badc = !(piv > tol * g0[c]) || !(g0[c] > 0.0);
+    bad = bad || badc;
+    const double x = badc ? 1.0 : piv;
+    double y = __builtin_amdgcn_rsq(x);
+    double t = x * y;
+    const double e = fma(-t, 0.5 * y, 0.5);
+    y = fma(y, e, y);  // 1 / sqrt(x)
+    t = fma(t, e, t);  // sqrt(x)
+    yc = (lane == c) ? y : yc;
+    p0[c] = (lane == c) ? t : p0[c] * y;
+    if (TWO) p1[c] *= y;
+#pragma unroll
+    for (int c2 = c + 1; c2 < kCholBs; ++c2) {
+      const double l = readlane_d(p0[c], c2);  // L(k0 + c2, k0 + c)
+      p0[c2] = fma(-p0[c], l, p0[c2]);
+      if (TWO) p1[c2] = fma(-p1[c], l, p1[c2]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kCholBs; ++c) {
+    if (c <= lane && r0 < Wp) sA[r0 + (k0 + c) * ld] = p0[c];
+    if (TWO && r1 < Wp) sA[r1 + (k0 + c) * ld] = p1[c];
+  }
+  if (lane < kCholBs) dinv[k0 + lane] = yc;
+  if (bad && lane == 0) *s_bad = 1;
+}
+
 __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qrs, int pass,
                                                    double tol) {
   extern __shared__ __align__(16) double smem[];
@@ -131,47 +176,13 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
   const int nb = Wp / kCholBs;
   for (int K = 0; K < nb; ++K) {
     const int k0 = K * kCholBs, k1 = k0 + kCholBs;
-    // ---- panel factorization, wave 0
+    // ---- panel factorization, wave 0 (the second row set only when the
+    // panel is taller than 64 rows)
     if (wave == 0) {
-      const int r0 = k0 + lane, r1 = k0 + 64 + lane;
-      const bool two = Wp - k0 > 64;
-      double p0[kCholBs], p1[kCholBs], g0[kCholBs];
-#pragma unroll
-      for (int c = 0; c < kCholBs; ++c) {
-        p0[c] = (c <= lane && r0 < Wp) ? sA[r0 + (k0 + c) * ld] : 0.0;
-        p1[c] = (two && r1 < Wp) ? sA[r1 + (k0 + c) * ld] : 0.0;
-        g0[c] = diag0[k0 + c];
-      }
-      bool bad = false;
-      double yc = 0.0;  // lane c: 1 / L(k0 + c, k0 + c)
-#pragma unroll
-      for (int c = 0; c < kCholBs; ++c) {
-        const double piv = readlane_d(p0[c], c);
-        const bool badc = !(piv > tol * g0[c]) || !(g0[c] > 0.0);
-        bad = bad || badc;
-        const double x = badc ? 1.0 : piv;
-        double y = __builtin_amdgcn_rsq(x);
-        double t = x * y;
-        const double e = fma(-t, 0.5 * y, 0.5);
-        y = fma(y, e, y);  // 1 / sqrt(x)
-        t = fma(t, e, t);  // sqrt(x)
-        yc = (lane == c) ? y : yc;
-        p0[c] = (lane == c) ? t : p0[c] * y;
-        p1[c] *= y;
-#pragma unroll
-        for (int c2 = c + 1; c2 < kCholBs; ++c2) {
-          const double l = readlane_d(p0[c], c2);  // L(k0 + c2, k0 + c)
-          p0[c2] = fma(-p0[c], l, p0[c2]);
-          p1[c2] = fma(-p1[c], l, p1[c2]);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < kCholBs; ++c) {
-        if (c <= lane && r0 < Wp) sA[r0 + (k0 + c) * ld] = p0[c];
-        if (two && r1 < Wp) sA[r1 + (k0 + c) * ld] = p1[c];
-      }
-      if (lane < kCholBs) dinv[k0 + lane] = yc;
-      if (bad && lane == 0) s_bad = 1;
+      if (Wp - k0 > 64)
+        chol_panel<true>(sA, ld, dinv, diag0, &s_bad, k0, Wp, lane, tol);
+      else
+        chol_panel<false>(sA, ld, dinv, diag0, &s_bad, k0, Wp, lane, tol);
     }
     __syncthreads();
     if (s_bad) {
