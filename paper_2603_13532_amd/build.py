@@ -21,6 +21,11 @@ HIPCC_FLAGS = [
     "-shared",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: the contraction loops skip empty
+    # 16 x 16 blocks with wave-uniform branches, and with AGPR accumulators
+    # the register allocator copies every accumulator out of and back into
+    # the AGPRs around each conditional MFMA, after waiting for it to finish
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-result",
 ]
 

@@ -232,22 +232,19 @@ struct SegCursor {
     return true;
   }
   __device__ __forceinline__ bool advance() { return skip(step); }
-  __device__ __forceinline__ void fetch(in_t (&ra)[PER], in_t (&rb)[PER]) const {
-    const int k0 = kt * BK;
+  // Loads of the current K-tile; with live == false every offset is out of
+  // range, so the same number of loads issue and all of them read zero.
+  // One straight-line sequence for full and ragged tiles alike: a branch
+  // between the two makes the compiler wait for every load in flight before
+  // the ragged variant overwrites the registers.
+  __device__ __forceinline__ void fetch(in_t (&ra)[PER], in_t (&rb)[PER], bool live) const {
+    const int left = live ? K - kt * BK : 0;  // depths of this tile inside K
     const rsrc_t rA = make_rsrc(A + (int64_t)kt * a_step);
     const rsrc_t rB = make_rsrc(B + (int64_t)kt * b_step);
-    if (k0 + BK <= K) {  // full K-tile: offsets as precomputed
 #pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        ra[j] = bload<in_t>(rA, offA[j]);
-        rb[j] = bload<in_t>(rB, offB[j]);
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        ra[j] = bload<in_t>(rA, k0 + kA[j] < K ? offA[j] : kOob);
-        rb[j] = bload<in_t>(rB, k0 + kB[j] < K ? offB[j] : kOob);
-      }
+    for (int j = 0; j < PER; ++j) {
+      ra[j] = bload<in_t>(rA, kA[j] < left ? offA[j] : kOob);
+      rb[j] = bload<in_t>(rB, kB[j] < left ? offB[j] : kOob);
     }
   }
 };
@@ -262,8 +259,9 @@ template <> struct Depth<P_FP32> { static constexpr int value = 8; };
 // producing kernel, about a microsecond) is hidden by depth rather than by
 // occupancy: D K-tiles are fetched ahead into registers, and each iteration
 // stages the next one into the idle half of the double-buffered LDS while
-// the MFMAs consume the other half.  `Cur` supplies fetch(ra, rb) for its
-// current K-tile, advance() to its next one, and the operand orientations.
+// the MFMAs consume the other half.  `Cur` supplies fetch(ra, rb, live) for
+// its current K-tile (zeros when not live), advance() to its next one, and
+// the operand orientations.
 template <int P, int D, class Cur>
 __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type (&s)[2],
                                       typename PT<P>::acc_t (&acc)[2][2], int t, int lane, int wm,
@@ -273,11 +271,22 @@ __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type
   const StageMap<P> map(t);
   in_t ra[D][PER], rb[D][PER], al[D];
   bool ax[D], bx[D];
-  int inflight = 0;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
+    al[d] = (in_t)0;
+    ax[d] = bx[d] = false;
+  }
+  int inflight = 0;
+  // Every slot issues its loads and is staged whether or not it holds a
+  // K-tile (a dead slot stages zeros into the buffer nobody reads next).
+  // With a conditional stage the compiler sinks each fetch down to its only
+  // use, D - 1 barriers later, and the ring degenerates into one load, one
+  // wait per K-tile; unconditional use keeps the fetches where they are and
+  // the wait before staging leaves the D - 1 younger slots in flight.
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    cur.fetch(ra[d], rb[d], have);
     if (have) {
-      cur.fetch(ra[d], rb[d]);
       ax[d] = cur.a_xc;
       bx[d] = cur.b_xc;
       al[d] = cur.alpha;
@@ -293,8 +302,8 @@ __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       // s[buf] holds slot d's tile; its registers take the next fetch
+      cur.fetch(ra[d], rb[d], have);
       if (have) {
-        cur.fetch(ra[d], rb[d]);
         ax[d] = cur.a_xc;
         bx[d] = cur.b_xc;
         al[d] = cur.alpha;
@@ -304,7 +313,7 @@ __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type
       mma_tile<P>(s[buf], acc, lane, wm, wn, mv, nv);
       --inflight;
       const int nx = (d + 1) % D;
-      if (inflight > 0) stage<P>(s[buf ^ 1], map, ax[nx], bx[nx], t, ra[nx], rb[nx], al[nx]);
+      stage<P>(s[buf ^ 1], map, ax[nx], bx[nx], t, ra[nx], rb[nx], al[nx]);
       __syncthreads();
       buf ^= 1;
       if (inflight == 0) return;
@@ -344,7 +353,9 @@ __global__ __launch_bounds__(NTHREADS) void gemm_kernel(const GemmDesc* __restri
   const int64_t b = local / D.tiles_n;
   const int M = D.M, N = D.N;
   const int m0 = tm * TILE, n0 = tn * TILE;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w & 1, wn = w >> 1;
+  // the wave index goes through readfirstlane so that the compiler sees it as
+  // uniform: branches on it stay scalar and the accumulators stay in place
+  const int t = threadIdx.x, lane = t & 63, w = uni(t >> 6), wm = w & 1, wn = w >> 1;
 
   acc_t acc[2][2];
   acc_zero<P>(acc);
@@ -364,7 +375,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_kernel(const GemmDesc* __restri
     cur.load();
     have = cur.skip(split);
   }
-  kloop<P, Depth<P>::value>(cur, have, s, acc, t, lane, wm, wn, M - m0, N - n0);
+  if (have) kloop<P, Depth<P>::value>(cur, have, s, acc, t, lane, wm, wn, M - m0, N - n0);
 
   const int64_t off = b * D.strideC;
   if (splits == 1) {
@@ -416,9 +427,10 @@ struct KrpCursor {
     if constexpr (LDS_P) return sP[soff[k] + x * rk[k] + dg];
     else return Pk[k][dg + (int64_t)(n0 + x) * rk[k]];
   }
-  __device__ __forceinline__ void fetch(in_t (&ra)[PER], in_t (&rb)[PER]) const {
+  __device__ __forceinline__ void fetch(in_t (&ra)[PER], in_t (&rb)[PER], bool live) const {
     constexpr int64_t es = sizeof(in_t);
     const rsrc_t rG = make_rsrc(G);
+    const int64_t Kc = live ? this->Kc : 0;
     if constexpr (P != P_FP64 && P != P_FP32) {
       const int x = t & (TILE - 1);
       const int a = m0 + x, tt = n0 + x;
@@ -512,7 +524,9 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
   const int tn = (int)(local / D.tiles_m);
   const int order = D.order, n = D.mode, m = D.m;
   const int m0 = tm * TILE, n0 = tn * TILE;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w & 1, wn = w >> 1;
+  // the wave index goes through readfirstlane so that the compiler sees it as
+  // uniform: branches on it stay scalar and the accumulators stay in place
+  const int t = threadIdx.x, lane = t & 63, w = uni(t >> 6), wm = w & 1, wn = w >> 1;
   const in_t* __restrict__ G = (const in_t*)D.G;
   const in_t alpha = (in_t)D.alpha;
   void* part_base = D.part;
@@ -624,7 +638,9 @@ __global__ __launch_bounds__(NTHREADS) void krp_adj_kernel(const KrpAdjDesc* __r
   const int order = D.order, n = D.mode, m = D.m;
   const int64_t Nc = D.Nc;
   const int64_t m0 = (int64_t)tm * TILE, n0 = tn * TILE;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w & 1, wn = w >> 1;
+  // the wave index goes through readfirstlane so that the compiler sees it as
+  // uniform: branches on it stay scalar and the accumulators stay in place
+  const int t = threadIdx.x, lane = t & 63, w = uni(t >> 6), wm = w & 1, wn = w >> 1;
   const in_t* __restrict__ Vb = (const in_t*)D.Vbar;
   const in_t alpha = (in_t)D.alpha;
   int64_t st[kMaxOrder];
