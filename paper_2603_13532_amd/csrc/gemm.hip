@@ -262,10 +262,15 @@ template <> struct Depth<P_FP32> { static constexpr int value = 8; };
 // the MFMAs consume the other half.  `Cur` supplies fetch(ra, rb, live) for
 // its current K-tile (zeros when not live), advance() to its next one, and
 // the operand orientations.
-template <int P, int D, class Cur>
+//
+// MMA = false is the copy run by a wave whose 32 x 32 quadrant lies wholly
+// outside the output tile: it fetches and stages its share and meets every
+// barrier, but issues no MFMAs (the choice is made once, outside the loop,
+// so the loop body stays one basic block).
+template <int P, int D, bool MMA, class Cur>
 __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type (&s)[2],
                                       typename PT<P>::acc_t (&acc)[2][2], int t, int lane, int wm,
-                                      int wn, int mv, int nv) {
+                                      int wn) {
   typedef typename PT<P>::in_t in_t;
   constexpr int PER = Stage<P>::PER_THREAD;
   const StageMap<P> map(t);
@@ -301,19 +306,24 @@ __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type
   while (true) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      // s[buf] holds slot d's tile; its registers take the next fetch
+      // s[buf] holds slot d's tile; its registers take the next fetch.  The
+      // fetch, the MFMAs and the staging of the next slot form one basic
+      // block (the cursor steps after them), so their instructions can be
+      // interleaved.
       cur.fetch(ra[d], rb[d], have);
+      const bool fa = cur.a_xc, fb = cur.b_xc;
+      const in_t fal = cur.alpha;
+      if constexpr (MMA) mma_tile<P>(s[buf], acc, lane, wm, wn);
+      const int nx = (d + 1) % D;
+      stage<P>(s[buf ^ 1], map, ax[nx], bx[nx], t, ra[nx], rb[nx], al[nx]);
+      --inflight;
       if (have) {
-        ax[d] = cur.a_xc;
-        bx[d] = cur.b_xc;
-        al[d] = cur.alpha;
+        ax[d] = fa;
+        bx[d] = fb;
+        al[d] = fal;
         ++inflight;
         have = cur.advance();
       }
-      mma_tile<P>(s[buf], acc, lane, wm, wn, mv, nv);
-      --inflight;
-      const int nx = (d + 1) % D;
-      stage<P>(s[buf ^ 1], map, ax[nx], bx[nx], t, ra[nx], rb[nx], al[nx]);
       __syncthreads();
       buf ^= 1;
       if (inflight == 0) return;
@@ -375,7 +385,12 @@ __global__ __launch_bounds__(NTHREADS) void gemm_kernel(const GemmDesc* __restri
     cur.load();
     have = cur.skip(split);
   }
-  if (have) kloop<P, Depth<P>::value>(cur, have, s, acc, t, lane, wm, wn, M - m0, N - n0);
+  if (have) {
+    if (wm * 32 < M - m0 && wn * 32 < N - n0)
+      kloop<P, Depth<P>::value, true>(cur, have, s, acc, t, lane, wm, wn);
+    else
+      kloop<P, Depth<P>::value, false>(cur, have, s, acc, t, lane, wm, wn);
+  }
 
   const int64_t off = b * D.strideC;
   if (splits == 1) {
@@ -598,12 +613,12 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
     KrpCursor<P, true> cur;
     TSK_KRP_CURSOR(cur)
     cur.sP = (typename KrpCursor<P, true>::lds_in_t*)sP;
-    kloop<P, Depth<P>::value>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn, rn - m0, m - n0);
+    kloop<P, Depth<P>::value, true>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn);
   } else {
     KrpCursor<P, false> cur;
     TSK_KRP_CURSOR(cur)
     cur.sP = nullptr;
-    kloop<P, Depth<P>::value>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn, rn - m0, m - n0);
+    kloop<P, Depth<P>::value, true>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn);
   }
 #undef TSK_KRP_CURSOR
   typedef typename std::conditional<P == P_FP64, double, float>::type vt;
@@ -713,7 +728,7 @@ __global__ __launch_bounds__(NTHREADS) void krp_adj_kernel(const KrpAdjDesc* __r
   while (kt < nkt) {
     const int kn = kt + 1;
     if (kn < nkt) TSK_ADJ_FETCH(kn);
-    mma_tile<P>(s[buf], acc, lane, wm, wn, (int)(rn - m0), (int)min<int64_t>(Nc - n0, TILE));
+    mma_tile<P>(s[buf], acc, lane, wm, wn);
     if (kn < nkt) stage<P>(s[buf ^ 1], smap, true, false, t, ra, rb, (in_t)1);
     __syncthreads();
     buf ^= 1;

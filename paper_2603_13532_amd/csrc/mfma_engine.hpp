@@ -118,30 +118,37 @@ __device__ __forceinline__ void lds_put(typename Lds<P>::type& s, int which, int
 }
 
 // ------------------------------------------------------------ compute step
-// mv, nv: rows and columns of the tile inside the output; 16 x 16 blocks
-// wholly outside it are skipped (a wave-uniform test), which matters for the
-// small ranks and sketch widths that leave most of a 64 x 64 tile empty.
+// One K-tile of the wave's 32 x 32 quadrant, straight-line code with no
+// test of the tile edge: rows and columns past it multiply the zeros that
+// staging put there.  A branch here would split the K-loop iteration into
+// basic blocks that the scheduler cannot interleave, and one wave issues in
+// order, so the loads, staging and address arithmetic of the next tile could
+// not hide behind these MFMAs.
 template <int P>
 __device__ __forceinline__ void mma_tile(const typename Lds<P>::type& s,
                                          typename PT<P>::acc_t (&acc)[2][2], int lane, int wm,
-                                         int wn, int mv, int nv) {
+                                         int wn) {
   const int r = lane & 15, kq = lane >> 4;
-  const bool oi0 = wm * 32 < mv, oi1 = wm * 32 + 16 < mv;
-  const bool oj0 = wn * 32 < nv, oj1 = wn * 32 + 16 < nv;
-  if (!oi0 || !oj0) return;  // the wave's whole quadrant is outside
   if constexpr (P == P_FP64 || P == P_FP32) {
-    constexpr int BK = PT<P>::BK;
+    // Fragments of the whole K-tile are read up front; every 16 x 16 block
+    // is computed (MFMAs under per-block branches also make the compiler
+    // copy the accumulators between register sets after each one).
+    constexpr int NS = PT<P>::BK / 4;
+    typename PT<P>::in_t a[NS][2], b[NS][2];
 #pragma unroll
-    for (int ks = 0; ks < BK; ks += 4) {
-      auto a0 = s.a[ks + kq][wm * 32 + r];
-      auto a1 = s.a[ks + kq][wm * 32 + 16 + r];
-      auto b0 = s.b[ks + kq][wn * 32 + r];
-      auto b1 = s.b[ks + kq][wn * 32 + 16 + r];
-      acc[0][0] = mma(a0, b0, acc[0][0]);
-      if (oj1) acc[0][1] = mma(a0, b1, acc[0][1]);
-      if (oi1) acc[1][0] = mma(a1, b0, acc[1][0]);
-      if (oi1 && oj1) acc[1][1] = mma(a1, b1, acc[1][1]);
+    for (int q = 0; q < NS; ++q) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a[q][i] = s.a[4 * q + kq][wm * 32 + 16 * i + r];
+        b[q][i] = s.b[4 * q + kq][wn * 32 + 16 * i + r];
+      }
     }
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mma(a[q][i], b[q][j], acc[i][j]);
   } else {
     constexpr int PARTS = PT<P>::PARTS;
     v8s a[PARTS][2], b[PARTS][2];
@@ -153,24 +160,23 @@ __device__ __forceinline__ void mma_tile(const typename Lds<P>::type& s,
         b[p][i] = *reinterpret_cast<const v8s*>(&s.b[p][wn * 32 + 16 * i + r][8 * kq]);
       }
     }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        if (!(i == 0 || oi1) || !(j == 0 || oj1)) continue;
-        // smallest cross products first so they are not absorbed early
-        if constexpr (PARTS == 3) {
-          acc[i][j] = mma_bf(a[0][i], b[2][j], acc[i][j]);
-          acc[i][j] = mma_bf(a[2][i], b[0][j], acc[i][j]);
-          acc[i][j] = mma_bf(a[1][i], b[1][j], acc[i][j]);
-        }
-        if constexpr (PARTS >= 2) {
-          acc[i][j] = mma_bf(a[0][i], b[1][j], acc[i][j]);
-          acc[i][j] = mma_bf(a[1][i], b[0][j], acc[i][j]);
-        }
-        acc[i][j] = mma_bf(a[0][i], b[0][j], acc[i][j]);
+    // smallest cross products first so they are not absorbed early
+    auto block = [&](int i, int j) {
+      if constexpr (PARTS == 3) {
+        acc[i][j] = mma_bf(a[0][i], b[2][j], acc[i][j]);
+        acc[i][j] = mma_bf(a[2][i], b[0][j], acc[i][j]);
+        acc[i][j] = mma_bf(a[1][i], b[1][j], acc[i][j]);
       }
-    }
+      if constexpr (PARTS >= 2) {
+        acc[i][j] = mma_bf(a[0][i], b[1][j], acc[i][j]);
+        acc[i][j] = mma_bf(a[1][i], b[0][j], acc[i][j]);
+      }
+      acc[i][j] = mma_bf(a[0][i], b[0][j], acc[i][j]);
+    };
+    block(0, 0);
+    block(0, 1);
+    block(1, 0);
+    block(1, 1);
   }
 }
 
