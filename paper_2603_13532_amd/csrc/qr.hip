@@ -645,6 +645,222 @@ __device__ __forceinline__ void hh_tsqr(const QrDesc& D, lds_f64* base, lds_f64*
   }
 }
 
+// Register-resident Householder QR of one n x W panel (n <= NW * NR,
+// W <= kWideCols) with NW waves: lane c holds column c, wave v holds rows
+// v, v + NW, ...; the arithmetic is that of hh_regs (and hh_core).  With
+// more waves each wave walks fewer rows per reflector and the waves sharing
+// a SIMD hide each other's latencies.  Per reflector j every lane needs the
+// entries of column j in its wave's rows: lane j writes them to a per-wave
+// LDS row and all lanes read it (LDS operations of one wave complete in
+// order; a broadcast through readlane measured no faster and spills SGPRs).
+// Every lane forms its column's partial dot product, and one barrier
+// exchanges the NW partials; lane j's partial is the squared norm below the
+// diagonal, so the norm needs no separate reduction.  The update is a
+// multiply and an FMA per element.  Registers shift by one row block every
+// NW reflectors (row j sits in register 0 of wave j % NW); rows leaving the
+// window are parked in LDS, which is all the LDS the panel needs, so tall
+// panels do not have to fit it whole.
+constexpr int kWideWaves = 8;
+constexpr int kWideCols = 64;
+constexpr int kWideRows = 384;  // 48 rows per wave: 225 VGPRs; 64 per wave spills
+constexpr int kWidePark = kWideCols + kWideWaves;  // parked rows: w rounded up to NW
+constexpr int kWideLdp = kWideCols + 1;
+
+// sum over the wave's rows below the reflector (register 0 only when fb) of
+// v_r a_r, v = column j read from the wave's broadcast row in batches of
+// eight (one batch in flight: the reads of a batch overlap, and the window
+// does not spill)
+template <int NR>
+__device__ __forceinline__ double hh_wide_dot(const lds_f64* cb, const double (&a)[NR], bool fb) {
+  static_assert(NR % 8 == 0, "rows per wave come in batches of eight");
+  double d = 0.0;
+#pragma unroll
+  for (int r0 = 0; r0 < NR; r0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = cb[r0 + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) d = fma(v[k], (r0 + k > 0 || fb) ? a[r0 + k] : 0.0, d);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return d;
+}
+// a_r = a_r m + coef v_r over the same rows (m = 1 and coef = 0 leave a
+// column unchanged; a column is scaled by m exactly, not through v = a)
+template <int NR>
+__device__ __forceinline__ void hh_wide_update(const lds_f64* cb, double (&a)[NR], bool fb,
+                                               double m, double coef) {
+  const double m0 = fb ? m : 1.0, c0 = fb ? coef : 0.0;
+#pragma unroll
+  for (int r0 = 0; r0 < NR; r0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = cb[r0 + k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const bool z = r0 + k == 0;
+      a[r0 + k] = fma(v[k], z ? c0 : coef, a[r0 + k] * (z ? m0 : m));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int NW, int NR>
+__device__ __forceinline__ void hh_wide(const QrDesc& D, lds_f64* park, lds_f64* colb,
+                                        lds_f64* part, lds_f64* tau, lds_f64* sgn, int n, int W,
+                                        int w) {
+  const int tid = threadIdx.x, lane = tid & 63, c = lane;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const double* Y = D.Y;
+  const int64_t ldy = n;
+  lds_f64* cb = colb + wave * NR;  // this wave's broadcast row
+  double a[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = wave + NW * r;
+    a[r] = (i < n && c < W) ? Y[i + (int64_t)c * ldy] : 0.0;
+  }
+  const int nq = (w + NW - 1) / NW;
+  int step = 0;  // parity of the exchange buffer
+  for (int q = 0; q < nq; ++q) {
+    for (int jw = 0; jw < NW; ++jw) {
+      const int j = NW * q + jw;
+      if (j >= w) break;
+      const bool fb = wave > jw;  // register 0 holds a row below j
+      lds_f64* pt = part + (NW + 1) * 64 * (step & 1);
+      ++step;
+      if (lane == j) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cb[r] = a[r];
+      }
+      __builtin_amdgcn_wave_barrier();
+      const double d = hh_wide_dot<NR>(cb, a, fb);
+      pt[wave * 64 + lane] = d;
+      if (wave == jw) pt[NW * 64 + lane] = a[0];  // row j
+      __syncthreads();
+      double S = 0.0, sigma = 0.0;
+#pragma unroll
+      for (int v = 0; v < NW; ++v) {
+        S += pt[v * 64 + lane];
+        sigma += pt[v * 64 + j];
+      }
+      const double arow = pt[NW * 64 + lane], alpha = pt[NW * 64 + j];
+      double t = 0.0, scal = 1.0, beta = alpha;
+      if (sigma > 0.0) {
+        const double mu = sqrt(alpha * alpha + sigma);
+        beta = (alpha <= 0.0) ? mu : -mu;
+        t = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      const double f = t * (arow + scal * S), fs = f * scal;
+      // rows below j: a -= fs v right of column j, a *= scal in column j
+      hh_wide_update<NR>(cb, a, fb, (c == j) ? scal : 1.0, (c > j) ? -fs : 0.0);
+      if (wave == jw) a[0] = (c > j) ? arow - f : ((c == j) ? beta : a[0]);
+      if (tid == 0) tau[j] = t;
+      __builtin_amdgcn_wave_barrier();
+    }
+    // park row NW q + wave and shift the window down by one row block
+    park[(NW * q + wave) * kWideLdp + c] = a[0];
+#pragma unroll
+    for (int r = 0; r < NR - 1; ++r) a[r] = a[r + 1];
+    a[NR - 1] = 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < w; i += NW * 64)
+    sgn[i] = (park[i * kWideLdp + i] < 0.0) ? -1.0 : 1.0;  // R with a non-negative diagonal
+  __syncthreads();
+  if (D.R != nullptr)
+    for (int e = tid; e < w * W; e += NW * 64) {
+      const int i = e % w, k = e / w;
+      D.R[i + (int64_t)k * w] = (i <= k) ? sgn[i] * park[i * kWideLdp + k] : 0.0;
+    }
+  // Q = H_0 ... H_{w-1} [I_w; 0], formed backwards: the window goes back to
+  // block nq - 1 and keeps only reflector entries (columns below w and left
+  // of the diagonal; rows in registers are all below the diagonal).
+#pragma unroll
+  for (int r = NR - 1; r > 0; --r) a[r] = (c < w) ? a[r - 1] : 0.0;
+  {
+    const int i = NW * (nq - 1) + wave;
+    a[0] = (i < n && c < w && c < i) ? park[i * kWideLdp + c] : 0.0;
+  }
+  for (int q = nq - 1; q >= 0; --q) {
+    for (int jw = NW - 1; jw >= 0; --jw) {
+      const int j = NW * q + jw;
+      if (j >= w) continue;
+      const bool fb = wave > jw;
+      lds_f64* pt = part + (NW + 1) * 64 * (step & 1);
+      ++step;
+      const double t = tau[j];
+      if (lane == j) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cb[r] = a[r];
+      }
+      __builtin_amdgcn_wave_barrier();
+      const double d = hh_wide_dot<NR>(cb, a, fb);
+      pt[wave * 64 + lane] = d;
+      if (wave == jw) pt[NW * 64 + lane] = a[0];
+      __syncthreads();
+      double S = 0.0;
+#pragma unroll
+      for (int v = 0; v < NW; ++v) S += pt[v * 64 + lane];
+      const double arow = pt[NW * 64 + lane];
+      const double f = t * (arow + S);
+      // rows below j: a -= f v right of column j, a *= -t in column j
+      hh_wide_update<NR>(cb, a, fb, (c == j) ? -t : 1.0, (c > j) ? -f : 0.0);
+      if (wave == jw) a[0] = (c > j) ? arow - f : ((c == j) ? 1.0 - t : a[0]);
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (q > 0) {
+#pragma unroll
+      for (int r = NR - 1; r > 0; --r) a[r] = a[r - 1];
+      const int i = NW * (q - 1) + wave;
+      a[0] = (i < n && c < w && c < i) ? park[i * kWideLdp + c] : 0.0;
+    }
+  }
+  double* Q = D.Q;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = wave + NW * r;
+    if (i < n && c < w) Q[i + (int64_t)c * n] = sgn[c] * a[r];
+  }
+}
+
+// Panels with W <= kWideCols and n <= kWideRows go here (one workgroup of
+// kWideWaves waves each); householder_kernel takes the others.
+__global__ __launch_bounds__(kWideWaves * 64) void householder_wide_kernel(
+    const QrDesc* __restrict__ qrs, int force, unsigned long long* counter) {
+  const QrDesc& D = qrs[blockIdx.x];
+  const bool broke = *D.flag != 0;
+  if (!force && !broke && !D.hh_direct) return;
+  const int64_t n = D.n, W = D.W;
+  if (!(W <= kWideCols && n <= kWideRows)) return;
+  const int64_t w = n < W ? n : W;
+  if (threadIdx.x == 0 && counter != nullptr) {
+    atomicAdd(counter, 1ull);                              // QRs done by Householder
+    if (broke && D.report_only) atomicAdd(counter + 1, 1ull);  // reported breakdowns
+  }
+  constexpr int NW = kWideWaves;
+  __shared__ double park_s[kWidePark * kWideLdp];
+  __shared__ double colb_s[NW * (kWideRows / NW)];
+  __shared__ double part_s[2 * (NW + 1) * 64];
+  __shared__ double tau_s[kWideCols], sgn_s[kWideCols];
+  lds_f64* park = (lds_f64*)park_s;
+  lds_f64* colb = (lds_f64*)colb_s;
+  lds_f64* part = (lds_f64*)part_s;
+  lds_f64* tau = (lds_f64*)tau_s;
+  lds_f64* sgn = (lds_f64*)sgn_s;
+  const int ni = (int)n, Wi = (int)W, wi = (int)w;
+  if (n <= 8 * NW)
+    hh_wide<NW, 8>(D, park, colb, part, tau, sgn, ni, Wi, wi);
+  else if (n <= 16 * NW)
+    hh_wide<NW, 16>(D, park, colb, part, tau, sgn, ni, Wi, wi);
+  else if (n <= 32 * NW)
+    hh_wide<NW, 32>(D, park, colb, part, tau, sgn, ni, Wi, wi);
+  else
+    hh_wide<NW, 48>(D, park, colb, part, tau, sgn, ni, Wi, wi);
+}
+static_assert(kWideRows <= 48 * kWideWaves, "register window of the wide Householder path");
+
 __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restrict__ qrs,
                                                           int force,
                                                           unsigned long long* counter,
@@ -654,6 +870,7 @@ __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restri
   const bool broke = *D.flag != 0;
   if (!force && !broke && !D.hh_direct) return;
   const int64_t n = D.n, W = D.W;
+  if (W <= kWideCols && n <= kWideRows) return;  // householder_wide_kernel's panel
   const int64_t w = n < W ? n : W;
   const int tid = threadIdx.x;
   if (tid == 0 && counter != nullptr) {
@@ -756,6 +973,10 @@ hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* f
     if (e != hipSuccess) return e;
     attr_set = true;
   }
+  householder_wide_kernel<<<dim3((unsigned)count), dim3(kWideWaves * 64), 0, stream>>>(
+      qr, force, (unsigned long long*)fallback_counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   householder_kernel<<<dim3((unsigned)count), dim3(256), (size_t)elems * sizeof(double), stream>>>(
       qr, force, (unsigned long long*)fallback_counter, elems);
   return hipGetLastError();

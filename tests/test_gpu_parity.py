@@ -175,11 +175,17 @@ def test_householder_policy_matches_cholqr2(tsk):
     ((700, 60, 50), [[12, 9, 8], [10, 11, 7], [9, 8, 10]], 40),
     # mode 0: 200 x 100 panel (W > 96 and not tall) -> panel in global memory
     ((200, 150, 120), [[40, 30, 35], [38, 36, 30], [30, 34, 33]], 100),
+    # every mode <= 384 x 64 -> eight-wave register panel (384 x 56, 64 x 56,
+    # 60 x 56), full rank and rank-deficient; large coefficients make the
+    # column norms large, where scaling a column through a (scal - 1) multiple
+    # of itself would lose digits
+    ((384, 64, 60), [[30, 30, 30], [20, 20, 20], [10, 10, 10]], 56),
+    ((384, 64, 60), [[12, 9, 8], [10, 11, 7], [9, 8, 10]], 56),
 ])
 def test_householder_panel_paths(tsk, dims, ranks, m):
-    """Householder with the panel in LDS, in two stacked halves (TSQR) and
-    in global memory, each against the oracle."""
-    ts = synth.random_sum(13, dims, ranks)
+    """Householder with the panel in registers (eight waves), in LDS, in two
+    stacked halves (TSQR) and in global memory, each against the oracle."""
+    ts = synth.random_sum(13, dims, ranks, coeffs=[300.0, -150.0, 80.0])
     check_recompress(tsk, ts, "krp", [m], 5, qr_policy="householder")
     if m <= 96:
         a_q, a_h = run(tsk, ts, "krp", [m], 5)
