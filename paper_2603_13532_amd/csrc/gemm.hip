@@ -518,6 +518,103 @@ struct KrpCursor {
   }
 };
 
+// The same K-tiles for a sketch whose other modes number NO (2 or 3: cores
+// of order 3 or 4) with their P slices in LDS.  The other modes are listed
+// compactly (radix, core stride, LDS column base), the thread's mixed-radix
+// digits advance from tile to tile by adding the digits of the tile step
+// with one carry each (no division after setup), and the Khatri-Rao entry
+// is NO LDS reads with no branch, so the whole K-loop iteration stays one
+// basic block.  Digits past the end of K wrap and stay inside their ranges;
+// those depths read zeros.
+template <int P, int NO>
+struct KrpFixed {
+  typedef typename PT<P>::in_t in_t;
+  typedef typename std::conditional<P == P_FP64, lds_cf64, lds_cf32>::type lds_in_t;
+  static constexpr int BK = PT<P>::BK;
+  static constexpr int PER = Stage<P>::PER_THREAD;
+  static constexpr bool FPK = (P == P_FP64 || P == P_FP32);  // one depth, PER rows per thread
+  static constexpr int NX = FPK ? PER : 1;                   // rows (and columns) per thread
+  const in_t* G;
+  in_t alpha;
+  lds_in_t* sP;
+  int rk[NO], inc[NO];  // radices of the other modes and the digits of one tile step
+  int st[NO];           // core strides of the other modes (in elements)
+  int pb[NX][NO];       // LDS index of P_k[.][n0 + x] without the digit
+  uint32_t rowoff[NX];  // byte offset of core row m0 + x (kOob outside)
+  bool tok[NX];         // column n0 + x inside the sketch width
+  int dg[NO];           // digits of the thread's first depth in the current tile
+  int64_t c, Kc, kt, nkt, step;
+  bool a_xc = false, b_xc = false;
+
+  // digits of v in the radices rk (the part beyond their product dropped)
+  __device__ __forceinline__ void digits(int64_t v, int (&d)[NO]) const {
+    uint64_t rem = (uint64_t)v;
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      const uint64_t q = rem / (uint64_t)rk[j];
+      d[j] = (int)(rem - q * (uint64_t)rk[j]);
+      rem = q;
+    }
+  }
+  __device__ __forceinline__ bool advance() {
+    kt += step;
+    c += (int64_t)BK * step;
+    int carry = 0;
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      const int d = dg[j] + inc[j] + carry;
+      carry = d >= rk[j] ? 1 : 0;
+      dg[j] = carry ? d - rk[j] : d;
+    }
+    return kt < nkt;
+  }
+  __device__ __forceinline__ void fetch(in_t (&ra)[PER], in_t (&rb)[PER], bool live) const {
+    constexpr uint32_t es = sizeof(in_t);
+    const rsrc_t rG = make_rsrc(G);
+    if constexpr (FPK) {
+      const bool valid = live && c < Kc;
+      uint32_t offg = 0;
+#pragma unroll
+      for (int j = 0; j < NO; ++j) offg += (uint32_t)(dg[j] * st[j]) * es;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        ra[i] = bload<in_t>(rG, (valid && rowoff[i] != kOob) ? rowoff[i] + offg : kOob);
+        in_t prod = sP[pb[i][0] + dg[0]];
+#pragma unroll
+        for (int j = 1; j < NO; ++j) prod *= sP[pb[i][j] + dg[j]];
+        rb[i] = (valid && tok[i]) ? prod : (in_t)0;
+      }
+    } else {
+      int d[NO];
+      uint32_t offg = 0;
+#pragma unroll
+      for (int j = 0; j < NO; ++j) {
+        d[j] = dg[j];
+        offg += (uint32_t)(d[j] * st[j]) * es;
+      }
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const bool valid = live && c + i < Kc;
+        ra[i] = bload<in_t>(rG, (valid && rowoff[0] != kOob) ? rowoff[0] + offg : kOob);
+        in_t prod = sP[pb[0][0] + d[0]];
+#pragma unroll
+        for (int j = 1; j < NO; ++j) prod *= sP[pb[0][j] + d[j]];
+        rb[i] = (valid && tok[0]) ? prod : (in_t)0;
+        // next depth: add one to the digits, branch-free
+        bool carry = true;
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+          const int nd = d[j] + (carry ? 1 : 0);
+          const bool wrap = nd == rk[j];
+          offg += carry ? (wrap ? (uint32_t)((1 - rk[j]) * st[j]) * es : (uint32_t)st[j] * es) : 0u;
+          d[j] = wrap ? 0 : nd;
+          carry = carry && wrap;
+        }
+      }
+    }
+  }
+};
+
 // KRP core sketch: rows a of G_(n) against Khatri-Rao columns t, K = c over
 // the other modes, first remaining mode fastest (unfolding index equation).
 template <int P>
@@ -609,7 +706,59 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
   CUR.kt = split;                    \
   CUR.nkt = (Kc + BK - 1) / BK;      \
   CUR.step = splits;
-  if (lds_p) {
+  // NO other modes listed compactly: radix, core stride and LDS base
+  auto fixed = [&](auto& cur, auto no) {
+    constexpr int NO = decltype(no)::value;
+    typedef typename std::remove_reference<decltype(cur)>::type Cur;
+    cur.G = G;
+    cur.alpha = alpha;
+    cur.sP = (typename Cur::lds_in_t*)sP;
+    // the j-th other mode is j below n, j + 1 from n on; its entries are
+    // picked by selects over statically indexed arrays (a runtime index into
+    // a register array would put the cursor in scratch memory)
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      const int kj = j < n ? j : j + 1;
+      int r = 1, so = 0;
+      int64_t sk = 1;
+#pragma unroll
+      for (int k = 0; k < kMaxOrder; ++k) {
+        if (k == kj) {
+          r = rk[k];
+          sk = st[k];
+          so = soff[k];
+        }
+      }
+      cur.rk[j] = r;
+      cur.st[j] = (int)sk;
+#pragma unroll
+      for (int i = 0; i < Cur::NX; ++i) {
+        const int x = Cur::FPK ? t / BK + (NTHREADS / BK) * i : (t & (TILE - 1));
+        cur.pb[i][j] = so + x * r;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < Cur::NX; ++i) {
+      const int x = Cur::FPK ? t / BK + (NTHREADS / BK) * i : (t & (TILE - 1));
+      cur.rowoff[i] = m0 + x < rn ? (uint32_t)((int64_t)(m0 + x) * stn * (int64_t)sizeof(in_t)) : kOob;
+      cur.tok[i] = n0 + x < m;
+    }
+    cur.Kc = Kc;
+    cur.kt = split;
+    cur.nkt = (Kc + BK - 1) / BK;
+    cur.step = splits;
+    cur.c = (int64_t)split * BK + (Cur::FPK ? t % BK : 8 * (t >> 6));
+    cur.digits(cur.c, cur.dg);
+    cur.digits((int64_t)BK * splits, cur.inc);
+    kloop<P, Depth<P>::value, true>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn);
+  };
+  if (lds_p && order == 3) {
+    KrpFixed<P, 2> cur;
+    fixed(cur, std::integral_constant<int, 2>());
+  } else if (lds_p && order == 4) {
+    KrpFixed<P, 3> cur;
+    fixed(cur, std::integral_constant<int, 3>());
+  } else if (lds_p) {
     KrpCursor<P, true> cur;
     TSK_KRP_CURSOR(cur)
     cur.sP = (typename KrpCursor<P, true>::lds_in_t*)sP;
