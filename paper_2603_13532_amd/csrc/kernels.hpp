@@ -68,7 +68,13 @@ hipError_t launch_copy(const CopyJob* jobs, int count, hipStream_t stream);
 hipError_t launch_chol(const QrDesc* qr, int count, int pass, double tol, int wmax,
                        hipStream_t stream);
 // max_elems: largest (n+1)*W + 2W among the descriptors (sizes the in-LDS panel).
+// Panels the eight-wave register kernel takes (the others go to the
+// general Householder kernel); `kernels` says which of the two to launch
+// (bit 0: register kernel, bit 1: general kernel), from the panel shapes.
+constexpr int kHhWideCols = 64;
+constexpr int kHhWideRows = 384;
+__host__ __device__ inline bool hh_wide_panel(int64_t n, int64_t W) { return W <= kHhWideCols && n <= kHhWideRows; }
 hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* fallback_counter,
-                              int64_t max_elems, hipStream_t stream);
+                              int64_t max_elems, int kernels, hipStream_t stream);
 
 }  // namespace tsk

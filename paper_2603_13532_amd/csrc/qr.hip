@@ -661,8 +661,8 @@ __device__ __forceinline__ void hh_tsqr(const QrDesc& D, lds_f64* base, lds_f64*
 // window are parked in LDS, which is all the LDS the panel needs, so tall
 // panels do not have to fit it whole.
 constexpr int kWideWaves = 8;
-constexpr int kWideCols = 64;
-constexpr int kWideRows = 384;  // 48 rows per wave: 225 VGPRs; 64 per wave spills
+constexpr int kWideCols = kHhWideCols;
+constexpr int kWideRows = kHhWideRows;  // 48 rows per wave: 225 VGPRs; 64 per wave spills
 constexpr int kWidePark = kWideCols + kWideWaves;  // parked rows: w rounded up to NW
 constexpr int kWideLdp = kWideCols + 1;
 
@@ -833,7 +833,7 @@ __global__ __launch_bounds__(kWideWaves * 64) void householder_wide_kernel(
   const bool broke = *D.flag != 0;
   if (!force && !broke && !D.hh_direct) return;
   const int64_t n = D.n, W = D.W;
-  if (!(W <= kWideCols && n <= kWideRows)) return;
+  if (!hh_wide_panel(n, W)) return;
   const int64_t w = n < W ? n : W;
   if (threadIdx.x == 0 && counter != nullptr) {
     atomicAdd(counter, 1ull);                              // QRs done by Householder
@@ -870,7 +870,7 @@ __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restri
   const bool broke = *D.flag != 0;
   if (!force && !broke && !D.hh_direct) return;
   const int64_t n = D.n, W = D.W;
-  if (W <= kWideCols && n <= kWideRows) return;  // householder_wide_kernel's panel
+  if (hh_wide_panel(n, W)) return;  // householder_wide_kernel's panel
   const int64_t w = n < W ? n : W;
   const int tid = threadIdx.x;
   if (tid == 0 && counter != nullptr) {
@@ -960,7 +960,7 @@ hipError_t launch_chol(const QrDesc* qr, int count, int pass, double tol, int wm
 }
 
 hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* fallback_counter,
-                              int64_t max_elems, hipStream_t stream) {
+                              int64_t max_elems, int kernels, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
   // LDS for the largest panel (plus tau, signs and reduction slots), capped
   int64_t elems = max_elems < kHhLdsMax ? max_elems : kHhLdsMax;
@@ -973,13 +973,18 @@ hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* f
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  householder_wide_kernel<<<dim3((unsigned)count), dim3(kWideWaves * 64), 0, stream>>>(
-      qr, force, (unsigned long long*)fallback_counter);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  householder_kernel<<<dim3((unsigned)count), dim3(256), (size_t)elems * sizeof(double), stream>>>(
-      qr, force, (unsigned long long*)fallback_counter, elems);
-  return hipGetLastError();
+  if (kernels & 1) {
+    householder_wide_kernel<<<dim3((unsigned)count), dim3(kWideWaves * 64), 0, stream>>>(
+        qr, force, (unsigned long long*)fallback_counter);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (kernels & 2) {
+    householder_kernel<<<dim3((unsigned)count), dim3(256), (size_t)elems * sizeof(double), stream>>>(
+        qr, force, (unsigned long long*)fallback_counter, elems);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 
 }  // namespace tsk

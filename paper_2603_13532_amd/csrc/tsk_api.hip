@@ -191,6 +191,7 @@ struct Step {
   int32_t value = 0;
   double tol = 0;
   int wmax = 0;  // chol: widest Gram of the launch
+  int hh_kernels = 3;  // householder: which of the two kernels have panels
 };
 
 // Workspace arena: addresses are planned against a base that may be null
@@ -918,7 +919,15 @@ void Builder::emit(Program& prog) {
     hh.meta = qmeta;
     hh.count = (int)qr.size();
     hh.ptr = d_counter;
-    for (const QrDesc& q : qr) hh.rows = std::max<int64_t>(hh.rows, (q.n + 1) * q.W + 2 * q.W);
+    hh.hh_kernels = 0;
+    for (const QrDesc& q : qr) {
+      if (hh_wide_panel(q.n, q.W)) {
+        hh.hh_kernels |= 1;
+      } else {
+        hh.hh_kernels |= 2;
+        hh.rows = std::max<int64_t>(hh.rows, (q.n + 1) * q.W + 2 * q.W);
+      }
+    }
     prog.steps.push_back(hh);
   }
   emit_copy_stage(ST_QCOPY);
@@ -1481,7 +1490,7 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
       case S_TRSM: e = launch_trsm_rt((const TrsmJob*)(meta + st.meta), st.count, stream); break;
       case S_HOUSE:
         e = launch_householder((const QrDesc*)(meta + st.meta), st.count, st.force, (int64_t*)st.ptr,
-                               st.rows, stream);
+                               st.rows, st.hh_kernels, stream);
         break;
     }
     if (e != hipSuccess) return fail(h, TSK_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -1712,6 +1721,11 @@ void check_program(const Program& prog, Checker& ck) {
           ck.span(q.tau, 0, q.W - 1, 8, "qr tau");
           ck.span(q.flag, 0, 0, 4, "qr flag");
           if (q.R) ck.span(q.R, 0, q.w * q.W - 1, 8, "qr R");
+          if (st.kind == S_HOUSE && !(st.hh_kernels & (hh_wide_panel(q.n, q.W) ? 1 : 2))) {
+            ck.ok = false;
+            ck.err = "householder panel whose kernel is not launched";
+            return;
+          }
           if (st.kind == S_CHOL && q.gram_part && q.W <= 96 && q.W <= q.n) {
             if (q.W > st.wmax) { ck.ok = false; ck.err = "chol LDS sized below a Gram width"; return; }
             ck.span(q.gram_part, 0, (int64_t)q.gram_splits * q.W * q.W - 1, 8, "qr gram");
