@@ -953,36 +953,43 @@ __global__ __launch_bounds__(256) void reduce_kernel(const ReduceJob* __restrict
   }
 }
 
-// Split-K tile reduction: one workgroup per 64 x 64 output tile, 16
-// elements per thread, one batch of 16 independent loads per split.
-__global__ __launch_bounds__(256) void tile_reduce_kernel(const ReduceJob* __restrict__ jobs) {
-  const ReduceJob J = jobs[blockIdx.x];
-  constexpr int EPT = 64 * 64 / 256;
-  const int t = threadIdx.x;
+// Split-K tile reduction: each 64 x 64 output tile is spread over
+// kReduceChunks workgroups (more of the chip's memory pipes busy) and every
+// thread loads its elements for eight splits at a time, so one round trip
+// covers eight partials (splits past the count read zeros through
+// out-of-range buffer offsets, which leaves the sums unchanged).  Partials
+// are added in split order, so the result does not depend on timing.
+constexpr int kReduceChunks = 4;
+template <typename PartT>
+__device__ __forceinline__ void reduce_tile(const ReduceJob& J, int chunk, int t) {
+  constexpr int EPT = TILE * TILE / (NTHREADS * kReduceChunks);
+  constexpr int SB = 8;  // splits per round trip
+  constexpr uint32_t es = sizeof(PartT);
+  const rsrc_t rp = make_rsrc(J.part);
+  const int e0 = chunk * (NTHREADS * EPT) + t;
   double sum[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) sum[i] = 0.0;
-  for (int s = 0; s < J.parts; ++s) {
-    if (J.part_f64) {
-      const double* p = (const double*)J.part + (int64_t)s * J.stride_part + t;
-      double v[EPT];
+  for (int s0 = 0; s0 < J.parts; s0 += SB) {
+    PartT v[SB][EPT];
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) v[i] = p[256 * i];
+    for (int b = 0; b < SB; ++b) {
+      const bool live = s0 + b < J.parts;
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) sum[i] += v[i];
-    } else {
-      const float* p = (const float*)J.part + (int64_t)s * J.stride_part + t;
-      float v[EPT];
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) v[i] = p[256 * i];
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) sum[i] += (double)v[i];
+      for (int i = 0; i < EPT; ++i) {
+        const uint32_t off = (uint32_t)(((int64_t)(s0 + b) * J.stride_part + e0 + NTHREADS * i) * es);
+        v[b][i] = bload<PartT>(rp, live ? off : kOob);
+      }
     }
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) sum[i] += (double)v[b][i];
   }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = t + 256 * i;
-    const int r = e & 63, c = e >> 6;
+    const int e = e0 + NTHREADS * i;
+    const int r = e & (TILE - 1), c = e / TILE;
     if (r >= J.rows || c >= J.cols) continue;
     const int64_t o = r + (int64_t)c * J.ld_out;
     if (J.out_f64) {
@@ -993,6 +1000,13 @@ __global__ __launch_bounds__(256) void tile_reduce_kernel(const ReduceJob* __res
       q[o] = (float)(J.beta ? (double)q[o] + sum[i] : sum[i]);
     }
   }
+}
+__global__ __launch_bounds__(NTHREADS) void tile_reduce_kernel(const ReduceJob* __restrict__ jobs) {
+  const ReduceJob J = jobs[blockIdx.x];
+  if (J.part_f64)
+    reduce_tile<double>(J, blockIdx.y, threadIdx.x);
+  else
+    reduce_tile<float>(J, blockIdx.y, threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void copy_kernel(const CopyJob* __restrict__ jobs) {
@@ -1093,7 +1107,7 @@ hipError_t launch_reduce(const ReduceJob* jobs, int count, hipStream_t stream) {
 
 hipError_t launch_tile_reduce(const ReduceJob* jobs, int count, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
-  tile_reduce_kernel<<<dim3((unsigned)count), dim3(256), 0, stream>>>(jobs);
+  tile_reduce_kernel<<<dim3((unsigned)count, kReduceChunks), dim3(NTHREADS), 0, stream>>>(jobs);
   return hipGetLastError();
 }
 
