@@ -131,20 +131,29 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
   for (int i = W + tid; i < Wp; i += 256) diag0[i] = 1.0;
   if (tid == 0) s_bad = 0;
 
-  // ---- Gram lower triangle = partial blocks summed in split order
+  // ---- Gram lower triangle = partial blocks summed in split order.  The
+  // packed lower triangle (row-major: e = i (i + 1) / 2 + j, j <= i) is
+  // spread evenly over the threads, eight elements per thread and round,
+  // each with the loads of eight splits in flight together.
   {
     const int splits = max(1, (int)D.gram_splits);
     const int64_t WW = (int64_t)W * W;
     const double* part = D.gram_part;
-    for (int j0 = wave; j0 < W; j0 += 16) {
-      // elements u: column j0 + 4 (u >> 1), rows lane + 64 (u & 1)
-      int off[8];
+    const int npk = W * (W + 1) / 2;
+    for (int e0 = 0; e0 < npk; e0 += 8 * 256) {
+      int off[8], ii[8], jj[8];
       bool ok[8];
       double acc[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int j = j0 + 4 * (u >> 1), i = lane + 64 * (u & 1);
-        ok[u] = j < W && i < W && i >= j;
+        const int e = e0 + tid + 256 * u;
+        int i = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+        if ((i + 1) * (i + 2) / 2 <= e) ++i;
+        if (i * (i + 1) / 2 > e) --i;
+        const int j = e - i * (i + 1) / 2;
+        ok[u] = e < npk;
+        ii[u] = i;
+        jj[u] = j;
         off[u] = ok[u] ? i + j * W : 0;
         acc[u] = 0.0;
       }
@@ -165,9 +174,8 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
 #pragma unroll
       for (int u = 0; u < 8; ++u)
         if (ok[u]) {
-          const int j = j0 + 4 * (u >> 1), i = lane + 64 * (u & 1);
-          sA[i + j * ld] = acc[u];
-          if (i == j) diag0[i] = acc[u];
+          sA[ii[u] + jj[u] * ld] = acc[u];
+          if (ii[u] == jj[u]) diag0[ii[u]] = acc[u];
         }
     }
   }
@@ -259,12 +267,25 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
     }
   }
 
-  // ---- outputs: R^-1 = X^T, R = L^T (upper triangular, zeros below)
-  for (int k = wave; k < W; k += 4)
-    for (int i = lane; i < W; i += 64) {
-      D.rinv[i + (int64_t)k * W] = (i <= k) ? sX[k + i * ld] : 0.0;
-      if (pass == 1) D.r1[i + (int64_t)k * W] = (i <= k) ? sA[k + i * ld] : 0.0;
+  // ---- outputs: R^-1 = X^T, R = L^T (upper triangular, zeros below); the
+  // LDS reads of eight elements per thread are in flight together
+  for (int e0 = 0; e0 < W * W; e0 += 8 * 256) {
+    double x[8], l[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = min(e0 + tid + 256 * u, W * W - 1), i = e % W, k = e / W;
+      x[u] = (i <= k) ? sX[k + i * ld] : 0.0;
+      l[u] = (i <= k) ? sA[k + i * ld] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + tid + 256 * u;
+      if (e < W * W) {
+        D.rinv[e] = x[u];
+        if (pass == 1) D.r1[e] = l[u];
+      }
+    }
+  }
   if (pass == 2 && D.R != nullptr) {
     // R = R2 R1 with R2(i, l) = L2(l, i); w == W on this path.  R1 is staged
     // in LDS (X is no longer needed).
