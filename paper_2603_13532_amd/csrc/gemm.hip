@@ -250,9 +250,11 @@ struct SegCursor {
 };
 
 // Register ring depth of the K-loop: K-tiles whose global loads are in
-// flight while one tile feeds the MFMAs.
-template <int P> struct Depth { static constexpr int value = 4; };
-template <> struct Depth<P_FP32> { static constexpr int value = 8; };
+// flight while one tile feeds the MFMAs.  Two for every precision: deeper
+// rings measured slower on the method's launches (their K-loops are short
+// and the extra registers cost occupancy), and the loop needs two slots
+// (the slot staged next is never the one just fetched).
+template <int P> struct Depth { static constexpr int value = 2; };
 
 // K-loop shared by the contraction kernels.  Most launches of the method put
 // one or two workgroups on a CU, so global latency (first touches after the
@@ -271,6 +273,7 @@ template <int P, int D, bool MMA, class Cur>
 __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type (&s)[2],
                                       typename PT<P>::acc_t (&acc)[2][2], int t, int lane, int wm,
                                       int wn) {
+  static_assert(D >= 2, "the slot staged next must differ from the one just fetched");
   typedef typename PT<P>::in_t in_t;
   constexpr int PER = Stage<P>::PER_THREAD;
   const StageMap<P> map(t);
