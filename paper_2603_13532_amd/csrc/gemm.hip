@@ -157,7 +157,7 @@ __device__ __forceinline__ void stage(typename Lds<P>::type& s, const StageMap<P
 // segment table is read through an LDS window of kSegCache entries, refilled
 // by the whole block when the cursor leaves it, so a segment change costs no
 // global round trip.
-constexpr int kSegCache = 64;
+constexpr int kSegCache = 32;  // small enough for four FP64 workgroups per CU
 typedef __attribute__((address_space(3))) GemmSeg lds_seg_t;
 typedef __attribute__((address_space(3))) uint64_t lds_u64_t;
 
@@ -336,8 +336,10 @@ __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type
 
 // ROLE only names the launch (one symbol per step of the method, so that
 // kernel traces separate them); the code is the same for every role.
+// At least four waves per SIMD (<= 128 VGPRs): with the LDS of one
+// workgroup under 40 KB, four workgroups share a CU.
 template <int P, int ROLE>
-__global__ __launch_bounds__(NTHREADS) void gemm_kernel(const GemmDesc* __restrict__ descs,
+__global__ __launch_bounds__(NTHREADS, 4) void gemm_kernel(const GemmDesc* __restrict__ descs,
                                                         int ndesc,
                                                         const GemmSeg* __restrict__ segs) {
   typedef typename PT<P>::in_t in_t;
@@ -415,7 +417,6 @@ __global__ __launch_bounds__(NTHREADS) void gemm_kernel(const GemmDesc* __restri
 // K).  With LDS_P the block's 64 columns of every P_k sit in LDS (slice k at
 // soff[k], column x at x * r_k), so the Khatri-Rao products wait only on LDS;
 // the core loads are buffer loads that nothing waits for before staging.
-constexpr int kKrpLds = 6144;  // elements of P slices kept in LDS
 typedef __attribute__((address_space(3))) const float lds_cf32;
 typedef __attribute__((address_space(3))) const double lds_cf64;
 
@@ -622,7 +623,7 @@ struct KrpFixed {
 // the other modes, first remaining mode fastest (unfolding index equation).
 template <int P>
 __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict__ descs,
-                                                       int ndesc) {
+                                                       int ndesc, int lds_cap) {
   typedef typename PT<P>::in_t in_t;
   typedef typename PT<P>::acc_t acc_t;
   constexpr int BK = PT<P>::BK;
@@ -666,8 +667,10 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
 
   acc_t acc[2][2];
   acc_zero<P>(acc);
-  // the block's 64 columns of every P_k (k != n) into LDS when they fit
-  __shared__ in_t sP[kKrpLds];
+  // the block's 64 columns of every P_k (k != n) into LDS when they fit the
+  // launch's dynamic LDS (sized for its largest slice set)
+  extern __shared__ __align__(16) unsigned char krp_dyn[];
+  in_t* sP = reinterpret_cast<in_t*>(krp_dyn);
   int soff[kMaxOrder];
   int total = 0;
 #pragma unroll
@@ -675,7 +678,7 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
     soff[k] = total;
     if (k < order && k != n) total += TILE * rk[k];
   }
-  const bool lds_p = total <= kKrpLds;
+  const bool lds_p = total <= lds_cap;
   if (lds_p) {
     const int cols = min(TILE, m - n0);
 #pragma unroll
@@ -1073,15 +1076,17 @@ hipError_t launch_gemm(int prec, int role, const GemmDesc* descs, int ndesc, con
 }
 
 hipError_t launch_krp(int prec, const KrpDesc* descs, int ndesc, int64_t total_tiles,
-                      hipStream_t stream) {
+                      int lds_elems, hipStream_t stream) {
   if (ndesc <= 0 || total_tiles <= 0) return hipSuccess;
+  if (lds_elems < 0 || lds_elems > kKrpLds) return hipErrorInvalidValue;
   const dim3 grid((unsigned)total_tiles), block(NTHREADS);
+  const size_t dyn = (size_t)lds_elems * (prec == P_FP64 ? sizeof(double) : sizeof(float));
   switch (prec) {
-    case P_FP64: krp_kernel<P_FP64><<<grid, block, 0, stream>>>(descs, ndesc); break;
-    case P_FP32: krp_kernel<P_FP32><<<grid, block, 0, stream>>>(descs, ndesc); break;
-    case P_BF16X1: krp_kernel<P_BF16X1><<<grid, block, 0, stream>>>(descs, ndesc); break;
-    case P_BF16X3: krp_kernel<P_BF16X3><<<grid, block, 0, stream>>>(descs, ndesc); break;
-    case P_BF16X6: krp_kernel<P_BF16X6><<<grid, block, 0, stream>>>(descs, ndesc); break;
+    case P_FP64: krp_kernel<P_FP64><<<grid, block, dyn, stream>>>(descs, ndesc, lds_elems); break;
+    case P_FP32: krp_kernel<P_FP32><<<grid, block, dyn, stream>>>(descs, ndesc, lds_elems); break;
+    case P_BF16X1: krp_kernel<P_BF16X1><<<grid, block, dyn, stream>>>(descs, ndesc, lds_elems); break;
+    case P_BF16X3: krp_kernel<P_BF16X3><<<grid, block, dyn, stream>>>(descs, ndesc, lds_elems); break;
+    case P_BF16X6: krp_kernel<P_BF16X6><<<grid, block, dyn, stream>>>(descs, ndesc, lds_elems); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

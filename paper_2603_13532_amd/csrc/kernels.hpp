@@ -27,8 +27,12 @@ hipError_t launch_gemm(int prec, int role, const GemmDesc* descs, int ndesc, con
                        int64_t total_tiles, hipStream_t stream);
 
 // KRP core sketches over `ndesc` device descriptors covering `total_tiles` tiles.
+// Elements of P slices a KRP workgroup may keep in LDS (the block's 64
+// columns of every P_k, k != n); launches size their LDS by the largest
+// such slice set among their descriptors (`lds_elems`, <= kKrpLds).
+constexpr int kKrpLds = 6144;
 hipError_t launch_krp(int prec, const KrpDesc* descs, int ndesc, int64_t total_tiles,
-                      hipStream_t stream);
+                      int lds_elems, hipStream_t stream);
 
 // Core adjoint of the KRP sketch (core-shaped outputs).
 hipError_t launch_krp_adj(int prec, const KrpAdjDesc* descs, int ndesc, int64_t total_tiles,

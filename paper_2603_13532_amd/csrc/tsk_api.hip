@@ -192,7 +192,22 @@ struct Step {
   double tol = 0;
   int wmax = 0;  // chol: widest Gram of the launch
   int hh_kernels = 3;  // householder: which of the two kernels have panels
+  int krp_lds = 0;     // krp: LDS elements for the P slices (largest that fits)
 };
+
+// LDS elements a KRP launch needs for its P slices: the largest slice set
+// (64 columns of every P_k, k != n) among its descriptors that fits
+// kKrpLds; larger ones read P from global memory.
+int krp_lds_elems(const KrpDesc* kd, size_t count) {
+  int need = 0;
+  for (size_t j = 0; j < count; ++j) {
+    int tot = 0;
+    for (int k = 0; k < kd[j].order; ++k)
+      if (k != kd[j].mode) tot += 64 * kd[j].r[k];
+    if (tot <= kKrpLds) need = std::max(need, tot);
+  }
+  return need;
+}
 
 // Workspace arena: addresses are planned against a base that may be null
 // (size query) and resolved when the caller's workspace is known.
@@ -879,6 +894,7 @@ void Builder::emit(Program& prog) {
     st.meta = prog.put(krp);
     st.count = (int)krp.size();
     st.tiles = krp_tiles;
+    st.krp_lds = krp_lds_elems(krp.data(), krp.size());
     prog.steps.push_back(st);
     if (!krp_red.empty()) {
       Step r{};
@@ -1050,6 +1066,7 @@ void build_backward(const Problem& P, const BackwardIO& io, Arena& ar, Program& 
     st.meta = prog.put(kd);
     st.count = (int)kd.size();
     st.tiles = tiles;
+    st.krp_lds = krp_lds_elems(kd.data(), kd.size());
     prog.steps.push_back(st);
   };
   auto krp_desc = [&](int i, int mode, const std::vector<const void*>& fs, void* out,
@@ -1475,7 +1492,10 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
         e = launch_gemm(st.prec, st.role, (const GemmDesc*)(meta + st.meta), st.count,
                         (const GemmSeg*)(meta + st.meta2), st.tiles, stream);
         break;
-      case S_KRP: e = launch_krp(st.prec, (const KrpDesc*)(meta + st.meta), st.count, st.tiles, stream); break;
+      case S_KRP:
+        e = launch_krp(st.prec, (const KrpDesc*)(meta + st.meta), st.count, st.tiles, st.krp_lds,
+                       stream);
+        break;
       case S_REDUCE: e = launch_reduce((const ReduceJob*)(meta + st.meta), st.count, stream); break;
       case S_TILE_REDUCE: e = launch_tile_reduce((const ReduceJob*)(meta + st.meta), st.count, stream); break;
       case S_COPY: e = launch_copy((const CopyJob*)(meta + st.meta), st.count, stream); break;
@@ -1642,6 +1662,7 @@ void check_program(const Program& prog, Checker& ck) {
             }
           }
           if (Kc != D.Kc) { ck.ok = false; ck.err = "krp Kc mismatch"; return; }
+          if (st.krp_lds < 0 || st.krp_lds > kKrpLds) { ck.ok = false; ck.err = "krp LDS size"; return; }
           ck.span(D.G, 0, cs - 1, e, "krp G");
           ck.span(D.V, 0, (int64_t)D.r[D.mode] * D.m - 1, e, "krp V");
           if (D.splits > 1) {
