@@ -59,7 +59,9 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 //     identity: X_K = L_KK^-1 B_K (thread per column), then
 //     B_{>K} -= L_{>K,K} X_K, next to the trailing update of the Gram
 //     A_{>K} -= L_{>K,K} L_{>K,K}^T; both updates use 2 x 2 register blocks
-//     over the 16 panel columns.
+//     over the 16 panel columns;
+//   * look-ahead: the next panel's columns are updated first, so that wave 0
+//     factors the next panel while the other waves finish block K.
 // LDS is sized by the widest Gram of the launch, so narrow Grams leave room
 // for several workgroups per CU.
 // One 16-column panel of the Cholesky factorization by one wave: lane l
@@ -181,23 +183,45 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
   }
   __syncthreads();
 
+  // Blocks of 16 columns with look-ahead: phase 1 (all threads) solves X_K
+  // and applies block K to the next panel's 16 columns; phase 2 factors that
+  // panel on wave 0 while the other waves apply block K to the rest of the
+  // trailing Gram and to B.  Each phase touches disjoint parts of LDS.
   const int nb = Wp / kCholBs;
-  for (int K = 0; K < nb; ++K) {
-    const int k0 = K * kCholBs, k1 = k0 + kCholBs;
-    // ---- panel factorization, wave 0 (the second row set only when the
-    // panel is taller than 64 rows)
-    if (wave == 0) {
-      if (Wp - k0 > 64)
-        chol_panel<true>(sA, ld, dinv, diag0, &s_bad, k0, Wp, lane, tol);
-      else
-        chol_panel<false>(sA, ld, dinv, diag0, &s_bad, k0, Wp, lane, tol);
+  auto panel = [&](int K) {
+    const int k0 = K * kCholBs;
+    if (Wp - k0 > 64)
+      chol_panel<true>(sA, ld, dinv, diag0, &s_bad, k0, Wp, lane, tol);
+    else
+      chol_panel<false>(sA, ld, dinv, diag0, &s_bad, k0, Wp, lane, tol);
+  };
+  // A(i0..i0+1, j0..j0+1) -= L(i0.., K) L(j0.., K)^T over the 16 columns of block K
+  auto sub22 = [&](int k0, int i0, int j0) {
+    double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
+#pragma unroll
+    for (int c = 0; c < kCholBs; ++c) {
+      const double2 li = *reinterpret_cast<const double2*>(&sA[i0 + (k0 + c) * ld]);
+      const double2 lj = *reinterpret_cast<const double2*>(&sA[j0 + (k0 + c) * ld]);
+      a00 = fma(li.x, lj.x, a00);
+      a01 = fma(li.x, lj.y, a01);
+      a10 = fma(li.y, lj.x, a10);
+      a11 = fma(li.y, lj.y, a11);
     }
-    __syncthreads();
-    if (s_bad) {
+    sA[i0 + j0 * ld] -= a00;
+    sA[i0 + 1 + j0 * ld] -= a10;
+    if (i0 > j0) sA[i0 + (j0 + 1) * ld] -= a01;
+    sA[i0 + 1 + (j0 + 1) * ld] -= a11;
+  };
+  if (wave == 0) panel(0);
+  __syncthreads();
+  for (int K = 0; K < nb; ++K) {
+    const int k0 = K * kCholBs, k1 = k0 + kCholBs, k2 = k1 + kCholBs;
+    if (s_bad) {  // panel K broke down
       if (tid == 0) *D.flag = 1;
       return;
     }
-    // ---- X_K = L_KK^-1 B_K for the columns col < k1 (thread per column)
+    const bool ahead = K + 1 < nb;
+    // ---- phase 1a: X_K = L_KK^-1 B_K for the columns col < k1 (thread per column)
     if (tid < k1) {
       const int col = tid;
       double b[kCholBs];
@@ -214,38 +238,35 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
 #pragma unroll
       for (int r = 0; r < kCholBs; ++r) sX[(k0 + r) + col * ld] = b[r];
     }
-    // ---- trailing Gram: A(i, j) -= sum_c L(i, k0 + c) L(j, k0 + c), i >= j >= k1
-    const int T = Wp - k1, nbk = T >> 1;
-    if (T > 0) {
-      const int nblk = nbk * (nbk + 1) / 2;
-      for (int e = tid; e < nblk; e += 256) {
+    // ---- phase 1b: block K applied to the next panel's columns [k1, k2):
+    // 2 x 2 blocks (bi, bj), bj < 8, bi >= bj, rows k1 + 2 bi
+    const int nbk = (Wp - k1) >> 1;
+    if (ahead)
+      for (int e = tid; e < nbk * (kCholBs / 2); e += 256) {
+        const int bi = e / (kCholBs / 2), bj = e % (kCholBs / 2);
+        if (bi >= bj) sub22(k0, k1 + 2 * bi, k1 + 2 * bj);
+      }
+    __syncthreads();
+    // ---- phase 2: panel K + 1 on wave 0; block K applied to the trailing
+    // Gram beyond the next panel (rows, columns >= k2) and to B by the others
+    // (by every wave after the last panel)
+    const int wb = ahead ? 64 : 0, nw = 256 - wb, wt = tid - wb;
+    if (ahead && wave == 0) {
+      panel(K + 1);
+    } else {
+      const int T2 = Wp - k2, nbk2 = T2 > 0 ? T2 >> 1 : 0;
+      const int nblk = nbk2 * (nbk2 + 1) / 2;
+      for (int e = wt; e < nblk; e += nw) {
         // packed lower-triangle block index -> (bi, bj), bi >= bj
         int bi = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
         if ((bi + 1) * (bi + 2) / 2 <= e) ++bi;
         if (bi * (bi + 1) / 2 > e) --bi;
         const int bj = e - bi * (bi + 1) / 2;
-        const int i0 = k1 + 2 * bi, j0 = k1 + 2 * bj;
-        double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
-#pragma unroll
-        for (int c = 0; c < kCholBs; ++c) {
-          const double2 li = *reinterpret_cast<const double2*>(&sA[i0 + (k0 + c) * ld]);
-          const double2 lj = *reinterpret_cast<const double2*>(&sA[j0 + (k0 + c) * ld]);
-          a00 = fma(li.x, lj.x, a00);
-          a01 = fma(li.x, lj.y, a01);
-          a10 = fma(li.y, lj.x, a10);
-          a11 = fma(li.y, lj.y, a11);
-        }
-        sA[i0 + j0 * ld] -= a00;
-        sA[i0 + 1 + j0 * ld] -= a10;
-        if (i0 > j0) sA[i0 + (j0 + 1) * ld] -= a01;
-        sA[i0 + 1 + (j0 + 1) * ld] -= a11;
+        sub22(k0, k2 + 2 * bi, k2 + 2 * bj);
       }
-    }
-    __syncthreads();
-    // ---- B(i, col) -= sum_c L(i, k0 + c) X(k0 + c, col), i >= k1 > col
-    if (T > 0) {
-      const int ncb = k1 >> 1, nblk = nbk * ncb;
-      for (int e = tid; e < nblk; e += 256) {
+      // B(i, col) -= sum_c L(i, k0 + c) X(k0 + c, col), i >= k1 > col
+      const int ncb = k1 >> 1, nblkb = nbk * ncb;
+      for (int e = wt; e < nblkb; e += nw) {
         const int bi = e / ncb, bj = e - bi * ncb;
         const int i0 = k1 + 2 * bi, j0 = 2 * bj;
         double b00 = 0.0, b01 = 0.0, b10 = 0.0, b11 = 0.0;
@@ -263,8 +284,8 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
         sX[i0 + (j0 + 1) * ld] -= b01;
         sX[i0 + 1 + (j0 + 1) * ld] -= b11;
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
 
   // ---- outputs: R^-1 = X^T, R = L^T (upper triangular, zeros below); the
