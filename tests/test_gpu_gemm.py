@@ -63,3 +63,32 @@ def test_gemm_layouts(env, prec, ta, tb, M, N, K, splits):
         want = a.astype(np.float32).astype(np.float64) @ b.astype(np.float32).astype(np.float64)
     err = np.linalg.norm(got - want) / np.linalg.norm(want)
     assert err < TOL[prec], err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("M,N,K,splits", [(100, 70, 700, 10), (64, 130, 1100, 17), (65, 64, 96, 9)])
+def test_gemm_many_splits(env, prec, M, N, K, splits):
+    """Split-K reductions spanning more than one batch of eight partials per
+    round trip (and splits that get no K-tile: 96 / 16 = 6 tiles for 9
+    splits), against float64 matmul on the CPU."""
+    import torch
+    tsk, _lib, fn = env
+    rng = np.random.default_rng(M + 7 * N + 13 * K + splits)
+    a = rng.standard_normal((M, K))
+    b = rng.standard_normal((K, N))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    A = tsk.fortran(torch.from_numpy(np.asfortranarray(a)).to(DEV, dt))
+    B = tsk.fortran(torch.from_numpy(np.asfortranarray(b)).to(DEV, dt))
+    C = tsk.empty_fortran((M, N), torch.float64, DEV)
+    ws = torch.empty(1 << 24, dtype=torch.uint8, device=DEV)
+    h = tsk.Handle.get(DEV)
+    st = fn(h.ptr, _lib.PRECISIONS[prec], M, N, K, A.data_ptr(), 1, M, B.data_ptr(), K, 1,
+            C.data_ptr(), M, 1, splits, ws.data_ptr(), ws.numel(), None)
+    assert st == 0
+    torch.cuda.synchronize()
+    if prec == "fp64":
+        want = a @ b
+    else:
+        want = a.astype(np.float32).astype(np.float64) @ b.astype(np.float32).astype(np.float64)
+    err = np.linalg.norm(C.cpu().numpy() - want) / np.linalg.norm(want)
+    assert err < TOL[prec], err
