@@ -52,7 +52,6 @@ static_assert(sizeof(GemmSeg) % 8 == 0, "segments are copied as 8-byte words");
 struct GemmDesc {
   void* C;
   void* part;          // splits > 1: per-tile partial blocks (64 x 64, accumulator type)
-  int32_t* counters;   // splits > 1: one arrival counter per output tile, zero on entry
   int64_t ldc, strideC, strideSplit;
   int32_t M, N, batch, splits;
   int32_t seg_begin, seg_count;
@@ -70,7 +69,6 @@ struct KrpDesc {
   const void* P[kMaxOrder];      // P_k = U_k^T Omega_k, r_k x m column-major (P[n] unused)
   void* V;                       // r_n x m, column-major, ld r_n
   void* part;                    // splits > 1: per-tile partial blocks
-  int32_t* counters;             // splits > 1: arrival counters, zero on entry
   int32_t r[kMaxOrder];
   int32_t order, mode, m, splits;
   int64_t strideSplit;           // unused (kept for layout stability)

@@ -214,8 +214,8 @@ int krp_lds_elems(const KrpDesc* kd, size_t count) {
 struct Arena {
   char* base = nullptr;
   size_t top = 0;
-  // int32 words that must be zero when the program starts (split-K arrival
-  // counters, QR flags): one block, cleared by a single fill at the start
+  // int32 words that must be zero when the program starts (QR flags): one
+  // block, cleared by a single fill at the start
   int32_t* ctr_base = nullptr;
   int64_t ctr_used = 0;
   void* take(size_t bytes) {
@@ -277,7 +277,6 @@ struct GemmBatch {
     D.strideSplit = 0;
     D.beta = beta;
     D.part = nullptr;
-    D.counters = nullptr;
     if (splits > 1) {
       const int64_t ntiles = (int64_t)D.tiles_m * D.tiles_n * batch;
       const size_t pe = prec == P_FP64 ? 8 : 4;
@@ -546,8 +545,7 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
         D.V = v;
         D.strideSplit = 0;
         D.part = nullptr;
-        D.counters = nullptr;
-        if (sp > 1) {
+            if (sp > 1) {
           const int64_t ntiles = (int64_t)D.tiles_m * D.tiles_n;
           D.part = ar.take((size_t)ntiles * sp * 64 * 64 * es);
           for (int64_t tl = 0; tl < ntiles; ++tl) {
