@@ -67,47 +67,65 @@ __device__ __forceinline__ int find_desc(const D* __restrict__ descs, int ndesc,
   return lo;
 }
 
-template <int P, typename OutT>
-__device__ __forceinline__ void store_tile(typename PT<P>::acc_t (&acc)[2][2], OutT* __restrict__ C,
-                                           int64_t ldc, int M, int N, int m0, int n0, bool accum,
-                                           int lane, int wm, int wn) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + acc_col(wn, j, lane);
-      if (col >= N) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + acc_row<P>(wm, i, lane, v);
-        if (row < M) {
-          OutT* p = C + (int64_t)row + (int64_t)col * ldc;
-          if (accum) *p = (OutT)((double)*p + (double)acc[i][j][v]);
-          else *p = (OutT)acc[i][j][v];
-        }
-      }
-    }
-}
-
 // Accumulator element type of a precision form.
 template <int P> struct AccElem { typedef float type; };
 template <> struct AccElem<P_FP64> { typedef double type; };
 
-// Split-K: every split writes its 64 x 64 partial tile (accumulator type,
-// column-major, ld 64); a reduce launch then adds the partials in split order,
-// applies beta and writes C, so the result does not depend on timing.
+// Epilogue through LDS: the accumulators go to a 64 x 64 tile in the K-loop's
+// LDS buffers (free once the loop's last barrier has passed), and every store
+// instruction then writes 64 consecutive rows of one column, coalesced,
+// instead of the MFMA layout's 16 columns x 4 scattered rows.
+constexpr int kEpiLd = TILE + 1;
 template <int P>
-__device__ __forceinline__ void store_partial(typename PT<P>::acc_t (&acc)[2][2], void* part_tile,
-                                              int lane, int wm, int wn) {
+__device__ __forceinline__ typename AccElem<P>::type* epi_stage(
+    typename PT<P>::acc_t (&acc)[2][2], void* lds, int lane, int wm, int wn) {
   typedef typename AccElem<P>::type ae;
-  ae* mine = (ae*)part_tile;
+  static_assert(sizeof(typename Lds<P>::type) * 2 >= sizeof(ae) * TILE * kEpiLd,
+                "the epilogue tile fits the K-loop buffers");
+  ae* T = (ae*)lds;
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        mine[acc_row<P>(wm, i, lane, v) + TILE * acc_col(wn, j, lane)] = (ae)acc[i][j][v];
+        T[acc_row<P>(wm, i, lane, v) + kEpiLd * acc_col(wn, j, lane)] = (ae)acc[i][j][v];
+  __syncthreads();
+  return T;
+}
+
+// C(m0 + r, n0 + c) (=|+=) tile(r, c) for r < M - m0, c < N - n0 (column-major C).
+template <int P, typename OutT>
+__device__ __forceinline__ void store_tile(typename PT<P>::acc_t (&acc)[2][2], OutT* __restrict__ C,
+                                           int64_t ldc, int M, int N, int m0, int n0, bool accum,
+                                           int lane, int wm, int wn, void* lds, int t) {
+  const typename AccElem<P>::type* T = epi_stage<P>(acc, lds, lane, wm, wn);
+  const int r = t & (TILE - 1), row = m0 + r;
+  if (row >= M) return;
+#pragma unroll 4
+  for (int c = t / TILE; c < TILE; c += NTHREADS / TILE) {
+    const int col = n0 + c;
+    if (col >= N) break;
+    OutT* p = C + (int64_t)row + (int64_t)col * ldc;
+    const double v = (double)T[r + kEpiLd * c];
+    if (accum) *p = (OutT)((double)*p + v);
+    else *p = (OutT)v;
+  }
+}
+
+// Split-K: every split writes its 64 x 64 partial tile (accumulator type,
+// column-major, ld 64); a reduce launch then adds the partials in split order,
+// applies beta and writes C, so the result does not depend on timing.
+template <int P>
+__device__ __forceinline__ void store_partial(typename PT<P>::acc_t (&acc)[2][2], void* part_tile,
+                                              int lane, int wm, int wn, void* lds, int t) {
+  typedef typename AccElem<P>::type ae;
+  const ae* T = epi_stage<P>(acc, lds, lane, wm, wn);
+  ae* mine = (ae*)part_tile;
+  const int r = t & (TILE - 1);
+#pragma unroll 4
+  for (int c = t / TILE; c < TILE; c += NTHREADS / TILE) mine[r + TILE * c] = T[r + kEpiLd * c];
 }
 
 // Stage one K-tile held in registers into an LDS buffer.
@@ -400,12 +418,15 @@ __global__ __launch_bounds__(NTHREADS, 4) void gemm_kernel(const GemmDesc* __res
   const int64_t off = b * D.strideC;
   if (splits == 1) {
     if (D.c_f64)
-      store_tile<P, double>(acc, (double*)D.C + off, D.ldc, M, N, m0, n0, D.beta != 0, lane, wm, wn);
+      store_tile<P, double>(acc, (double*)D.C + off, D.ldc, M, N, m0, n0, D.beta != 0, lane, wm, wn,
+                            s, t);
     else
-      store_tile<P, float>(acc, (float*)D.C + off, D.ldc, M, N, m0, n0, D.beta != 0, lane, wm, wn);
+      store_tile<P, float>(acc, (float*)D.C + off, D.ldc, M, N, m0, n0, D.beta != 0, lane, wm, wn,
+                           s, t);
   } else {
     typedef typename AccElem<P>::type ae;
-    store_partial<P>(acc, (ae*)D.part + (tile_ns * splits + split) * (TILE * TILE), lane, wm, wn);
+    store_partial<P>(acc, (ae*)D.part + (tile_ns * splits + split) * (TILE * TILE), lane, wm, wn,
+                     s, t);
   }
 }
 
@@ -778,10 +799,11 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
 #undef TSK_KRP_CURSOR
   typedef typename std::conditional<P == P_FP64, double, float>::type vt;
   if (splits == 1) {
-    store_tile<P, vt>(acc, (vt*)Vout, rn, rn, m, m0, n0, false, lane, wm, wn);
+    store_tile<P, vt>(acc, (vt*)Vout, rn, rn, m, m0, n0, false, lane, wm, wn, s, t);
   } else {
     typedef typename AccElem<P>::type ae;
-    store_partial<P>(acc, (ae*)part_base + (tile_ns * splits + split) * (TILE * TILE), lane, wm, wn);
+    store_partial<P>(acc, (ae*)part_base + (tile_ns * splits + split) * (TILE * TILE), lane, wm, wn,
+                     s, t);
   }
 }
 
