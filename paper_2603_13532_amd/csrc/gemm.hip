@@ -1037,15 +1037,43 @@ __global__ __launch_bounds__(NTHREADS) void tile_reduce_kernel(const ReduceJob* 
     reduce_tile<float>(J, blockIdx.y, threadIdx.x);
 }
 
-__global__ __launch_bounds__(256) void copy_kernel(const CopyJob* __restrict__ jobs) {
-  const CopyJob& J = jobs[blockIdx.y];
-  for (int64_t c = blockIdx.x; c < J.cols; c += gridDim.x) {
-    for (int64_t r = threadIdx.x; r < J.rows; r += blockDim.x) {
-      const int64_t is = r + c * J.ld_src, id = r + c * J.ld_dst;
-      const double v = J.src_f64 ? ((const double*)J.src)[is] : (double)((const float*)J.src)[is];
-      if (J.dst_f64) ((double*)J.dst)[id] = v;
-      else ((float*)J.dst)[id] = (float)v;
-    }
+template <class S, class D>
+__device__ __forceinline__ void copy_chunk(const S* __restrict__ src, D* __restrict__ dst,
+                                           int64_t base, int64_t n, int t) {
+  constexpr int E = kCopyChunk / 256;
+  S v[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int64_t e = base + k * 256 + t;
+    v[k] = e < n ? src[e] : S(0);
+  }
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int64_t e = base + k * 256 + t;
+    if (e < n) dst[e] = (D)v[k];
+  }
+}
+
+// One workgroup per chunk of kCopyChunk elements; the job holding the chunk
+// is found by binary search over the jobs' first chunks.
+__global__ __launch_bounds__(256) void copy_kernel(const CopyJob* __restrict__ jobs, int count) {
+  const int64_t chunk = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].chunk_begin <= chunk) lo = mid;
+    else hi = mid - 1;
+  }
+  const CopyJob& J = jobs[lo];
+  const int64_t n = J.rows * J.cols;
+  const int64_t base = (chunk - J.chunk_begin) * kCopyChunk;
+  const int t = threadIdx.x;
+  if (J.src_f64) {
+    if (J.dst_f64) copy_chunk((const double*)J.src, (double*)J.dst, base, n, t);
+    else copy_chunk((const double*)J.src, (float*)J.dst, base, n, t);
+  } else {
+    if (J.dst_f64) copy_chunk((const float*)J.src, (double*)J.dst, base, n, t);
+    else copy_chunk((const float*)J.src, (float*)J.dst, base, n, t);
   }
 }
 
@@ -1141,9 +1169,9 @@ hipError_t launch_tile_reduce(const ReduceJob* jobs, int count, hipStream_t stre
   return hipGetLastError();
 }
 
-hipError_t launch_copy(const CopyJob* jobs, int count, hipStream_t stream) {
-  if (count <= 0) return hipSuccess;
-  copy_kernel<<<dim3(64, (unsigned)count), dim3(256), 0, stream>>>(jobs);
+hipError_t launch_copy(const CopyJob* jobs, int count, int64_t chunks, hipStream_t stream) {
+  if (count <= 0 || chunks <= 0) return hipSuccess;
+  copy_kernel<<<dim3((unsigned)chunks), dim3(256), 0, stream>>>(jobs, count);
   return hipGetLastError();
 }
 

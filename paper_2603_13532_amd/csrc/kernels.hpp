@@ -58,14 +58,20 @@ hipError_t launch_tile_reduce(const ReduceJob* jobs, int count, hipStream_t stre
 // that captured graphs hold no memset nodes).
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t stream);
 
-// Typed copies with conversion: dst[i*ld_d + r] = src[i*ld_s + r], rows x cols.
+// Typed copies with conversion of contiguous rows x cols matrices
+// (ld_dst == ld_src == rows): dst[e] = src[e]. A launch splits every job into
+// chunks of kCopyChunk elements; chunk_begin is the job's first chunk in the
+// launch (a prefix sum over the jobs before it), and one workgroup copies one
+// chunk.
+constexpr int kCopyChunk = 2048;
 struct CopyJob {
   void* dst;
   const void* src;
   int64_t rows, cols, ld_dst, ld_src;
   int32_t dst_f64, src_f64;
+  int64_t chunk_begin;
 };
-hipError_t launch_copy(const CopyJob* jobs, int count, hipStream_t stream);
+hipError_t launch_copy(const CopyJob* jobs, int count, int64_t chunks, hipStream_t stream);
 
 // Cholesky QR passes and the Householder fallback over `count` modes.
 // wmax: widest Gram (W) among the descriptors; sizes the dynamic LDS.

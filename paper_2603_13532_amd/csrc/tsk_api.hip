@@ -355,10 +355,17 @@ void emit_gemm(Program& prog, GemmBatch& gb) {
   }
 }
 
-void emit_copies(Program& prog, const std::vector<CopyJob>& jobs) {
+void emit_copies(Program& prog, std::vector<CopyJob> jobs) {
   if (jobs.empty()) return;
   Step c{};
   c.kind = S_COPY;
+  int64_t chunks = 0;
+  for (CopyJob& J : jobs) {
+    J.chunk_begin = chunks;
+    chunks += (J.rows * J.cols + kCopyChunk - 1) / kCopyChunk;
+    c.bytes += (double)(J.rows * J.cols) * ((J.src_f64 ? 8 : 4) + (J.dst_f64 ? 8 : 4));
+  }
+  c.tiles = chunks;
   c.meta = prog.put(jobs);
   c.count = (int)jobs.size();
   prog.steps.push_back(c);
@@ -1496,7 +1503,7 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
         break;
       case S_REDUCE: e = launch_reduce((const ReduceJob*)(meta + st.meta), st.count, stream); break;
       case S_TILE_REDUCE: e = launch_tile_reduce((const ReduceJob*)(meta + st.meta), st.count, stream); break;
-      case S_COPY: e = launch_copy((const CopyJob*)(meta + st.meta), st.count, stream); break;
+      case S_COPY: e = launch_copy((const CopyJob*)(meta + st.meta), st.count, st.tiles, stream); break;
       case S_FILL: e = launch_fill_i32((int32_t*)st.ptr, st.rows, st.value, stream); break;
       case S_CHOL:
         e = launch_chol((const QrDesc*)(meta + st.meta), st.count, st.pass, st.tol, st.wmax, stream);
@@ -1684,11 +1691,16 @@ void check_program(const Program& prog, Checker& ck) {
       }
       case S_COPY: {
         const CopyJob* js = (const CopyJob*)(blob + st.meta);
+        int64_t chunks = 0;
         for (int i = 0; i < st.count; ++i) {
           const CopyJob& J = js[i];
+          if (J.ld_dst != J.rows || J.ld_src != J.rows) { ck.ok = false; ck.err = "copy job not contiguous"; return; }
+          if (J.chunk_begin != chunks) { ck.ok = false; ck.err = "copy chunk prefix mismatch"; return; }
+          chunks += (J.rows * J.cols + kCopyChunk - 1) / kCopyChunk;
           ck.span(J.dst, 0, max_off({{J.rows, 1}, {J.cols, J.ld_dst}}), J.dst_f64 ? 8 : 4, "copy dst");
           ck.span(J.src, 0, max_off({{J.rows, 1}, {J.cols, J.ld_src}}), J.src_f64 ? 8 : 4, "copy src");
         }
+        if (chunks != st.tiles) { ck.ok = false; ck.err = "copy chunk count mismatch"; return; }
         break;
       }
       case S_KRP_ADJ: {
