@@ -114,7 +114,16 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
   extern __shared__ __align__(16) double smem[];
   const QrDesc& D = qrs[blockIdx.x];
   const int W = (int)D.W;
-  if (D.hh_direct || *D.flag != 0 || W > kCholMax || D.W > D.n) return;
+  if (D.hh_direct) return;
+  // The first pass initialises the mode's breakdown flag (no clearing launch
+  // is needed before the program); the second skips modes that broke down.
+  const bool fits = W <= kCholMax && D.W <= D.n;
+  if (pass == 1) {
+    if (threadIdx.x == 0) *D.flag = fits ? 0 : 1;
+  } else if (*D.flag != 0) {
+    return;
+  }
+  if (!fits) return;
   const int Wp = chol_pad(W), ld = chol_ld(W);
   double* sA = smem;            // Gram, then L (lower triangle), column-major
   double* sX = smem + Wp * ld;  // identity, then L^-1 (lower triangle)
@@ -136,7 +145,9 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
   // ---- Gram lower triangle = partial blocks summed in split order.  The
   // packed lower triangle (row-major: e = i (i + 1) / 2 + j, j <= i) is
   // spread evenly over the threads, eight elements per thread and round,
-  // each with the loads of eight splits in flight together.
+  // each with the loads of eight splits in flight together.  The partial
+  // blocks are full W x W Gram matrices, so G(i, j) is read at its mirror
+  // (j, i): consecutive j are then consecutive addresses.
   {
     const int splits = max(1, (int)D.gram_splits);
     const int64_t WW = (int64_t)W * W;
@@ -156,7 +167,7 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
         ok[u] = e < npk;
         ii[u] = i;
         jj[u] = j;
-        off[u] = ok[u] ? i + j * W : 0;
+        off[u] = ok[u] ? j + i * W : 0;
         acc[u] = 0.0;
       }
       for (int s0 = 0; s0 < splits; s0 += 8) {
@@ -316,9 +327,18 @@ __global__ __launch_bounds__(256) void chol_kernel(const QrDesc* __restrict__ qr
     __syncthreads();
     for (int k = wave; k < W; k += 4)
       for (int i = lane; i < W; i += 64) {
-        double acc = 0.0;
-        for (int l = i; l <= k; ++l) acc = fma(sA[l + i * ld], sX[l + k * ld], acc);
-        D.R[i + (int64_t)k * W] = (i <= k) ? acc : 0.0;
+        // four independent partial sums, so that the LDS reads and FMAs of
+        // consecutive l overlap
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int l = i;
+        for (; l + 3 <= k; l += 4) {
+          a0 = fma(sA[l + i * ld], sX[l + k * ld], a0);
+          a1 = fma(sA[l + 1 + i * ld], sX[l + 1 + k * ld], a1);
+          a2 = fma(sA[l + 2 + i * ld], sX[l + 2 + k * ld], a2);
+          a3 = fma(sA[l + 3 + i * ld], sX[l + 3 + k * ld], a3);
+        }
+        for (; l <= k; ++l) a0 = fma(sA[l + i * ld], sX[l + k * ld], a0);
+        D.R[i + (int64_t)k * W] = (i <= k) ? (a0 + a1) + (a2 + a3) : 0.0;
       }
   }
 }
@@ -872,7 +892,7 @@ __device__ __forceinline__ void hh_wide(const QrDesc& D, lds_f64* park, lds_f64*
 __global__ __launch_bounds__(kWideWaves * 64) void householder_wide_kernel(
     const QrDesc* __restrict__ qrs, int force, unsigned long long* counter) {
   const QrDesc& D = qrs[blockIdx.x];
-  const bool broke = *D.flag != 0;
+  const bool broke = !D.hh_direct && *D.flag != 0;  // flag written by the first chol pass
   if (!force && !broke && !D.hh_direct) return;
   const int64_t n = D.n, W = D.W;
   if (!hh_wide_panel(n, W)) return;
@@ -909,7 +929,7 @@ __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restri
                                                           int64_t lds_elems) {
   extern __shared__ __align__(16) double hsm[];
   const QrDesc& D = qrs[blockIdx.x];
-  const bool broke = *D.flag != 0;
+  const bool broke = !D.hh_direct && *D.flag != 0;  // flag written by the first chol pass
   if (!force && !broke && !D.hh_direct) return;
   const int64_t n = D.n, W = D.W;
   if (hh_wide_panel(n, W)) return;  // householder_wide_kernel's panel

@@ -214,8 +214,8 @@ int krp_lds_elems(const KrpDesc* kd, size_t count) {
 struct Arena {
   char* base = nullptr;
   size_t top = 0;
-  // int32 words that must be zero when the program starts (QR flags): one
-  // block, cleared by a single fill at the start
+  // int32 words of per-mode state (QR breakdown flags), one block; each flag
+  // is written by the first Cholesky pass before anything reads it
   int32_t* ctr_base = nullptr;
   int64_t ctr_used = 0;
   void* take(size_t bytes) {
@@ -1547,15 +1547,6 @@ tsk_status plan_many(tsk_handle h, const std::vector<Problem>& Ps, const std::ve
   B.nsums = (int)Ps.size();
   B.d_counter = h ? h->d_counter : nullptr;
   for (size_t j = 0; j < Ps.size(); ++j) build_sum(Ps[j], outs[j], B);
-  if (nctr > 0) {
-    Step f{};
-    f.kind = S_FILL;
-    f.ptr = ar.ctr_base;
-    f.rows = nctr;
-    f.value = 0;
-    f.bytes = 4.0 * nctr;
-    prog.steps.push_back(f);
-  }
   B.emit(prog);
   prog.meta_region = align_up(ar.top, 256);
   *bytes = prog.meta_region + align_up(prog.blob.size(), 256) + 256;
