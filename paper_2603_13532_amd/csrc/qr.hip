@@ -795,6 +795,9 @@ __device__ __forceinline__ void hh_wide(const QrDesc& D, lds_f64* park, lds_f64*
 #pragma unroll
         for (int r = 0; r < NR; ++r) cb[r] = a[r];
       }
+      // the other lanes read what lane j wrote: the fence keeps the compiler
+      // from forwarding or reusing earlier values of the row
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
       const double d = hh_wide_dot<NR>(cb, a, fb);
       pt[wave * 64 + lane] = d;
@@ -857,6 +860,9 @@ __device__ __forceinline__ void hh_wide(const QrDesc& D, lds_f64* park, lds_f64*
 #pragma unroll
         for (int r = 0; r < NR; ++r) cb[r] = a[r];
       }
+      // the other lanes read what lane j wrote: the fence keeps the compiler
+      // from forwarding or reusing earlier values of the row
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
       const double d = hh_wide_dot<NR>(cb, a, fb);
       pt[wave * 64 + lane] = d;
