@@ -257,3 +257,37 @@ def test_cholqr2_policy_reports_rank_deficiency(tsk):
     tsk.qr_fallback_count(DEV)  # cleared after one report
     x = T.sum_to_dense(ts)
     assert T.rel_err(RC.reconstruct(np_of(h), [np_of(q) for q in qs]), x) < 1e-12
+
+
+def test_breakdown_flags_do_not_outlive_a_call(tsk):
+    """The per-mode Cholesky breakdown flags live in the workspace and are
+    set by the first Cholesky pass of every call.  On one workspace, a call
+    on a rank-deficient sum (every mode falls back to Householder) followed
+    by a call on a full-rank sum of the same shapes: the second call takes no
+    fallback and matches a call on a fresh workspace bit for bit."""
+    import torch
+    low = synth.e1_low_rank_sum(seed=9, d=3, n=40, terms=12, r_true=6)
+    full = synth.random_sum(11, (40,) * 3, np.ones((12, 3), dtype=np.int64))
+    cores, factors = to_torch(low, DEV)
+    rc = tsk.Recompressor(cores, factors, "krp", [9], 3, coeffs=low["coeffs"])
+    c0 = tsk.qr_fallback_count(DEV)
+    qs, h = rc()
+    torch.cuda.synchronize()
+    c1 = tsk.qr_fallback_count(DEV)
+    assert c1 > c0  # total rank 6 < sketch width 9: the modes break down
+    x = T.sum_to_dense(low)
+    assert T.rel_err(RC.reconstruct(np_of(h), [np_of(q) for q in qs]), x) < 1e-12
+    fc, ff = to_torch(full, DEV)
+    with torch.no_grad():
+        for a, b in zip(cores, fc):
+            a.copy_(b)
+        for fa, fb in zip(factors, ff):
+            for a, b in zip(fa, fb):
+                a.copy_(b)
+    qs, h = rc()
+    torch.cuda.synchronize()
+    assert tsk.qr_fallback_count(DEV) == c1
+    q_ref, h_ref = run(tsk, full, "krp", [9], 3)
+    assert torch.equal(h, h_ref)
+    for q, qr in zip(qs, q_ref):
+        assert torch.equal(q, qr)
