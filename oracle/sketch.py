@@ -63,35 +63,3 @@ def structured_sketch_kron(tsum: dict, omegas) -> list:
 def structured_sketch(tsum: dict, omegas, kind: str) -> list:
     return structured_sketch_krp(tsum, omegas) if kind == "krp" else structured_sketch_kron(tsum, omegas)
 
-
-def factor_sketches(tsum: dict, omegas) -> list:
-    """P_k^(i) = U_k^(i)^T Omega_k for every term i and mode k (r x width).
-    For the Kronecker sketch the paper's M_k is the transpose of this."""
-    return [[us[k].T @ omegas[k] for k in range(len(us))] for us in tsum["factors"]]
-
-
-def core_sketches_krp(tsum: dict, omegas) -> list:
-    """V^(i)_(n) = G^(i)_(n) (KRP of P_j^(i), j != n, reverse order): r_n x m."""
-    d = len(tsum["dims"])
-    out = []
-    for g, us in zip(tsum["cores"], tsum["factors"]):
-        ms = [us[j].T @ omegas[j] for j in range(d)]
-        out.append([unfold(g, n) @ khatri_rao_list([ms[j] for j in reversed(range(d)) if j != n])
-                    for n in range(d)])
-    return out
-
-
-def core_sketches_kron(tsum: dict, omegas) -> list:
-    """V^(i)_(n) = (G^(i) x_{j != n} Omega_j^T U_j^(i))_(n): r_n x S_n."""
-    d = len(tsum["dims"])
-    out = []
-    for g, us in zip(tsum["cores"], tsum["factors"]):
-        row = []
-        for n in range(d):
-            v = g
-            for j in range(d):
-                if j != n:
-                    v = ttm(v, omegas[j].T @ us[j], j)
-            row.append(unfold(v, n))
-        out.append(row)
-    return out

@@ -156,6 +156,16 @@ tsk_status validate(tsk_handle h, const tsk_tucker_sum* sum, const tsk_sketch_sp
       P.W.push_back(S);
     }
   }
+  if (P.kind == TSK_SKETCH_KRP) {
+    // the Khatri-Rao kernels address a whole core through 31-bit byte offsets
+    const int64_t es = P.ps == P_FP64 ? 8 : 4;
+    for (int i = 0; i < P.s; ++i) {
+      int64_t cs = 1;
+      for (int k = 0; k < P.d; ++k) cs *= P.r(i, k);
+      if (cs * es >= (int64_t(1) << 31))
+        return fail(h, TSK_ERR_UNSUPPORTED, "core %d exceeds 2^31 bytes in the sketch precision", i);
+    }
+  }
   for (int n = 0; n < P.d; ++n) {
     P.w.push_back(std::min(P.dims[n], P.W[n]));
     if (P.dims[n] * P.W[n] > (int64_t(1) << 34))
@@ -218,6 +228,10 @@ struct Arena {
   // is written by the first Cholesky pass before anything reads it
   int32_t* ctr_base = nullptr;
   int64_t ctr_used = 0;
+  // Set when a planned launch would address an operand element beyond what
+  // the kernels' 31-bit in-tile byte offsets reach; the call then fails with
+  // TSK_ERR_UNSUPPORTED before anything is enqueued.
+  std::string too_far;
   void* take(size_t bytes) {
     top = align_up(top, 256);
     void* p = base + top;
@@ -305,6 +319,14 @@ struct GemmBatch {
     tiles += (int64_t)D.tiles_m * D.tiles_n * batch * splits;
     const double ein = prec == P_FP64 ? 8.0 : 4.0, ec = c_f64 ? 8.0 : 4.0;
     for (const auto& g : sg) {
+      // The K-loop reads a 64 x BK panel through 32-bit byte offsets from the
+      // panel origin, and offsets from 2^31 up read as zero: the farthest
+      // element, 63 rows and BK - 1 depths away, must stay below that.
+      const int64_t es = prec == P_FP64 ? 8 : 4, bk = 32;
+      const int64_t farA = (63 * std::abs(g.a_sx) + (bk - 1) * std::abs(g.a_sk)) * es;
+      const int64_t farB = (63 * std::abs(g.b_sx) + (bk - 1) * std::abs(g.b_sk)) * es;
+      if (std::max(farA, farB) >= (int64_t(1) << 31) && ar->too_far.empty())
+        ar->too_far = "an operand stride reaches past 2^31 bytes inside one 64-row tile";
       segs.push_back(g);
       flops += 2.0 * M * N * (double)g.K * batch;
       bytes += ein * (double)M * g.K * (g.strideA != 0 ? batch : 1) +
@@ -1539,6 +1561,7 @@ tsk_status plan_many(tsk_handle h, const std::vector<Problem>& Ps, const std::ve
     B0.nsums = (int)Ps.size();
     for (size_t j = 0; j < Ps.size(); ++j) build_sum(Ps[j], outs[j], B0);
     nctr = a0.ctr_used;
+    if (!a0.too_far.empty()) return fail(h, TSK_ERR_UNSUPPORTED, "%s", a0.too_far.c_str());
   }
   Arena ar;
   ar.base = ws;
@@ -1847,7 +1870,10 @@ static int selfcheck_impl(int32_t batch, const tsk_tucker_sum* sums, const tsk_s
   fake_handle.d_counter = (int64_t*)fake(256, "counter");
   Program p0;
   size_t need = 0;
-  plan_many(&fake_handle, Ps, outs, nullptr, p0, &need);
+  if (tsk_status st = plan_many(&fake_handle, Ps, outs, nullptr, p0, &need); st != TSK_OK) {
+    say(fake_handle.err);
+    return st;
+  }
   char* ws = (char*)fake(need, "workspace");
   Program prog;
   size_t need2 = 0;
@@ -1873,6 +1899,7 @@ static tsk_status plan_backward(const Problem& P, const BackwardIO& io, char* ws
   ar.base = ws;
   ar.ctr_base = (int32_t*)ar.take(256);
   build_backward(P, io, ar, prog);
+  if (!ar.too_far.empty()) return TSK_ERR_UNSUPPORTED;
   prog.meta_region = align_up(ar.top, 256);
   *bytes = prog.meta_region + align_up(prog.blob.size(), 256) + 256;
   return TSK_OK;
@@ -1938,7 +1965,10 @@ extern "C" int tsk_plan_selfcheck_backward(const tsk_tucker_sum* sum, const tsk_
   io.Hbar = fake(hsize * eo, "Hbar");
   Program p0;
   size_t need = 0;
-  plan_backward(P, io, nullptr, p0, &need);
+  if (plan_backward(P, io, nullptr, p0, &need) != TSK_OK) {
+    say("an operand stride reaches past 2^31 bytes inside one tile");
+    return TSK_ERR_UNSUPPORTED;
+  }
   char* ws = (char*)fake(need, "workspace");
   Program prog;
   size_t need2 = 0;
@@ -2116,7 +2146,7 @@ tsk_status tucker_sum_workspace_size(tsk_handle h, const tsk_tucker_sum* sum,
     out.R.assign(P.d, nullptr);
     Program prog;
     size_t b = 0;
-    plan(h, P, out, nullptr, prog, &b);
+    if (tsk_status pst = plan(h, P, out, nullptr, prog, &b); pst != TSK_OK) return pst;
     best = std::max(best, b);
   }
   *bytes = best;
@@ -2141,7 +2171,7 @@ tsk_status tucker_sum_sketch(tsk_handle h, const tsk_tucker_sum* sum, const tsk_
   if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   Program prog;
   size_t need = 0;
-  plan(h, P, out, (char*)ws, prog, &need);
+  if (tsk_status pst = plan(h, P, out, (char*)ws, prog, &need); pst != TSK_OK) return pst;
   if (ws_bytes < need)
     return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
   if ((st = set_device(h)) != TSK_OK) return st;
@@ -2175,7 +2205,7 @@ tsk_status tucker_sum_recompress(tsk_handle h, const tsk_tucker_sum* sum,
   if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   Program prog;
   size_t need = 0;
-  plan(h, P, out, (char*)ws, prog, &need);
+  if (tsk_status pst = plan(h, P, out, (char*)ws, prog, &need); pst != TSK_OK) return pst;
   if (ws_bytes < need)
     return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
   if ((st = set_device(h)) != TSK_OK) return st;
@@ -2267,7 +2297,7 @@ tsk_status tucker_sum_batched_workspace_size(tsk_handle h, int32_t batch, const 
     }
     Program prog;
     size_t nb = 0;
-    plan_many(h, Ps, outs, nullptr, prog, &nb);
+    if (tsk_status pst = plan_many(h, Ps, outs, nullptr, prog, &nb); pst != TSK_OK) return pst;
     best = std::max(best, nb);
   }
   *bytes = best;
@@ -2301,7 +2331,7 @@ tsk_status tucker_sum_recompress_batched(tsk_handle h, int32_t batch, const tsk_
   if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   Program prog;
   size_t need = 0;
-  plan_many(h, Ps, outs, (char*)ws, prog, &need);
+  if (tsk_status pst = plan_many(h, Ps, outs, (char*)ws, prog, &need); pst != TSK_OK) return pst;
   if (ws_bytes < need)
     return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
   if ((st = set_device(h)) != TSK_OK) return st;
@@ -2358,7 +2388,8 @@ tsk_status tucker_sum_backward_workspace_size(tsk_handle h, const tsk_tucker_sum
       io.factor_bar.assign((size_t)P.s * P.d, nullptr);
       Program prog;
       size_t nb = 0;
-      plan_backward(P, io, nullptr, prog, &nb);
+      if (plan_backward(P, io, nullptr, prog, &nb) != TSK_OK)
+        return fail(h, TSK_ERR_UNSUPPORTED, "an operand stride reaches past 2^31 bytes inside one tile");
       best = std::max(best, nb);
     }
   *bytes = best;
@@ -2384,7 +2415,8 @@ tsk_status tucker_sum_recompress_backward(tsk_handle h, const tsk_tucker_sum* su
   if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   Program prog;
   size_t need = 0;
-  plan_backward(P, io, (char*)ws, prog, &need);
+  if (plan_backward(P, io, (char*)ws, prog, &need) != TSK_OK)
+    return fail(h, TSK_ERR_UNSUPPORTED, "an operand stride reaches past 2^31 bytes inside one tile");
   if (ws_bytes < need)
     return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
   if ((st = set_device(h)) != TSK_OK) return st;

@@ -11,12 +11,27 @@ import pytest
 from conftest import ROOT, read_golden
 
 HEADER = os.path.join(ROOT, "include", "tsk.h")
+TEST_HEADER = os.path.join(ROOT, "include", "tsk_test.h")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b((?:tsk|tucker_sum)_\w+)\s*\(", text)))
+
+
+def exported_functions():
+    """Dynamic symbols the built library defines with the ABI's prefixes."""
+    import subprocess
+    from paper_2603_13532_amd import _lib
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    names = set()
+    for line in out.splitlines():
+        parts = line.split()
+        if len(parts) == 3 and parts[1] in ("T", "t") and re.match(r"(tsk|tucker_sum)_", parts[2]):
+            names.add(parts[2])
+    return names
 
 
 @pytest.fixture(scope="module")
@@ -30,6 +45,17 @@ def test_every_declared_symbol_is_exported(lib):
     assert "tucker_sum_sketch" in names and "tucker_sum_recompress" in names
     for name in names:
         assert hasattr(lib, name), name
+
+
+def test_every_export_is_declared(lib):
+    """No undeclared entry points: every exported tsk_* / tucker_sum_*
+    symbol is declared in the public header or in the test header, and every
+    test-header function is exported."""
+    public, testing = set(declared_functions()), set(declared_functions(TEST_HEADER))
+    assert not public & testing
+    exported = exported_functions()
+    assert exported - public - testing == set()
+    assert testing <= exported
 
 
 def test_binding_prototypes_cover_header():

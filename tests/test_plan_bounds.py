@@ -87,6 +87,28 @@ def test_selfcheck_detects_invalid_problem():
     assert rc == 1 and "ranks" in msg
 
 
+@pytest.mark.parametrize("n,prec,ok", [(4_000_000, "fp64", True), (5_000_000, "fp64", False),
+                                       (4_000_000, "fp32", True), (5_000_000, "fp32", False)])
+def test_long_modes_beyond_31_bit_tile_offsets_are_rejected(n, prec, ok):
+    """The contraction kernels reach a 64-row panel through 32-bit byte
+    offsets from its origin, and offsets of 2^31 and up read as zero.  The
+    Gram product of the QR reads the FP64 Y_n with stride n across a tile
+    (in every precision form), so a mode of 5M rows must be refused as
+    unsupported instead of silently computing with zeros."""
+    rc, msg = selfcheck((n, 6), [[2, 2]], "krp", [4], prec, prec, prec == "fp64", prec == "fp64")
+    if ok:
+        assert rc == 0, msg
+    else:
+        assert rc == 2 and "2^31" in msg, (rc, msg)
+
+
+def test_khatri_rao_core_beyond_31_bit_offsets_is_rejected():
+    rc, msg = selfcheck((20, 20), [[2 ** 14, 2 ** 14]], "krp", [4])
+    assert rc == 2 and "2^31" in msg, (rc, msg)
+    rc, msg = selfcheck((20, 20), [[2 ** 14, 2 ** 14]], "krp", [4], "fp32", "fp32", False, False)
+    assert rc == 0, msg
+
+
 def selfcheck_batched(sums, kind_sizes, prec="fp32", in_f64=False, out_f64=False):
     from paper_2603_13532_amd import _lib
     lib = _lib.load()
