@@ -157,6 +157,29 @@ tsk_status tucker_sum_recompress(tsk_handle handle, const tsk_tucker_sum* sum,
                                  tsk_dtype out_dtype, double* const* R_out, void* ws,
                                  size_t ws_bytes, void* stream);
 
+/* tucker_sum_recompress for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same computation and the same kernels, with no workspace
+ * argument.  Intermediates live in a static device array of
+ * TSK_NOALLOC_SCRATCH_BYTES that every device the library runs on holds
+ * until the process ends; launch descriptors are uploaded from pinned host
+ * memory that tsk_create set aside (at most TSK_NOALLOC_DESCRIPTOR_BYTES).
+ * The call performs no device or pinned-host allocation and no free.
+ * Returns TSK_ERR_WORKSPACE_TOO_SMALL (nothing enqueued) when the problem
+ * needs more scratch than the array holds (tucker_sum_workspace_size gives
+ * the need), TSK_ERR_UNSUPPORTED when its descriptors exceed the staging.
+ * All calls on one device share the array, which keeps the last call's
+ * contents: calls whose executions overlap on one device (different streams,
+ * threads or handles) race and must be serialised by the caller.  Before
+ * reusing the staging the call waits for the previous no-allocation call's
+ * descriptor upload on the same handle. */
+#define TSK_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+#define TSK_NOALLOC_DESCRIPTOR_BYTES ((size_t)1 << 20)
+tsk_status tucker_sum_recompress_noalloc(tsk_handle handle, const tsk_tucker_sum* sum,
+                                         const tsk_sketch_spec* spec, void* const* Q_out,
+                                         void* H_out, tsk_dtype out_dtype, double* const* R_out,
+                                         void* stream);
+
 /* Per-launch timing.  While enabled, every kernel a call enqueues is
  * bracketed by two HIP events on the call's stream (not inside stream
  * capture).  tsk_profile_report() waits for the recorded events, writes a

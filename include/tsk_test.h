@@ -41,7 +41,8 @@ int tsk_plan_selfcheck_backward(const tsk_tucker_sum* sum, const tsk_sketch_spec
                                 int out_dtype, int with_qbar, char* msg, size_t msglen);
 
 /* The batched self-check, then one line per planned launch in msg: kernel,
- * descriptors, workgroups, largest K-split and segment count. */
+ * descriptors, workgroups, largest K-split and segment count; a last line
+ * gives the workspace and descriptor-blob sizes in bytes. */
 int tsk_plan_describe(int32_t batch, const tsk_tucker_sum* sums, const tsk_sketch_spec* specs,
                       int out_dtype, char* msg, size_t msglen);
 

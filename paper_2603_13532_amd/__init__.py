@@ -22,7 +22,7 @@ __all__ = [
     "fortran", "empty_fortran", "krp_width", "kron_sizes", "sketch_widths", "sketch_omega",
     "tucker_sum_sketch", "tucker_sum_recompress", "qr_fallback_count", "Handle", "TskError",
     "Recompressor", "BatchRecompressor", "tucker_sum_recompress_batched",
-    "tucker_sum_recompress_backward", "recompress",
+    "tucker_sum_recompress_backward", "recompress", "tucker_sum_recompress_noalloc",
 ]
 
 
@@ -223,6 +223,29 @@ def tucker_sum_recompress(cores, factors, kind, sizes, seed, coeffs=None, omega=
                                        c_void_p(ws.data_ptr()), ws.numel(),
                                        c_void_p(_stream_ptr(m.device))), h.ptr)
     return (qs, hh, rs) if return_r else (qs, hh)
+
+
+def tucker_sum_recompress_noalloc(cores, factors, kind, sizes, seed, Q_out, H_out, coeffs=None,
+                                  sketch_prec="fp64", project_prec="fp64", qr_policy="auto",
+                                  R_out=None):
+    """tucker_sum_recompress into caller-allocated outputs (Q_out list, H_out,
+    optional R_out list; column-major, shapes as tucker_sum_recompress
+    returns) through the entry point that allocates nothing: intermediates
+    live in the library's static per-device scratch array, so calls that
+    overlap on one device race."""
+    m = _Marshal(cores, factors, coeffs, kind, sizes, seed, None, sketch_prec, project_prec,
+                 qr_policy)
+    h = Handle.get(m.device)
+    out_dtype = H_out.dtype
+    for t in list(Q_out) + [H_out] + list(R_out or []):
+        if not is_fortran(t):
+            raise ValueError("outputs must be column-major (empty_fortran)")
+    c_q = (c_void_p * m.d)(*[q.data_ptr() for q in Q_out])
+    c_r = None if R_out is None else (c_void_p * m.d)(*[r.data_ptr() for r in R_out])
+    check(load().tucker_sum_recompress_noalloc(h.ptr, byref(m.sum), byref(m.spec), c_q,
+                                               c_void_p(H_out.data_ptr()), _dtype_code(out_dtype),
+                                               c_r, c_void_p(_stream_ptr(m.device))), h.ptr)
+    return Q_out, H_out
 
 
 class Recompressor:

@@ -69,6 +69,9 @@ PROTOTYPES = {
     "tucker_sum_recompress": (c_int, [c_void_p, POINTER(TuckerSum), POINTER(SketchSpec),
                                       POINTER(c_void_p), c_void_p, c_int, POINTER(c_void_p),
                                       c_void_p, c_size_t, c_void_p]),
+    "tucker_sum_recompress_noalloc": (c_int, [c_void_p, POINTER(TuckerSum), POINTER(SketchSpec),
+                                              POINTER(c_void_p), c_void_p, c_int,
+                                              POINTER(c_void_p), c_void_p]),
     "tsk_qr_fallback_count": (c_int, [c_void_p, c_void_p, POINTER(c_int64)]),
     "tucker_sum_batched_workspace_size": (c_int, [c_void_p, c_int32, POINTER(TuckerSum),
                                                   POINTER(SketchSpec), POINTER(c_size_t)]),

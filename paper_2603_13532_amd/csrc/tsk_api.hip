@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -45,7 +46,21 @@ struct tsk_handle_ {
   std::vector<Staging> ring;
   size_t ring_next = 0;
   std::vector<void*> pinned_keep;  // staging owned by captured graphs
+  // tucker_sum_recompress_noalloc: the device address of this device's
+  // static scratch array, and pinned staging for its descriptor upload,
+  // both set up by tsk_create
+  char* scratch_dev = nullptr;
+  void* fixed_stage = nullptr;
+  hipEvent_t fixed_stage_done = nullptr;
 };
+
+// Device memory of tucker_sum_recompress_noalloc: one array per device,
+// held from library load until the process ends.  Host code never uses the
+// array's name as an address; it uses the per-device pointer that
+// hipGetSymbolAddress returns (tsk_handle_::scratch_dev).
+constexpr size_t kScratchBytes = TSK_NOALLOC_SCRATCH_BYTES;
+constexpr size_t kFixedStageBytes = TSK_NOALLOC_DESCRIPTOR_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -1482,17 +1497,32 @@ tsk_status acquire_staging(tsk_handle h, size_t bytes, bool capturing, void** ho
   return TSK_OK;
 }
 
-tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream) {
+// `fixed_stage`: upload the descriptors from the handle's preallocated
+// pinned buffer (waiting for its previous upload) and record no profiling
+// events, so that the call allocates nothing.
+tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream,
+                       bool fixed_stage = false) {
   char* meta = ws + prog.meta_region;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(stream, &cs) != hipSuccess)
     return fail(h, TSK_ERR_DEVICE, "hipStreamIsCapturing failed");
   const bool capturing = cs == hipStreamCaptureStatusActive;
+  const bool prof = h->prof && !capturing && !fixed_stage;
   if (!prog.blob.empty()) {
     void* host = nullptr;
     hipEvent_t ev = nullptr;
-    tsk_status st = acquire_staging(h, prog.blob.size(), capturing, &host, &ev);
-    if (st != TSK_OK) return st;
+    if (fixed_stage) {
+      if (prog.blob.size() > kFixedStageBytes)
+        return fail(h, TSK_ERR_UNSUPPORTED, "launch descriptors %zu bytes > %zu", prog.blob.size(),
+                    kFixedStageBytes);
+      if (hipEventSynchronize(h->fixed_stage_done) != hipSuccess)
+        return fail(h, TSK_ERR_DEVICE, "waiting for the previous descriptor upload failed");
+      host = h->fixed_stage;
+      ev = h->fixed_stage_done;
+    } else {
+      tsk_status st = acquire_staging(h, prog.blob.size(), capturing, &host, &ev);
+      if (st != TSK_OK) return st;
+    }
     std::memcpy(host, prog.blob.data(), prog.blob.size());
     if (hipMemcpyAsync(meta, host, prog.blob.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
       return fail(h, TSK_ERR_DEVICE, "descriptor upload failed");
@@ -1502,7 +1532,7 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
   for (const Step& st : prog.steps) {
     hipError_t e = hipSuccess;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (h->prof && !capturing) {
+    if (prof) {
       for (hipEvent_t* ev : {&ev0, &ev1}) {
         if (!h->event_pool.empty()) {
           *ev = h->event_pool.back();
@@ -1887,7 +1917,14 @@ static int selfcheck_impl(int32_t batch, const tsk_tucker_sum* sums, const tsk_s
     say(ck.err);
     return 98;
   }
-  say(describe ? describe_program(prog) : std::string("ok"));
+  if (describe) {
+    char tail[128];
+    snprintf(tail, sizeof tail, "workspace %zu bytes, descriptors %zu bytes\n", need,
+             prog.blob.size());
+    say(describe_program(prog) + tail);
+  } else {
+    say("ok");
+  }
   return 0;
 }
 
@@ -2027,6 +2064,33 @@ tsk_status tsk_create(tsk_handle* handle, int device) {
     delete h;
     return TSK_ERR_DEVICE;
   }
+  {
+    // each device holds its own copy of `scratch`: look its address up once
+    // per device, with that device current
+    static std::mutex mu;
+    static std::map<int, char*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+        hipFree(h->d_counter);
+        delete h;
+        return TSK_ERR_DEVICE;
+      }
+      it = addr.emplace(device, (char*)p).first;
+    }
+    h->scratch_dev = it->second;
+  }
+  if (hipHostMalloc(&h->fixed_stage, kFixedStageBytes, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&h->fixed_stage_done, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(h->fixed_stage_done, nullptr) != hipSuccess) {
+    if (h->fixed_stage) hipHostFree(h->fixed_stage);
+    if (h->fixed_stage_done) hipEventDestroy(h->fixed_stage_done);
+    hipFree(h->d_counter);
+    delete h;
+    return TSK_ERR_OUT_OF_MEMORY;
+  }
   *handle = h;
   return TSK_OK;
 }
@@ -2040,6 +2104,8 @@ tsk_status tsk_destroy(tsk_handle h) {
     if (sl.host) hipHostFree(sl.host);
   }
   for (void* p : h->pinned_keep) hipHostFree(p);
+  if (h->fixed_stage_done) hipEventDestroy(h->fixed_stage_done);
+  if (h->fixed_stage) hipHostFree(h->fixed_stage);
   for (auto& r : h->prof_records) {
     hipEventDestroy(r.begin);
     hipEventDestroy(r.end);
@@ -2210,6 +2276,41 @@ tsk_status tucker_sum_recompress(tsk_handle h, const tsk_tucker_sum* sum,
     return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
   if ((st = set_device(h)) != TSK_OK) return st;
   return run_program(h, prog, (char*)ws, (hipStream_t)stream);
+}
+
+tsk_status tucker_sum_recompress_noalloc(tsk_handle h, const tsk_tucker_sum* sum,
+                                         const tsk_sketch_spec* spec, void* const* Q_out,
+                                         void* H_out, tsk_dtype out_dtype, double* const* R_out,
+                                         void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  Problem P;
+  tsk_status st = validate(h, sum, spec, P);
+  if (st != TSK_OK) return st;
+  if (Q_out == nullptr || H_out == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "Q_out or H_out is NULL");
+  if (out_dtype != TSK_F64 && out_dtype != TSK_F32) return fail(h, TSK_ERR_INVALID_ARG, "bad out_dtype");
+  Outputs out;
+  out.recompress = true;
+  out.out_f64 = out_dtype == TSK_F64;
+  out.H = H_out;
+  for (int n = 0; n < P.d; ++n) {
+    if (Q_out[n] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "Q_out[%d] is NULL", n);
+    out.Q.push_back(Q_out[n]);
+    if (R_out != nullptr) {
+      if (R_out[n] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "R_out[%d] is NULL", n);
+      out.R.push_back(R_out[n]);
+    }
+  }
+  if (h->scratch_dev == nullptr) return fail(h, TSK_ERR_DEVICE, "no scratch address for the device");
+  Program prog;
+  size_t need = 0;
+  if (tsk_status pst = plan(h, P, out, h->scratch_dev, prog, &need); pst != TSK_OK) return pst;
+  if (need > kScratchBytes)
+    return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL,
+                "problem needs %zu bytes of device scratch; the no-allocation call holds %zu", need,
+                kScratchBytes);
+  if ((st = set_device(h)) != TSK_OK) return st;
+  return run_program(h, prog, h->scratch_dev, (hipStream_t)stream, true);
 }
 
 tsk_status tsk_profile_enable(tsk_handle h, int32_t on) {
