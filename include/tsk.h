@@ -157,6 +157,23 @@ tsk_status tucker_sum_recompress(tsk_handle handle, const tsk_tucker_sum* sum,
                                  tsk_dtype out_dtype, double* const* R_out, void* ws,
                                  size_t ws_bytes, void* stream);
 
+/* Stage 3 alone (Section 3.3, projection of each summand by linearity):
+ *   H = sum_i c_i G^(i) x_1 B_1^T U_1^(i) ... x_d B_d^T U_d^(i)
+ * for caller-given bases B_k (bases[k]: device n_k x widths[k], column-major,
+ * ld n_k, element type basis_dtype; orthonormal columns are what makes
+ * [[H; B]] the projection of the sum, but any matrices are accepted), in the
+ * arithmetic project_prec.  H_out is a device widths[0] x ... x widths[d-1]
+ * buffer of out_dtype.  The core projection of tucker_sum_recompress is this
+ * computation on its Q_n; with the Stage 4 factors it gives the truncated
+ * core.  Workspace as for tucker_sum_recompress. */
+tsk_status tucker_sum_project_workspace_size(tsk_handle handle, const tsk_tucker_sum* sum,
+                                             const int64_t* widths, tsk_dtype basis_dtype,
+                                             tsk_precision project_prec, size_t* bytes);
+tsk_status tucker_sum_project(tsk_handle handle, const tsk_tucker_sum* sum,
+                              const void* const* bases, const int64_t* widths,
+                              tsk_dtype basis_dtype, tsk_precision project_prec, void* H_out,
+                              tsk_dtype out_dtype, void* ws, size_t ws_bytes, void* stream);
+
 /* tucker_sum_recompress for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the same computation and the same kernels, with no workspace

@@ -40,6 +40,11 @@ int tsk_plan_selfcheck_batched(int32_t batch, const tsk_tucker_sum* sums,
 int tsk_plan_selfcheck_backward(const tsk_tucker_sum* sum, const tsk_sketch_spec* spec,
                                 int out_dtype, int with_qbar, char* msg, size_t msglen);
 
+/* Self-check of tucker_sum_project (basis_dtype, out_dtype: tsk_dtype
+ * values; project_prec: a tsk_precision value). */
+int tsk_plan_selfcheck_project(const tsk_tucker_sum* sum, const int64_t* widths, int basis_dtype,
+                               int project_prec, int out_dtype, char* msg, size_t msglen);
+
 /* The batched self-check, then one line per planned launch in msg: kernel,
  * descriptors, workgroups, largest K-split and segment count; a last line
  * gives the workspace and descriptor-blob sizes in bytes. */

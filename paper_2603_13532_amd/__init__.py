@@ -23,6 +23,7 @@ __all__ = [
     "tucker_sum_sketch", "tucker_sum_recompress", "qr_fallback_count", "Handle", "TskError",
     "Recompressor", "BatchRecompressor", "tucker_sum_recompress_batched",
     "tucker_sum_recompress_backward", "recompress", "tucker_sum_recompress_noalloc",
+    "tucker_sum_project",
 ]
 
 
@@ -223,6 +224,31 @@ def tucker_sum_recompress(cores, factors, kind, sizes, seed, coeffs=None, omega=
                                        c_void_p(ws.data_ptr()), ws.numel(),
                                        c_void_p(_stream_ptr(m.device))), h.ptr)
     return (qs, hh, rs) if return_r else (qs, hh)
+
+
+def tucker_sum_project(cores, factors, bases, coeffs=None, project_prec="fp64", out_dtype=None):
+    """Stage 3 alone: H = sum_i c_i G^(i) x_k B_k^T U_k^(i) for the given bases
+    (list of d tensors of shape (n_k, w_k), float64 or float32)."""
+    m = _Marshal(cores, factors, coeffs, "krp", [1], 0, None, project_prec, project_prec, "auto")
+    h = Handle.get(m.device)
+    bases = [fortran(b) for b in bases]
+    bdt = bases[0].dtype
+    if any(b.dtype != bdt or b.dim() != 2 or b.shape[0] != m.dims[k] for k, b in enumerate(bases)):
+        raise ValueError("bases must be (n_k, w_k) tensors of one dtype")
+    out_dtype = m.dtype if out_dtype is None else out_dtype
+    widths = [int(b.shape[1]) for b in bases]
+    c_w = (c_int64 * m.d)(*widths)
+    c_b = (c_void_p * m.d)(*[b.data_ptr() for b in bases])
+    nbytes = c_size_t()
+    check(load().tucker_sum_project_workspace_size(h.ptr, byref(m.sum), c_w, _dtype_code(bdt),
+                                                   PRECISIONS[project_prec], byref(nbytes)), h.ptr)
+    ws = h.workspace(nbytes.value)
+    hh = empty_fortran(tuple(widths), out_dtype, m.device)
+    check(load().tucker_sum_project(h.ptr, byref(m.sum), c_b, c_w, _dtype_code(bdt),
+                                    PRECISIONS[project_prec], c_void_p(hh.data_ptr()),
+                                    _dtype_code(out_dtype), c_void_p(ws.data_ptr()), ws.numel(),
+                                    c_void_p(_stream_ptr(m.device))), h.ptr)
+    return hh
 
 
 def tucker_sum_recompress_noalloc(cores, factors, kind, sizes, seed, Q_out, H_out, coeffs=None,

@@ -69,6 +69,11 @@ PROTOTYPES = {
     "tucker_sum_recompress": (c_int, [c_void_p, POINTER(TuckerSum), POINTER(SketchSpec),
                                       POINTER(c_void_p), c_void_p, c_int, POINTER(c_void_p),
                                       c_void_p, c_size_t, c_void_p]),
+    "tucker_sum_project_workspace_size": (c_int, [c_void_p, POINTER(TuckerSum), POINTER(c_int64),
+                                                  c_int, c_int, POINTER(c_size_t)]),
+    "tucker_sum_project": (c_int, [c_void_p, POINTER(TuckerSum), POINTER(c_void_p),
+                                   POINTER(c_int64), c_int, c_int, c_void_p, c_int, c_void_p,
+                                   c_size_t, c_void_p]),
     "tucker_sum_recompress_noalloc": (c_int, [c_void_p, POINTER(TuckerSum), POINTER(SketchSpec),
                                               POINTER(c_void_p), c_void_p, c_int,
                                               POINTER(c_void_p), c_void_p]),

@@ -101,17 +101,12 @@ struct Problem {
   int r(int i, int k) const { return ranks[(size_t)i * d + k]; }
 };
 
+tsk_status validate_sum(tsk_handle h, const tsk_tucker_sum* sum, Problem& P);
+tsk_status validate_spec(tsk_handle h, const tsk_sketch_spec* spec, Problem& P);
+
 tsk_status validate(tsk_handle h, const tsk_tucker_sum* sum, const tsk_sketch_spec* spec,
                     Problem& P) {
   if (sum == nullptr || spec == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "sum or spec is NULL");
-  if (sum->order < 2 || sum->order > kMaxOrder)
-    return fail(h, TSK_ERR_INVALID_ARG, "order %d outside [2, %d]", sum->order, kMaxOrder);
-  if (sum->num_terms < 1) return fail(h, TSK_ERR_INVALID_ARG, "num_terms %d < 1", sum->num_terms);
-  if (sum->dims == nullptr || sum->ranks == nullptr || sum->cores == nullptr ||
-      sum->factors == nullptr)
-    return fail(h, TSK_ERR_INVALID_ARG, "dims, ranks, cores or factors is NULL");
-  if (sum->dtype != TSK_F64 && sum->dtype != TSK_F32)
-    return fail(h, TSK_ERR_INVALID_ARG, "bad dtype %d", (int)sum->dtype);
   if (spec->kind != TSK_SKETCH_KRP && spec->kind != TSK_SKETCH_KRON)
     return fail(h, TSK_ERR_INVALID_ARG, "bad sketch kind %d", (int)spec->kind);
   if (spec->sizes == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "sketch sizes is NULL");
@@ -120,14 +115,29 @@ tsk_status validate(tsk_handle h, const tsk_tucker_sum* sum, const tsk_sketch_sp
     return fail(h, TSK_ERR_INVALID_ARG, "bad precision");
   if (spec->qr_policy < 0 || spec->qr_policy > 2)
     return fail(h, TSK_ERR_INVALID_ARG, "bad qr_policy %d", spec->qr_policy);
-  P.d = sum->order;
-  P.s = sum->num_terms;
-  P.in_f64 = sum->dtype == TSK_F64;
+  if (tsk_status st = validate_sum(h, sum, P); st != TSK_OK) return st;
   P.kind = spec->kind;
   P.seed = spec->seed;
   P.ps = spec->sketch_prec;
   P.pp = spec->project_prec;
   P.qr_policy = spec->qr_policy;
+  return validate_spec(h, spec, P);
+}
+
+// The Tucker sum alone: order, terms, sizes and pointers.
+tsk_status validate_sum(tsk_handle h, const tsk_tucker_sum* sum, Problem& P) {
+  if (sum == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "sum is NULL");
+  if (sum->order < 2 || sum->order > kMaxOrder)
+    return fail(h, TSK_ERR_INVALID_ARG, "order %d outside [2, %d]", sum->order, kMaxOrder);
+  if (sum->num_terms < 1) return fail(h, TSK_ERR_INVALID_ARG, "num_terms %d < 1", sum->num_terms);
+  if (sum->dims == nullptr || sum->ranks == nullptr || sum->cores == nullptr ||
+      sum->factors == nullptr)
+    return fail(h, TSK_ERR_INVALID_ARG, "dims, ranks, cores or factors is NULL");
+  if (sum->dtype != TSK_F64 && sum->dtype != TSK_F32)
+    return fail(h, TSK_ERR_INVALID_ARG, "bad dtype %d", (int)sum->dtype);
+  P.d = sum->order;
+  P.s = sum->num_terms;
+  P.in_f64 = sum->dtype == TSK_F64;
   for (int k = 0; k < P.d; ++k) {
     if (sum->dims[k] < 1) return fail(h, TSK_ERR_INVALID_ARG, "dims[%d] = %lld < 1", k, (long long)sum->dims[k]);
     if (sum->dims[k] > (1 << 30)) return fail(h, TSK_ERR_UNSUPPORTED, "dims[%d] too large", k);
@@ -150,6 +160,11 @@ tsk_status validate(tsk_handle h, const tsk_tucker_sum* sum, const tsk_sketch_sp
     }
     P.coeffs.push_back(sum->coeffs ? sum->coeffs[i] : 1.0);
   }
+  return TSK_OK;
+}
+
+// Sketch sizes and widths of a validated sum.
+tsk_status validate_spec(tsk_handle h, const tsk_sketch_spec* spec, Problem& P) {
   if (P.kind == TSK_SKETCH_KRP) {
     if (spec->sizes[0] < 1) return fail(h, TSK_ERR_INVALID_ARG, "KRP width %d < 1", spec->sizes[0]);
     for (int k = 0; k < P.d; ++k) {
@@ -469,6 +484,134 @@ struct Builder {
   }
   void emit(Program& prog);
 };
+
+// Stage 3 (Section 3.3): W_k^(i) = Q_k^T U_k^(i), then the multi-TTM
+// H = sum_i c_i G^(i) x_1 W_1^(i) ... x_d W_d^(i), modes 0..d-2 per term and
+// the last mode K-concatenated over the terms.  Q[n] is n_n x w_n (FP64 when
+// q_f64, else FP32); core_s / fac_s are the inputs already held in the
+// sketch element type (s64), reused when it is also the projection's.
+void build_projection(const Problem& P, const std::vector<const void*>& Q, bool q_f64,
+                      const std::vector<const void*>& core_s,
+                      const std::vector<const void*>& fac_s, bool s64, void* H, bool out_f64,
+                      Builder& B) {
+  Arena& ar = B.ar;
+  const int d = P.d, s = P.s;
+  const bool tp64 = is_fp64(P.pp);
+  const size_t ep = esize(tp64);
+  const bool ts64 = s64;
+  std::vector<const void*> Qp(d);
+  std::vector<CopyJob>& cq = B.copies[ST_QCOPY];
+  for (int n = 0; n < d; ++n) {
+    if (tp64 == q_f64) {
+      Qp[n] = Q[n];
+    } else {
+      void* p = ar.take(P.dims[n] * P.w[n] * ep);
+      cq.push_back(CopyJob{p, Q[n], P.dims[n], P.w[n], P.dims[n], P.dims[n], tp64 ? 1 : 0,
+                           q_f64 ? 1 : 0});
+      Qp[n] = p;
+    }
+  }
+  // inputs in the projection element type
+  std::vector<const void*> core_p(s), fac_p((size_t)s * d);
+  for (int i = 0; i < s; ++i) {
+    int64_t csize = 1;
+    for (int k = 0; k < d; ++k) csize *= P.r(i, k);
+    if (P.in_f64 == tp64) {
+      core_p[i] = P.cores[i];
+    } else if (ts64 == tp64) {
+      core_p[i] = core_s[i];
+    } else {
+      void* p = ar.take(csize * ep);
+      cq.push_back(CopyJob{p, P.cores[i], csize, 1, csize, csize, tp64, P.in_f64});
+      core_p[i] = p;
+    }
+    for (int k = 0; k < d; ++k) {
+      const size_t idx = (size_t)i * d + k;
+      if (P.in_f64 == tp64) {
+        fac_p[idx] = P.factors[idx];
+      } else if (ts64 == tp64) {
+        fac_p[idx] = fac_s[idx];
+      } else {
+        void* p = ar.take(P.dims[k] * P.r(i, k) * ep);
+        cq.push_back(CopyJob{p, P.factors[idx], P.dims[k], P.r(i, k), P.dims[k], P.dims[k], tp64,
+                             P.in_f64});
+        fac_p[idx] = p;
+      }
+    }
+  }
+  std::vector<void*> Wm((size_t)s * d);
+  {
+    GemmBatch& gb = B.g(ST_PROJW, P.pp, R_PROJ_W);
+    int64_t tiles0 = 0, kt = 0;
+    for (int i = 0; i < s; ++i)
+      for (int k = 0; k < d; ++k) {
+        tiles0 += ceil_div(P.w[k], 64) * ceil_div(P.r(i, k), 64);
+        kt = std::max<int64_t>(kt, ceil_div(P.dims[k], tp64 ? 16 : 32));
+      }
+    const int splits = B.splits(tiles0, kt);
+    for (int i = 0; i < s; ++i)
+      for (int k = 0; k < d; ++k) {
+        const int64_t n = P.dims[k], r = P.r(i, k), w = P.w[k];
+        void* p = ar.take(w * r * ep);
+        Wm[(size_t)i * d + k] = p;
+        gb.add(p, tp64, w, 0, (int)w, (int)r, 1, 0,
+               {seg(Qp[k], n, 1, 0, fac_p[(size_t)i * d + k], n, 1, 0, n)}, splits);
+      }
+  }
+  // multi-TTM, modes 0..d-2 per term, then the last mode K-concatenated over terms
+  std::vector<std::vector<int64_t>> shape(s);
+  std::vector<const void*> cur(s);
+  std::vector<void*> buf0(s), buf1(s);
+  for (int i = 0; i < s; ++i) {
+    for (int k = 0; k < d; ++k) shape[i].push_back(P.r(i, k));
+    int64_t mx = 1;
+    std::vector<int64_t> sh = shape[i];
+    for (int k = 0; k < d - 1; ++k) {
+      sh[k] = P.w[k];
+      int64_t sz = 1;
+      for (auto x : sh) sz *= x;
+      mx = std::max(mx, sz);
+    }
+    buf0[i] = ar.take(mx * ep);
+    buf1[i] = ar.take(mx * ep);
+    cur[i] = core_p[i];
+  }
+  for (int k = 0; k < d - 1; ++k) {
+    GemmBatch& gb = B.g(ST_TTM + k, P.pp, R_PROJ_TTM);
+    for (int i = 0; i < s; ++i) {
+      const int64_t rk = shape[i][k], w = P.w[k];
+      const void* Wk = Wm[(size_t)i * d + k];  // w x r_k
+      void* outp = (k % 2 == 0) ? buf0[i] : buf1[i];
+      int64_t L = 1, Rr = 1;
+      for (int j = 0; j < k; ++j) L *= shape[i][j];
+      for (int j = k + 1; j < d; ++j) Rr *= shape[i][j];
+      if (k == 0) {
+        gb.add(outp, tp64, w, 0, (int)w, (int)Rr, 1, 0, {seg(Wk, 1, w, 0, cur[i], rk, 1, 0, rk)});
+      } else {
+        gb.add(outp, tp64, L, L * w, (int)L, (int)w, (int)Rr, 0,
+               {seg(cur[i], 1, L, L * rk, Wk, 1, w, 0, rk)});
+      }
+      shape[i][k] = w;
+      cur[i] = outp;
+    }
+  }
+  {
+    GemmBatch& gb = B.g(ST_FINAL, P.pp, R_PROJ_FINAL);
+    int64_t L = 1;
+    for (int k = 0; k < d - 1; ++k) L *= P.w[k];
+    const int64_t w = P.w[d - 1];
+    std::vector<GemmSeg> sg;
+    for (int i = 0; i < s; ++i) {
+      const int64_t rl = shape[i][d - 1];
+      sg.push_back(seg(cur[i], 1, L, 0, Wm[(size_t)i * d + d - 1], 1, w, 0, rl, P.coeffs[i]));
+    }
+    int64_t kt = 0;
+    for (int i = 0; i < s; ++i) kt += ceil_div(shape[i][d - 1], tp64 ? 16 : 32);
+    const int splits = B.splits(ceil_div(L, 64) * ceil_div(w, 64), kt);
+    gb.add(H, out_f64, L, 0, (int)L, (int)w, 1, 0, sg, splits);
+  }
+}
+
 
 // Build the launch program for one Tucker sum.  All workspace addresses come
 // from `ar`; the meta blob is placed last by the caller.
@@ -790,122 +933,14 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
   }
   for (auto& q : qd) B.qr.push_back(q);
 
-  // ---- core projection (Section 3.3): W_k^(i) = Q_k^T U_k^(i), then the
-  // multi-TTM H = sum_i c_i G^(i) x_1 W_1^(i) ... x_d W_d^(i)
-  std::vector<const void*> Qp(d);
+  // ---- core projection (Section 3.3)
   std::vector<CopyJob>& cq = B.copies[ST_QCOPY];
-  for (int n = 0; n < d; ++n) {
-    if (tp64) {
-      Qp[n] = Qd[n];
-    } else {
-      void* p = ar.take(P.dims[n] * P.w[n] * 4);
-      cq.push_back(CopyJob{p, Qd[n], P.dims[n], P.w[n], P.dims[n], P.dims[n], 0, 1});
-      Qp[n] = p;
-    }
-    if (!out.out_f64)
+  if (!out.out_f64)
+    for (int n = 0; n < d; ++n)
       cq.push_back(CopyJob{out.Q[n], Qd[n], P.dims[n], P.w[n], P.dims[n], P.dims[n], 0, 1});
-  }
-  // inputs in the projection element type
-  std::vector<const void*> core_p(s), fac_p((size_t)s * d);
-  for (int i = 0; i < s; ++i) {
-    int64_t csize = 1;
-    for (int k = 0; k < d; ++k) csize *= P.r(i, k);
-    if (P.in_f64 == tp64) {
-      core_p[i] = P.cores[i];
-    } else if (ts64 == tp64) {
-      core_p[i] = core_s[i];
-    } else {
-      void* p = ar.take(csize * ep);
-      cq.push_back(CopyJob{p, P.cores[i], csize, 1, csize, csize, tp64, P.in_f64});
-      core_p[i] = p;
-    }
-    for (int k = 0; k < d; ++k) {
-      const size_t idx = (size_t)i * d + k;
-      if (P.in_f64 == tp64) {
-        fac_p[idx] = P.factors[idx];
-      } else if (ts64 == tp64) {
-        fac_p[idx] = fac_s[idx];
-      } else {
-        void* p = ar.take(P.dims[k] * P.r(i, k) * ep);
-        cq.push_back(CopyJob{p, P.factors[idx], P.dims[k], P.r(i, k), P.dims[k], P.dims[k], tp64,
-                             P.in_f64});
-        fac_p[idx] = p;
-      }
-    }
-  }
-  std::vector<void*> Wm((size_t)s * d);
-  {
-    GemmBatch& gb = B.g(ST_PROJW, P.pp, R_PROJ_W);
-    int64_t tiles0 = 0, kt = 0;
-    for (int i = 0; i < s; ++i)
-      for (int k = 0; k < d; ++k) {
-        tiles0 += ceil_div(P.w[k], 64) * ceil_div(P.r(i, k), 64);
-        kt = std::max<int64_t>(kt, ceil_div(P.dims[k], tp64 ? 16 : 32));
-      }
-    const int splits = B.splits(tiles0, kt);
-    for (int i = 0; i < s; ++i)
-      for (int k = 0; k < d; ++k) {
-        const int64_t n = P.dims[k], r = P.r(i, k), w = P.w[k];
-        void* p = ar.take(w * r * ep);
-        Wm[(size_t)i * d + k] = p;
-        gb.add(p, tp64, w, 0, (int)w, (int)r, 1, 0,
-               {seg(Qp[k], n, 1, 0, fac_p[(size_t)i * d + k], n, 1, 0, n)}, splits);
-      }
-  }
-  // multi-TTM, modes 0..d-2 per term, then the last mode K-concatenated over terms
-  std::vector<std::vector<int64_t>> shape(s);
-  std::vector<const void*> cur(s);
-  std::vector<void*> buf0(s), buf1(s);
-  for (int i = 0; i < s; ++i) {
-    for (int k = 0; k < d; ++k) shape[i].push_back(P.r(i, k));
-    int64_t mx = 1;
-    std::vector<int64_t> sh = shape[i];
-    for (int k = 0; k < d - 1; ++k) {
-      sh[k] = P.w[k];
-      int64_t sz = 1;
-      for (auto x : sh) sz *= x;
-      mx = std::max(mx, sz);
-    }
-    buf0[i] = ar.take(mx * ep);
-    buf1[i] = ar.take(mx * ep);
-    cur[i] = core_p[i];
-  }
-  for (int k = 0; k < d - 1; ++k) {
-    GemmBatch& gb = B.g(ST_TTM + k, P.pp, R_PROJ_TTM);
-    for (int i = 0; i < s; ++i) {
-      const int64_t rk = shape[i][k], w = P.w[k];
-      const void* Wk = Wm[(size_t)i * d + k];  // w x r_k
-      void* outp = (k % 2 == 0) ? buf0[i] : buf1[i];
-      int64_t L = 1, Rr = 1;
-      for (int j = 0; j < k; ++j) L *= shape[i][j];
-      for (int j = k + 1; j < d; ++j) Rr *= shape[i][j];
-      if (k == 0) {
-        gb.add(outp, tp64, w, 0, (int)w, (int)Rr, 1, 0, {seg(Wk, 1, w, 0, cur[i], rk, 1, 0, rk)});
-      } else {
-        gb.add(outp, tp64, L, L * w, (int)L, (int)w, (int)Rr, 0,
-               {seg(cur[i], 1, L, L * rk, Wk, 1, w, 0, rk)});
-      }
-      shape[i][k] = w;
-      cur[i] = outp;
-    }
-  }
-  {
-    GemmBatch& gb = B.g(ST_FINAL, P.pp, R_PROJ_FINAL);
-    int64_t L = 1;
-    for (int k = 0; k < d - 1; ++k) L *= P.w[k];
-    const int64_t w = P.w[d - 1];
-    std::vector<GemmSeg> sg;
-    for (int i = 0; i < s; ++i) {
-      const int64_t rl = shape[i][d - 1];
-      sg.push_back(seg(cur[i], 1, L, 0, Wm[(size_t)i * d + d - 1], 1, w, 0, rl, P.coeffs[i]));
-    }
-    int64_t kt = 0;
-    for (int i = 0; i < s; ++i) kt += ceil_div(shape[i][d - 1], tp64 ? 16 : 32);
-    const int splits = B.splits(ceil_div(L, 64) * ceil_div(w, 64), kt);
-    gb.add(out.H, out.out_f64, L, 0, (int)L, (int)w, 1, 0, sg, splits);
-  }
+  std::vector<const void*> Qc(Qd.begin(), Qd.end());
+  build_projection(P, Qc, true, core_s, fac_s, ts64, out.H, out.out_f64, B);
 }
-
 
 void Builder::emit(Program& prog) {
   auto emit_copy_stage = [&](int stage) {
@@ -1611,6 +1646,46 @@ tsk_status plan(tsk_handle h, const Problem& P, const Outputs& out, char* ws, Pr
   return plan_many(h, std::vector<Problem>{P}, std::vector<Outputs>{out}, ws, prog, bytes);
 }
 
+// Stage 3 alone: bases Q (FP64 when q_f64) of widths P.w.
+tsk_status plan_project(tsk_handle h, const Problem& P, const std::vector<const void*>& Q,
+                        bool q_f64, void* H, bool out_f64, char* ws, Program& prog,
+                        size_t* bytes) {
+  Arena ar;
+  ar.base = ws;
+  ar.ctr_base = (int32_t*)ar.take(256);
+  Builder B(ar);
+  B.d_counter = h ? h->d_counter : nullptr;
+  build_projection(P, Q, q_f64, P.cores, P.factors, P.in_f64, H, out_f64, B);
+  if (!ar.too_far.empty()) return fail(h, TSK_ERR_UNSUPPORTED, "%s", ar.too_far.c_str());
+  B.emit(prog);
+  prog.meta_region = align_up(ar.top, 256);
+  *bytes = prog.meta_region + align_up(prog.blob.size(), 256) + 256;
+  return TSK_OK;
+}
+
+// Problem of a Stage-3-only call: the sum, the bases' widths and the
+// projection arithmetic.
+tsk_status validate_project(tsk_handle h, const tsk_tucker_sum* sum, const int64_t* widths,
+                            int32_t project_prec, Problem& P) {
+  if (tsk_status st = validate_sum(h, sum, P); st != TSK_OK) return st;
+  if (widths == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "widths is NULL");
+  if (project_prec < TSK_PREC_FP64 || project_prec > TSK_PREC_BF16X6)
+    return fail(h, TSK_ERR_INVALID_ARG, "bad precision");
+  P.pp = project_prec;
+  P.ps = project_prec;
+  int64_t hsize = 1;
+  for (int n = 0; n < P.d; ++n) {
+    if (widths[n] < 1) return fail(h, TSK_ERR_INVALID_ARG, "widths[%d] < 1", n);
+    if (P.dims[n] * widths[n] > (int64_t(1) << 34))
+      return fail(h, TSK_ERR_UNSUPPORTED, "basis of mode %d too large", n);
+    hsize *= widths[n];
+    if (hsize > (int64_t(1) << 34)) return fail(h, TSK_ERR_UNSUPPORTED, "projected core too large");
+    P.w.push_back(widths[n]);
+    P.W.push_back(widths[n]);
+  }
+  return TSK_OK;
+}
+
 tsk_status set_device(tsk_handle h) {
   if (hipSetDevice(h->device) != hipSuccess) return fail(h, TSK_ERR_DEVICE, "hipSetDevice failed");
   return TSK_OK;
@@ -2024,6 +2099,72 @@ extern "C" int tsk_plan_selfcheck_backward(const tsk_tucker_sum* sum, const tsk_
 }
 
 
+extern "C" int tsk_plan_selfcheck_project(const tsk_tucker_sum* sum, const int64_t* widths,
+                                          int basis_dtype, int project_prec, int out_dtype,
+                                          char* msg, size_t msglen) {
+  auto say = [&](const std::string& s) {
+    if (msg && msglen) {
+      std::strncpy(msg, s.c_str(), msglen - 1);
+      msg[msglen - 1] = 0;
+    }
+  };
+  tsk_handle_ scratch_handle;
+  Problem P;
+  if (tsk_status st = validate_project(&scratch_handle, sum, widths, project_prec, P); st != TSK_OK) {
+    say(scratch_handle.err);
+    return st;
+  }
+  Checker ck;
+  uintptr_t next = (uintptr_t)1 << 44;
+  auto fake = [&](size_t bytes, const char* name) {
+    void* p = (void*)next;
+    ck.add(p, bytes, name);
+    next += align_up(bytes, (size_t)1 << 20) + ((size_t)1 << 30);
+    return p;
+  };
+  const size_t ein = P.in_f64 ? 8 : 4, eb = basis_dtype == TSK_F64 ? 8 : 4,
+               eo = out_dtype == TSK_F64 ? 8 : 4;
+  for (int i = 0; i < P.s; ++i) {
+    int64_t cs = 1;
+    for (int k = 0; k < P.d; ++k) cs *= P.r(i, k);
+    P.cores[i] = fake(cs * ein, "core");
+    for (int k = 0; k < P.d; ++k)
+      P.factors[(size_t)i * P.d + k] = fake(P.dims[k] * P.r(i, k) * ein, "factor");
+  }
+  std::vector<const void*> Q;
+  int64_t hsize = 1;
+  for (int n = 0; n < P.d; ++n) {
+    Q.push_back(fake(P.dims[n] * P.w[n] * eb, "basis"));
+    hsize *= P.w[n];
+  }
+  void* H = fake(hsize * eo, "H");
+  tsk_handle_ fake_handle;
+  Program p0;
+  size_t need = 0;
+  if (tsk_status st = plan_project(&fake_handle, P, Q, basis_dtype == TSK_F64, H,
+                                   out_dtype == TSK_F64, nullptr, p0, &need);
+      st != TSK_OK) {
+    say(fake_handle.err);
+    return st;
+  }
+  char* ws = (char*)fake(need, "workspace");
+  Program prog;
+  size_t need2 = 0;
+  plan_project(&fake_handle, P, Q, basis_dtype == TSK_F64, H, out_dtype == TSK_F64, ws, prog,
+               &need2);
+  if (need2 != need) {
+    say("workspace size differs between the size query and the call");
+    return 99;
+  }
+  check_program(prog, ck);
+  if (!ck.ok) {
+    say(ck.err);
+    return 98;
+  }
+  say("ok");
+  return 0;
+}
+
 // Host-only bounds self-check of a planned call (tests; not part of the ABI header).
 extern "C" int tsk_plan_describe(int32_t batch, const tsk_tucker_sum* sums,
                                  const tsk_sketch_spec* specs, int out_dtype, char* msg,
@@ -2311,6 +2452,61 @@ tsk_status tucker_sum_recompress_noalloc(tsk_handle h, const tsk_tucker_sum* sum
                 kScratchBytes);
   if ((st = set_device(h)) != TSK_OK) return st;
   return run_program(h, prog, h->scratch_dev, (hipStream_t)stream, true);
+}
+
+tsk_status tucker_sum_project_workspace_size(tsk_handle h, const tsk_tucker_sum* sum,
+                                             const int64_t* widths, tsk_dtype basis_dtype,
+                                             tsk_precision project_prec, size_t* bytes) {
+  if (h == nullptr || bytes == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL handle or bytes");
+  h->err.clear();
+  Problem P;
+  tsk_status st = validate_project(h, sum, widths, project_prec, P);
+  if (st != TSK_OK) return st;
+  if (basis_dtype != TSK_F64 && basis_dtype != TSK_F32)
+    return fail(h, TSK_ERR_INVALID_ARG, "bad basis dtype");
+  std::vector<const void*> Q(P.d, nullptr);
+  size_t best = 0;
+  for (int o = 0; o < 2; ++o) {
+    Program prog;
+    size_t b = 0;
+    if ((st = plan_project(h, P, Q, basis_dtype == TSK_F64, nullptr, o == 1, nullptr, prog, &b)) !=
+        TSK_OK)
+      return st;
+    best = std::max(best, b);
+  }
+  *bytes = best;
+  return TSK_OK;
+}
+
+tsk_status tucker_sum_project(tsk_handle h, const tsk_tucker_sum* sum, const void* const* bases,
+                              const int64_t* widths, tsk_dtype basis_dtype,
+                              tsk_precision project_prec, void* H_out, tsk_dtype out_dtype,
+                              void* ws, size_t ws_bytes, void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  Problem P;
+  tsk_status st = validate_project(h, sum, widths, project_prec, P);
+  if (st != TSK_OK) return st;
+  if (basis_dtype != TSK_F64 && basis_dtype != TSK_F32)
+    return fail(h, TSK_ERR_INVALID_ARG, "bad basis dtype");
+  if (out_dtype != TSK_F64 && out_dtype != TSK_F32) return fail(h, TSK_ERR_INVALID_ARG, "bad out_dtype");
+  if (bases == nullptr || H_out == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "bases or H_out is NULL");
+  std::vector<const void*> Q;
+  for (int n = 0; n < P.d; ++n) {
+    if (bases[n] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "bases[%d] is NULL", n);
+    Q.push_back(bases[n]);
+  }
+  if (ws == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  Program prog;
+  size_t need = 0;
+  if ((st = plan_project(h, P, Q, basis_dtype == TSK_F64, H_out, out_dtype == TSK_F64, (char*)ws,
+                         prog, &need)) != TSK_OK)
+    return st;
+  if (ws_bytes < need)
+    return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  if ((st = set_device(h)) != TSK_OK) return st;
+  return run_program(h, prog, (char*)ws, (hipStream_t)stream);
 }
 
 tsk_status tsk_profile_enable(tsk_handle h, int32_t on) {

@@ -1,0 +1,78 @@
+"""Precision ladder through the product path: each arithmetic form of the
+library (tucker_sum_sketch, tucker_sum_project on the oracle's bases, and
+tucker_sum_recompress end to end) against the FP64 oracle on the same
+FP32-stored inputs (FP64 inputs for the fp64 form), on ragged shapes that
+reach every Khatri-Rao cursor of the core sketch, on the structured workload
+(d=3, 512^3, 16 terms; KRP and Kronecker) and on the precision workload (d=4,
+256^4, 8 terms, cores 32^4).
+
+Besides the relative Frobenius errors, every element of Y and of H is held to
+the componentwise envelope tol * |terms| (the same chain evaluated on the
+absolute values of its inputs), which catches a wrong block anywhere,
+including the small trailing slices of a decaying H that a normwise check
+cannot see."""
+import pytest
+
+import ladder
+
+pytestmark = pytest.mark.gpu
+
+# Frobenius bounds per form: the sketch Y, H given the oracle's Q, the
+# recompressed tensor end to end.  fp64: the plain form's bounds.  fp32 and
+# bf16x6: Y and H within the FP32-path bar of 1e-6; end to end they stay
+# under it on the ragged and structured cases, and reach 1.8e-6 (fp32) and
+# 1.5e-6 (bf16x6) on the d=4 precision workload, whose core sketch
+# accumulates K = 32^3 products per entry in FP32.  bf16x3: a 16-bit split
+# of each operand, sketch ~1e-5, inside the BF16 sketch-stage bar of 1e-3.
+# bf16x1: one BF16 product per product, sketch 4e-3 to 8e-3, above that bar
+# (each operand rounded to BF16 alone costs ~1e-3).
+BOUNDS = {
+    "fp64": {"y": 1e-13, "h": 1e-13, "x": 1e-12},
+    "fp32": {"y": 1e-6, "h": 1e-6, "x": 3e-6},
+    "bf16x6": {"y": 1e-6, "h": 1e-6, "x": 2e-6},
+    "bf16x3": {"y": 3e-5, "h": 1e-6, "x": 1e-4},
+    "bf16x1": {"y": 2e-2, "h": 1e-6, "x": 3e-2},
+}
+
+
+@pytest.fixture(scope="module")
+def tsk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_13532_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def refs():
+    return {}
+
+
+def check(m):
+    b = BOUNDS[m["form"]]
+    tag = f"{m['case']} {m['form']}"
+    print(f"{tag}: Y {m['y_rel']:.2e} (env {m['y_env']:.1e}, col {m['y_col']:.1e}), "
+          f"H|Q {m['h_rel']:.2e} (env {m['h_env']:.1e}), X {m['x_rel']:.2e}, Q {m['q_rel']}")
+    assert m["y_rel"] <= b["y"], tag
+    assert m["y_col"] <= 4 * b["y"], tag
+    assert m["y_env"] <= 1.0, tag
+    assert m["h_rel"] <= b["h"], tag
+    assert m["h_env"] <= 1.0, tag
+    assert m["x_rel"] <= b["x"], tag
+    assert m["orth"] <= (1e-12 if m["form"] == "fp64" else 1e-6), tag
+    if m["form"] == "fp64" and m["q_rel"] is not None:
+        assert m["q_rel"] <= 1e-10 and m["q_col"] <= 1e-9, tag
+
+
+@pytest.mark.parametrize("form", list(ladder.FORMS))
+@pytest.mark.parametrize("name", ladder.SMALL)
+def test_ladder_ragged(tsk, refs, name, form):
+    check(ladder.measure(tsk, name, form, refs))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("form", list(ladder.FORMS))
+@pytest.mark.parametrize("name", ladder.LARGE)
+def test_ladder_workloads(tsk, refs, name, form):
+    check(ladder.measure(tsk, name, form, refs))

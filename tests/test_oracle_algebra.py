@@ -7,6 +7,7 @@ import pytest
 
 from oracle import tensor as T
 from oracle import sketch as S
+from oracle import recompress as RC
 
 
 def rng(seed=0):
@@ -240,3 +241,24 @@ def test_kron_identity_sketch_gives_unfolding():
     ys = S.structured_sketch_kron(ts, om)
     for n in range(3):
         assert np.allclose(ys[n], T.unfold(x, n), rtol=1e-13, atol=1e-13)
+
+
+def test_tucker_rel_diff_matches_dense():
+    """The basis-union difference used by the GPU parity tests equals the
+    dense difference of the two reconstructions, for non-orthonormal
+    factors of different widths too."""
+    from helpers import tucker_rel_diff
+    rng = np.random.default_rng(0)
+    h = rng.standard_normal((5, 6, 7))
+    q = [np.linalg.qr(rng.standard_normal((n, w)))[0] for n, w in ((9, 5), (10, 6), (11, 7))]
+    h2 = h + 1e-9 * rng.standard_normal(h.shape)
+    q2 = [x + 1e-10 * rng.standard_normal(x.shape) for x in q]
+    a = RC.reconstruct(h, q)
+    b = RC.reconstruct(h2, q2)
+    want = np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert abs(tucker_rel_diff(h, q, h2, q2) - want) < 1e-6 * want
+    h3 = rng.standard_normal((5, 4, 7))
+    q3 = [q[0], rng.standard_normal((10, 4)), q[2]]
+    b3 = RC.reconstruct(h3, q3)
+    want3 = np.linalg.norm(a - b3) / np.linalg.norm(b3)
+    assert abs(tucker_rel_diff(h, q, h3, q3) - want3) < 1e-10 * want3

@@ -186,3 +186,46 @@ def test_backward_plan_in_bounds(dims, ranks, m):
 def test_backward_rejects_kron_and_oversketch():
     rc, msg = selfcheck_backward((10, 40, 40), [[3, 3, 3]], 12)
     assert rc == 2 and "sketch width" in msg
+
+
+def selfcheck_project(dims, ranks, widths, basis_f64, prec, in_f64, out_f64):
+    from paper_2603_13532_amd import _lib
+    lib = _lib.load()
+    fn = lib.tsk_plan_selfcheck_project
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.POINTER(_lib.TuckerSum), ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                   ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
+    ranks = np.asarray(ranks)
+    s, d = ranks.shape
+    c_dims = (ctypes.c_int64 * d)(*dims)
+    c_ranks = (ctypes.c_int32 * (s * d))(*[int(x) for x in ranks.ravel()])
+    c_cores = (ctypes.c_void_p * s)(*([0x1000] * s))
+    c_fac = (ctypes.c_void_p * (s * d))(*([0x1000] * (s * d)))
+    tsum = _lib.TuckerSum(d, s, c_dims, c_ranks, c_cores, c_fac, None, 0 if in_f64 else 1)
+    c_w = (ctypes.c_int64 * d)(*widths)
+    msg = ctypes.create_string_buffer(512)
+    rc = fn(ctypes.byref(tsum), c_w, 0 if basis_f64 else 1, _lib.PRECISIONS[prec],
+            0 if out_f64 else 1, msg, 512)
+    return rc, msg.value.decode()
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_project_plan_in_bounds(case):
+    """Stage 3 alone on the same shapes, with basis widths both the sketch's
+    and ragged ones (wider than the mode, narrower, a single column)."""
+    dims, ranks, kind, sizes = CASES[case]
+    d = len(dims)
+    w_sketch = [min(n, sizes[0]) for n in dims] if kind == "krp" else \
+        [min(n, int(np.prod([sizes[k] for k in range(d) if k != i]))) for i, n in enumerate(dims)]
+    for widths in (w_sketch, [1] * d, [n + 3 for n in dims]):
+        for prec in ("fp64", "fp32", "bf16x6"):
+            for basis_f64 in (True, False):
+                for in_f64 in (True, False):
+                    rc, msg = selfcheck_project(dims, ranks, widths, basis_f64, prec, in_f64,
+                                                not in_f64)
+                    if rc == 2 and widths[0] > dims[0]:
+                        # refused, not misplanned: the wide intermediates'
+                        # strides pass the kernels' 31-bit tile offsets
+                        assert "2^31" in msg
+                        continue
+                    assert rc == 0, (widths, prec, basis_f64, in_f64, msg)
