@@ -389,7 +389,9 @@ void emit_gemm(Program& prog, GemmBatch& gb) {
   st.kind = S_GEMM;
   st.prec = gb.prec;
   st.role = gb.role;
-  st.flops = gb.flops;
+  // algorithmic flops: the QR's Gram is symmetric and its basis step a
+  // triangular solve, n W^2 each, although the kernel forms the full product
+  st.flops = (gb.role == R_QR_GRAM || gb.role == R_QR_BASIS) ? gb.flops / 2 : gb.flops;
   st.bytes = gb.bytes;
   st.meta = prog.put(gb.descs);
   st.meta2 = prog.put(gb.segs);
@@ -765,7 +767,9 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
         if (k != D.mode) pbytes += (double)D.r[k] * D.m * es;
       }
       B.krp_flops += 2.0 * D.r[D.mode] * D.m * (double)D.Kc;
-      B.krp_bytes += (double)cs * es + pbytes + (double)D.r[D.mode] * D.m * es;
+      // algorithmic bytes: each core once per term (not once per mode), the
+      // factor sketches it multiplies, and the output
+      B.krp_bytes += (D.mode == 0 ? (double)cs * es : 0.0) + pbytes + (double)D.r[D.mode] * D.m * es;
     }
   } else {
     // Kronecker: V = G x_{k != n} (Omega_k^T U_k), TTM chain in ascending mode order
@@ -1000,7 +1004,7 @@ void Builder::emit(Program& prog) {
           if (q.gram_part != nullptr) {
             c.wmax = std::max(c.wmax, (int)q.W);
             const double W = (double)q.W;
-            c.flops += 2.0 * W * W * W / 3.0;
+            c.flops += W * W * W / 3.0;  // the Cholesky factorization
             c.bytes += 8.0 * W * W * (q.gram_splits + 2);
           }
         prog.steps.push_back(c);
