@@ -174,6 +174,45 @@ tsk_status tucker_sum_project(tsk_handle handle, const tsk_tucker_sum* sum,
                               tsk_dtype basis_dtype, tsk_precision project_prec, void* H_out,
                               tsk_dtype out_dtype, void* ws, size_t ws_bytes, void* stream);
 
+/* Stage 1 of Algorithms 4/5: phase 1 of Algorithm 3 (effective subranks
+ * from the weighted Gram matrix, Section 3.2).  For every mode n:
+ * V_n = [w_1 U_n^(1), ..., w_s U_n^(s)] with w_i = |c_i| ||G^(i)||_F, the
+ * eigenvalues lambda_1 >= lambda_2 >= ... of V_n^T V_n clipped at zero, the
+ * rank r_n = the smallest r >= 1 with sum_{j > r} lambda_j <= (eps^2 / d)
+ * sum_j lambda_j, and ell_out[n] = r_n + p[n] (p: host [d] oversampling,
+ * >= 0).  Sketch sizes then follow from tsk_krp_width / tsk_kron_sizes
+ * (phase 2).  FP64 throughout; requires sum_i r_n^(i) <= 4096 per mode.
+ * Synchronises `stream` to return the sizes on the host. */
+tsk_status tucker_sum_subranks_workspace_size(tsk_handle handle, const tsk_tucker_sum* sum,
+                                              size_t* bytes);
+tsk_status tucker_sum_subranks(tsk_handle handle, const tsk_tucker_sum* sum, double eps,
+                               const int32_t* p, int32_t* ell_out, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* Stage 4 of Algorithms 4/5: ST-HOSVD of the projected core with relative
+ * tolerance eps and the rank rule of Algorithm 2, phase 2.  With
+ * theta = eps^2 ||H||_F^2 / d, for n = 1..d in order: the eigenvalues
+ * lambda_1 >= lambda_2 >= ... of G_(n) G_(n)^T (G the current core, first
+ * H), the rank r_n = the smallest r >= 1 with sum_{i > r} lambda_i <= theta,
+ * V_n = the r_n leading eigenvectors, G <- G x_n V_n^T; then the factors
+ * U_n = Q_n V_n.  Everything in FP64.
+ *   dims, widths: host [order]; widths[k] = w_k <= min(dims[k], 96).
+ *   Q[k]: device n_k x w_k (ld n_k); H: device w_1 x ... x w_d (the outputs
+ *     of tucker_sum_recompress with out_dtype TSK_F64).
+ *   U_out[k]: device n_k x w_k buffers, of which the first r_k columns
+ *     (ld n_k) are written; G_out: device buffer of prod_k w_k doubles that
+ *     receives the r_1 x ... x r_d core; ranks_out: host [order].
+ * The ranks decide the shapes of later launches, so the call synchronises
+ * `stream` once per mode and returns after the work is enqueued (the last
+ * launches may still be running).  The result [[G; U_1..U_d]] is within
+ * eps ||H|| of [[H; Q]] when the Q_k have orthonormal columns. */
+tsk_status tucker_truncate_workspace_size(tsk_handle handle, int32_t order, const int64_t* dims,
+                                          const int64_t* widths, double eps, size_t* bytes);
+tsk_status tucker_truncate(tsk_handle handle, int32_t order, const int64_t* dims,
+                           const int64_t* widths, const double* const* Q, const double* H,
+                           double eps, double* const* U_out, double* G_out, int32_t* ranks_out,
+                           void* ws, size_t ws_bytes, void* stream);
+
 /* tucker_sum_recompress for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the same computation and the same kernels, with no workspace

@@ -45,6 +45,14 @@ int tsk_plan_selfcheck_backward(const tsk_tucker_sum* sum, const tsk_sketch_spec
 int tsk_plan_selfcheck_project(const tsk_tucker_sum* sum, const int64_t* widths, int basis_dtype,
                                int project_prec, int out_dtype, char* msg, size_t msglen);
 
+/* Self-check of tucker_truncate with the mode ranks the device would
+ * report (ranks: host [order], 1 <= ranks[k] <= widths[k]). */
+int tsk_plan_selfcheck_truncate(int32_t order, const int64_t* dims, const int64_t* widths,
+                                const int32_t* ranks, char* msg, size_t msglen);
+
+/* Self-check of tucker_sum_subranks. */
+int tsk_plan_selfcheck_subranks(const tsk_tucker_sum* sum, char* msg, size_t msglen);
+
 /* The batched self-check, then one line per planned launch in msg: kernel,
  * descriptors, workgroups, largest K-split and segment count; a last line
  * gives the workspace and descriptor-blob sizes in bytes. */

@@ -175,13 +175,18 @@ def st_hosvd(h: np.ndarray, eps: float):
 def effective_subranks(tsum: dict, eps: float, p) -> list:
     """Stage 1, phase 1 of Algorithm 3: V_n = [||G^(i)|| U_n^(i)]_i,
     eigenvalues of V_n^T V_n clipped at 0 and sorted, smallest r with
-    discarded sum <= eps^2/d * total, plus oversampling p_n."""
+    discarded sum <= eps^2/d * total, plus oversampling p_n.  The summands
+    are c_i X^(i) (coefficients scale the cores), so the weight of term i is
+    |c_i| ||G^(i)||_F."""
     d = len(tsum["dims"])
     p = np.broadcast_to(np.asarray(p), (d,))
+    coeffs = tsum.get("coeffs")
+    if coeffs is None:
+        coeffs = np.ones(len(tsum["cores"]))
     ell = []
     for n in range(d):
-        v = np.concatenate([np.sqrt(np.sum(g ** 2)) * us[n]
-                            for g, us in zip(tsum["cores"], tsum["factors"])], axis=1)
+        v = np.concatenate([abs(float(c)) * np.sqrt(np.sum(g ** 2)) * us[n]
+                            for c, g, us in zip(coeffs, tsum["cores"], tsum["factors"])], axis=1)
         lam = np.sort(np.maximum(0.0, np.linalg.eigvalsh(v.T @ v)))[::-1]
         tau = eps ** 2 / d * float(np.sum(lam))
         tail = np.concatenate([np.cumsum(lam[::-1])[::-1][1:], [0.0]])

@@ -23,7 +23,7 @@ __all__ = [
     "tucker_sum_sketch", "tucker_sum_recompress", "qr_fallback_count", "Handle", "TskError",
     "Recompressor", "BatchRecompressor", "tucker_sum_recompress_batched",
     "tucker_sum_recompress_backward", "recompress", "tucker_sum_recompress_noalloc",
-    "tucker_sum_project",
+    "tucker_sum_project", "tucker_truncate", "round_sum", "effective_subranks", "sketch_sum",
 ]
 
 
@@ -249,6 +249,84 @@ def tucker_sum_project(cores, factors, bases, coeffs=None, project_prec="fp64", 
                                     _dtype_code(out_dtype), c_void_p(ws.data_ptr()), ws.numel(),
                                     c_void_p(_stream_ptr(m.device))), h.ptr)
     return hh
+
+
+def tucker_truncate(Q, H, eps):
+    """Stage 4: ST-HOSVD of the core H (FP64) with relative tolerance eps
+    and U_n = Q_n V_n.  Returns (G, [U_1..U_d], ranks), G of shape ranks and
+    U_n of shape (n_n, r_n) (views of the library's outputs)."""
+    dev = H.device
+    d = H.dim()
+    Qf = [fortran(q.to(torch.float64)) for q in Q]
+    Hf = fortran(H.to(torch.float64))
+    dims = [int(q.shape[0]) for q in Qf]
+    widths = [int(x) for x in Hf.shape]
+    if [int(q.shape[1]) for q in Qf] != widths:
+        raise ValueError("Q_k must have as many columns as H has entries along mode k")
+    h = Handle.get(dev)
+    c_dims = (c_int64 * d)(*dims)
+    c_w = (c_int64 * d)(*widths)
+    nbytes = c_size_t()
+    check(load().tucker_truncate_workspace_size(h.ptr, d, c_dims, c_w, float(eps),
+                                                byref(nbytes)), h.ptr)
+    ws = h.workspace(nbytes.value)
+    U = [empty_fortran((n, w), torch.float64, dev) for n, w in zip(dims, widths)]
+    total = 1
+    for w in widths:
+        total *= w
+    G = torch.empty(total, dtype=torch.float64, device=dev)
+    ranks = (c_int32 * d)()
+    check(load().tucker_truncate(h.ptr, d, c_dims, c_w, (c_void_p * d)(*[q.data_ptr() for q in Qf]),
+                                 c_void_p(Hf.data_ptr()), float(eps),
+                                 (c_void_p * d)(*[u.data_ptr() for u in U]),
+                                 c_void_p(G.data_ptr()), ranks, c_void_p(ws.data_ptr()),
+                                 ws.numel(), c_void_p(_stream_ptr(dev))), h.ptr)
+    r = list(ranks)
+    n = 1
+    for x in r:
+        n *= x
+    core = G[:n].reshape(tuple(reversed(r))).permute(tuple(reversed(range(d))))
+    return core, [u[:, :rk] for u, rk in zip(U, r)], r
+
+
+def round_sum(cores, factors, kind, sizes, seed, eps, coeffs=None, sketch_prec="fp64",
+              project_prec="fp64"):
+    """Sketch-based sum with fixed sketch sizes followed by Stage 4: the
+    recompression (Stages 2-3, FP64 outputs) and the ST-HOSVD truncation of
+    its core with tolerance eps.  Returns (G, [U_1..U_d], ranks)."""
+    qs, hh = tucker_sum_recompress(cores, factors, kind, sizes, seed, coeffs=coeffs,
+                                   sketch_prec=sketch_prec, project_prec=project_prec,
+                                   out_dtype=torch.float64)
+    return tucker_truncate(qs, hh, eps)
+
+
+def effective_subranks(cores, factors, eps, p, coeffs=None):
+    """Stage 1 (phase 1 of Algorithm 3): ell_n = r_n + p_n per mode."""
+    m = _Marshal(cores, factors, coeffs, "krp", [1], 0, None, "fp64", "fp64", "auto")
+    h = Handle.get(m.device)
+    pv = [int(x) for x in (p if hasattr(p, "__len__") else [p] * m.d)]
+    nbytes = c_size_t()
+    check(load().tucker_sum_subranks_workspace_size(h.ptr, byref(m.sum), byref(nbytes)), h.ptr)
+    ws = h.workspace(nbytes.value)
+    out = (c_int32 * m.d)()
+    check(load().tucker_sum_subranks(h.ptr, byref(m.sum), float(eps), (c_int32 * m.d)(*pv), out,
+                                     c_void_p(ws.data_ptr()), ws.numel(),
+                                     c_void_p(_stream_ptr(m.device))), h.ptr)
+    return list(out)
+
+
+def sketch_sum(cores, factors, kind, eps, p, seed, coeffs=None, sketch_prec="fp64",
+               project_prec="fp64"):
+    """The whole sketch-based sum of Algorithm 5 (kind "krp") or 4 ("kron")
+    as a sequence of the library's calls: Stage 1 sizes from eps and p, the
+    sketch width (max ell for KRP, the heuristic q_k for Kronecker), Stages
+    2-3, and the Stage 4 truncation with eps.  Returns (G, [U..], ranks,
+    sizes)."""
+    ell = effective_subranks(cores, factors, eps, p, coeffs=coeffs)
+    sizes = [krp_width(ell)] if kind == "krp" else kron_sizes(ell)
+    g, us, ranks = round_sum(cores, factors, kind, sizes, seed, eps, coeffs=coeffs,
+                             sketch_prec=sketch_prec, project_prec=project_prec)
+    return g, us, ranks, sizes
 
 
 def tucker_sum_recompress_noalloc(cores, factors, kind, sizes, seed, Q_out, H_out, coeffs=None,

@@ -1039,13 +1039,23 @@ __global__ __launch_bounds__(NTHREADS) void tile_reduce_kernel(const ReduceJob* 
 
 template <class S, class D>
 __device__ __forceinline__ void copy_chunk(const S* __restrict__ src, D* __restrict__ dst,
-                                           int64_t base, int64_t n, int t) {
+                                           int64_t base, int64_t n, int t, const double* norm2,
+                                           double mul) {
   constexpr int E = kCopyChunk / 256;
   S v[E];
 #pragma unroll
   for (int k = 0; k < E; ++k) {
     const int64_t e = base + k * 256 + t;
     v[k] = e < n ? src[e] : S(0);
+  }
+  if (norm2 != nullptr) {
+    const double sc = mul * sqrt(*norm2);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int64_t e = base + k * 256 + t;
+      if (e < n) dst[e] = (D)((double)v[k] * sc);
+    }
+    return;
   }
 #pragma unroll
   for (int k = 0; k < E; ++k) {
@@ -1069,11 +1079,11 @@ __global__ __launch_bounds__(256) void copy_kernel(const CopyJob* __restrict__ j
   const int64_t base = (chunk - J.chunk_begin) * kCopyChunk;
   const int t = threadIdx.x;
   if (J.src_f64) {
-    if (J.dst_f64) copy_chunk((const double*)J.src, (double*)J.dst, base, n, t);
-    else copy_chunk((const double*)J.src, (float*)J.dst, base, n, t);
+    if (J.dst_f64) copy_chunk((const double*)J.src, (double*)J.dst, base, n, t, J.norm2, J.mul);
+    else copy_chunk((const double*)J.src, (float*)J.dst, base, n, t, J.norm2, J.mul);
   } else {
-    if (J.dst_f64) copy_chunk((const float*)J.src, (double*)J.dst, base, n, t);
-    else copy_chunk((const float*)J.src, (float*)J.dst, base, n, t);
+    if (J.dst_f64) copy_chunk((const float*)J.src, (double*)J.dst, base, n, t, J.norm2, J.mul);
+    else copy_chunk((const float*)J.src, (float*)J.dst, base, n, t, J.norm2, J.mul);
   }
 }
 

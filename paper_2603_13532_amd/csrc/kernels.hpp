@@ -64,12 +64,16 @@ hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t
 // launch (a prefix sum over the jobs before it), and one workgroup copies one
 // chunk.
 constexpr int kCopyChunk = 2048;
+// With norm2 set, every element is also multiplied by mul * sqrt(*norm2)
+// (a scale known only on the device).
 struct CopyJob {
   void* dst;
   const void* src;
   int64_t rows, cols, ld_dst, ld_src;
   int32_t dst_f64, src_f64;
   int64_t chunk_begin;
+  const double* norm2;
+  double mul;
 };
 hipError_t launch_copy(const CopyJob* jobs, int count, int64_t chunks, hipStream_t stream);
 
@@ -86,5 +90,29 @@ constexpr int kHhWideRows = 384;
 __host__ __device__ inline bool hh_wide_panel(int64_t n, int64_t W) { return W <= kHhWideCols && n <= kHhWideRows; }
 hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* fallback_counter,
                               int64_t max_elems, int kernels, hipStream_t stream);
+
+// Symmetric eigendecomposition of a W x W matrix (W <= kEigMaxW) by one
+// workgroup: eigenvalues in decreasing order into lam[0..W), their
+// eigenvectors as the columns of V (ld ldv), eigenvalues clipped at zero
+// when clip != 0.  With rank != null, the rank rule: theta = theta_scale *
+// trace(C) is computed and stored when set_theta != 0, else read from
+// *theta, and *rank = the smallest r >= 1 with sum_{i >= r} lam_i <= theta.
+constexpr int kEigMaxW = 96;
+struct EigJob {
+  const double* C;
+  double* V;
+  double* lam;
+  double* theta;
+  int32_t* rank;
+  int64_t ldc, ldv;
+  double tol, theta_scale;
+  int32_t W, set_theta, clip, pad_;
+};
+hipError_t launch_jacobi_eig(const EigJob* jobs, int count, int wmax, hipStream_t stream);
+// Eigenvalues only (lam, decreasing; no eigenvectors) of larger matrices,
+// W <= kTriMaxW: V is a W x W workspace (ld ldv) that the reduction to
+// tridiagonal form overwrites.  Same rank rule.
+constexpr int kTriMaxW = 4096;
+hipError_t launch_tridiag_eig(const EigJob* jobs, int count, int wmax, hipStream_t stream);
 
 }  // namespace tsk

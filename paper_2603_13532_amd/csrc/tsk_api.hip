@@ -212,7 +212,7 @@ tsk_status validate_spec(tsk_handle h, const tsk_sketch_spec* spec, Problem& P) 
 
 // ------------------------------------------------------------------ program
 enum StepKind { S_OMEGA, S_GEMM, S_KRP, S_REDUCE, S_TILE_REDUCE, S_COPY, S_FILL, S_CHOL, S_HOUSE,
-                S_KRP_ADJ, S_SYM, S_TRSM };
+                S_KRP_ADJ, S_SYM, S_TRSM, S_EIG };
 
 struct Step {
   StepKind kind;
@@ -1497,6 +1497,7 @@ std::string step_name(const Step& st) {
     }
     case S_SYM: return "sym_kernel";
     case S_TRSM: return "trsm_rt_kernel";
+    case S_EIG: return st.pass == 1 ? "tridiag_eig_kernel" : "jacobi_eig_kernel";
   }
   return "unknown";
 }
@@ -1604,6 +1605,10 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
         break;
       case S_SYM: e = launch_sym((const SymJob*)(meta + st.meta), st.count, stream); break;
       case S_TRSM: e = launch_trsm_rt((const TrsmJob*)(meta + st.meta), st.count, stream); break;
+      case S_EIG:
+        e = st.pass == 1 ? launch_tridiag_eig((const EigJob*)(meta + st.meta), st.count, st.wmax, stream)
+                         : launch_jacobi_eig((const EigJob*)(meta + st.meta), st.count, st.wmax, stream);
+        break;
       case S_HOUSE:
         e = launch_householder((const QrDesc*)(meta + st.meta), st.count, st.force, (int64_t*)st.ptr,
                                st.rows, st.hh_kernels, stream);
@@ -1695,6 +1700,337 @@ tsk_status set_device(tsk_handle h) {
   return TSK_OK;
 }
 
+
+// ------------------------------------------------------------------ Stage 4
+// ST-HOSVD of the projected core H with relative tolerance eps (Algorithms
+// 4/5, Stage 4; rank rule of Algorithm 2, phase 2): for n = 1..d in order,
+// the Gram G_(n) G_(n)^T of the current core, its eigendecomposition, the
+// rank r_n (smallest r with discarded eigenvalues summing to at most
+// theta = eps^2 ||H||^2 / d), and G <- G x_n V_n^T with the r_n leading
+// eigenvectors V_n; finally U_n = Q_n V_n.  The ranks decide the shapes of
+// the next mode's launches, so each mode ends with a host read of r_n.
+struct TruncIO {
+  int d = 0;
+  std::vector<int64_t> dims, w;  // mode sizes n_k and core widths w_k
+  std::vector<const double*> Q;  // n_k x w_k
+  const double* H = nullptr;     // w_1 x ... x w_d
+  double eps = 0;
+  std::vector<double*> U;        // n_k x w_k capacity
+  double* G = nullptr;           // prod w_k capacity
+};
+
+// Fixed workspace of a truncation: ranks, theta, the Gram, eigenvectors and
+// eigenvalues of every mode, two core buffers; then one phase region
+// (Gram split-K partials) and the descriptor blob.
+struct TruncLayout {
+  int32_t* ranks = nullptr;
+  double* theta = nullptr;
+  double* C = nullptr;
+  std::vector<double*> V, lam;
+  double* buf[2] = {nullptr, nullptr};
+  size_t phase_base = 0;
+};
+
+static void trunc_layout(const TruncIO& io, Arena& ar, TruncLayout& L) {
+  L.ranks = (int32_t*)ar.take(sizeof(int32_t) * 64);
+  L.theta = (double*)ar.take(sizeof(double) * 4);
+  int64_t wmax = 1, hs = 1;
+  for (int n = 0; n < io.d; ++n) {
+    wmax = std::max(wmax, io.w[n]);
+    hs *= io.w[n];
+  }
+  L.C = (double*)ar.take(wmax * wmax * 8);
+  L.V.resize(io.d);
+  L.lam.resize(io.d);
+  for (int n = 0; n < io.d; ++n) {
+    L.V[n] = (double*)ar.take(io.w[n] * io.w[n] * 8);
+    L.lam[n] = (double*)ar.take(io.w[n] * 8);
+  }
+  L.buf[0] = (double*)ar.take(hs * 8);
+  L.buf[1] = (double*)ar.take(hs * 8);
+  L.phase_base = align_up(ar.top, 256);
+}
+
+// Launches of one phase: the TTM that truncates mode n - 1 (if n > 0, with
+// rank rprev), then the Gram and eigendecomposition of mode n (if n < d);
+// at n == d also U_k = Q_k V_k for every mode.  `shape` is the core's shape
+// before the TTM; `src` the core, `dst` where the TTM writes.
+static void trunc_phase(const TruncIO& io, const TruncLayout& L, int n,
+                        const std::vector<int64_t>& shape_in, const double* src, double* dst,
+                        const std::vector<int32_t>& ranks, Arena& ar, Program& prog) {
+  const int d = io.d;
+  std::vector<int64_t> shape = shape_in;
+  const double* cur = src;
+  if (n > 0) {
+    const int k = n - 1;
+    const int64_t Wk = shape[k], rk = ranks[k];
+    int64_t Lo = 1, Ro = 1;
+    for (int j = 0; j < k; ++j) Lo *= shape[j];
+    for (int j = k + 1; j < d; ++j) Ro *= shape[j];
+    GemmBatch gb(P_FP64, R_OTHER, &ar);
+    if (k == 0) {
+      // out (r_0 x R) = V_0^T (r_0 x W_0) . G_(0) (W_0 x R)
+      gb.add(dst, true, rk, 0, (int)rk, (int)Ro, 1, 0, {seg(L.V[k], Wk, 1, 0, cur, Wk, 1, 0, Wk)});
+    } else {
+      // per trailing index b: out_b (L x r_k) = G_b (L x W_k) . V_k (W_k x r_k)
+      gb.add(dst, true, Lo, Lo * rk, (int)Lo, (int)rk, (int)Ro, 0,
+             {seg(cur, 1, Lo, Lo * Wk, L.V[k], Wk, 1, 0, Wk)});
+    }
+    emit_gemm(prog, gb);
+    shape[k] = rk;
+    cur = dst;
+  }
+  if (n < d) {
+    const int64_t Wn = shape[n];
+    int64_t Lo = 1, Ro = 1;
+    for (int j = 0; j < n; ++j) Lo *= shape[j];
+    for (int j = n + 1; j < d; ++j) Ro *= shape[j];
+    GemmBatch gb(P_FP64, R_OTHER, &ar);
+    std::vector<GemmSeg> sg;
+    if (n == 0) {
+      sg.push_back(seg(cur, 1, Wn, 0, cur, 1, Wn, 0, Ro));
+    } else {
+      for (int64_t c = 0; c < Ro; ++c) {
+        const double* base = cur + c * Lo * Wn;
+        sg.push_back(seg(base, Lo, 1, 0, base, Lo, 1, 0, Lo));
+      }
+    }
+    const int64_t tiles = ceil_div(Wn, 64) * ceil_div(Wn, 64);
+    const int splits = choose_splits(tiles, ceil_div(Lo * Ro, 16));
+    gb.add(L.C, true, Wn, 0, (int)Wn, (int)Wn, 1, 0, sg, splits);
+    emit_gemm(prog, gb);
+  } else {
+    GemmBatch gb(P_FP64, R_OTHER, &ar);
+    for (int k = 0; k < d; ++k) {
+      const int64_t nk = io.dims[k], Wk = io.w[k];
+      gb.add(io.U[k], true, nk, 0, (int)nk, (int)ranks[k], 1, 0,
+             {seg(io.Q[k], 1, nk, 0, L.V[k], Wk, 1, 0, Wk)});
+    }
+    emit_gemm(prog, gb);
+  }
+  if (n < d) {
+    EigJob J{};
+    J.C = L.C;
+    J.V = L.V[n];
+    J.lam = L.lam[n];
+    J.theta = L.theta;
+    J.rank = L.ranks + n;
+    J.ldc = shape[n];
+    J.ldv = shape[n];
+    J.tol = 1e-15;
+    J.theta_scale = io.eps * io.eps / d;
+    J.W = (int32_t)shape[n];
+    J.set_theta = n == 0 ? 1 : 0;
+    J.clip = 1;
+    Step st{};
+    st.kind = S_EIG;
+    st.meta = prog.put(std::vector<EigJob>{J});
+    st.count = 1;
+    st.wmax = (int)shape[n];
+    st.flops = 0;
+    prog.steps.push_back(st);
+  }
+}
+
+// Workspace of a truncation: the fixed part, then the largest phase (every
+// rank at its maximum, which bounds the split-K partials and descriptors of
+// any smaller ranks).
+static size_t trunc_workspace(const TruncIO& io, bool* too_far) {
+  Arena a0;
+  TruncLayout L;
+  trunc_layout(io, a0, L);
+  size_t phase = 0, blob = 0;
+  std::vector<int32_t> ranks(io.w.begin(), io.w.end());
+  for (int n = 0; n <= io.d; ++n) {
+    Arena ar;
+    ar.base = nullptr;
+    ar.top = L.phase_base;
+    Program prog;
+    trunc_phase(io, L, n, io.w, nullptr, nullptr, ranks, ar, prog);
+    if (!ar.too_far.empty()) *too_far = true;
+    phase = std::max(phase, ar.top);
+    blob = std::max(blob, prog.blob.size());
+  }
+  return align_up(phase, 256) + align_up(blob, 256) + 256;
+}
+
+static tsk_status validate_trunc(tsk_handle h, int32_t order, const int64_t* dims,
+                                 const int64_t* widths, double eps, TruncIO& io) {
+  if (order < 2 || order > kMaxOrder) return fail(h, TSK_ERR_INVALID_ARG, "order %d outside [2, %d]", order, kMaxOrder);
+  if (dims == nullptr || widths == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "dims or widths is NULL");
+  if (!(eps >= 0.0) || eps > 1.0) return fail(h, TSK_ERR_INVALID_ARG, "eps must be in [0, 1]");
+  io.d = order;
+  io.eps = eps;
+  int64_t hs = 1;
+  for (int k = 0; k < order; ++k) {
+    if (dims[k] < 1 || widths[k] < 1) return fail(h, TSK_ERR_INVALID_ARG, "mode %d: size < 1", k);
+    if (widths[k] > dims[k]) return fail(h, TSK_ERR_INVALID_ARG, "mode %d: width above the mode size", k);
+    if (widths[k] > kEigMaxW)
+      return fail(h, TSK_ERR_UNSUPPORTED, "mode %d: width %lld above %d", k, (long long)widths[k], kEigMaxW);
+    if (dims[k] > (1 << 30)) return fail(h, TSK_ERR_UNSUPPORTED, "dims[%d] too large", k);
+    hs *= widths[k];
+    io.dims.push_back(dims[k]);
+    io.w.push_back(widths[k]);
+  }
+  if (hs > (int64_t(1) << 31)) return fail(h, TSK_ERR_UNSUPPORTED, "core too large");
+  return TSK_OK;
+}
+
+// ------------------------------------------------------------------ Stage 1
+// Phase 1 of Algorithm 3 for every mode: V_n = [w_1 U_n^(1), ..., w_s U_n^(s)]
+// with w_i = |c_i| ||G^(i)||_F (the summands are c_i X^(i)), the eigenvalues
+// of V_n^T V_n clipped at zero in decreasing order, and the smallest rank
+// r_n >= 1 whose discarded eigenvalues sum to at most eps^2/d of their
+// total.  Launches: FP64 copies of FP32 inputs; the squared core norms (one
+// 1 x 1 GEMM per term); V_n assembled by copies scaled on the device;
+// V_n^T V_n (one GEMM per mode); the eigenvalues (Jacobi in LDS for
+// sum_i r_n^(i) <= 96, tridiagonal reduction and bisection above).
+struct SubrankOut {
+  int32_t* ranks = nullptr;  // device [d]
+};
+
+static void plan_subranks(const Problem& P, double eps, Arena& ar, Program& prog, SubrankOut& out) {
+  const int d = P.d, s = P.s;
+  out.ranks = (int32_t*)ar.take(sizeof(int32_t) * 64);
+  double* theta = (double*)ar.take(sizeof(double) * kMaxOrder);
+  // inputs in FP64
+  std::vector<CopyJob> conv;
+  std::vector<const double*> G(s), U((size_t)s * d);
+  for (int i = 0; i < s; ++i) {
+    int64_t cs = 1;
+    for (int k = 0; k < d; ++k) cs *= P.r(i, k);
+    if (P.in_f64) {
+      G[i] = (const double*)P.cores[i];
+    } else {
+      double* p = (double*)ar.take(cs * 8);
+      conv.push_back(CopyJob{p, P.cores[i], cs, 1, cs, cs, 1, 0});
+      G[i] = p;
+    }
+    for (int k = 0; k < d; ++k) {
+      const size_t idx = (size_t)i * d + k;
+      if (P.in_f64) {
+        U[idx] = (const double*)P.factors[idx];
+      } else {
+        double* p = (double*)ar.take(P.dims[k] * P.r(i, k) * 8);
+        conv.push_back(CopyJob{p, P.factors[idx], P.dims[k], P.r(i, k), P.dims[k], P.dims[k], 1, 0});
+        U[idx] = p;
+      }
+    }
+  }
+  emit_copies(prog, conv);
+  // squared Frobenius norms of the cores
+  double* norm2 = (double*)ar.take(sizeof(double) * s);
+  {
+    GemmBatch gb(P_FP64, R_OTHER, &ar);
+    int64_t kt = 0;
+    for (int i = 0; i < s; ++i) {
+      int64_t cs = 1;
+      for (int k = 0; k < d; ++k) cs *= P.r(i, k);
+      kt = std::max<int64_t>(kt, ceil_div(cs, 16));
+    }
+    const int splits = choose_splits(s, kt);
+    for (int i = 0; i < s; ++i) {
+      int64_t cs = 1;
+      for (int k = 0; k < d; ++k) cs *= P.r(i, k);
+      gb.add(norm2 + i, true, 1, 0, 1, 1, 1, 0, {seg(G[i], 1, 1, 0, G[i], 1, 1, 0, cs)},
+             (int)std::min<int64_t>(splits, std::max<int64_t>(1, ceil_div(cs, 16) / 2)));
+    }
+    emit_gemm(prog, gb);
+  }
+  // V_n, then V_n^T V_n, per mode
+  std::vector<CopyJob> scaled;
+  std::vector<double*> V(d), B(d), lam(d), scratch(d);
+  std::vector<int64_t> Wn(d);
+  for (int n = 0; n < d; ++n) {
+    int64_t W = 0;
+    for (int i = 0; i < s; ++i) W += P.r(i, n);
+    Wn[n] = W;
+    V[n] = (double*)ar.take(P.dims[n] * W * 8);
+    B[n] = (double*)ar.take(W * W * 8);
+    lam[n] = (double*)ar.take(W * 8);
+    scratch[n] = (double*)ar.take(W * W * 8);
+    int64_t col = 0;
+    for (int i = 0; i < s; ++i) {
+      CopyJob J{V[n] + P.dims[n] * col, U[(size_t)i * d + n], P.dims[n], P.r(i, n), P.dims[n],
+                P.dims[n], 1, 1};
+      J.norm2 = norm2 + i;
+      J.mul = std::fabs(P.coeffs[i]);
+      scaled.push_back(J);
+      col += P.r(i, n);
+    }
+  }
+  emit_copies(prog, scaled);
+  {
+    GemmBatch gb(P_FP64, R_OTHER, &ar);
+    for (int n = 0; n < d; ++n) {
+      const int64_t W = Wn[n], nn = P.dims[n];
+      const int splits = choose_splits(ceil_div(W, 64) * ceil_div(W, 64) * d, ceil_div(nn, 16));
+      gb.add(B[n], true, W, 0, (int)W, (int)W, 1, 0, {seg(V[n], nn, 1, 0, V[n], nn, 1, 0, nn)},
+             splits);
+    }
+    emit_gemm(prog, gb);
+  }
+  std::vector<EigJob> small, large;
+  int wsmall = 0, wlarge = 0;
+  for (int n = 0; n < d; ++n) {
+    EigJob J{};
+    J.C = B[n];
+    J.V = scratch[n];
+    J.lam = lam[n];
+    J.theta = theta + n;
+    J.rank = out.ranks + n;
+    J.ldc = Wn[n];
+    J.ldv = Wn[n];
+    J.tol = 1e-15;
+    J.theta_scale = eps * eps / d;
+    J.W = (int32_t)Wn[n];
+    J.set_theta = 1;
+    J.clip = 1;
+    if (Wn[n] <= kEigMaxW) {
+      small.push_back(J);
+      wsmall = std::max<int>(wsmall, (int)Wn[n]);
+    } else {
+      large.push_back(J);
+      wlarge = std::max<int>(wlarge, (int)Wn[n]);
+    }
+  }
+  for (int which = 0; which < 2; ++which) {
+    const std::vector<EigJob>& js = which == 0 ? small : large;
+    if (js.empty()) continue;
+    Step st{};
+    st.kind = S_EIG;
+    st.pass = which;  // 0: Jacobi in LDS, 1: tridiagonal reduction
+    st.meta = prog.put(js);
+    st.count = (int)js.size();
+    st.wmax = which == 0 ? wsmall : wlarge;
+    prog.steps.push_back(st);
+  }
+}
+
+static tsk_status validate_subranks(tsk_handle h, const tsk_tucker_sum* sum, double eps,
+                                    Problem& P) {
+  if (tsk_status st = validate_sum(h, sum, P); st != TSK_OK) return st;
+  if (!(eps >= 0.0) || eps > 1.0) return fail(h, TSK_ERR_INVALID_ARG, "eps must be in [0, 1]");
+  for (int n = 0; n < P.d; ++n) {
+    int64_t W = 0;
+    for (int i = 0; i < P.s; ++i) W += P.r(i, n);
+    if (W > kTriMaxW)
+      return fail(h, TSK_ERR_UNSUPPORTED, "mode %d: sum of ranks %lld above %d", n, (long long)W,
+                  kTriMaxW);
+  }
+  return TSK_OK;
+}
+
+static tsk_status plan_subranks_sized(tsk_handle h, const Problem& P, double eps, char* ws,
+                                      Program& prog, SubrankOut& out, size_t* bytes) {
+  Arena ar;
+  ar.base = ws;
+  plan_subranks(P, eps, ar, prog, out);
+  if (!ar.too_far.empty()) return fail(h, TSK_ERR_UNSUPPORTED, "%s", ar.too_far.c_str());
+  prog.meta_region = align_up(ar.top, 256);
+  *bytes = prog.meta_region + align_up(prog.blob.size(), 256) + 256;
+  return TSK_OK;
+}
 
 // ------------------------------------------------------------------ plan self-check
 // Host-only verification that every address a planned launch sequence can
@@ -1822,6 +2158,7 @@ void check_program(const Program& prog, Checker& ck) {
           chunks += (J.rows * J.cols + kCopyChunk - 1) / kCopyChunk;
           ck.span(J.dst, 0, max_off({{J.rows, 1}, {J.cols, J.ld_dst}}), J.dst_f64 ? 8 : 4, "copy dst");
           ck.span(J.src, 0, max_off({{J.rows, 1}, {J.cols, J.ld_src}}), J.src_f64 ? 8 : 4, "copy src");
+          if (J.norm2) ck.span(J.norm2, 0, 0, 8, "copy scale");
         }
         if (chunks != st.tiles) { ck.ok = false; ck.err = "copy chunk count mismatch"; return; }
         break;
@@ -1861,6 +2198,26 @@ void check_program(const Program& prog, Checker& ck) {
           ck.span(J.R, 0, J.w * J.w - 1, 8, "trsm R");
           ck.span(J.Z, 0, J.n * J.w - 1, 8, "trsm Z");
           ck.span(J.X, 0, J.n * J.w - 1, 8, "trsm X");
+        }
+        break;
+      }
+      case S_EIG: {
+        const EigJob* js = (const EigJob*)(blob + st.meta);
+        for (int i = 0; i < st.count; ++i) {
+          const EigJob& J = js[i];
+          const int wcap = st.pass == 1 ? kTriMaxW : kEigMaxW;
+          if (J.W < 1 || J.W > wcap || J.W > st.wmax || J.ldc < J.W || J.ldv < J.W) {
+            ck.ok = false;
+            ck.err = "eigen job outside the kernel's sizes";
+            return;
+          }
+          ck.span(J.C, 0, (J.W - 1) * J.ldc + J.W - 1, 8, "eig C");
+          ck.span(J.V, 0, (J.W - 1) * J.ldv + J.W - 1, 8, "eig V");
+          ck.span(J.lam, 0, J.W - 1, 8, "eig lam");
+          if (J.rank) {
+            ck.span(J.rank, 0, 0, 4, "eig rank");
+            ck.span(J.theta, 0, 0, 8, "eig theta");
+          }
         }
         break;
       }
@@ -2156,6 +2513,142 @@ extern "C" int tsk_plan_selfcheck_project(const tsk_tucker_sum* sum, const int64
   size_t need2 = 0;
   plan_project(&fake_handle, P, Q, basis_dtype == TSK_F64, H, out_dtype == TSK_F64, ws, prog,
                &need2);
+  if (need2 != need) {
+    say("workspace size differs between the size query and the call");
+    return 99;
+  }
+  check_program(prog, ck);
+  if (!ck.ok) {
+    say(ck.err);
+    return 98;
+  }
+  say("ok");
+  return 0;
+}
+
+// Every phase of a truncation planned with the given ranks (as the device
+// would report them), each launch checked against the workspace and the
+// caller's buffers.
+extern "C" int tsk_plan_selfcheck_truncate(int32_t order, const int64_t* dims,
+                                           const int64_t* widths, const int32_t* ranks,
+                                           char* msg, size_t msglen) {
+  auto say = [&](const std::string& s) {
+    if (msg && msglen) {
+      std::strncpy(msg, s.c_str(), msglen - 1);
+      msg[msglen - 1] = 0;
+    }
+  };
+  tsk_handle_ scratch_handle;
+  TruncIO io;
+  if (tsk_status st = validate_trunc(&scratch_handle, order, dims, widths, 0.5, io); st != TSK_OK) {
+    say(scratch_handle.err);
+    return st;
+  }
+  Checker ck;
+  uintptr_t next = (uintptr_t)1 << 44;
+  auto fake = [&](size_t bytes, const char* name) {
+    void* p = (void*)next;
+    ck.add(p, bytes, name);
+    next += align_up(bytes, (size_t)1 << 20) + ((size_t)1 << 30);
+    return p;
+  };
+  int64_t hs = 1;
+  for (int k = 0; k < order; ++k) {
+    if (ranks[k] < 1 || ranks[k] > widths[k]) {
+      say("rank outside [1, width]");
+      return TSK_ERR_INVALID_ARG;
+    }
+    io.Q.push_back((const double*)fake(dims[k] * widths[k] * 8, "Q"));
+    io.U.push_back((double*)fake(dims[k] * widths[k] * 8, "U"));
+    hs *= widths[k];
+  }
+  io.H = (const double*)fake(hs * 8, "H");
+  io.G = (double*)fake(hs * 8, "G");
+  bool far = false;
+  const size_t need = trunc_workspace(io, &far);
+  if (far) {
+    say("stride beyond 31-bit offsets");
+    return TSK_ERR_UNSUPPORTED;
+  }
+  char* ws = (char*)fake(need, "workspace");
+  Arena fixed;
+  fixed.base = ws;
+  TruncLayout L;
+  trunc_layout(io, fixed, L);
+  std::vector<int64_t> shape = io.w;
+  std::vector<int32_t> rk(order, 0);
+  const double* cur = io.H;
+  int which = 0;
+  for (int n = 0; n <= order; ++n) {
+    double* dst = (n == order) ? io.G : L.buf[which];
+    Arena ar;
+    ar.base = ws;
+    ar.top = L.phase_base;
+    Program prog;
+    trunc_phase(io, L, n, shape, cur, dst, rk, ar, prog);
+    prog.meta_region = align_up(ar.top, 256);
+    if (prog.meta_region + align_up(prog.blob.size(), 256) + 256 > need) {
+      say("phase exceeds the planned workspace");
+      return 99;
+    }
+    check_program(prog, ck);
+    if (!ck.ok) {
+      say(ck.err);
+      return 98;
+    }
+    if (n > 0) {
+      shape[n - 1] = rk[n - 1];
+      cur = dst;
+      which ^= 1;
+    }
+    if (n < order) rk[n] = ranks[n];
+  }
+  say("ok");
+  return 0;
+}
+
+extern "C" int tsk_plan_selfcheck_subranks(const tsk_tucker_sum* sum, char* msg, size_t msglen) {
+  auto say = [&](const std::string& s) {
+    if (msg && msglen) {
+      std::strncpy(msg, s.c_str(), msglen - 1);
+      msg[msglen - 1] = 0;
+    }
+  };
+  tsk_handle_ scratch_handle;
+  Problem P;
+  if (tsk_status st = validate_subranks(&scratch_handle, sum, 0.5, P); st != TSK_OK) {
+    say(scratch_handle.err);
+    return st;
+  }
+  Checker ck;
+  uintptr_t next = (uintptr_t)1 << 44;
+  auto fake = [&](size_t bytes, const char* name) {
+    void* q = (void*)next;
+    ck.add(q, bytes, name);
+    next += align_up(bytes, (size_t)1 << 20) + ((size_t)1 << 30);
+    return q;
+  };
+  const size_t ein = P.in_f64 ? 8 : 4;
+  for (int i = 0; i < P.s; ++i) {
+    int64_t cs = 1;
+    for (int k = 0; k < P.d; ++k) cs *= P.r(i, k);
+    P.cores[i] = fake(cs * ein, "core");
+    for (int k = 0; k < P.d; ++k)
+      P.factors[(size_t)i * P.d + k] = fake(P.dims[k] * P.r(i, k) * ein, "factor");
+  }
+  tsk_handle_ fake_handle;
+  Program p0;
+  SubrankOut o0;
+  size_t need = 0;
+  if (tsk_status st = plan_subranks_sized(&fake_handle, P, 0.5, nullptr, p0, o0, &need); st != TSK_OK) {
+    say(fake_handle.err);
+    return st;
+  }
+  char* ws = (char*)fake(need, "workspace");
+  Program prog;
+  SubrankOut o1;
+  size_t need2 = 0;
+  plan_subranks_sized(&fake_handle, P, 0.5, ws, prog, o1, &need2);
   if (need2 != need) {
     say("workspace size differs between the size query and the call");
     return 99;
@@ -2511,6 +3004,128 @@ tsk_status tucker_sum_project(tsk_handle h, const tsk_tucker_sum* sum, const voi
     return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
   if ((st = set_device(h)) != TSK_OK) return st;
   return run_program(h, prog, (char*)ws, (hipStream_t)stream);
+}
+
+tsk_status tucker_truncate_workspace_size(tsk_handle h, int32_t order, const int64_t* dims,
+                                         const int64_t* widths, double eps, size_t* bytes) {
+  if (h == nullptr || bytes == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL handle or bytes");
+  h->err.clear();
+  TruncIO io;
+  tsk_status st = validate_trunc(h, order, dims, widths, eps, io);
+  if (st != TSK_OK) return st;
+  io.Q.assign(order, nullptr);
+  io.U.assign(order, nullptr);
+  bool far = false;
+  *bytes = trunc_workspace(io, &far);
+  if (far) return fail(h, TSK_ERR_UNSUPPORTED, "an operand stride reaches past 2^31 bytes inside one tile");
+  return TSK_OK;
+}
+
+tsk_status tucker_truncate(tsk_handle h, int32_t order, const int64_t* dims,
+                           const int64_t* widths, const double* const* Q, const double* H,
+                           double eps, double* const* U_out, double* G_out, int32_t* ranks_out,
+                           void* ws, size_t ws_bytes, void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  TruncIO io;
+  tsk_status st = validate_trunc(h, order, dims, widths, eps, io);
+  if (st != TSK_OK) return st;
+  if (Q == nullptr || H == nullptr || U_out == nullptr || G_out == nullptr || ranks_out == nullptr)
+    return fail(h, TSK_ERR_INVALID_ARG, "NULL Q, H, U_out, G_out or ranks_out");
+  for (int k = 0; k < order; ++k) {
+    if (Q[k] == nullptr || U_out[k] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "Q[%d] or U_out[%d] is NULL", k, k);
+    io.Q.push_back(Q[k]);
+    io.U.push_back(U_out[k]);
+  }
+  io.H = H;
+  io.G = G_out;
+  if (ws == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  bool far = false;
+  const size_t need = trunc_workspace(io, &far);
+  if (far) return fail(h, TSK_ERR_UNSUPPORTED, "an operand stride reaches past 2^31 bytes inside one tile");
+  if (ws_bytes < need)
+    return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  if ((st = set_device(h)) != TSK_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Arena fixed;
+  fixed.base = (char*)ws;
+  TruncLayout L;
+  trunc_layout(io, fixed, L);
+  std::vector<int64_t> shape = io.w;
+  std::vector<int32_t> ranks(order, 0);
+  const double* cur = io.H;
+  int which = 0;
+  for (int n = 0; n <= order; ++n) {
+    // the last TTM writes the caller's core; the others ping-pong
+    double* dst = (n == order) ? io.G : L.buf[which];
+    Arena ar;
+    ar.base = (char*)ws;
+    ar.top = L.phase_base;
+    Program prog;
+    trunc_phase(io, L, n, shape, cur, dst, ranks, ar, prog);
+    prog.meta_region = align_up(ar.top, 256);
+    if (prog.meta_region + align_up(prog.blob.size(), 256) + 256 > need)
+      return fail(h, TSK_ERR_DEVICE, "truncation phase exceeds its planned workspace");
+    if ((st = run_program(h, prog, (char*)ws, s)) != TSK_OK) return st;
+    if (n > 0) {
+      shape[n - 1] = ranks[n - 1];
+      cur = dst;
+      which ^= 1;
+    }
+    if (n < order) {
+      int32_t r = 0;
+      if (hipStreamSynchronize(s) != hipSuccess ||
+          hipMemcpy(&r, L.ranks + n, sizeof r, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(h, TSK_ERR_DEVICE, "reading the rank of mode %d failed", n);
+      if (r < 1 || r > shape[n]) return fail(h, TSK_ERR_DEVICE, "rank %d of mode %d out of range", r, n);
+      ranks[n] = r;
+    }
+  }
+  for (int k = 0; k < order; ++k) ranks_out[k] = ranks[k];
+  return TSK_OK;
+}
+
+tsk_status tucker_sum_subranks_workspace_size(tsk_handle h, const tsk_tucker_sum* sum,
+                                              size_t* bytes) {
+  if (h == nullptr || bytes == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL handle or bytes");
+  h->err.clear();
+  Problem P;
+  tsk_status st = validate_subranks(h, sum, 0.5, P);
+  if (st != TSK_OK) return st;
+  Program prog;
+  SubrankOut out;
+  return plan_subranks_sized(h, P, 0.5, nullptr, prog, out, bytes);
+}
+
+tsk_status tucker_sum_subranks(tsk_handle h, const tsk_tucker_sum* sum, double eps,
+                               const int32_t* p, int32_t* ell_out, void* ws, size_t ws_bytes,
+                               void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  Problem P;
+  tsk_status st = validate_subranks(h, sum, eps, P);
+  if (st != TSK_OK) return st;
+  if (p == nullptr || ell_out == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "p or ell_out is NULL");
+  for (int n = 0; n < P.d; ++n)
+    if (p[n] < 0) return fail(h, TSK_ERR_INVALID_ARG, "p[%d] < 0", n);
+  if (ws == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  Program prog;
+  SubrankOut out;
+  size_t need = 0;
+  if ((st = plan_subranks_sized(h, P, eps, (char*)ws, prog, out, &need)) != TSK_OK) return st;
+  if (ws_bytes < need)
+    return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  if ((st = set_device(h)) != TSK_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = run_program(h, prog, (char*)ws, s)) != TSK_OK) return st;
+  int32_t r[kMaxOrder];
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(r, out.ranks, sizeof(int32_t) * P.d, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(h, TSK_ERR_DEVICE, "reading the effective subranks failed");
+  for (int n = 0; n < P.d; ++n) ell_out[n] = r[n] + p[n];
+  return TSK_OK;
 }
 
 tsk_status tsk_profile_enable(tsk_handle h, int32_t on) {

@@ -17,7 +17,7 @@ TEST_HEADER = os.path.join(ROOT, "include", "tsk_test.h")
 def declared_functions(header=HEADER):
     text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b((?:tsk|tucker_sum)_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b((?:tsk|tucker)_\w+)\s*\(", text)))
 
 
 def exported_functions():
@@ -29,7 +29,7 @@ def exported_functions():
     names = set()
     for line in out.splitlines():
         parts = line.split()
-        if len(parts) == 3 and parts[1] in ("T", "t") and re.match(r"(tsk|tucker_sum)_", parts[2]):
+        if len(parts) == 3 and parts[1] in ("T", "t") and re.match(r"(tsk|tucker)_", parts[2]):
             names.add(parts[2])
     return names
 

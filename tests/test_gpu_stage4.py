@@ -1,0 +1,130 @@
+"""Stage 4 on the GPU (tucker_truncate): ST-HOSVD of the projected core with
+tolerance eps against the oracle's st_hosvd, on the oracle's own Q and H
+(the stage alone) and on the library's recompression (round_sum)."""
+import numpy as np
+import pytest
+
+import synth
+from helpers import np_of, tucker_rel_diff
+from oracle import recompress as RC
+from oracle import tensor as T
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def tsk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_13532_amd as m
+    return m
+
+
+def condition_bound(h, ranks):
+    """The GPU factors the mode Grams, whose eigenvectors near the cut are
+    determined to about u sigma_1^2 / sigma_r^2 of the kept singular value:
+    the reconstructions then differ by about u sigma_1 / sigma_r of ||H||
+    (the oracle takes singular vectors of the unfoldings directly)."""
+    worst = 1.0
+    g = h
+    for n, r in enumerate(ranks):
+        s = np.linalg.svd(T.unfold(g, n), compute_uv=False)
+        worst = max(worst, s[0] / s[r - 1])
+        l = np.linalg.svd(T.unfold(g, n), full_matrices=False)[0][:, :r]
+        g = T.ttm(g, l.T, n)
+    return 256 * U64 * worst
+
+
+def stage_alone(tsk, ts, kind, sizes, seed, eps):
+    import torch
+    ref = RC.recompress(ts, kind, sizes, seed)
+    g_ref, v_ref = RC.st_hosvd(ref["H"], eps)
+    u_ref = [q @ v for q, v in zip(ref["Q"], v_ref)]
+    qd = [torch.from_numpy(np.asfortranarray(q)).to(DEV) for q in ref["Q"]]
+    hd = tsk.fortran(torch.from_numpy(np.asfortranarray(ref["H"])).to(DEV))
+    g, us, ranks = tsk.tucker_truncate(qd, hd, eps)
+    torch.cuda.synchronize()
+    assert tuple(ranks) == g_ref.shape, (ranks, g_ref.shape)
+    diff = tucker_rel_diff(np_of(g), [np_of(u) for u in us], g_ref, u_ref)
+    bound = max(1e-12, condition_bound(ref["H"], ranks))
+    print(f"ranks {ranks}, reconstruction vs oracle {diff:.2e} (bound {bound:.1e})")
+    assert diff <= bound
+    # the truncation error the tolerance promises
+    x_ref = (ref["H"], ref["Q"])
+    err = tucker_rel_diff(np_of(g), [np_of(u) for u in us], *x_ref)
+    assert err <= eps * (1 + 1e-9)
+    for u in us:
+        un = np_of(u)
+        assert np.linalg.norm(un.T @ un - np.eye(un.shape[1])) < 1e-12
+    return ranks
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-3])
+def test_truncate_tiny_kron(tsk, eps):
+    ts = synth.config_tiny()
+    stage_alone(tsk, ts, "kron", RC.kron_sizes(ts["ell"]), ts["omega_seed"], eps)
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-3, 1e-6])
+def test_truncate_structured_krp(tsk, eps):
+    """d=3, 512^3, 16 terms, decaying cores: H is 74^3."""
+    ts = synth.config_structured()
+    stage_alone(tsk, ts, "krp", [74], ts["omega_seed"], eps)
+
+
+def test_truncate_structured_kron(tsk):
+    """Kronecker sketch of the same sum: H is 81^3."""
+    ts = synth.config_structured()
+    stage_alone(tsk, ts, "kron", RC.kron_sizes(ts["ell"]), ts["omega_seed"], 1e-3)
+
+
+def test_truncate_ragged_four_modes(tsk):
+    ts = synth.random_sum(21, (40, 30, 20, 25), [[6, 5, 4, 7], [3, 8, 2, 5]], decay=0.2)
+    stage_alone(tsk, ts, "krp", [11], 3, 1e-3)
+
+
+def test_truncate_low_rank_recovers_the_rank(tsk):
+    """Rank-10 sum sketched wider (the section 5.1.1 construction): the
+    truncated ranks are the true multilinear ranks and the sum is recovered."""
+    ts = synth.e1_low_rank_sum(seed=5, d=4, n=24, terms=20, r_true=10)
+    ranks = stage_alone(tsk, ts, "krp", [12], 12, 1e-6)
+    assert list(ranks) == [10, 10, 10, 10]
+
+
+def test_round_sum_matches_oracle(tsk):
+    """Stages 2-4 on the GPU (recompression, then truncation) against the
+    oracle's recompression and st_hosvd."""
+    import torch
+    from helpers import to_torch
+    ts = synth.config_structured()
+    eps = 1e-3
+    ref = RC.recompress(ts, "krp", [74], ts["omega_seed"])
+    g_ref, v_ref = RC.st_hosvd(ref["H"], eps)
+    cores, factors = to_torch(ts, DEV)
+    g, us, ranks = tsk.round_sum(cores, factors, "krp", [74], ts["omega_seed"], eps)
+    torch.cuda.synchronize()
+    assert tuple(ranks) == g_ref.shape
+    diff = tucker_rel_diff(np_of(g), [np_of(u) for u in us], g_ref,
+                           [q @ v for q, v in zip(ref["Q"], v_ref)])
+    assert diff < 1e-11
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.3])
+def test_truncate_structured_krp_coarse(tsk, eps):
+    """Coarse tolerances cut the structured core well below 74 per mode."""
+    ts = synth.config_structured()
+    ranks = stage_alone(tsk, ts, "krp", [74], ts["omega_seed"], eps)
+    assert max(ranks) < 74
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-4, 1e-6])
+def test_truncate_fast_decay(tsk, eps):
+    """Steeply decaying cores (10^(-0.3 (i+j+k))): the ranks fall with eps."""
+    ts = synth.random_sum(34, (200, 180, 160), [[20, 20, 20], [16, 18, 14], [12, 12, 12]],
+                          decay=0.3)
+    ranks = stage_alone(tsk, ts, "krp", [40], 9, eps)
+    if eps >= 1e-4:
+        assert max(ranks) < 40

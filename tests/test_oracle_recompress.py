@@ -202,3 +202,119 @@ def test_stage4_st_hosvd_tolerance():
 def test_stage1_effective_subranks():
     ts = synth.e1_low_rank_sum(seed=7, d=3, n=30, terms=15, r_true=6)
     assert RC.effective_subranks(ts, 1e-6, 2) == [8, 8, 8]
+
+
+def _rank_rule(lam, theta):
+    """Smallest r >= 1 whose discarded values sum to at most theta (hand
+    evaluation of the rule, independent of the oracle's code)."""
+    lam = list(lam)
+    for r in range(1, len(lam) + 1):
+        if sum(lam[r:]) <= theta:
+            return r
+    return len(lam)
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-3, 0.05, 0.3])
+def test_stage4_diagonal_core_closed_form(eps):
+    """H = [[C; A_1, A_2, A_3]] with a diagonal core c_iii = s_i and
+    orthonormal A_k: every unfolding's singular values are s (the Khatri-Rao
+    product of orthonormal columns is orthonormal), the truncated core stays
+    diagonal, so the ranks follow the rule on s and its prefixes and the
+    result is A_k[:, :r] diag(s[:r]) exactly."""
+    rng = np.random.default_rng(3)
+    s = 10.0 ** (-0.25 * np.arange(12)) * (1 + 0.1 * rng.random(12))
+    n = (15, 13, 14)
+    A = [np.linalg.qr(rng.standard_normal((nk, 12)))[0] for nk in n]
+    C = np.zeros((12, 12, 12))
+    for i in range(12):
+        C[i, i, i] = s[i]
+    H = T.tucker_to_dense(C, A)
+    theta = eps ** 2 * float(np.sum(s ** 2)) / 3
+    r1 = _rank_rule(s ** 2, theta)
+    r2 = _rank_rule(s[:r1] ** 2, theta)
+    r3 = _rank_rule(s[:r2] ** 2, theta)
+    g, vs = RC.st_hosvd(H, eps)
+    assert g.shape == (r1, r2, r3)
+    want = np.zeros(n)
+    for i in range(r3):
+        want += s[i] * np.einsum("a,b,c->abc", A[0][:, i], A[1][:, i], A[2][:, i])
+    assert np.linalg.norm(T.tucker_to_dense(g, vs) - want) < 1e-12 * np.linalg.norm(H)
+    err2 = float(np.sum(s[r3:] ** 2))
+    assert abs(np.linalg.norm(T.tucker_to_dense(g, vs) - H) ** 2 - err2) < 1e-12 * float(np.sum(s ** 2))
+
+
+def test_stage4_two_modes_is_truncated_svd():
+    """d = 2: ST-HOSVD keeps the leading singular triplets of the matrix
+    (Eckart-Young): H = A diag(s) B^T built with known A, B, s."""
+    rng = np.random.default_rng(4)
+    s = np.array([5.0, 3.0, 2.0, 0.5, 0.1, 0.01, 0.001])
+    A = np.linalg.qr(rng.standard_normal((20, 7)))[0]
+    B = np.linalg.qr(rng.standard_normal((16, 7)))[0]
+    H = A @ np.diag(s) @ B.T
+    eps = 0.05
+    theta = eps ** 2 * float(np.sum(s ** 2)) / 2
+    r = _rank_rule(s ** 2, theta)
+    g, vs = RC.st_hosvd(H, eps)
+    assert g.shape[0] == r
+    want = A[:, :r] @ np.diag(s[:r]) @ B[:, :r].T
+    assert np.linalg.norm(vs[0] @ g @ vs[1].T - want) < 1e-12 * np.linalg.norm(H)
+
+
+def test_stage4_error_bound_and_monotone_ranks():
+    """||H - [[G; V]]|| <= eps ||H|| (ST-HOSVD: the squared error is at most
+    the discarded sum of every mode, each <= theta = eps^2 ||H||^2 / d), and
+    ranks do not grow as eps grows."""
+    rng = np.random.default_rng(5)
+    H = synth.decaying_core(rng, (14, 12, 10), rate=0.15)
+    prev = None
+    for eps in (1e-8, 1e-4, 1e-2, 0.1, 0.5):
+        g, vs = RC.st_hosvd(H, eps)
+        err = np.linalg.norm(T.tucker_to_dense(g, vs) - H)
+        assert err <= eps * np.linalg.norm(H) * (1 + 1e-12)
+        if prev is not None:
+            assert all(a <= b for a, b in zip(g.shape, prev))
+        prev = g.shape
+
+
+def test_stage1_single_orthonormal_term_closed_form():
+    """One term with orthonormal U_n: V_n = ||G|| U_n, so V_n^T V_n =
+    ||G||^2 I and the kept rank is r - floor(eps^2 r / d) plus p."""
+    for eps, p in ((1e-3, 0), (0.5, 1), (0.9, 2)):
+        ts = synth.random_sum(8, (30, 25, 20), [[9, 7, 5]])
+        want = [r - int(np.floor(eps ** 2 * r / 3 + 1e-12)) + p for r in (9, 7, 5)]
+        assert RC.effective_subranks(ts, eps, p) == want
+
+
+def test_stage1_shared_and_orthogonal_factors():
+    """Terms sharing one factor add their weights into one eigenvalue per
+    column (rank r, not s r); terms with orthogonal factors keep separate
+    eigenvalue groups ||G_i||^2, and the light group is dropped exactly when
+    its total is at most eps^2 / d times the whole."""
+    rng = np.random.default_rng(9)
+    U = [np.linalg.qr(rng.standard_normal((40, 12)))[0] for _ in range(3)]
+    g1 = rng.standard_normal((6, 6, 6))
+    g2 = 1e-3 * rng.standard_normal((6, 6, 6))
+    shared = synth.tucker_sum((40, 40, 40), [[6, 6, 6]] * 3,
+                              [g1, 2 * g1, -g1], [[u[:, :6] for u in U]] * 3)
+    assert RC.effective_subranks(shared, 1e-6, 0) == [6, 6, 6]
+    orth = synth.tucker_sum((40, 40, 40), [[6, 6, 6]] * 2, [g1, g2],
+                            [[u[:, :6] for u in U], [u[:, 6:] for u in U]])
+    w1, w2 = np.sum(g1 ** 2), np.sum(g2 ** 2)
+    for eps in (1e-4, 1e-1):
+        tau = eps ** 2 / 3 * 6 * (w1 + w2)
+        got = RC.effective_subranks(orth, eps, 0)
+        lam = sorted([w1] * 6 + [w2] * 6, reverse=True)
+        assert got == [_rank_rule(lam, tau)] * 3
+        assert (got[0] == 6) == (6 * w2 <= tau)
+
+
+def test_stage1_coefficients_scale_the_cores():
+    """A coefficient c_i acts as the core c_i G^(i) (and its sign does not
+    matter to a Gram matrix)."""
+    ts = synth.random_sum(12, (30, 25, 20), [[5, 4, 6], [3, 6, 2], [4, 4, 4]],
+                          coeffs=[2.0, -1e-3, 0.5])
+    scaled = dict(ts)
+    scaled["cores"] = [abs(c) * g for c, g in zip(ts["coeffs"], ts["cores"])]
+    scaled["coeffs"] = np.ones(3)
+    for eps in (1e-6, 1e-3, 0.2):
+        assert RC.effective_subranks(ts, eps, 1) == RC.effective_subranks(scaled, eps, 1)

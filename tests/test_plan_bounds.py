@@ -229,3 +229,56 @@ def test_project_plan_in_bounds(case):
                         assert "2^31" in msg
                         continue
                     assert rc == 0, (widths, prec, basis_f64, in_f64, msg)
+
+
+@pytest.mark.parametrize("dims,widths,ranks", [
+    ((64, 64, 64), (25, 25, 25), (25, 25, 25)),
+    ((64, 64, 64), (25, 25, 25), (1, 1, 1)),
+    ((512, 512, 512), (74, 74, 74), (30, 74, 2)),
+    ((512, 512, 512), (81, 81, 81), (81, 40, 81)),
+    ((256,) * 4, (56,) * 4, (20, 56, 3, 56)),
+    ((40, 30), (11, 11), (5, 11)),
+    ((9, 96, 96, 5, 7), (9, 96, 33, 5, 7), (9, 50, 1, 5, 2)),
+])
+def test_truncate_plan_in_bounds(dims, widths, ranks):
+    """Every launch of every mode of the Stage-4 truncation, planned with
+    the ranks the device could report, stays inside the workspace and the
+    caller's buffers."""
+    from paper_2603_13532_amd import _lib
+    lib = _lib.load()
+    fn = lib.tsk_plan_selfcheck_truncate
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                   ctypes.POINTER(ctypes.c_int32), ctypes.c_char_p, ctypes.c_size_t]
+    d = len(dims)
+    msg = ctypes.create_string_buffer(512)
+    rc = fn(d, (ctypes.c_int64 * d)(*dims), (ctypes.c_int64 * d)(*widths),
+            (ctypes.c_int32 * d)(*ranks), msg, 512)
+    assert rc == 0, msg.value.decode()
+
+
+@pytest.mark.parametrize("dims,ranks", [
+    ((64, 64, 64), np.full((4, 3), 8)),
+    ((130, 70, 90), [[70, 5, 33], [1, 66, 12], [40, 40, 40]]),
+    ((512, 512, 512), None),
+    ((40, 30, 20, 25), [[6, 5, 4, 7], [3, 8, 2, 5]]),
+])
+def test_subranks_plan_in_bounds(dims, ranks):
+    from paper_2603_13532_amd import _lib
+    if ranks is None:
+        ranks = synth.config_structured()["ranks"]
+    lib = _lib.load()
+    fn = lib.tsk_plan_selfcheck_subranks
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.POINTER(_lib.TuckerSum), ctypes.c_char_p, ctypes.c_size_t]
+    ranks = np.asarray(ranks)
+    s, d = ranks.shape
+    c_dims = (ctypes.c_int64 * d)(*dims)
+    c_ranks = (ctypes.c_int32 * (s * d))(*[int(x) for x in ranks.ravel()])
+    c_cores = (ctypes.c_void_p * s)(*([0x1000] * s))
+    c_fac = (ctypes.c_void_p * (s * d))(*([0x1000] * (s * d)))
+    for in_f64 in (True, False):
+        tsum = _lib.TuckerSum(d, s, c_dims, c_ranks, c_cores, c_fac, None, 0 if in_f64 else 1)
+        msg = ctypes.create_string_buffer(512)
+        rc = fn(ctypes.byref(tsum), msg, 512)
+        assert rc == 0, msg.value.decode()
