@@ -76,22 +76,32 @@ template <> struct AccElem<P_FP64> { typedef double type; };
 // instruction then writes 64 consecutive rows of one column, coalesced,
 // instead of the MFMA layout's 16 columns x 4 scattered rows.
 constexpr int kEpiLd = TILE + 1;
+// With kw waves per quadrant (K split among them), the waves of phase 0
+// write their quadrant and those of each later phase add theirs, in phase
+// order (the sum does not depend on timing).
 template <int P>
 __device__ __forceinline__ typename AccElem<P>::type* epi_stage(
-    typename PT<P>::acc_t (&acc)[2][2], void* lds, int lane, int wm, int wn) {
+    typename PT<P>::acc_t (&acc)[2][2], void* lds, int lane, int wm, int wn, int phase = 0,
+    int kw = 1) {
   typedef typename AccElem<P>::type ae;
   static_assert(sizeof(typename Lds<P>::type) * 2 >= sizeof(ae) * TILE * kEpiLd,
                 "the epilogue tile fits the K-loop buffers");
   ae* T = (ae*)lds;
   __syncthreads();
+  for (int ph = 0; ph < kw; ++ph) {
+    if (phase == ph) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        T[acc_row<P>(wm, i, lane, v) + kEpiLd * acc_col(wn, j, lane)] = (ae)acc[i][j][v];
-  __syncthreads();
+          for (int v = 0; v < 4; ++v) {
+            ae& cell = T[acc_row<P>(wm, i, lane, v) + kEpiLd * acc_col(wn, j, lane)];
+            cell = (ph == 0) ? (ae)acc[i][j][v] : cell + (ae)acc[i][j][v];
+          }
+    }
+    __syncthreads();
+  }
   return T;
 }
 
@@ -99,8 +109,9 @@ __device__ __forceinline__ typename AccElem<P>::type* epi_stage(
 template <int P, typename OutT>
 __device__ __forceinline__ void store_tile(typename PT<P>::acc_t (&acc)[2][2], OutT* __restrict__ C,
                                            int64_t ldc, int M, int N, int m0, int n0, bool accum,
-                                           int lane, int wm, int wn, void* lds, int t) {
-  const typename AccElem<P>::type* T = epi_stage<P>(acc, lds, lane, wm, wn);
+                                           int lane, int wm, int wn, void* lds, int t, int phase = 0,
+                                           int kw = 1) {
+  const typename AccElem<P>::type* T = epi_stage<P>(acc, lds, lane, wm, wn, phase, kw);
   const int r = t & (TILE - 1), row = m0 + r;
   if (row >= M) return;
 #pragma unroll 4
@@ -119,9 +130,10 @@ __device__ __forceinline__ void store_tile(typename PT<P>::acc_t (&acc)[2][2], O
 // applies beta and writes C, so the result does not depend on timing.
 template <int P>
 __device__ __forceinline__ void store_partial(typename PT<P>::acc_t (&acc)[2][2], void* part_tile,
-                                              int lane, int wm, int wn, void* lds, int t) {
+                                              int lane, int wm, int wn, void* lds, int t,
+                                              int phase = 0, int kw = 1) {
   typedef typename AccElem<P>::type ae;
-  const ae* T = epi_stage<P>(acc, lds, lane, wm, wn);
+  const ae* T = epi_stage<P>(acc, lds, lane, wm, wn, phase, kw);
   ae* mine = (ae*)part_tile;
   const int r = t & (TILE - 1);
 #pragma unroll 4
@@ -287,10 +299,10 @@ template <int P> struct Depth { static constexpr int value = 2; };
 // outside the output tile: it fetches and stages its share and meets every
 // barrier, but issues no MFMAs (the choice is made once, outside the loop,
 // so the loop body stays one basic block).
-template <int P, int D, bool MMA, class Cur>
+template <int P, int D, bool MMA, class Cur, int KW = 1>
 __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type (&s)[2],
                                       typename PT<P>::acc_t (&acc)[2][2], int t, int lane, int wm,
-                                      int wn) {
+                                      int wn, int phase = 0) {
   static_assert(D >= 2, "the slot staged next must differ from the one just fetched");
   typedef typename PT<P>::in_t in_t;
   constexpr int PER = Stage<P>::PER_THREAD;
@@ -334,7 +346,7 @@ __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type
       cur.fetch(ra[d], rb[d], have);
       const bool fa = cur.a_xc, fb = cur.b_xc;
       const in_t fal = cur.alpha;
-      if constexpr (MMA) mma_tile<P>(s[buf], acc, lane, wm, wn);
+      if constexpr (MMA) mma_tile<P, KW>(s[buf], acc, lane, wm, wn, phase);
       const int nx = (d + 1) % D;
       stage<P>(s[buf ^ 1], map, ax[nx], bx[nx], t, ra[nx], rb[nx], al[nx]);
       --inflight;
@@ -350,6 +362,53 @@ __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type
       if (inflight == 0) return;
     }
   }
+}
+
+// Which quadrant each wave computes, and over which K-steps.  A tile whose
+// valid region (rows [0, mr), columns [0, nc) of the 64 x 64 tile) covers
+// all four 32 x 32 quadrants gives one to each wave (kw = 1).  A smaller one
+// covers one or two quadrants: with the 4-deep FP64/FP32 instructions its
+// waves share them, kw = 4 or 2 waves per quadrant each taking every kw-th
+// step of the K-tile, so no SIMD idles; BF16 K-tiles are a single step, and
+// their waves outside the region skip the MFMAs (kw = 1, `active` false).
+struct WaveRole {
+  int kw, wm, wn, phase;
+  bool active;
+};
+template <int P>
+__device__ __forceinline__ WaveRole wave_role(int w, int mr, int nc) {
+  if constexpr (P == P_FP64 || P == P_FP32) {
+    const int qm = mr > 32 ? 2 : 1, qn = nc > 32 ? 2 : 1;
+    if (qm * qn == 1) return WaveRole{4, 0, 0, w, true};
+    if (qm * qn == 2) {
+      const int q = w & 1;
+      return WaveRole{2, qm == 2 ? q : 0, qm == 2 ? 0 : q, w >> 1, true};
+    }
+  }
+  const int wm = w & 1, wn = w >> 1;
+  return WaveRole{1, wm, wn, 0, wm * 32 < mr && wn * 32 < nc};
+}
+
+// K-loop with the wave role chosen per tile (one branch, outside the loop).
+template <int P, class Cur>
+__device__ __forceinline__ void kloop_role(Cur& cur, bool have, typename Lds<P>::type (&s)[2],
+                                           typename PT<P>::acc_t (&acc)[2][2], int t, int lane,
+                                           const WaveRole& role) {
+  constexpr int D = Depth<P>::value;
+  if constexpr (P == P_FP64 || P == P_FP32) {
+    if (role.kw == 4) {
+      kloop<P, D, true, Cur, 4>(cur, have, s, acc, t, lane, role.wm, role.wn, role.phase);
+      return;
+    }
+    if (role.kw == 2) {
+      kloop<P, D, true, Cur, 2>(cur, have, s, acc, t, lane, role.wm, role.wn, role.phase);
+      return;
+    }
+  }
+  if (role.active)
+    kloop<P, D, true, Cur>(cur, have, s, acc, t, lane, role.wm, role.wn);
+  else
+    kloop<P, D, false, Cur>(cur, have, s, acc, t, lane, role.wm, role.wn);
 }
 
 // ROLE only names the launch (one symbol per step of the method, so that
@@ -388,7 +447,7 @@ __global__ __launch_bounds__(NTHREADS, 4) void gemm_kernel(const GemmDesc* __res
   const int m0 = tm * TILE, n0 = tn * TILE;
   // the wave index goes through readfirstlane so that the compiler sees it as
   // uniform: branches on it stay scalar and the accumulators stay in place
-  const int t = threadIdx.x, lane = t & 63, w = uni(t >> 6), wm = w & 1, wn = w >> 1;
+  const int t = threadIdx.x, lane = t & 63, w = uni(t >> 6);
 
   acc_t acc[2][2];
   acc_zero<P>(acc);
@@ -408,25 +467,27 @@ __global__ __launch_bounds__(NTHREADS, 4) void gemm_kernel(const GemmDesc* __res
     cur.load();
     have = cur.skip(split);
   }
+  // one quadrant per wave here: the shared-quadrant variants of the K-loop
+  // push this kernel past its 128-register budget (it spills), and at two
+  // workgroups per CU the lost occupancy costs what the shared quadrants save
+  const WaveRole role{1, w & 1, w >> 1, 0, (w & 1) * 32 < M - m0 && (w >> 1) * 32 < N - n0};
   if (have) {
-    if (wm * 32 < M - m0 && wn * 32 < N - n0)
-      kloop<P, Depth<P>::value, true>(cur, have, s, acc, t, lane, wm, wn);
-    else
-      kloop<P, Depth<P>::value, false>(cur, have, s, acc, t, lane, wm, wn);
+    if (role.active) kloop<P, Depth<P>::value, true>(cur, have, s, acc, t, lane, role.wm, role.wn);
+    else kloop<P, Depth<P>::value, false>(cur, have, s, acc, t, lane, role.wm, role.wn);
   }
 
   const int64_t off = b * D.strideC;
   if (splits == 1) {
     if (D.c_f64)
-      store_tile<P, double>(acc, (double*)D.C + off, D.ldc, M, N, m0, n0, D.beta != 0, lane, wm, wn,
-                            s, t);
+      store_tile<P, double>(acc, (double*)D.C + off, D.ldc, M, N, m0, n0, D.beta != 0, lane,
+                            role.wm, role.wn, s, t, role.phase, role.kw);
     else
-      store_tile<P, float>(acc, (float*)D.C + off, D.ldc, M, N, m0, n0, D.beta != 0, lane, wm, wn,
-                           s, t);
+      store_tile<P, float>(acc, (float*)D.C + off, D.ldc, M, N, m0, n0, D.beta != 0, lane,
+                           role.wm, role.wn, s, t, role.phase, role.kw);
   } else {
     typedef typename AccElem<P>::type ae;
-    store_partial<P>(acc, (ae*)D.part + (tile_ns * splits + split) * (TILE * TILE), lane, wm, wn,
-                     s, t);
+    store_partial<P>(acc, (ae*)D.part + (tile_ns * splits + split) * (TILE * TILE), lane,
+                     role.wm, role.wn, s, t, role.phase, role.kw);
   }
 }
 
@@ -686,6 +747,7 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
   const int rn = rk[n];
   const int64_t stn = st[n];
 
+  const WaveRole role = wave_role<P>(w, rn - m0, m - n0);
   acc_t acc[2][2];
   acc_zero<P>(acc);
   // the block's 64 columns of every P_k (k != n) into LDS when they fit the
@@ -777,7 +839,7 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
     cur.c = (int64_t)split * BK + (Cur::FPK ? t % BK : 8 * (t >> 6));
     cur.digits(cur.c, cur.dg);
     cur.digits((int64_t)BK * splits, cur.inc);
-    kloop<P, Depth<P>::value, true>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn);
+    kloop_role<P>(cur, cur.kt < cur.nkt, s, acc, t, lane, role);
   };
   if (lds_p && order == 3) {
     KrpFixed<P, 2> cur;
@@ -789,21 +851,22 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
     KrpCursor<P, true> cur;
     TSK_KRP_CURSOR(cur)
     cur.sP = (typename KrpCursor<P, true>::lds_in_t*)sP;
-    kloop<P, Depth<P>::value, true>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn);
+    kloop_role<P>(cur, cur.kt < cur.nkt, s, acc, t, lane, role);
   } else {
     KrpCursor<P, false> cur;
     TSK_KRP_CURSOR(cur)
     cur.sP = nullptr;
-    kloop<P, Depth<P>::value, true>(cur, cur.kt < cur.nkt, s, acc, t, lane, wm, wn);
+    kloop_role<P>(cur, cur.kt < cur.nkt, s, acc, t, lane, role);
   }
 #undef TSK_KRP_CURSOR
   typedef typename std::conditional<P == P_FP64, double, float>::type vt;
   if (splits == 1) {
-    store_tile<P, vt>(acc, (vt*)Vout, rn, rn, m, m0, n0, false, lane, wm, wn, s, t);
+    store_tile<P, vt>(acc, (vt*)Vout, rn, rn, m, m0, n0, false, lane, role.wm, role.wn, s, t,
+                      role.phase, role.kw);
   } else {
     typedef typename AccElem<P>::type ae;
-    store_partial<P>(acc, (ae*)part_base + (tile_ns * splits + split) * (TILE * TILE), lane, wm, wn,
-                     s, t);
+    store_partial<P>(acc, (ae*)part_base + (tile_ns * splits + split) * (TILE * TILE), lane,
+                     role.wm, role.wn, s, t, role.phase, role.kw);
   }
 }
 

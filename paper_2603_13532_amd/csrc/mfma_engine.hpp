@@ -124,32 +124,41 @@ __device__ __forceinline__ void lds_put(typename Lds<P>::type& s, int which, int
 // basic blocks that the scheduler cannot interleave, and one wave issues in
 // order, so the loads, staging and address arithmetic of the next tile could
 // not hide behind these MFMAs.
-template <int P>
+//
+// KW waves share one quadrant (FP64/FP32 only): the wave with `phase` p
+// takes the 4-deep steps p, p + KW, ... of each K-tile, so a tile whose
+// valid region covers fewer than four quadrants still keeps every wave's
+// MFMA pipe busy; the partial accumulators are summed in the epilogue.
+template <int P, int KW = 1>
 __device__ __forceinline__ void mma_tile(const typename Lds<P>::type& s,
                                          typename PT<P>::acc_t (&acc)[2][2], int lane, int wm,
-                                         int wn) {
+                                         int wn, int phase = 0) {
   const int r = lane & 15, kq = lane >> 4;
   if constexpr (P == P_FP64 || P == P_FP32) {
     // Fragments of the whole K-tile are read up front; every 16 x 16 block
     // is computed (MFMAs under per-block branches also make the compiler
     // copy the accumulators between register sets after each one).
     constexpr int NS = PT<P>::BK / 4;
-    typename PT<P>::in_t a[NS][2], b[NS][2];
+    static_assert(NS % KW == 0, "the waves of a quadrant split the K-tile's steps evenly");
+    constexpr int NQ = NS / KW;
+    typename PT<P>::in_t a[NQ][2], b[NQ][2];
 #pragma unroll
-    for (int q = 0; q < NS; ++q) {
+    for (int qq = 0; qq < NQ; ++qq) {
+      const int q = (KW == 1) ? qq : phase + KW * qq;
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        a[q][i] = s.a[4 * q + kq][wm * 32 + 16 * i + r];
-        b[q][i] = s.b[4 * q + kq][wn * 32 + 16 * i + r];
+        a[qq][i] = s.a[4 * q + kq][wm * 32 + 16 * i + r];
+        b[qq][i] = s.b[4 * q + kq][wn * 32 + 16 * i + r];
       }
     }
 #pragma unroll
-    for (int q = 0; q < NS; ++q)
+    for (int qq = 0; qq < NQ; ++qq)
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = mma(a[q][i], b[q][j], acc[i][j]);
+        for (int j = 0; j < 2; ++j) acc[i][j] = mma(a[qq][i], b[qq][j], acc[i][j]);
   } else {
+    static_assert(KW == 1, "BF16 K-tiles are one MFMA step deep");
     constexpr int PARTS = PT<P>::PARTS;
     v8s a[PARTS][2], b[PARTS][2];
 #pragma unroll

@@ -893,15 +893,59 @@ __device__ __forceinline__ void hh_wide(const QrDesc& D, lds_f64* park, lds_f64*
   }
 }
 
+// Whether descriptor D needs the Householder path of the given kind (the
+// eight-wave register kernel when `wide`, the general kernel otherwise).
+__device__ __forceinline__ bool hh_needed(const QrDesc& D, int force, bool wide) {
+  if (hh_wide_panel(D.n, D.W) != wide) return false;
+  return force || D.hh_direct || *D.flag != 0;  // flag written by the first chol pass
+}
+
+// Index of the b-th descriptor (in descriptor order) that needs this
+// kernel, or -1: the launch covers every mode, but whether a mode breaks
+// down is known only on the device, so workgroup b takes the b-th mode that
+// does.  The modes that run then sit on consecutive workgroups, which the
+// dispatcher spreads over distinct CUs, instead of wherever their
+// descriptors fall.  Block-wide: every thread returns the same index.
+template <int T>
+__device__ int hh_nth_job(const QrDesc* __restrict__ qrs, int count, int force, bool wide,
+                          int b) {
+  constexpr int NWV = T / 64;
+  __shared__ int s_cnt[NWV];
+  __shared__ int s_found;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  if (t == 0) s_found = -1;
+  int base = 0;
+  for (int c0 = 0; c0 < count; c0 += T) {
+    const int i = c0 + t;
+    const bool need = i < count && hh_needed(qrs[i], force, wide);
+    const unsigned long long m = __ballot(need);
+    if (lane == 0) s_cnt[wv] = __popcll(m);
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int v = 0; v < NWV; ++v) {
+      if (v < wv) before += s_cnt[v];
+      total += s_cnt[v];
+    }
+    const int rank = base + before + __popcll(m & ((1ull << lane) - 1ull));
+    if (need && rank == b) s_found = i;
+    base += total;
+    __syncthreads();
+    if (s_found >= 0 || base > b) break;
+  }
+  const int r = s_found;
+  __syncthreads();
+  return r;
+}
+
 // Panels with W <= kWideCols and n <= kWideRows go here (one workgroup of
 // kWideWaves waves each); householder_kernel takes the others.
 __global__ __launch_bounds__(kWideWaves * 64) void householder_wide_kernel(
-    const QrDesc* __restrict__ qrs, int force, unsigned long long* counter) {
-  const QrDesc& D = qrs[blockIdx.x];
-  const bool broke = !D.hh_direct && *D.flag != 0;  // flag written by the first chol pass
-  if (!force && !broke && !D.hh_direct) return;
+    const QrDesc* __restrict__ qrs, int count, int force, unsigned long long* counter) {
+  const int job = hh_nth_job<kWideWaves * 64>(qrs, count, force, true, blockIdx.x);
+  if (job < 0) return;
+  const QrDesc& D = qrs[job];
+  const bool broke = !D.hh_direct && *D.flag != 0;
   const int64_t n = D.n, W = D.W;
-  if (!hh_wide_panel(n, W)) return;
   const int64_t w = n < W ? n : W;
   if (threadIdx.x == 0 && counter != nullptr) {
     atomicAdd(counter, 1ull);                              // QRs done by Householder
@@ -930,15 +974,15 @@ __global__ __launch_bounds__(kWideWaves * 64) void householder_wide_kernel(
 static_assert(kWideRows <= 48 * kWideWaves, "register window of the wide Householder path");
 
 __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restrict__ qrs,
-                                                          int force,
+                                                          int count, int force,
                                                           unsigned long long* counter,
                                                           int64_t lds_elems) {
   extern __shared__ __align__(16) double hsm[];
-  const QrDesc& D = qrs[blockIdx.x];
-  const bool broke = !D.hh_direct && *D.flag != 0;  // flag written by the first chol pass
-  if (!force && !broke && !D.hh_direct) return;
+  const int job = hh_nth_job<256>(qrs, count, force, false, blockIdx.x);
+  if (job < 0) return;
+  const QrDesc& D = qrs[job];
+  const bool broke = !D.hh_direct && *D.flag != 0;
   const int64_t n = D.n, W = D.W;
-  if (hh_wide_panel(n, W)) return;  // householder_wide_kernel's panel
   const int64_t w = n < W ? n : W;
   const int tid = threadIdx.x;
   if (tid == 0 && counter != nullptr) {
@@ -1043,13 +1087,13 @@ hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* f
   }
   if (kernels & 1) {
     householder_wide_kernel<<<dim3((unsigned)count), dim3(kWideWaves * 64), 0, stream>>>(
-        qr, force, (unsigned long long*)fallback_counter);
+        qr, count, force, (unsigned long long*)fallback_counter);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (kernels & 2) {
     householder_kernel<<<dim3((unsigned)count), dim3(256), (size_t)elems * sizeof(double), stream>>>(
-        qr, force, (unsigned long long*)fallback_counter, elems);
+        qr, count, force, (unsigned long long*)fallback_counter, elems);
     return hipGetLastError();
   }
   return hipSuccess;
