@@ -196,7 +196,8 @@ tsk_status tucker_sum_subranks(tsk_handle handle, const tsk_tucker_sum* sum, dou
  * H), the rank r_n = the smallest r >= 1 with sum_{i > r} lambda_i <= theta,
  * V_n = the r_n leading eigenvectors, G <- G x_n V_n^T; then the factors
  * U_n = Q_n V_n.  Everything in FP64.
- *   dims, widths: host [order]; widths[k] = w_k <= min(dims[k], 96).
+ *   dims, widths: host [order]; widths[k] = w_k <= min(dims[k], 1024) (above
+ *     96 the eigensolver keeps its matrices in the workspace, not in LDS).
  *   Q[k]: device n_k x w_k (ld n_k); H: device w_1 x ... x w_d (the outputs
  *     of tucker_sum_recompress with out_dtype TSK_F64).
  *   U_out[k]: device n_k x w_k buffers, of which the first r_k columns
@@ -212,6 +213,27 @@ tsk_status tucker_truncate(tsk_handle handle, int32_t order, const int64_t* dims
                            const int64_t* widths, const double* const* Q, const double* H,
                            double eps, double* const* U_out, double* G_out, int32_t* ranks_out,
                            void* ws, size_t ws_bytes, void* stream);
+
+/* The paper's deterministic baseline for the same sum: Algorithm 1
+ * (TuckerAxby) over all terms, i.e. the concatenated factors
+ * W_n = [U_n^(1), ..., U_n^(s)] (n_n x R_n, R_n = sum_i r_n^(i)) and the
+ * dense R_1 x ... x R_d core holding c_i G^(i) in disjoint blocks along the
+ * super-diagonal, followed by Algorithm 2 (TuckerRounding): the thin QR
+ * W_n = Q_n R_n with R_n absorbed into the core, then ST-HOSVD of that core
+ * with relative tolerance tau (theta = tau^2 ||core||^2 / d, the rank rule
+ * of tucker_truncate).  FP64 throughout.  Outputs as for tucker_truncate,
+ * with widths w_n = min(n_n, R_n): U_out[k] device n_k x w_k capacity (the
+ * first r_k columns written), G_out device prod_k w_k capacity, ranks_out
+ * host [d].  The dense core has prod_n R_n entries (the memory growth the
+ * sketched sum avoids); requires w_n <= 1024.  Synchronises `stream` once
+ * per mode. */
+tsk_status tucker_sum_round_deterministic_workspace_size(tsk_handle handle,
+                                                        const tsk_tucker_sum* sum, double tau,
+                                                        size_t* bytes);
+tsk_status tucker_sum_round_deterministic(tsk_handle handle, const tsk_tucker_sum* sum,
+                                          double tau, double* const* U_out, double* G_out,
+                                          int32_t* ranks_out, void* ws, size_t ws_bytes,
+                                          void* stream);
 
 /* tucker_sum_recompress for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -53,6 +53,11 @@ int tsk_plan_selfcheck_truncate(int32_t order, const int64_t* dims, const int64_
 /* Self-check of tucker_sum_subranks. */
 int tsk_plan_selfcheck_subranks(const tsk_tucker_sum* sum, char* msg, size_t msglen);
 
+/* Self-check of the first launch sequence of tucker_sum_round_deterministic
+ * (concatenation, QR, dense core, TTM chain; the truncation that follows is
+ * covered by tsk_plan_selfcheck_truncate). */
+int tsk_plan_selfcheck_deterministic(const tsk_tucker_sum* sum, char* msg, size_t msglen);
+
 /* The batched self-check, then one line per planned launch in msg: kernel,
  * descriptors, workgroups, largest K-split and segment count; a last line
  * gives the workspace and descriptor-blob sizes in bytes. */

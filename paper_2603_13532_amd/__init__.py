@@ -24,6 +24,7 @@ __all__ = [
     "Recompressor", "BatchRecompressor", "tucker_sum_recompress_batched",
     "tucker_sum_recompress_backward", "recompress", "tucker_sum_recompress_noalloc",
     "tucker_sum_project", "tucker_truncate", "round_sum", "effective_subranks", "sketch_sum",
+    "round_deterministic",
 ]
 
 
@@ -327,6 +328,36 @@ def sketch_sum(cores, factors, kind, eps, p, seed, coeffs=None, sketch_prec="fp6
     g, us, ranks = round_sum(cores, factors, kind, sizes, seed, eps, coeffs=coeffs,
                              sketch_prec=sketch_prec, project_prec=project_prec)
     return g, us, ranks, sizes
+
+
+def round_deterministic(cores, factors, tau, coeffs=None):
+    """The paper's deterministic baseline (Algorithm 1 over all terms, then
+    Algorithm 2 with tolerance tau) on the GPU.  Returns (G, [U..], ranks)."""
+    m = _Marshal(cores, factors, coeffs, "krp", [1], 0, None, "fp64", "fp64", "auto")
+    h = Handle.get(m.device)
+    nbytes = c_size_t()
+    check(load().tucker_sum_round_deterministic_workspace_size(h.ptr, byref(m.sum), float(tau),
+                                                               byref(nbytes)), h.ptr)
+    ws = h.workspace(nbytes.value)
+    R = [sum(int(g.shape[k]) for g in m.cores) for k in range(m.d)]
+    widths = [min(n, r) for n, r in zip(m.dims, R)]
+    U = [empty_fortran((n, w), torch.float64, m.device) for n, w in zip(m.dims, widths)]
+    total = 1
+    for w in widths:
+        total *= w
+    G = torch.empty(total, dtype=torch.float64, device=m.device)
+    ranks = (c_int32 * m.d)()
+    check(load().tucker_sum_round_deterministic(h.ptr, byref(m.sum), float(tau),
+                                                (c_void_p * m.d)(*[u.data_ptr() for u in U]),
+                                                c_void_p(G.data_ptr()), ranks,
+                                                c_void_p(ws.data_ptr()), ws.numel(),
+                                                c_void_p(_stream_ptr(m.device))), h.ptr)
+    r = list(ranks)
+    n = 1
+    for x in r:
+        n *= x
+    core = G[:n].reshape(tuple(reversed(r))).permute(tuple(reversed(range(m.d))))
+    return core, [u[:, :rk] for u, rk in zip(U, r)], r
 
 
 def tucker_sum_recompress_noalloc(cores, factors, kind, sizes, seed, Q_out, H_out, coeffs=None,

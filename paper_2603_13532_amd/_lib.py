@@ -83,6 +83,11 @@ PROTOTYPES = {
     "tucker_truncate": (c_int, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_int64),
                                 POINTER(c_void_p), c_void_p, c_double, POINTER(c_void_p),
                                 c_void_p, POINTER(c_int32), c_void_p, c_size_t, c_void_p]),
+    "tucker_sum_round_deterministic_workspace_size": (c_int, [c_void_p, POINTER(TuckerSum),
+                                                              c_double, POINTER(c_size_t)]),
+    "tucker_sum_round_deterministic": (c_int, [c_void_p, POINTER(TuckerSum), c_double,
+                                               POINTER(c_void_p), c_void_p, POINTER(c_int32),
+                                               c_void_p, c_size_t, c_void_p]),
     "tucker_sum_recompress_noalloc": (c_int, [c_void_p, POINTER(TuckerSum), POINTER(SketchSpec),
                                               POINTER(c_void_p), c_void_p, c_int,
                                               POINTER(c_void_p), c_void_p]),

@@ -35,6 +35,10 @@ __device__ __forceinline__ int rr_index(int i, int r, int Wp) {
   return i == 0 ? 0 : 1 + (i - 1 + r) % (Wp - 1);
 }
 
+// GLOBAL: the matrix and its eigenvectors live in the job's workspace (A at
+// J.work, Wp x Wp each) instead of LDS, for widths above kEigMaxW; the
+// rotation parameters stay in LDS.
+template <bool GLOBAL>
 __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigJob* __restrict__ jobs) {
   const EigJob J = jobs[blockIdx.x];
   const int W = J.W;
@@ -42,9 +46,9 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigJob* _
   const int half = Wp / 2;
   const int t = threadIdx.x;
   extern __shared__ __align__(16) unsigned char eig_dyn[];
-  double* A = (double*)eig_dyn;  // Wp x Wp, column-major (ld Wp)
-  double* V = A + Wp * Wp;       // Wp x Wp
-  double* cs = V + Wp * Wp;      // c, s per pair
+  double* A = GLOBAL ? J.work : (double*)eig_dyn;  // Wp x Wp, column-major (ld Wp)
+  double* V = A + (size_t)Wp * Wp;                 // Wp x Wp
+  double* cs = GLOBAL ? (double*)eig_dyn : V + (size_t)Wp * Wp;  // c, s per pair
   int* pr = (int*)(cs + 2 * half);  // p, q per pair
   __shared__ int s_rotated;
 
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigJob* _
     } else {
       theta = *J.theta;
     }
-    // smallest r >= 1 with sum_{i >= r} lam_i <= theta (i 0-based)
+    // smallest r >= 1 with sum_{i >= r} lam_i <= theta (i 0-based) 
     double tail = 0.0;
     int r = W;
     for (int i = W - 1; i >= 1; --i) {
@@ -375,17 +379,23 @@ size_t jacobi_eig_lds(int wmax) {
 
 hipError_t launch_jacobi_eig(const EigJob* jobs, int count, int wmax, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
-  if (wmax < 1 || wmax > kEigMaxW) return hipErrorInvalidValue;
+  if (wmax < 1 || wmax > kEigMaxWGlobal) return hipErrorInvalidValue;
+  if (wmax > kEigMaxW) {
+    const int Wp = wmax + (wmax & 1);
+    const size_t lds = (size_t)Wp * sizeof(double) + (size_t)Wp * sizeof(int);
+    jacobi_eig_kernel<true><<<dim3((unsigned)count), dim3(kEigThreads), lds, stream>>>(jobs);
+    return hipGetLastError();
+  }
   static bool attr_set = false;
   if (!attr_set) {
-    const hipError_t e = hipFuncSetAttribute((const void*)jacobi_eig_kernel,
+    const hipError_t e = hipFuncSetAttribute((const void*)jacobi_eig_kernel<false>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              (int)jacobi_eig_lds(kEigMaxW));
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   const size_t lds = jacobi_eig_lds(wmax);
-  jacobi_eig_kernel<<<dim3((unsigned)count), dim3(kEigThreads), lds, stream>>>(jobs);
+  jacobi_eig_kernel<false><<<dim3((unsigned)count), dim3(kEigThreads), lds, stream>>>(jobs);
   return hipGetLastError();
 }
 

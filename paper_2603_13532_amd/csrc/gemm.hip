@@ -1150,6 +1150,32 @@ __global__ __launch_bounds__(256) void copy_kernel(const CopyJob* __restrict__ j
   }
 }
 
+__global__ __launch_bounds__(256) void block_scatter_kernel(const BlockJob* __restrict__ jobs,
+                                                            int count) {
+  const int64_t chunk = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].chunk_begin <= chunk) lo = mid;
+    else hi = mid - 1;
+  }
+  const BlockJob& J = jobs[lo];
+  const int64_t base = (chunk - J.chunk_begin) * kCopyChunk;
+  for (int k = 0; k < kCopyChunk / 256; ++k) {
+    const int64_t e = base + k * 256 + threadIdx.x;
+    if (e >= J.count) break;
+    int64_t rem = e, off = 0, stride = 1;
+    for (int m = 0; m < J.order; ++m) {
+      const int64_t i = rem % J.r[m];
+      rem /= J.r[m];
+      off += (i + J.off[m]) * stride;
+      stride *= J.ext[m];
+    }
+    const double v = J.src_f64 ? ((const double*)J.src)[e] : (double)((const float*)J.src)[e];
+    J.dst[off] = J.alpha * v;
+  }
+}
+
 __global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* p, int64_t count, int32_t value) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
        e += (int64_t)gridDim.x * blockDim.x)
@@ -1239,6 +1265,13 @@ hipError_t launch_reduce(const ReduceJob* jobs, int count, hipStream_t stream) {
 hipError_t launch_tile_reduce(const ReduceJob* jobs, int count, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
   tile_reduce_kernel<<<dim3((unsigned)count, kReduceChunks), dim3(NTHREADS), 0, stream>>>(jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_scatter(const BlockJob* jobs, int count, int64_t chunks,
+                                hipStream_t stream) {
+  if (count <= 0 || chunks <= 0) return hipSuccess;
+  block_scatter_kernel<<<dim3((unsigned)chunks), dim3(256), 0, stream>>>(jobs, count);
   return hipGetLastError();
 }
 

@@ -77,6 +77,23 @@ struct CopyJob {
 };
 hipError_t launch_copy(const CopyJob* jobs, int count, int64_t chunks, hipStream_t stream);
 
+// Dense placement of one scaled core into a larger tensor (the
+// super-diagonal core of Algorithm 1): dst[(i_k + off_k)_k] = alpha *
+// src[(i_k)_k] over the r_1 x ... x r_d source (column-major), dst of
+// extents ext (column-major).  One workgroup per kCopyChunk source
+// elements; chunk_begin as for CopyJob.
+struct BlockJob {
+  double* dst;
+  const void* src;
+  int64_t r[kMaxOrder], off[kMaxOrder], ext[kMaxOrder];
+  int32_t order, src_f64;
+  double alpha;
+  int64_t count;
+  int64_t chunk_begin;
+};
+hipError_t launch_block_scatter(const BlockJob* jobs, int count, int64_t chunks,
+                                hipStream_t stream);
+
 // Cholesky QR passes and the Householder fallback over `count` modes.
 // wmax: widest Gram (W) among the descriptors; sizes the dynamic LDS.
 hipError_t launch_chol(const QrDesc* qr, int count, int pass, double tol, int wmax,
@@ -97,13 +114,17 @@ hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* f
 // when clip != 0.  With rank != null, the rank rule: theta = theta_scale *
 // trace(C) is computed and stored when set_theta != 0, else read from
 // *theta, and *rank = the smallest r >= 1 with sum_{i >= r} lam_i <= theta.
+// Widths above kEigMaxW (up to kEigMaxWGlobal) keep the matrix and its
+// eigenvectors in `work` (2 Wp^2 doubles, Wp = W rounded up to even).
 constexpr int kEigMaxW = 96;
+constexpr int kEigMaxWGlobal = 1024;
 struct EigJob {
   const double* C;
   double* V;
   double* lam;
   double* theta;
   int32_t* rank;
+  double* work;
   int64_t ldc, ldv;
   double tol, theta_scale;
   int32_t W, set_theta, clip, pad_;

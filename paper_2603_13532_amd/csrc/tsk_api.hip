@@ -212,7 +212,7 @@ tsk_status validate_spec(tsk_handle h, const tsk_sketch_spec* spec, Problem& P) 
 
 // ------------------------------------------------------------------ program
 enum StepKind { S_OMEGA, S_GEMM, S_KRP, S_REDUCE, S_TILE_REDUCE, S_COPY, S_FILL, S_CHOL, S_HOUSE,
-                S_KRP_ADJ, S_SYM, S_TRSM, S_EIG };
+                S_KRP_ADJ, S_SYM, S_TRSM, S_EIG, S_SCATTER };
 
 struct Step {
   StepKind kind;
@@ -486,6 +486,66 @@ struct Builder {
   }
   void emit(Program& prog);
 };
+
+// Thin QR (FP64, diag R >= 0) of the n_k x W_k matrices Y[k] into Q[k]
+// (n_k x min(n_k, W_k)) and, when R is not empty, R[k] (min(n_k, W_k) x
+// W_k): Cholesky QR2 where W_k <= 96 <= ... fits (W_k <= min(96, n_k) and
+// policy != 1), with a device-side Householder fallback on breakdown, and
+// Householder directly otherwise.
+void plan_qr(Builder& B, const std::vector<int64_t>& dims, const std::vector<int64_t>& Wd,
+             const std::vector<const double*>& Y, const std::vector<double*>& Q,
+             const std::vector<double*>& R, int qr_policy) {
+  Arena& ar = B.ar;
+  const int d = (int)dims.size();
+  std::vector<QrDesc> qd(d);
+  int32_t* flags = ar.counters(d);
+  for (int n = 0; n < d; ++n) {
+    const int64_t nn = dims[n], W = Wd[n], w = std::min(nn, W);
+    QrDesc& q = qd[n];
+    q.Y = Y[n];
+    q.Q = Q[n];
+    q.R = R.empty() ? nullptr : R[n];
+    q.n = nn;
+    q.W = W;
+    q.w = w;
+    q.flag = flags + n;
+    q.hh = (double*)ar.take((nn * W + W) * 8);  // panel, then the R-diagonal signs
+    q.tau = (double*)ar.take(W * 8);
+    const bool chol = qr_policy != 1 && W <= 96 && W <= nn;
+    q.hh_direct = chol ? 0 : 1;
+    q.report_only = qr_policy == 2 ? 1 : 0;
+    if (chol) {
+      B.any_chol = true;
+      q.gram_splits = (int)std::min<int64_t>(16, std::max<int64_t>(1, nn / 64));
+      q.gram_part = (double*)ar.take((size_t)q.gram_splits * W * W * 8);
+      q.rinv = (double*)ar.take(W * W * 8);
+      q.r1 = (double*)ar.take(W * W * 8);
+      q.q1 = (double*)ar.take(nn * W * 8);
+    }
+  }
+  for (int pass = 1; pass <= 2; ++pass) {
+    GemmBatch& gram = B.g(pass == 1 ? ST_GRAM1 : ST_GRAM2, P_FP64, R_QR_GRAM);
+    GemmBatch& qq = B.g(pass == 1 ? ST_BASIS1 : ST_BASIS2, P_FP64, R_QR_BASIS);
+    for (int n = 0; n < d; ++n) {
+      const QrDesc& q = qd[n];
+      if (q.gram_part == nullptr) continue;
+      const double* src = pass == 1 ? q.Y : q.q1;
+      // K-split of the Gram over row blocks, partials summed by the Cholesky kernel
+      const int64_t rows_per = ceil_div(q.n, q.gram_splits);
+      for (int sp = 0; sp < q.gram_splits; ++sp) {
+        const int64_t r0 = sp * rows_per, rl = std::max<int64_t>(0, std::min<int64_t>(rows_per, q.n - r0));
+        double* C = q.gram_part + (size_t)sp * q.W * q.W;
+        // an empty block (K = 0) writes zeros
+        gram.add(C, true, q.W, 0, (int)q.W, (int)q.W, 1, 0,
+                 {seg(rl > 0 ? src + r0 : src, q.n, 1, 0, rl > 0 ? src + r0 : src, q.n, 1, 0, rl)});
+      }
+      double* dst = pass == 1 ? q.q1 : q.Q;
+      qq.add(dst, true, q.n, 0, (int)q.n, (int)q.W, 1, 0,
+             {seg(src, 1, q.n, 0, q.rinv, q.W, 1, 0, q.W)});
+    }
+  }
+  for (auto& q : qd) B.qr.push_back(q);
+}
 
 // Stage 3 (Section 3.3): W_k^(i) = Q_k^T U_k^(i), then the multi-TTM
 // H = sum_i c_i G^(i) x_1 W_1^(i) ... x_d W_d^(i), modes 0..d-2 per term and
@@ -886,56 +946,10 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
   if (!out.recompress) return;
 
   // ---- thin QR of every Y_n in FP64
-  std::vector<QrDesc> qd(d);
   std::vector<double*> Qd(d);
-  int32_t* flags = ar.counters(d);
-  for (int n = 0; n < d; ++n) {
-    const int64_t nn = P.dims[n], W = P.W[n], w = P.w[n];
-    QrDesc& q = qd[n];
-    q.Y = Y[n];
-    Qd[n] = out.out_f64 ? (double*)out.Q[n] : (double*)ar.take(nn * w * 8);
-    q.Q = Qd[n];
-    q.R = out.R.empty() ? nullptr : out.R[n];
-    q.n = nn;
-    q.W = W;
-    q.w = w;
-    q.flag = flags + n;
-    q.hh = (double*)ar.take((nn * W + W) * 8);  // panel, then the R-diagonal signs
-    q.tau = (double*)ar.take(W * 8);
-    const bool chol = P.qr_policy != 1 && W <= 96 && W <= nn;
-    q.hh_direct = chol ? 0 : 1;
-    q.report_only = P.qr_policy == 2 ? 1 : 0;
-    if (chol) {
-      B.any_chol = true;
-      q.gram_splits = (int)std::min<int64_t>(16, std::max<int64_t>(1, nn / 64));
-      q.gram_part = (double*)ar.take((size_t)q.gram_splits * W * W * 8);
-      q.rinv = (double*)ar.take(W * W * 8);
-      q.r1 = (double*)ar.take(W * W * 8);
-      q.q1 = (double*)ar.take(nn * W * 8);
-    }
-  }
-  for (int pass = 1; pass <= 2; ++pass) {
-    GemmBatch& gram = B.g(pass == 1 ? ST_GRAM1 : ST_GRAM2, P_FP64, R_QR_GRAM);
-    GemmBatch& qq = B.g(pass == 1 ? ST_BASIS1 : ST_BASIS2, P_FP64, R_QR_BASIS);
-    for (int n = 0; n < d; ++n) {
-      const QrDesc& q = qd[n];
-      if (q.gram_part == nullptr) continue;
-      const double* src = pass == 1 ? q.Y : q.q1;
-      // K-split of the Gram over row blocks, partials summed by the Cholesky kernel
-      const int64_t rows_per = ceil_div(q.n, q.gram_splits);
-      for (int sp = 0; sp < q.gram_splits; ++sp) {
-        const int64_t r0 = sp * rows_per, rl = std::max<int64_t>(0, std::min<int64_t>(rows_per, q.n - r0));
-        double* C = q.gram_part + (size_t)sp * q.W * q.W;
-        // an empty block (K = 0) writes zeros
-        gram.add(C, true, q.W, 0, (int)q.W, (int)q.W, 1, 0,
-                 {seg(rl > 0 ? src + r0 : src, q.n, 1, 0, rl > 0 ? src + r0 : src, q.n, 1, 0, rl)});
-      }
-      double* dst = pass == 1 ? q.q1 : q.Q;
-      qq.add(dst, true, q.n, 0, (int)q.n, (int)q.W, 1, 0,
-             {seg(src, 1, q.n, 0, q.rinv, q.W, 1, 0, q.W)});
-    }
-  }
-  for (auto& q : qd) B.qr.push_back(q);
+  for (int n = 0; n < d; ++n)
+    Qd[n] = out.out_f64 ? (double*)out.Q[n] : (double*)ar.take(P.dims[n] * P.w[n] * 8);
+  plan_qr(B, P.dims, P.W, std::vector<const double*>(Y.begin(), Y.end()), Qd, out.R, P.qr_policy);
 
   // ---- core projection (Section 3.3)
   std::vector<CopyJob>& cq = B.copies[ST_QCOPY];
@@ -1498,6 +1512,7 @@ std::string step_name(const Step& st) {
     case S_SYM: return "sym_kernel";
     case S_TRSM: return "trsm_rt_kernel";
     case S_EIG: return st.pass == 1 ? "tridiag_eig_kernel" : "jacobi_eig_kernel";
+    case S_SCATTER: return "block_scatter_kernel";
   }
   return "unknown";
 }
@@ -1605,6 +1620,9 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
         break;
       case S_SYM: e = launch_sym((const SymJob*)(meta + st.meta), st.count, stream); break;
       case S_TRSM: e = launch_trsm_rt((const TrsmJob*)(meta + st.meta), st.count, stream); break;
+      case S_SCATTER:
+        e = launch_block_scatter((const BlockJob*)(meta + st.meta), st.count, st.tiles, stream);
+        break;
       case S_EIG:
         e = st.pass == 1 ? launch_tridiag_eig((const EigJob*)(meta + st.meta), st.count, st.wmax, stream)
                          : launch_jacobi_eig((const EigJob*)(meta + st.meta), st.count, st.wmax, stream);
@@ -1728,6 +1746,7 @@ struct TruncLayout {
   double* C = nullptr;
   std::vector<double*> V, lam;
   double* buf[2] = {nullptr, nullptr};
+  double* work = nullptr;  // eigensolver workspace for widths above the LDS limit
   size_t phase_base = 0;
 };
 
@@ -1748,6 +1767,10 @@ static void trunc_layout(const TruncIO& io, Arena& ar, TruncLayout& L) {
   }
   L.buf[0] = (double*)ar.take(hs * 8);
   L.buf[1] = (double*)ar.take(hs * 8);
+  if (wmax > kEigMaxW) {
+    const int64_t Wp = wmax + (wmax & 1);
+    L.work = (double*)ar.take(2 * Wp * Wp * 8);
+  }
   L.phase_base = align_up(ar.top, 256);
 }
 
@@ -1822,6 +1845,7 @@ static void trunc_phase(const TruncIO& io, const TruncLayout& L, int n,
     J.W = (int32_t)shape[n];
     J.set_theta = n == 0 ? 1 : 0;
     J.clip = 1;
+    J.work = L.work;
     Step st{};
     st.kind = S_EIG;
     st.meta = prog.put(std::vector<EigJob>{J});
@@ -1865,14 +1889,200 @@ static tsk_status validate_trunc(tsk_handle h, int32_t order, const int64_t* dim
   for (int k = 0; k < order; ++k) {
     if (dims[k] < 1 || widths[k] < 1) return fail(h, TSK_ERR_INVALID_ARG, "mode %d: size < 1", k);
     if (widths[k] > dims[k]) return fail(h, TSK_ERR_INVALID_ARG, "mode %d: width above the mode size", k);
-    if (widths[k] > kEigMaxW)
-      return fail(h, TSK_ERR_UNSUPPORTED, "mode %d: width %lld above %d", k, (long long)widths[k], kEigMaxW);
+    if (widths[k] > kEigMaxWGlobal)
+      return fail(h, TSK_ERR_UNSUPPORTED, "mode %d: width %lld above %d", k, (long long)widths[k],
+                  kEigMaxWGlobal);
     if (dims[k] > (1 << 30)) return fail(h, TSK_ERR_UNSUPPORTED, "dims[%d] too large", k);
     hs *= widths[k];
     io.dims.push_back(dims[k]);
     io.w.push_back(widths[k]);
   }
   if (hs > (int64_t(1) << 31)) return fail(h, TSK_ERR_UNSUPPORTED, "core too large");
+  return TSK_OK;
+}
+
+// The launches of a truncation, mode by mode, in `ws` (of `need` bytes, as
+// trunc_workspace computed); ranks_out: host [d].
+static tsk_status truncate_run(tsk_handle h, const TruncIO& io, char* ws, size_t need,
+                               hipStream_t s, int32_t* ranks_out) {
+  const int order = io.d;
+  Arena fixed;
+  fixed.base = ws;
+  TruncLayout L;
+  trunc_layout(io, fixed, L);
+  std::vector<int64_t> shape = io.w;
+  std::vector<int32_t> ranks(order, 0);
+  const double* cur = io.H;
+  int which = 0;
+  for (int n = 0; n <= order; ++n) {
+    // the last TTM writes the caller's core; the others ping-pong
+    double* dst = (n == order) ? io.G : L.buf[which];
+    Arena ar;
+    ar.base = ws;
+    ar.top = L.phase_base;
+    Program prog;
+    trunc_phase(io, L, n, shape, cur, dst, ranks, ar, prog);
+    prog.meta_region = align_up(ar.top, 256);
+    if (prog.meta_region + align_up(prog.blob.size(), 256) + 256 > need)
+      return fail(h, TSK_ERR_DEVICE, "truncation phase exceeds its planned workspace");
+    tsk_status st = run_program(h, prog, ws, s);
+    if (st != TSK_OK) return st;
+    if (n > 0) {
+      shape[n - 1] = ranks[n - 1];
+      cur = dst;
+      which ^= 1;
+    }
+    if (n < order) {
+      int32_t r = 0;
+      if (hipStreamSynchronize(s) != hipSuccess ||
+          hipMemcpy(&r, L.ranks + n, sizeof r, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(h, TSK_ERR_DEVICE, "reading the rank of mode %d failed", n);
+      if (r < 1 || r > shape[n]) return fail(h, TSK_ERR_DEVICE, "rank %d of mode %d out of range", r, n);
+      ranks[n] = r;
+    }
+  }
+  for (int k = 0; k < order; ++k) ranks_out[k] = ranks[k];
+  return TSK_OK;
+}
+
+// ------------------------------------------------------------------ deterministic baseline
+// The paper's baseline for the sum: Algorithm 1 (TuckerAxby) over all
+// terms, W_n = [U_n^(1), ..., U_n^(s)] (n_n x R_n, R_n = sum_i r_n^(i)) and
+// the dense R_1 x ... x R_d core with c_i G^(i) in disjoint blocks along the
+// super-diagonal; then Algorithm 2 (TuckerRounding): W_n = Q_n R_n (thin
+// QR), C <- C x_n R_n for every n, and the ST-HOSVD of C with tolerance tau
+// and theta = tau^2 ||C||^2 / d (the Stage 4 machinery on Q_n and C).
+// Phase 1 (one launch sequence): the concatenated factors, their QR, the
+// dense core and its TTM chain.
+struct DetPlan {
+  std::vector<int64_t> R, w;      // concatenated widths and min(n, R)
+  std::vector<double*> Wf, Q, Rm;  // n x R factors, n x w bases, w x R triangles
+  double* C = nullptr;             // R_1 x ... x R_d super-diagonal core
+  double* core = nullptr;          // w_1 x ... x w_d after the TTM chain
+};
+
+static void plan_det_phase1(const Problem& P, Arena& ar, Program& prog, DetPlan& D) {
+  const int d = P.d, s = P.s;
+  ar.ctr_base = (int32_t*)ar.take(sizeof(int32_t) * 64);
+  D.R.assign(d, 0);
+  for (int n = 0; n < d; ++n)
+    for (int i = 0; i < s; ++i) D.R[n] += P.r(i, n);
+  std::vector<CopyJob> cat;
+  int64_t csz = 1;
+  for (int n = 0; n < d; ++n) {
+    D.w.push_back(std::min(P.dims[n], D.R[n]));
+    D.Wf.push_back((double*)ar.take(P.dims[n] * D.R[n] * 8));
+    D.Q.push_back((double*)ar.take(P.dims[n] * D.w[n] * 8));
+    D.Rm.push_back((double*)ar.take(D.w[n] * D.R[n] * 8));
+    int64_t col = 0;
+    for (int i = 0; i < s; ++i) {
+      cat.push_back(CopyJob{D.Wf[n] + P.dims[n] * col, P.factors[(size_t)i * d + n], P.dims[n],
+                            P.r(i, n), P.dims[n], P.dims[n], 1, P.in_f64 ? 1 : 0});
+      col += P.r(i, n);
+    }
+    csz *= D.R[n];
+  }
+  D.C = (double*)ar.take(csz * 8);
+  Builder B(ar);
+  B.copies[ST_CONVERT] = cat;
+  plan_qr(B, P.dims, D.R, std::vector<const double*>(D.Wf.begin(), D.Wf.end()), D.Q, D.Rm, 0);
+  B.emit(prog);
+  // the dense super-diagonal core: zeros, then the scaled cores in their blocks
+  Step fill{};
+  fill.kind = S_FILL;
+  fill.ptr = D.C;
+  fill.rows = 2 * csz;
+  fill.value = 0;
+  prog.steps.push_back(fill);
+  std::vector<BlockJob> blocks;
+  std::vector<int64_t> off(d, 0);
+  int64_t chunks = 0;
+  for (int i = 0; i < s; ++i) {
+    BlockJob J{};
+    J.dst = D.C;
+    J.src = P.cores[i];
+    J.order = d;
+    J.src_f64 = P.in_f64 ? 1 : 0;
+    J.alpha = P.coeffs[i];
+    J.count = 1;
+    for (int k = 0; k < kMaxOrder; ++k) {
+      J.r[k] = k < d ? P.r(i, k) : 1;
+      J.off[k] = k < d ? off[k] : 0;
+      J.ext[k] = k < d ? D.R[k] : 1;
+      if (k < d) J.count *= P.r(i, k);
+    }
+    J.chunk_begin = chunks;
+    chunks += ceil_div(J.count, kCopyChunk);
+    blocks.push_back(J);
+    for (int k = 0; k < d; ++k) off[k] += P.r(i, k);
+  }
+  Step sc{};
+  sc.kind = S_SCATTER;
+  sc.meta = prog.put(blocks);
+  sc.count = (int)blocks.size();
+  sc.tiles = chunks;
+  prog.steps.push_back(sc);
+  // C <- C x_k R_k, k = 1..d, through two ping-pong buffers; the last into core
+  std::vector<int64_t> shape = D.R;
+  int64_t mx = 1;
+  {
+    std::vector<int64_t> sh = D.R;
+    for (int k = 0; k < d; ++k) {
+      sh[k] = D.w[k];
+      int64_t sz = 1;
+      for (auto x : sh) sz *= x;
+      mx = std::max(mx, sz);
+    }
+  }
+  double* buf[2] = {(double*)ar.take(mx * 8), (double*)ar.take(mx * 8)};
+  const double* cur = D.C;
+  for (int k = 0; k < d; ++k) {
+    double* out = k == d - 1 ? (D.core = (double*)ar.take(mx * 8)) : buf[k & 1];
+    const int64_t Rk = shape[k], wk = D.w[k];
+    int64_t Lo = 1, Ro = 1;
+    for (int j = 0; j < k; ++j) Lo *= shape[j];
+    for (int j = k + 1; j < d; ++j) Ro *= shape[j];
+    GemmBatch gb(P_FP64, R_OTHER, &ar);
+    if (k == 0) {
+      // out (w_0 x Ro) = R_0 (w_0 x R_0) . C_(0) (R_0 x Ro)
+      const int splits = choose_splits(ceil_div(wk, 64) * ceil_div(Ro, 64), ceil_div(Rk, 16));
+      gb.add(out, true, wk, 0, (int)wk, (int)Ro, 1, 0,
+             {seg(D.Rm[k], 1, wk, 0, cur, Rk, 1, 0, Rk)}, splits);
+    } else {
+      // per trailing index b: out_b (Lo x w_k) = C_b (Lo x R_k) . R_k^T (R_k x w_k)
+      gb.add(out, true, Lo, Lo * wk, (int)Lo, (int)wk, (int)Ro, 0,
+             {seg(cur, 1, Lo, Lo * Rk, D.Rm[k], 1, wk, 0, Rk)});
+    }
+    emit_gemm(prog, gb);
+    shape[k] = wk;
+    cur = out;
+  }
+}
+
+static tsk_status validate_det(tsk_handle h, const tsk_tucker_sum* sum, double tau, Problem& P,
+                               TruncIO& io) {
+  if (tsk_status st = validate_sum(h, sum, P); st != TSK_OK) return st;
+  if (!(tau >= 0.0) || tau > 1.0) return fail(h, TSK_ERR_INVALID_ARG, "tau must be in [0, 1]");
+  int64_t csz = 1;
+  std::vector<int64_t> w(P.d);
+  for (int n = 0; n < P.d; ++n) {
+    int64_t R = 0;
+    for (int i = 0; i < P.s; ++i) R += P.r(i, n);
+    csz *= R;
+    if (csz > (int64_t(1) << 32)) return fail(h, TSK_ERR_UNSUPPORTED, "dense core of the formal sum too large");
+    w[n] = std::min(P.dims[n], R);
+  }
+  return validate_trunc(h, P.d, P.dims.data(), w.data(), tau, io);
+}
+
+static tsk_status plan_det_sized(tsk_handle h, const Problem& P, char* ws, Program& prog,
+                                 DetPlan& D, size_t* phase1_bytes) {
+  Arena ar;
+  ar.base = ws;
+  plan_det_phase1(P, ar, prog, D);
+  if (!ar.too_far.empty()) return fail(h, TSK_ERR_UNSUPPORTED, "%s", ar.too_far.c_str());
+  prog.meta_region = align_up(ar.top, 256);
+  *phase1_bytes = align_up(prog.meta_region + align_up(prog.blob.size(), 256) + 256, 256);
   return TSK_OK;
 }
 
@@ -2201,11 +2411,33 @@ void check_program(const Program& prog, Checker& ck) {
         }
         break;
       }
+      case S_SCATTER: {
+        const BlockJob* js = (const BlockJob*)(blob + st.meta);
+        int64_t chunks = 0;
+        for (int i = 0; i < st.count; ++i) {
+          const BlockJob& J = js[i];
+          if (J.chunk_begin != chunks) { ck.ok = false; ck.err = "scatter chunk prefix mismatch"; return; }
+          chunks += (J.count + kCopyChunk - 1) / kCopyChunk;
+          int64_t cnt = 1, last = 0, stride = 1, total = 1;
+          for (int m = 0; m < J.order; ++m) {
+            if (J.off[m] + J.r[m] > J.ext[m]) { ck.ok = false; ck.err = "scatter block outside"; return; }
+            cnt *= J.r[m];
+            last += (J.off[m] + J.r[m] - 1) * stride;
+            stride *= J.ext[m];
+            total *= J.ext[m];
+          }
+          if (cnt != J.count) { ck.ok = false; ck.err = "scatter count mismatch"; return; }
+          ck.span(J.src, 0, J.count - 1, J.src_f64 ? 8 : 4, "scatter src");
+          ck.span(J.dst, 0, last, 8, "scatter dst");
+        }
+        if (chunks != st.tiles) { ck.ok = false; ck.err = "scatter chunk count mismatch"; return; }
+        break;
+      }
       case S_EIG: {
         const EigJob* js = (const EigJob*)(blob + st.meta);
         for (int i = 0; i < st.count; ++i) {
           const EigJob& J = js[i];
-          const int wcap = st.pass == 1 ? kTriMaxW : kEigMaxW;
+          const int wcap = st.pass == 1 ? kTriMaxW : kEigMaxWGlobal;
           if (J.W < 1 || J.W > wcap || J.W > st.wmax || J.ldc < J.W || J.ldv < J.W) {
             ck.ok = false;
             ck.err = "eigen job outside the kernel's sizes";
@@ -2214,6 +2446,10 @@ void check_program(const Program& prog, Checker& ck) {
           ck.span(J.C, 0, (J.W - 1) * J.ldc + J.W - 1, 8, "eig C");
           ck.span(J.V, 0, (J.W - 1) * J.ldv + J.W - 1, 8, "eig V");
           ck.span(J.lam, 0, J.W - 1, 8, "eig lam");
+          if (st.pass == 0 && J.W > kEigMaxW) {
+            const int64_t Wp = J.W + (J.W & 1);
+            ck.span(J.work, 0, 2 * Wp * Wp - 1, 8, "eig work");
+          }
           if (J.rank) {
             ck.span(J.rank, 0, 0, 4, "eig rank");
             ck.span(J.theta, 0, 0, 8, "eig theta");
@@ -2662,6 +2898,63 @@ extern "C" int tsk_plan_selfcheck_subranks(const tsk_tucker_sum* sum, char* msg,
   return 0;
 }
 
+extern "C" int tsk_plan_selfcheck_deterministic(const tsk_tucker_sum* sum, char* msg,
+                                                size_t msglen) {
+  auto say = [&](const std::string& s) {
+    if (msg && msglen) {
+      std::strncpy(msg, s.c_str(), msglen - 1);
+      msg[msglen - 1] = 0;
+    }
+  };
+  tsk_handle_ scratch_handle;
+  Problem P;
+  TruncIO io;
+  if (tsk_status st = validate_det(&scratch_handle, sum, 0.1, P, io); st != TSK_OK) {
+    say(scratch_handle.err);
+    return st;
+  }
+  Checker ck;
+  uintptr_t next = (uintptr_t)1 << 44;
+  auto fake = [&](size_t bytes, const char* name) {
+    void* q = (void*)next;
+    ck.add(q, bytes, name);
+    next += align_up(bytes, (size_t)1 << 20) + ((size_t)1 << 30);
+    return q;
+  };
+  const size_t ein = P.in_f64 ? 8 : 4;
+  for (int i = 0; i < P.s; ++i) {
+    int64_t cs = 1;
+    for (int k = 0; k < P.d; ++k) cs *= P.r(i, k);
+    P.cores[i] = fake(cs * ein, "core");
+    for (int k = 0; k < P.d; ++k)
+      P.factors[(size_t)i * P.d + k] = fake(P.dims[k] * P.r(i, k) * ein, "factor");
+  }
+  tsk_handle_ fake_handle;
+  Program p0;
+  DetPlan d0;
+  size_t need = 0;
+  if (tsk_status st = plan_det_sized(&fake_handle, P, nullptr, p0, d0, &need); st != TSK_OK) {
+    say(fake_handle.err);
+    return st;
+  }
+  char* ws = (char*)fake(need, "workspace");
+  Program prog;
+  DetPlan d1;
+  size_t need2 = 0;
+  plan_det_sized(&fake_handle, P, ws, prog, d1, &need2);
+  if (need2 != need) {
+    say("workspace size differs between the size query and the call");
+    return 99;
+  }
+  check_program(prog, ck);
+  if (!ck.ok) {
+    say(ck.err);
+    return 98;
+  }
+  say("ok");
+  return 0;
+}
+
 // Host-only bounds self-check of a planned call (tests; not part of the ABI header).
 extern "C" int tsk_plan_describe(int32_t batch, const tsk_tucker_sum* sums,
                                  const tsk_sketch_spec* specs, int out_dtype, char* msg,
@@ -3047,43 +3340,7 @@ tsk_status tucker_truncate(tsk_handle h, int32_t order, const int64_t* dims,
   if (ws_bytes < need)
     return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
   if ((st = set_device(h)) != TSK_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
-  Arena fixed;
-  fixed.base = (char*)ws;
-  TruncLayout L;
-  trunc_layout(io, fixed, L);
-  std::vector<int64_t> shape = io.w;
-  std::vector<int32_t> ranks(order, 0);
-  const double* cur = io.H;
-  int which = 0;
-  for (int n = 0; n <= order; ++n) {
-    // the last TTM writes the caller's core; the others ping-pong
-    double* dst = (n == order) ? io.G : L.buf[which];
-    Arena ar;
-    ar.base = (char*)ws;
-    ar.top = L.phase_base;
-    Program prog;
-    trunc_phase(io, L, n, shape, cur, dst, ranks, ar, prog);
-    prog.meta_region = align_up(ar.top, 256);
-    if (prog.meta_region + align_up(prog.blob.size(), 256) + 256 > need)
-      return fail(h, TSK_ERR_DEVICE, "truncation phase exceeds its planned workspace");
-    if ((st = run_program(h, prog, (char*)ws, s)) != TSK_OK) return st;
-    if (n > 0) {
-      shape[n - 1] = ranks[n - 1];
-      cur = dst;
-      which ^= 1;
-    }
-    if (n < order) {
-      int32_t r = 0;
-      if (hipStreamSynchronize(s) != hipSuccess ||
-          hipMemcpy(&r, L.ranks + n, sizeof r, hipMemcpyDeviceToHost) != hipSuccess)
-        return fail(h, TSK_ERR_DEVICE, "reading the rank of mode %d failed", n);
-      if (r < 1 || r > shape[n]) return fail(h, TSK_ERR_DEVICE, "rank %d of mode %d out of range", r, n);
-      ranks[n] = r;
-    }
-  }
-  for (int k = 0; k < order; ++k) ranks_out[k] = ranks[k];
-  return TSK_OK;
+  return truncate_run(h, io, (char*)ws, need, (hipStream_t)stream, ranks_out);
 }
 
 tsk_status tucker_sum_subranks_workspace_size(tsk_handle h, const tsk_tucker_sum* sum,
@@ -3126,6 +3383,64 @@ tsk_status tucker_sum_subranks(tsk_handle h, const tsk_tucker_sum* sum, double e
     return fail(h, TSK_ERR_DEVICE, "reading the effective subranks failed");
   for (int n = 0; n < P.d; ++n) ell_out[n] = r[n] + p[n];
   return TSK_OK;
+}
+
+tsk_status tucker_sum_round_deterministic_workspace_size(tsk_handle h,
+                                                        const tsk_tucker_sum* sum, double tau,
+                                                        size_t* bytes) {
+  if (h == nullptr || bytes == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL handle or bytes");
+  h->err.clear();
+  Problem P;
+  TruncIO io;
+  tsk_status st = validate_det(h, sum, tau, P, io);
+  if (st != TSK_OK) return st;
+  Program prog;
+  DetPlan D;
+  size_t p1 = 0;
+  if ((st = plan_det_sized(h, P, nullptr, prog, D, &p1)) != TSK_OK) return st;
+  io.Q.assign(P.d, nullptr);
+  io.U.assign(P.d, nullptr);
+  bool far = false;
+  *bytes = p1 + trunc_workspace(io, &far);
+  if (far) return fail(h, TSK_ERR_UNSUPPORTED, "an operand stride reaches past 2^31 bytes inside one tile");
+  return TSK_OK;
+}
+
+tsk_status tucker_sum_round_deterministic(tsk_handle h, const tsk_tucker_sum* sum, double tau,
+                                          double* const* U_out, double* G_out,
+                                          int32_t* ranks_out, void* ws, size_t ws_bytes,
+                                          void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  Problem P;
+  TruncIO io;
+  tsk_status st = validate_det(h, sum, tau, P, io);
+  if (st != TSK_OK) return st;
+  if (U_out == nullptr || G_out == nullptr || ranks_out == nullptr)
+    return fail(h, TSK_ERR_INVALID_ARG, "NULL U_out, G_out or ranks_out");
+  for (int k = 0; k < P.d; ++k)
+    if (U_out[k] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "U_out[%d] is NULL", k);
+  if (ws == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  Program prog;
+  DetPlan D;
+  size_t p1 = 0;
+  if ((st = plan_det_sized(h, P, (char*)ws, prog, D, &p1)) != TSK_OK) return st;
+  for (int k = 0; k < P.d; ++k) {
+    io.Q.push_back(D.Q[k]);
+    io.U.push_back(U_out[k]);
+  }
+  io.H = D.core;
+  io.G = G_out;
+  bool far = false;
+  const size_t tneed = trunc_workspace(io, &far);
+  if (far) return fail(h, TSK_ERR_UNSUPPORTED, "an operand stride reaches past 2^31 bytes inside one tile");
+  if (ws_bytes < p1 + tneed)
+    return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, p1 + tneed);
+  if ((st = set_device(h)) != TSK_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = run_program(h, prog, (char*)ws, s)) != TSK_OK) return st;
+  return truncate_run(h, io, (char*)ws + p1, tneed, s, ranks_out);
 }
 
 tsk_status tsk_profile_enable(tsk_handle h, int32_t on) {

@@ -142,3 +142,30 @@ def tucker_rel_diff(ha, qa, hb, qb, device=None):
     out = float(torch.linalg.vector_norm(ca - cb) / torch.linalg.vector_norm(cb))
     del ca, cb
     return out
+
+
+def condition_bound(h, ranks):
+    """The GPU factors the mode Grams, whose eigenvectors near the cut are
+    determined to about u sigma_1^2 / sigma_r^2 of the kept singular value:
+    the reconstructions then differ by about u sigma_1 / sigma_r of ||H||
+    (the oracle takes singular vectors of the unfoldings directly)."""
+    worst = 1.0
+    g = h
+    for n, r in enumerate(ranks):
+        s = np.linalg.svd(_unfold(g, n), compute_uv=False)
+        worst = max(worst, s[0] / s[r - 1])
+        l = np.linalg.svd(_unfold(g, n), full_matrices=False)[0][:, :r]
+        g = _ttm_o(g, l.T, n)
+    return 256 * 2.0 ** -53 * worst
+
+
+
+
+def _unfold(x, n):
+    from oracle import tensor as T
+    return T.unfold(x, n)
+
+
+def _ttm_o(x, a, n):
+    from oracle import tensor as T
+    return T.ttm(x, a, n)

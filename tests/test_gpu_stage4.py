@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import synth
-from helpers import np_of, tucker_rel_diff
+from helpers import condition_bound, np_of, tucker_rel_diff
 from oracle import recompress as RC
 from oracle import tensor as T
 
@@ -21,21 +21,6 @@ def tsk():
         pytest.skip("no GPU")
     import paper_2603_13532_amd as m
     return m
-
-
-def condition_bound(h, ranks):
-    """The GPU factors the mode Grams, whose eigenvectors near the cut are
-    determined to about u sigma_1^2 / sigma_r^2 of the kept singular value:
-    the reconstructions then differ by about u sigma_1 / sigma_r of ||H||
-    (the oracle takes singular vectors of the unfoldings directly)."""
-    worst = 1.0
-    g = h
-    for n, r in enumerate(ranks):
-        s = np.linalg.svd(T.unfold(g, n), compute_uv=False)
-        worst = max(worst, s[0] / s[r - 1])
-        l = np.linalg.svd(T.unfold(g, n), full_matrices=False)[0][:, :r]
-        g = T.ttm(g, l.T, n)
-    return 256 * U64 * worst
 
 
 def stage_alone(tsk, ts, kind, sizes, seed, eps):

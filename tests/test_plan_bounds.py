@@ -239,6 +239,7 @@ def test_project_plan_in_bounds(case):
     ((256,) * 4, (56,) * 4, (20, 56, 3, 56)),
     ((40, 30), (11, 11), (5, 11)),
     ((9, 96, 96, 5, 7), (9, 96, 33, 5, 7), (9, 50, 1, 5, 2)),
+    ((200, 150, 120), (200, 120, 97), (30, 120, 5)),  # widths past the LDS eigensolver
 ])
 def test_truncate_plan_in_bounds(dims, widths, ranks):
     """Every launch of every mode of the Stage-4 truncation, planned with
@@ -269,6 +270,32 @@ def test_subranks_plan_in_bounds(dims, ranks):
         ranks = synth.config_structured()["ranks"]
     lib = _lib.load()
     fn = lib.tsk_plan_selfcheck_subranks
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.POINTER(_lib.TuckerSum), ctypes.c_char_p, ctypes.c_size_t]
+    ranks = np.asarray(ranks)
+    s, d = ranks.shape
+    c_dims = (ctypes.c_int64 * d)(*dims)
+    c_ranks = (ctypes.c_int32 * (s * d))(*[int(x) for x in ranks.ravel()])
+    c_cores = (ctypes.c_void_p * s)(*([0x1000] * s))
+    c_fac = (ctypes.c_void_p * (s * d))(*([0x1000] * (s * d)))
+    for in_f64 in (True, False):
+        tsum = _lib.TuckerSum(d, s, c_dims, c_ranks, c_cores, c_fac, None, 0 if in_f64 else 1)
+        msg = ctypes.create_string_buffer(512)
+        rc = fn(ctypes.byref(tsum), msg, 512)
+        assert rc == 0, msg.value.decode()
+
+
+@pytest.mark.parametrize("dims,ranks", [
+    ((64, 64, 64), np.full((4, 3), 8)),                       # tall factors, CholQR2
+    ((130, 70, 90), [[70, 5, 33], [1, 66, 12], [40, 40, 40]]),  # wide mode 1 (R > n)
+    ((24,) * 4, np.ones((20, 4), dtype=int)),
+    ((40, 30, 20, 25), [[6, 5, 4, 7], [3, 8, 2, 5]]),
+    ((200, 200, 200), np.full((60, 3), 17)),                   # section 5.1.2 shape, R = 1020
+])
+def test_deterministic_plan_in_bounds(dims, ranks):
+    from paper_2603_13532_amd import _lib
+    lib = _lib.load()
+    fn = lib.tsk_plan_selfcheck_deterministic
     fn.restype = ctypes.c_int
     fn.argtypes = [ctypes.POINTER(_lib.TuckerSum), ctypes.c_char_p, ctypes.c_size_t]
     ranks = np.asarray(ranks)
