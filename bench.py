@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--forms", default="fp64,fp32,bf16x6,bf16x3")
-    ap.add_argument("--legs", default="structured,precision,gradient,tiny",
+    ap.add_argument("--legs", default="structured,precision,gradient,tiny,stages,lowrank",
                     help="workloads timed beside the headline batch (comma list, may be empty)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -419,6 +419,79 @@ def grad_leg(tsk, args, dev):
     return out
 
 
+def wall_ms(fn, reps):
+    """Median wall time (ms) of fn() with the device drained around each call
+    (the Stage 1 and Stage 4 calls read ranks back on the host)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        t.append((time.perf_counter() - t0) * 1e3)
+    t.sort()
+    return t[len(t) // 2]
+
+
+def stages_leg(tsk, dev, steps):
+    """Stage 1 (effective subranks, eps = 1e-3, p = 5) on the structured sum
+    (16 terms, sum of ranks 515 per mode: the tridiagonal-reduction
+    eigensolver), and Stage 4 (ST-HOSVD, eps = 1e-3) of its 74^3 core from
+    the fixed-size recompression (m = 74)."""
+    import synth
+    ts = synth.config_structured()
+    cores = [to_dev(tsk, g, torch_f64(), dev) for g in ts["cores"]]
+    factors = [[to_dev(tsk, u, torch_f64(), dev) for u in us] for us in ts["factors"]]
+    eps, p, seed = 1e-3, 5, ts["omega_seed"]
+    qs, hh = tsk.tucker_sum_recompress(cores, factors, "krp", [74], seed, out_dtype=torch_f64())
+    reps = max(3, steps // 4)
+    out = {"eps": eps, "p": p, "ell": tsk.effective_subranks(cores, factors, eps, p)}
+    out["stage1_ms"] = wall_ms(lambda: tsk.effective_subranks(cores, factors, eps, p), reps)
+    out["stage4_ms"] = wall_ms(lambda: tsk.tucker_truncate(qs, hh, eps), reps)
+    out["stage4_ranks"] = tsk.tucker_truncate(qs, hh, eps)[2]
+    log(f"structured sum: stage 1 {out['stage1_ms']:.2f} ms (ell {out['ell']}), stage 4 of the "
+        f"74^3 core {out['stage4_ms']:.2f} ms (ranks {out['stage4_ranks']})")
+    return out
+
+
+def low_rank_leg(tsk, dev, steps):
+    """The section 5.1.1 construction at the paper's size (order 4, n = 4000,
+    100 rank-1 terms in a shared rank-10 subspace, p = 2, eps = 1e-6): the
+    eps-driven KRP and Kronecker sums against the deterministic baseline
+    (Algorithm 1 over all terms, then Algorithm 2), all on the GPU, with the
+    agreement of the two results."""
+    import synth
+    ts = synth.e1_low_rank_sum(seed=1, d=4, n=4000, terms=100, r_true=10)
+    cores = [to_dev(tsk, g, torch_f64(), dev) for g in ts["cores"]]
+    factors = [[to_dev(tsk, u, torch_f64(), dev) for u in us] for us in ts["factors"]]
+    eps, p, seed = 1e-6, 2, 7
+    reps = max(3, steps // 4)
+    out = {"workload": "order 4, n=4000, 100 rank-1 terms in a shared rank-10 subspace, eps=1e-6, p=2"}
+    res = {}
+    for kind in ("krp", "kron"):
+        out[f"{kind}_ms"] = wall_ms(lambda: tsk.sketch_sum(cores, factors, kind, eps, p, seed), reps)
+        res[kind] = tsk.sketch_sum(cores, factors, kind, eps, p, seed)
+    out["deterministic_ms"] = wall_ms(lambda: tsk.round_deterministic(cores, factors, eps), 2)
+    g, us, ranks = tsk.round_deterministic(cores, factors, eps)
+    for kind in ("krp", "kron"):
+        gk, uk, rk, sizes = res[kind]
+        out[f"{kind}_ranks"] = rk
+        out[f"{kind}_vs_deterministic"] = xhat_rel_diff(gk, uk, g, us)
+        out[f"{kind}_speedup_vs_deterministic"] = out["deterministic_ms"] / out[f"{kind}_ms"]
+    out["deterministic_ranks"] = ranks
+    log(f"low-rank sum n=4000: krp {out['krp_ms']:.1f} ms, kron {out['kron_ms']:.1f} ms, "
+        f"deterministic {out['deterministic_ms']:.1f} ms; krp vs deterministic "
+        f"{out['krp_vs_deterministic']:.1e}")
+    return out
+
+
+def torch_f64():
+    import torch
+    return torch.float64
+
+
 def cpu_baseline(sums, seconds):
     """The oracle on the host cores: as many sums of the batch (in order) as
     fit in `seconds`, with the BLAS thread pool at its default, then again
@@ -562,6 +635,10 @@ def main():
         legs["precision_workload"] = "d=4, 256^4, s=8, cores 32^4, KRP m=56"
     if "gradient" in want:
         legs["gradient"] = grad_leg(tsk, args, dev)
+    if "stages" in want:
+        legs["stages_1_and_4"] = stages_leg(tsk, dev, args.steps)
+    if "lowrank" in want:
+        legs["low_rank_construction"] = low_rank_leg(tsk, dev, args.steps)
     if "tiny" in want:
         ts = synth.config_tiny()
         legs["tiny_kron"] = single_leg(tsk, args, ts, "kron", RC.kron_sizes(ts["ell"]),
