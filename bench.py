@@ -13,10 +13,12 @@ in HBM.
 
 Forms (the same FP32 input values throughout; the plain form holds them in
 FP64 storage):
-  fp64        every stage FP64 (the plain form)
-  fp32        FP32 MFMA contractions, FP64 QR
-  bf16x6      split-BF16 contractions (3 parts, 6 products), FP64 QR
-  bf16x3      split-BF16 sketch (2 parts, 3 products), bf16x6 projection
+  fp64          every stage FP64 (the plain form)
+  fp32          FP32 MFMA contractions, FP64 QR
+  bf16x6        split-BF16 contractions (3 parts, 6 products), FP64 QR
+  bf16x3        split-BF16 sketch (2 parts, 3 products), bf16x6 projection
+  fp64s_fp32p   FP64 sketch and QR, FP32 projection
+  fp64s_bf16x6p FP64 sketch and QR, bf16x6 projection
 Each form's error is ||X_hat - X_hat_oracle|| / ||X_hat_oracle|| for every
 one of the 256 sums against the FP64 oracle on the same values.  `value` is
 the recompressions/s of the fastest form whose error is at most 1e-6 on
@@ -49,6 +51,11 @@ FORMS = {
     "fp32": ("f32", "fp32", "fp32"),
     "bf16x6": ("f32", "bf16x6", "bf16x6"),
     "bf16x3": ("f32", "bf16x3", "bf16x6"),
+    # FP64 sketch (so the basis of the range carries no FP32 rounding into
+    # the sums whose rank sits just below the sketch width) with a mixed
+    # projection
+    "fp64s_fp32p": ("f32", "fp64", "fp32"),
+    "fp64s_bf16x6p": ("f32", "fp64", "bf16x6"),
 }
 BF16_PRODUCTS = {"bf16x1": 1, "bf16x3": 3, "bf16x6": 6}
 ERR_BAR = 1e-6
@@ -67,7 +74,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--forms", default="fp64,fp32,bf16x6,bf16x3")
+    ap.add_argument("--forms", default="fp64,fp32,bf16x6,bf16x3,fp64s_fp32p,fp64s_bf16x6p")
     ap.add_argument("--legs", default="structured,precision,gradient,tiny,stages,lowrank",
                     help="workloads timed beside the headline batch (comma list, may be empty)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -647,7 +654,9 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(sums, args.cpu_seconds)
 
     dtype = {"fp64": "f64", "fp32": "f32", "bf16x6": "bf16x6 (f32 accumulate)",
-             "bf16x3": "bf16x3/bf16x6 (f32 accumulate)"}[best]
+             "bf16x3": "bf16x3/bf16x6 (f32 accumulate)",
+             "fp64s_fp32p": "f64 sketch, f32 projection",
+             "fp64s_bf16x6p": "f64 sketch, bf16x6 projection (f32 accumulate)"}[best]
     line = {
         "metric": METRIC,
         "value": chosen["recompressions_per_s"],

@@ -20,6 +20,9 @@ FORMS = {
     "bf16x6": ("bf16x6", "bf16x6"),
     "bf16x3": ("bf16x3", "bf16x6"),
     "bf16x1": ("bf16x1", "bf16x6"),
+    # FP64 sketch and QR, mixed projection (FP32 inputs)
+    "fp64s_fp32p": ("fp64", "fp32"),
+    "fp64s_bf16x6p": ("fp64", "bf16x6"),
 }
 
 

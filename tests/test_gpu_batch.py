@@ -95,18 +95,21 @@ def test_batched_fp64_matches_oracle_every_sum(tsk, batch_refs):
             assert e["q"] < 1e-9 and e["h"] < 1e-10, (i, e)
 
 
-@pytest.mark.parametrize("form,bound", [("fp32", 6e-6), ("bf16x6", 4e-6), ("bf16x3", 2e-4)])
+@pytest.mark.parametrize("form,bound", [("fp32", 6e-6), ("bf16x6", 4e-6), ("bf16x3", 2e-4),
+                                        ("fp64s_fp32p", 1e-6), ("fp64s_bf16x6p", 1e-6)])
 def test_batched_mixed_forms_every_sum(tsk, batch_refs, form, bound):
     """The FP32-class forms on all 256 sums of the batch workload (FP32
     inputs) against the oracle on the same FP32 values: the worst sum's
     end-to-end error is printed and held to the form's measured level
     (fp32 4.3e-6, bf16x6 2.8e-6, bf16x3 1.1e-4: sums whose total rank is
     just below the sketch width amplify the sketch's rounding error through
-    the basis of its range)."""
+    the basis of its range).  With the sketch and QR in FP64 and only the
+    projection mixed, every sum stays within 1e-6."""
     import torch
     _, _, sums32, ref32 = batch_refs
     sp, pp = {"fp32": ("fp32", "fp32"), "bf16x6": ("bf16x6", "bf16x6"),
-              "bf16x3": ("bf16x3", "bf16x6")}[form]
+              "bf16x3": ("bf16x3", "bf16x6"), "fp64s_fp32p": ("fp64", "fp32"),
+              "fp64s_bf16x6p": ("fp64", "bf16x6")}[form]
     errs = batch_errors(tsk, sums32, ref32, torch.float32, sp, pp)
     xs = sorted(e["x"] for e in errs)
     over = sum(x > 1e-6 for x in xs)
