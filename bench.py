@@ -39,6 +39,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -75,7 +77,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--forms", default="fp64,fp32,bf16x6,bf16x3,fp64s_fp32p,fp64s_bf16x6p")
-    ap.add_argument("--legs", default="structured,precision,gradient,tiny,stages,lowrank",
+    ap.add_argument("--legs", default="structured,precision,gradient,tiny,stages,lowrank,ndg",
                     help="workloads timed beside the headline batch (comma list, may be empty)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -494,6 +496,71 @@ def low_rank_leg(tsk, dev, steps):
     return out
 
 
+def ndg_leg(tsk, dev, steps):
+    """Section 5.3's speed-up run at the paper's size: N_x = 32, k = 1 (64
+    nodes), N_xi = 100, Xi = 12, eps = 1e-6, p = 5, T_f = 0.005 with
+    dt = 0.1 h / ((2k+1) Xi), from the rank-6 initial condition.  Every step
+    recompresses the 64 node sums (9 Tucker terms each) with the batched
+    sketched sum (KRP and Kronecker: batched Stage 1, Stages 2-3, Stage 4)
+    and, for comparison, with the deterministic baseline node by node, all
+    on the GPU.  Wall time per step (host included: sizes and ranks come back
+    to the host), and the final states of the sketched runs against the
+    deterministic one."""
+    import torch
+    from synth import ndg
+    from paper_2603_13532_amd import ndg as gndg
+    st = ndg.setup(nx=32, k=1, nxi=100, xi_max=12.0)
+    nsteps = int(np.ceil(0.005 / st["dt"] - 1e-9))
+    st["dt"] = 0.005 / nsteps
+    terms = ndg.euler_terms(st)
+    init = gndg.to_device(ndg.initial_state(st), dev)
+    scales = {k: torch.from_numpy(v).to(dev) for k, v in st["scale"].items()}
+    eps, p = 1e-6, 5
+    out = {"workload": f"NDG transport, N_x=32, k=1 (64 node sums of {len(terms[0])} terms), "
+                       f"N_xi=100, Xi=12, eps=1e-6, p=5, {nsteps} forward-Euler steps to T=0.005"}
+
+    def run(stepper):
+        stepper(init)  # first call: handle, kernels, workspace
+        torch.cuda.synchronize()
+        states, t, info = init, [], None
+        for _ in range(nsteps):
+            t0 = time.perf_counter()
+            states, info = stepper(states)
+            torch.cuda.synchronize()
+            t.append((time.perf_counter() - t0) * 1e3)
+        return states, t, info
+
+    finals = {}
+    for kind in ("krp", "kron"):
+        def sk(x, kind=kind):
+            new, ranks, sizes = gndg.euler_step(x, terms, scales, eps, p, kind=kind, seed=5)
+            return new, (ranks, sizes)
+        states, t, (ranks, sizes) = run(sk)
+        finals[kind] = states
+        out[f"{kind}_ms_per_step"] = float(np.median(t))
+        out[f"{kind}_total_ms"] = float(np.sum(t))
+        out[f"{kind}_final_ranks_max"] = [int(max(r[k] for r in ranks)) for k in range(3)]
+        out[f"{kind}_final_sizes_max"] = [int(max(s_[k] for s_ in sizes))
+                                          for k in range(len(sizes[0]))]
+
+    def det(x):
+        new, ranks = gndg.euler_step_deterministic(x, terms, scales, eps)
+        return new, ranks
+    states, t, ranks = run(det)
+    out["deterministic_ms_per_step"] = float(np.median(t))
+    out["deterministic_total_ms"] = float(np.sum(t))
+    out["deterministic_final_ranks_max"] = [int(max(r[k] for r in ranks)) for k in range(3)]
+    for kind in ("krp", "kron"):
+        out[f"{kind}_speedup_vs_deterministic"] = (out["deterministic_total_ms"] /
+                                                   out[f"{kind}_total_ms"])
+        out[f"{kind}_final_vs_deterministic_max"] = max(
+            xhat_rel_diff(ga, ua, gb, ub) for (ga, ua), (gb, ub) in zip(finals[kind], states))
+    log(f"NDG {nsteps} steps: krp {out['krp_ms_per_step']:.2f} ms/step, kron "
+        f"{out['kron_ms_per_step']:.2f}, deterministic {out['deterministic_ms_per_step']:.2f}; "
+        f"final krp vs deterministic {out['krp_final_vs_deterministic_max']:.1e}")
+    return out
+
+
 def torch_f64():
     import torch
     return torch.float64
@@ -646,6 +713,8 @@ def main():
         legs["stages_1_and_4"] = stages_leg(tsk, dev, args.steps)
     if "lowrank" in want:
         legs["low_rank_construction"] = low_rank_leg(tsk, dev, args.steps)
+    if "ndg" in want:
+        legs["ndg_transport"] = ndg_leg(tsk, dev, args.steps)
     if "tiny" in want:
         ts = synth.config_tiny()
         legs["tiny_kron"] = single_leg(tsk, args, ts, "kron", RC.kron_sizes(ts["ell"]),

@@ -189,6 +189,17 @@ tsk_status tucker_sum_subranks(tsk_handle handle, const tsk_tucker_sum* sum, dou
                                const int32_t* p, int32_t* ell_out, void* ws, size_t ws_bytes,
                                void* stream);
 
+/* Stage 1 for many independent sums at once (the per-node sums of a
+ * time step, Section 5.3): each launch of tucker_sum_subranks runs once for
+ * every sum of the batch.  sums: host [batch]; p and ell_out: host arrays of
+ * sum_j order_j entries, sum j's modes after those of sums 0..j-1.
+ * Synchronises `stream` once. */
+tsk_status tucker_sum_subranks_batched_workspace_size(tsk_handle handle, int32_t batch,
+                                                      const tsk_tucker_sum* sums, size_t* bytes);
+tsk_status tucker_sum_subranks_batched(tsk_handle handle, int32_t batch,
+                                       const tsk_tucker_sum* sums, double eps, const int32_t* p,
+                                       int32_t* ell_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Stage 4 of Algorithms 4/5: ST-HOSVD of the projected core with relative
  * tolerance eps and the rank rule of Algorithm 2, phase 2.  With
  * theta = eps^2 ||H||_F^2 / d, for n = 1..d in order: the eigenvalues
@@ -213,6 +224,31 @@ tsk_status tucker_truncate(tsk_handle handle, int32_t order, const int64_t* dims
                            const int64_t* widths, const double* const* Q, const double* H,
                            double eps, double* const* U_out, double* G_out, int32_t* ranks_out,
                            void* ws, size_t ws_bytes, void* stream);
+
+/* One Stage 4 truncation of a batch (tucker_truncate_batched): the
+ * arguments of tucker_truncate for one core.  The workspace query reads only
+ * order, dims, widths and eps. */
+typedef struct {
+  int32_t order;               /* d >= 2                                             */
+  const int64_t* dims;         /* host [d]                                           */
+  const int64_t* widths;       /* host [d], w_k <= min(n_k, 1024)                    */
+  const double* const* Q;      /* host array of d device ptrs, n_k x w_k              */
+  const double* H;             /* device w_1 x ... x w_d                             */
+  double eps;                  /* relative tolerance in [0, 1]                       */
+  double* const* U_out;        /* host array of d device ptrs, n_k x w_k capacity     */
+  double* G_out;               /* device, prod_k w_k doubles                         */
+  int32_t* ranks_out;          /* host [d]                                           */
+} tsk_truncation;
+
+/* Stage 4 for many independent cores at once: tucker_truncate on every job,
+ * mode by mode, with each kind of launch (TTM, Gram, eigensolver, the final
+ * U_n = Q_n V_n) grouped over the jobs, and one synchronisation of `stream`
+ * per mode that reads every job's rank of that mode.  Jobs may differ in
+ * order and sizes; their outputs must not overlap each other or any input. */
+tsk_status tucker_truncate_batched_workspace_size(tsk_handle handle, int32_t batch,
+                                                  const tsk_truncation* jobs, size_t* bytes);
+tsk_status tucker_truncate_batched(tsk_handle handle, int32_t batch, const tsk_truncation* jobs,
+                                   void* ws, size_t ws_bytes, void* stream);
 
 /* The paper's deterministic baseline for the same sum: Algorithm 1
  * (TuckerAxby) over all terms, i.e. the concatenated factors

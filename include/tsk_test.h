@@ -50,8 +50,18 @@ int tsk_plan_selfcheck_project(const tsk_tucker_sum* sum, const int64_t* widths,
 int tsk_plan_selfcheck_truncate(int32_t order, const int64_t* dims, const int64_t* widths,
                                 const int32_t* ranks, char* msg, size_t msglen);
 
+/* The same for tucker_truncate_batched over `batch` jobs of one order:
+ * dims, widths and ranks hold order entries per job, job after job. */
+int tsk_plan_selfcheck_truncate_batched(int32_t batch, int32_t order, const int64_t* dims,
+                                        const int64_t* widths, const int32_t* ranks, char* msg,
+                                        size_t msglen);
+
 /* Self-check of tucker_sum_subranks. */
 int tsk_plan_selfcheck_subranks(const tsk_tucker_sum* sum, char* msg, size_t msglen);
+
+/* Self-check of tucker_sum_subranks_batched. */
+int tsk_plan_selfcheck_subranks_batched(int32_t batch, const tsk_tucker_sum* sums, char* msg,
+                                        size_t msglen);
 
 /* Self-check of the first launch sequence of tucker_sum_round_deterministic
  * (concatenation, QR, dense core, TTM chain; the truncation that follows is

@@ -24,7 +24,8 @@ __all__ = [
     "Recompressor", "BatchRecompressor", "tucker_sum_recompress_batched",
     "tucker_sum_recompress_backward", "recompress", "tucker_sum_recompress_noalloc",
     "tucker_sum_project", "tucker_truncate", "round_sum", "effective_subranks", "sketch_sum",
-    "round_deterministic",
+    "round_deterministic", "effective_subranks_batched", "tucker_truncate_batched",
+    "sketch_sum_batched",
 ]
 
 
@@ -114,46 +115,68 @@ class Handle:
 
 
 # ---------------------------------------------------------------- marshalling
+def _tensor_info(t, seen):
+    """(tensor, column-major tensor, dtype, device, shape, pointer) of t,
+    memoised in `seen` (keyed by id; the entry keeps t alive, so ids stay
+    unique while `seen` does)."""
+    got = seen.get(id(t)) if seen is not None else None
+    if got is None:
+        f = fortran(t)
+        dv = f.device
+        got = (t, f, f.dtype, (dv.type, dv.index), tuple(f.shape), f.data_ptr(), dv)
+        if seen is not None:
+            seen[id(t)] = got
+    return got
+
+
 class _Marshal:
-    """Keeps the ctypes arrays alive for the duration of one call."""
+    """Keeps the ctypes arrays alive for the duration of one call.  Calls
+    over many sums that share tensors pass one `seen` dict, so that each
+    distinct tensor is laid out and inspected once."""
 
     def __init__(self, cores, factors, coeffs, kind, sizes, seed, omega, sketch_prec,
-                 project_prec, qr_policy):
+                 project_prec, qr_policy, seen=None):
         s = len(cores)
         d = len(factors[0])
-        dt = cores[0].dtype
-        dev = cores[0].device
-        self.cores = [fortran(g) for g in cores]
-        self.factors = [[fortran(u) for u in us] for us in factors]
-        for g, us in zip(self.cores, self.factors):
-            if g.dim() != d or len(us) != d:
+        ci = [_tensor_info(g, seen) for g in cores]
+        fi = [[_tensor_info(u, seen) for u in us] for us in factors]
+        dt, dkey, dev = ci[0][2], ci[0][3], ci[0][6]
+        for g, us in zip(ci, fi):
+            if len(g[4]) != d or len(us) != d:
                 raise ValueError("every core must have one dimension per factor")
+            if g[2] is not dt or g[3] != dkey:
+                raise ValueError("all cores and factors must share dtype and device")
             for k, u in enumerate(us):
-                if u.dtype != dt or g.dtype != dt or u.device != dev or g.device != dev:
+                if u[2] is not dt or u[3] != dkey:
                     raise ValueError("all cores and factors must share dtype and device")
-                if u.dim() != 2 or u.shape[1] != g.shape[k]:
-                    raise ValueError(f"factor {k} shape {tuple(u.shape)} does not match core")
-        self.dims = [int(u.shape[0]) for u in self.factors[0]]
-        for us in self.factors:
-            if [int(u.shape[0]) for u in us] != self.dims:
+                if len(u[4]) != 2 or u[4][1] != g[4][k]:
+                    raise ValueError(f"factor {k} shape {u[4]} does not match core")
+        self.cores = [g[1] for g in ci]
+        self.factors = [[u[1] for u in us] for us in fi]
+        self.dims = [u[4][0] for u in fi[0]]
+        for us in fi:
+            if [u[4][0] for u in us] != self.dims:
                 raise ValueError("all terms must share the mode sizes")
         self.d, self.s, self.dtype, self.device = d, s, dt, dev
         self.c_dims = (c_int64 * d)(*self.dims)
-        self.c_ranks = (c_int32 * (s * d))(*[int(x) for g in self.cores for x in g.shape])
-        self.c_cores = (c_void_p * s)(*[g.data_ptr() for g in self.cores])
-        self.c_factors = (c_void_p * (s * d))(*[u.data_ptr() for us in self.factors for u in us])
+        self.c_ranks = (c_int32 * (s * d))(*[x for g in ci for x in g[4]])
+        self.c_cores = (c_void_p * s)(*[g[5] for g in ci])
+        self.c_factors = (c_void_p * (s * d))(*[u[5] for us in fi for u in us])
         self.c_coeffs = None if coeffs is None else (c_double * s)(*[float(c) for c in coeffs])
         self.sum = _lib.TuckerSum(d, s, self.c_dims, self.c_ranks, self.c_cores, self.c_factors,
                                   self.c_coeffs, _dtype_code(dt))
-        kind = kind.lower()
-        sizes = [int(x) for x in sizes]
-        self.c_sizes = (c_int32 * len(sizes))(*sizes)
         self.omega = None
         self.c_omega = None
         if omega is not None:
             self.omega = [fortran(o.to(dt)) for o in omega]
             self.c_omega = (c_void_p * d)(*[o.data_ptr() for o in self.omega])
-        self.spec = _lib.SketchSpec(KINDS[kind], self.c_sizes, int(seed) & (2 ** 64 - 1),
+        self.set_spec(kind, sizes, seed, sketch_prec, project_prec, qr_policy)
+
+    def set_spec(self, kind, sizes, seed, sketch_prec="fp64", project_prec="fp64",
+                 qr_policy="auto"):
+        sizes = [int(x) for x in sizes]
+        self.c_sizes = (c_int32 * len(sizes))(*sizes)
+        self.spec = _lib.SketchSpec(KINDS[kind.lower()], self.c_sizes, int(seed) & (2 ** 64 - 1),
                                     self.c_omega, PRECISIONS[sketch_prec], PRECISIONS[project_prec],
                                     QR_POLICIES[qr_policy])
 
@@ -330,6 +353,110 @@ def sketch_sum(cores, factors, kind, eps, p, seed, coeffs=None, sketch_prec="fp6
     return g, us, ranks, sizes
 
 
+def _core_view(G, r):
+    n = 1
+    for x in r:
+        n *= x
+    return G[:n].reshape(tuple(reversed(r))).permute(tuple(reversed(range(len(r)))))
+
+
+def effective_subranks_batched(sums, eps, p):
+    """Stage 1 for many sums in one launch sequence (one synchronisation).
+    `sums`: list of dicts with keys cores, factors and optionally coeffs; p:
+    an int or a per-mode list shared by every sum.  Returns a list of ell
+    lists."""
+    seen = {}
+    ms = [_Marshal(x["cores"], x["factors"], x.get("coeffs"), "krp", [1], 0, None, "fp64",
+                   "fp64", "auto", seen) for x in sums]
+    return _subranks_batched(ms, eps, p)
+
+
+def _subranks_batched(ms, eps, p):
+    B = len(ms)
+    h = Handle.get(ms[0].device)
+    c_sums = (_lib.TuckerSum * B)(*[m.sum for m in ms])
+    pv = []
+    for m in ms:
+        pv += [int(x) for x in (p if hasattr(p, "__len__") else [p] * m.d)]
+    total = len(pv)
+    nbytes = c_size_t()
+    check(load().tucker_sum_subranks_batched_workspace_size(h.ptr, B, c_sums, byref(nbytes)),
+          h.ptr)
+    ws = h.workspace(nbytes.value)
+    out = (c_int32 * total)()
+    check(load().tucker_sum_subranks_batched(h.ptr, B, c_sums, float(eps), (c_int32 * total)(*pv),
+                                             out, c_void_p(ws.data_ptr()), ws.numel(),
+                                             c_void_p(_stream_ptr(ms[0].device))), h.ptr)
+    res, at = [], 0
+    for m in ms:
+        res.append(list(out[at:at + m.d]))
+        at += m.d
+    return res
+
+
+def tucker_truncate_batched(jobs, eps):
+    """Stage 4 for many cores at once: `jobs` is a list of (Q list, H) pairs
+    (FP64, as tucker_truncate takes them).  Returns a list of (G, [U..],
+    ranks)."""
+    dev = jobs[0][1].device
+    h = Handle.get(dev)
+    keep, structs, outs = [], [], []
+    for Q, H in jobs:
+        d = H.dim()
+        Qf = [fortran(q.to(torch.float64)) for q in Q]
+        Hf = fortran(H.to(torch.float64))
+        dims = [int(q.shape[0]) for q in Qf]
+        widths = [int(x) for x in Hf.shape]
+        if [int(q.shape[1]) for q in Qf] != widths:
+            raise ValueError("Q_k must have as many columns as H has entries along mode k")
+        U = [empty_fortran((n, w), torch.float64, dev) for n, w in zip(dims, widths)]
+        total = 1
+        for w in widths:
+            total *= w
+        G = torch.empty(total, dtype=torch.float64, device=dev)
+        arrs = ((c_int64 * d)(*dims), (c_int64 * d)(*widths),
+                (c_void_p * d)(*[q.data_ptr() for q in Qf]),
+                (c_void_p * d)(*[u.data_ptr() for u in U]), (c_int32 * d)())
+        keep.append((Qf, Hf, arrs))
+        structs.append(_lib.Truncation(d, arrs[0], arrs[1], arrs[2], Hf.data_ptr(), float(eps),
+                                       arrs[3], G.data_ptr(), arrs[4]))
+        outs.append((G, U, arrs[4]))
+    B = len(structs)
+    c_jobs = (_lib.Truncation * B)(*structs)
+    nbytes = c_size_t()
+    check(load().tucker_truncate_batched_workspace_size(h.ptr, B, c_jobs, byref(nbytes)), h.ptr)
+    ws = h.workspace(nbytes.value)
+    check(load().tucker_truncate_batched(h.ptr, B, c_jobs, c_void_p(ws.data_ptr()), ws.numel(),
+                                         c_void_p(_stream_ptr(dev))), h.ptr)
+    res = []
+    for G, U, cr in outs:
+        r = list(cr)
+        res.append((_core_view(G, r), [u[:, :rk] for u, rk in zip(U, r)], r))
+    return res
+
+
+def sketch_sum_batched(sums, kind, eps, p, seed, sketch_prec="fp64", project_prec="fp64"):
+    """Algorithm 5 (kind "krp") or 4 ("kron") for many independent sums,
+    each stage one launch sequence over all of them: Stage 1 sizes from eps
+    and p, the sketch widths, Stages 2-3 (tucker_sum_recompress_batched,
+    FP64 outputs) and the Stage 4 truncation with eps.  `sums`: list of dicts
+    with cores, factors and optionally coeffs; `seed`: an int shared by every
+    sum or a list.  Returns a list of (G, [U..], ranks, sizes)."""
+    seen = {}
+    ms = [_Marshal(x["cores"], x["factors"], x.get("coeffs"), "krp", [1], 0, None, sketch_prec,
+                   project_prec, "auto", seen) for x in sums]
+    ells = _subranks_batched(ms, eps, p)
+    seeds = seed if hasattr(seed, "__len__") else [seed] * len(sums)
+    sizes = []
+    for m, ell, sd in zip(ms, ells, seeds):
+        sz = [krp_width(ell)] if kind == "krp" else kron_sizes(ell)
+        sizes.append(sz)
+        m.set_spec(kind, sz, sd, sketch_prec, project_prec)
+    q, h = BatchRecompressor(None, sketch_prec, project_prec, torch.float64, _marshals=ms)()
+    tr = tucker_truncate_batched(list(zip(q, h)), eps)
+    return [(g, us, r, sz) for (g, us, r), sz in zip(tr, sizes)]
+
+
 def round_deterministic(cores, factors, tau, coeffs=None):
     """The paper's deterministic baseline (Algorithm 1 over all terms, then
     Algorithm 2 with tolerance tau) on the GPU.  Returns (G, [U..], ranks)."""
@@ -439,9 +566,11 @@ class BatchRecompressor:
     kind and precisions."""
 
     def __init__(self, sums, sketch_prec="fp64", project_prec="fp64", out_dtype=None,
-                 qr_policy="auto"):
-        self.ms = [_Marshal(x["cores"], x["factors"], x.get("coeffs"), x["kind"], x["sizes"],
-                            x["seed"], None, sketch_prec, project_prec, qr_policy) for x in sums]
+                 qr_policy="auto", _marshals=None):
+        seen = {}
+        self.ms = _marshals if _marshals is not None else [
+            _Marshal(x["cores"], x["factors"], x.get("coeffs"), x["kind"], x["sizes"], x["seed"],
+                     None, sketch_prec, project_prec, qr_policy, seen) for x in sums]
         m0 = self.ms[0]
         self.h = Handle.get(m0.device)
         self.out_dtype = m0.dtype if out_dtype is None else out_dtype

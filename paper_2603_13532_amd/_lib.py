@@ -50,6 +50,20 @@ class SketchSpec(ctypes.Structure):
     ]
 
 
+class Truncation(ctypes.Structure):
+    _fields_ = [
+        ("order", c_int32),
+        ("dims", POINTER(c_int64)),
+        ("widths", POINTER(c_int64)),
+        ("Q", POINTER(c_void_p)),
+        ("H", c_void_p),
+        ("eps", c_double),
+        ("U_out", POINTER(c_void_p)),
+        ("G_out", c_void_p),
+        ("ranks_out", POINTER(c_int32)),
+    ]
+
+
 # name -> (restype, argtypes); every function declared in include/tsk.h
 PROTOTYPES = {
     "tsk_create": (c_int, [POINTER(c_void_p), c_int]),
@@ -78,6 +92,15 @@ PROTOTYPES = {
                                                    POINTER(c_size_t)]),
     "tucker_sum_subranks": (c_int, [c_void_p, POINTER(TuckerSum), c_double, POINTER(c_int32),
                                     POINTER(c_int32), c_void_p, c_size_t, c_void_p]),
+    "tucker_sum_subranks_batched_workspace_size": (c_int, [c_void_p, c_int32, POINTER(TuckerSum),
+                                                           POINTER(c_size_t)]),
+    "tucker_sum_subranks_batched": (c_int, [c_void_p, c_int32, POINTER(TuckerSum), c_double,
+                                            POINTER(c_int32), POINTER(c_int32), c_void_p,
+                                            c_size_t, c_void_p]),
+    "tucker_truncate_batched_workspace_size": (c_int, [c_void_p, c_int32, POINTER(Truncation),
+                                                       POINTER(c_size_t)]),
+    "tucker_truncate_batched": (c_int, [c_void_p, c_int32, POINTER(Truncation), c_void_p,
+                                        c_size_t, c_void_p]),
     "tucker_truncate_workspace_size": (c_int, [c_void_p, c_int32, POINTER(c_int64),
                                                POINTER(c_int64), c_double, POINTER(c_size_t)]),
     "tucker_truncate": (c_int, [c_void_p, c_int32, POINTER(c_int64), POINTER(c_int64),

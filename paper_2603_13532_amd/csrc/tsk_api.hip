@@ -1737,145 +1737,198 @@ struct TruncIO {
   double* G = nullptr;           // prod w_k capacity
 };
 
-// Fixed workspace of a truncation: ranks, theta, the Gram, eigenvectors and
-// eigenvalues of every mode, two core buffers; then one phase region
-// (Gram split-K partials) and the descriptor blob.
-struct TruncLayout {
-  int32_t* ranks = nullptr;
-  double* theta = nullptr;
+// Fixed workspace of a batch of truncations: the ranks and theta of every
+// job in one block each (so that one copy reads every rank of a phase);
+// then per job the Gram, the eigenvectors and eigenvalues of every mode, two
+// core buffers and, for widths above the LDS limit, the eigensolver's
+// workspace.  One phase region (Gram split-K partials) and the descriptor
+// blob follow.
+struct TruncJobMem {
   double* C = nullptr;
   std::vector<double*> V, lam;
   double* buf[2] = {nullptr, nullptr};
-  double* work = nullptr;  // eigensolver workspace for widths above the LDS limit
+  double* work = nullptr;
+};
+
+struct TruncLayout {
+  int32_t* ranks = nullptr;  // [jobs * kMaxOrder]
+  double* theta = nullptr;   // [jobs]
+  std::vector<TruncJobMem> job;
   size_t phase_base = 0;
 };
 
-static void trunc_layout(const TruncIO& io, Arena& ar, TruncLayout& L) {
-  L.ranks = (int32_t*)ar.take(sizeof(int32_t) * 64);
-  L.theta = (double*)ar.take(sizeof(double) * 4);
-  int64_t wmax = 1, hs = 1;
-  for (int n = 0; n < io.d; ++n) {
-    wmax = std::max(wmax, io.w[n]);
-    hs *= io.w[n];
-  }
-  L.C = (double*)ar.take(wmax * wmax * 8);
-  L.V.resize(io.d);
-  L.lam.resize(io.d);
-  for (int n = 0; n < io.d; ++n) {
-    L.V[n] = (double*)ar.take(io.w[n] * io.w[n] * 8);
-    L.lam[n] = (double*)ar.take(io.w[n] * 8);
-  }
-  L.buf[0] = (double*)ar.take(hs * 8);
-  L.buf[1] = (double*)ar.take(hs * 8);
-  if (wmax > kEigMaxW) {
-    const int64_t Wp = wmax + (wmax & 1);
-    L.work = (double*)ar.take(2 * Wp * Wp * 8);
+static void trunc_layout(const std::vector<TruncIO>& ios, Arena& ar, TruncLayout& L) {
+  const size_t J = ios.size();
+  L.ranks = (int32_t*)ar.take(sizeof(int32_t) * kMaxOrder * J);
+  L.theta = (double*)ar.take(sizeof(double) * J);
+  L.job.assign(J, TruncJobMem{});
+  for (size_t j = 0; j < J; ++j) {
+    const TruncIO& io = ios[j];
+    TruncJobMem& M = L.job[j];
+    int64_t wmax = 1, hs = 1;
+    for (int n = 0; n < io.d; ++n) {
+      wmax = std::max(wmax, io.w[n]);
+      hs *= io.w[n];
+    }
+    M.C = (double*)ar.take(wmax * wmax * 8);
+    M.V.resize(io.d);
+    M.lam.resize(io.d);
+    for (int n = 0; n < io.d; ++n) {
+      M.V[n] = (double*)ar.take(io.w[n] * io.w[n] * 8);
+      M.lam[n] = (double*)ar.take(io.w[n] * 8);
+    }
+    M.buf[0] = (double*)ar.take(hs * 8);
+    M.buf[1] = (double*)ar.take(hs * 8);
+    if (wmax > kEigMaxW) {
+      const int64_t Wp = wmax + (wmax & 1);
+      M.work = (double*)ar.take(2 * Wp * Wp * 8);
+    }
   }
   L.phase_base = align_up(ar.top, 256);
 }
 
-// Launches of one phase: the TTM that truncates mode n - 1 (if n > 0, with
-// rank rprev), then the Gram and eigendecomposition of mode n (if n < d);
-// at n == d also U_k = Q_k V_k for every mode.  `shape` is the core's shape
-// before the TTM; `src` the core, `dst` where the TTM writes.
-static void trunc_phase(const TruncIO& io, const TruncLayout& L, int n,
-                        const std::vector<int64_t>& shape_in, const double* src, double* dst,
-                        const std::vector<int32_t>& ranks, Arena& ar, Program& prog) {
-  const int d = io.d;
-  std::vector<int64_t> shape = shape_in;
-  const double* cur = src;
-  if (n > 0) {
-    const int k = n - 1;
-    const int64_t Wk = shape[k], rk = ranks[k];
-    int64_t Lo = 1, Ro = 1;
-    for (int j = 0; j < k; ++j) Lo *= shape[j];
-    for (int j = k + 1; j < d; ++j) Ro *= shape[j];
-    GemmBatch gb(P_FP64, R_OTHER, &ar);
-    if (k == 0) {
-      // out (r_0 x R) = V_0^T (r_0 x W_0) . G_(0) (W_0 x R)
-      gb.add(dst, true, rk, 0, (int)rk, (int)Ro, 1, 0, {seg(L.V[k], Wk, 1, 0, cur, Wk, 1, 0, Wk)});
-    } else {
-      // per trailing index b: out_b (L x r_k) = G_b (L x W_k) . V_k (W_k x r_k)
-      gb.add(dst, true, Lo, Lo * rk, (int)Lo, (int)rk, (int)Ro, 0,
-             {seg(cur, 1, Lo, Lo * Wk, L.V[k], Wk, 1, 0, Wk)});
-    }
-    emit_gemm(prog, gb);
-    shape[k] = rk;
-    cur = dst;
+// Where a job stands between phases: the core's current shape, the ranks
+// chosen so far, the core the next phase reads and where its TTM writes.
+struct TruncState {
+  std::vector<int64_t> shape;
+  std::vector<int32_t> ranks;
+  const double* cur = nullptr;
+  double* dst = nullptr;
+};
+
+// Launches of phase n of every job: the TTMs that truncate mode n - 1 (if
+// n > 0, with rank ranks[n - 1]), then the Grams and eigendecompositions of
+// mode n (if n < d); at n == d also U_k = Q_k V_k for every mode of the job.
+// Jobs of lower order than n take no part.  Each kind of launch is one
+// grouped launch over the jobs.
+static void trunc_phase(const std::vector<TruncIO>& ios, const TruncLayout& L, int n,
+                        const std::vector<TruncState>& S, Arena& ar, Program& prog) {
+  GemmBatch ttm(P_FP64, R_OTHER, &ar), gram(P_FP64, R_OTHER, &ar), fin(P_FP64, R_OTHER, &ar);
+  std::vector<EigJob> small, large;
+  int wsmall = 0, wlarge = 0;
+  int64_t gram_tiles = 0;
+  for (size_t j = 0; j < ios.size(); ++j) {
+    const TruncIO& io = ios[j];
+    if (n < io.d) gram_tiles += ceil_div(S[j].shape[n], 64) * ceil_div(S[j].shape[n], 64);
   }
-  if (n < d) {
-    const int64_t Wn = shape[n];
-    int64_t Lo = 1, Ro = 1;
-    for (int j = 0; j < n; ++j) Lo *= shape[j];
-    for (int j = n + 1; j < d; ++j) Ro *= shape[j];
-    GemmBatch gb(P_FP64, R_OTHER, &ar);
-    std::vector<GemmSeg> sg;
-    if (n == 0) {
-      sg.push_back(seg(cur, 1, Wn, 0, cur, 1, Wn, 0, Ro));
+  for (size_t j = 0; j < ios.size(); ++j) {
+    const TruncIO& io = ios[j];
+    const TruncJobMem& M = L.job[j];
+    const int d = io.d;
+    if (n > d) continue;
+    std::vector<int64_t> shape = S[j].shape;
+    const double* cur = S[j].cur;
+    if (n > 0) {
+      const int k = n - 1;
+      const int64_t Wk = shape[k], rk = S[j].ranks[k];
+      int64_t Lo = 1, Ro = 1;
+      for (int i = 0; i < k; ++i) Lo *= shape[i];
+      for (int i = k + 1; i < d; ++i) Ro *= shape[i];
+      if (k == 0) {
+        // out (r_0 x R) = V_0^T (r_0 x W_0) . G_(0) (W_0 x R)
+        ttm.add(S[j].dst, true, rk, 0, (int)rk, (int)Ro, 1, 0,
+                {seg(M.V[k], Wk, 1, 0, cur, Wk, 1, 0, Wk)});
+      } else {
+        // per trailing index b: out_b (L x r_k) = G_b (L x W_k) . V_k (W_k x r_k)
+        ttm.add(S[j].dst, true, Lo, Lo * rk, (int)Lo, (int)rk, (int)Ro, 0,
+                {seg(cur, 1, Lo, Lo * Wk, M.V[k], Wk, 1, 0, Wk)});
+      }
+      shape[k] = rk;
+      cur = S[j].dst;
+    }
+    if (n < d) {
+      const int64_t Wn = shape[n];
+      int64_t Lo = 1, Ro = 1;
+      for (int i = 0; i < n; ++i) Lo *= shape[i];
+      for (int i = n + 1; i < d; ++i) Ro *= shape[i];
+      std::vector<GemmSeg> sg;
+      if (n == 0) {
+        sg.push_back(seg(cur, 1, Wn, 0, cur, 1, Wn, 0, Ro));
+      } else {
+        for (int64_t c = 0; c < Ro; ++c) {
+          const double* base = cur + c * Lo * Wn;
+          sg.push_back(seg(base, Lo, 1, 0, base, Lo, 1, 0, Lo));
+        }
+      }
+      const int splits = choose_splits(gram_tiles, ceil_div(Lo * Ro, 16));
+      gram.add(M.C, true, Wn, 0, (int)Wn, (int)Wn, 1, 0, sg, splits);
+      EigJob J{};
+      J.C = M.C;
+      J.V = M.V[n];
+      J.lam = M.lam[n];
+      J.theta = L.theta + j;
+      J.rank = L.ranks + j * kMaxOrder + n;
+      J.ldc = Wn;
+      J.ldv = Wn;
+      J.tol = 1e-15;
+      J.theta_scale = io.eps * io.eps / d;
+      J.W = (int32_t)Wn;
+      J.set_theta = n == 0 ? 1 : 0;
+      J.clip = 1;
+      J.work = M.work;
+      if (Wn <= kEigMaxW) {
+        small.push_back(J);
+        wsmall = std::max<int>(wsmall, (int)Wn);
+      } else {
+        large.push_back(J);
+        wlarge = std::max<int>(wlarge, (int)Wn);
+      }
     } else {
-      for (int64_t c = 0; c < Ro; ++c) {
-        const double* base = cur + c * Lo * Wn;
-        sg.push_back(seg(base, Lo, 1, 0, base, Lo, 1, 0, Lo));
+      for (int k = 0; k < d; ++k) {
+        const int64_t nk = io.dims[k], Wk = io.w[k];
+        fin.add(io.U[k], true, nk, 0, (int)nk, (int)S[j].ranks[k], 1, 0,
+                {seg(io.Q[k], 1, nk, 0, M.V[k], Wk, 1, 0, Wk)});
       }
     }
-    const int64_t tiles = ceil_div(Wn, 64) * ceil_div(Wn, 64);
-    const int splits = choose_splits(tiles, ceil_div(Lo * Ro, 16));
-    gb.add(L.C, true, Wn, 0, (int)Wn, (int)Wn, 1, 0, sg, splits);
-    emit_gemm(prog, gb);
-  } else {
-    GemmBatch gb(P_FP64, R_OTHER, &ar);
-    for (int k = 0; k < d; ++k) {
-      const int64_t nk = io.dims[k], Wk = io.w[k];
-      gb.add(io.U[k], true, nk, 0, (int)nk, (int)ranks[k], 1, 0,
-             {seg(io.Q[k], 1, nk, 0, L.V[k], Wk, 1, 0, Wk)});
-    }
-    emit_gemm(prog, gb);
   }
-  if (n < d) {
-    EigJob J{};
-    J.C = L.C;
-    J.V = L.V[n];
-    J.lam = L.lam[n];
-    J.theta = L.theta;
-    J.rank = L.ranks + n;
-    J.ldc = shape[n];
-    J.ldv = shape[n];
-    J.tol = 1e-15;
-    J.theta_scale = io.eps * io.eps / d;
-    J.W = (int32_t)shape[n];
-    J.set_theta = n == 0 ? 1 : 0;
-    J.clip = 1;
-    J.work = L.work;
+  emit_gemm(prog, ttm);
+  emit_gemm(prog, gram);
+  emit_gemm(prog, fin);
+  // The LDS Jacobi and its global-memory form are separate launches: the
+  // global form reads every job's eigensolver workspace.
+  for (int which = 0; which < 2; ++which) {
+    const std::vector<EigJob>& js = which == 0 ? small : large;
+    if (js.empty()) continue;
     Step st{};
     st.kind = S_EIG;
-    st.meta = prog.put(std::vector<EigJob>{J});
-    st.count = 1;
-    st.wmax = (int)shape[n];
-    st.flops = 0;
+    st.meta = prog.put(js);
+    st.count = (int)js.size();
+    st.wmax = which == 0 ? wsmall : wlarge;
     prog.steps.push_back(st);
   }
 }
 
-// Workspace of a truncation: the fixed part, then the largest phase (every
-// rank at its maximum, which bounds the split-K partials and descriptors of
-// any smaller ranks).
-static size_t trunc_workspace(const TruncIO& io, bool* too_far) {
+// Workspace of a batch of truncations: the fixed part, then the largest
+// phase with every rank at its maximum.  A phase's Gram tiles do not depend
+// on the ranks, and smaller ranks only shorten K, which never raises the
+// split count, so this bounds the partials and descriptors of any ranks.
+static size_t trunc_workspace(const std::vector<TruncIO>& ios, bool* too_far) {
   Arena a0;
   TruncLayout L;
-  trunc_layout(io, a0, L);
+  trunc_layout(ios, a0, L);
   size_t phase = 0, blob = 0;
-  std::vector<int32_t> ranks(io.w.begin(), io.w.end());
-  for (int n = 0; n <= io.d; ++n) {
+  std::vector<TruncState> S(ios.size());
+  int dmax = 0;
+  for (size_t j = 0; j < ios.size(); ++j) {
+    S[j].shape = ios[j].w;
+    S[j].ranks.assign(ios[j].w.begin(), ios[j].w.end());
+    dmax = std::max(dmax, ios[j].d);
+  }
+  for (int n = 0; n <= dmax; ++n) {
     Arena ar;
     ar.base = nullptr;
     ar.top = L.phase_base;
     Program prog;
-    trunc_phase(io, L, n, io.w, nullptr, nullptr, ranks, ar, prog);
+    trunc_phase(ios, L, n, S, ar, prog);
     if (!ar.too_far.empty()) *too_far = true;
     phase = std::max(phase, ar.top);
     blob = std::max(blob, prog.blob.size());
   }
   return align_up(phase, 256) + align_up(blob, 256) + 256;
+}
+
+static size_t trunc_workspace(const TruncIO& io, bool* too_far) {
+  return trunc_workspace(std::vector<TruncIO>{io}, too_far);
 }
 
 static tsk_status validate_trunc(tsk_handle h, int32_t order, const int64_t* dims,
@@ -1901,48 +1954,90 @@ static tsk_status validate_trunc(tsk_handle h, int32_t order, const int64_t* dim
   return TSK_OK;
 }
 
-// The launches of a truncation, mode by mode, in `ws` (of `need` bytes, as
-// trunc_workspace computed); ranks_out: host [d].
-static tsk_status truncate_run(tsk_handle h, const TruncIO& io, char* ws, size_t need,
-                               hipStream_t s, int32_t* ranks_out) {
-  const int order = io.d;
-  Arena fixed;
-  fixed.base = ws;
-  TruncLayout L;
-  trunc_layout(io, fixed, L);
-  std::vector<int64_t> shape = io.w;
-  std::vector<int32_t> ranks(order, 0);
-  const double* cur = io.H;
-  int which = 0;
-  for (int n = 0; n <= order; ++n) {
-    // the last TTM writes the caller's core; the others ping-pong
-    double* dst = (n == order) ? io.G : L.buf[which];
+// Drives the phases of a batch of truncations in `ws` (of `need` bytes, as
+// trunc_workspace computed).  `run(prog)` launches (or checks) a phase's
+// program; `rank_of(j, n)` returns the rank job j chose for mode n after
+// the phase that decided it (read from the device, or given by a
+// self-check), 0 on failure.  The last TTM of a job writes the caller's
+// core; the others ping-pong between the job's two buffers.
+template <typename Run, typename RankOf>
+static tsk_status trunc_drive(tsk_handle h, const std::vector<TruncIO>& ios, const TruncLayout& L,
+                              char* ws, size_t need, Run run, RankOf rank_of,
+                              std::vector<std::vector<int32_t>>& ranks) {
+  const size_t J = ios.size();
+  std::vector<TruncState> S(J);
+  std::vector<int> which(J, 0);
+  int dmax = 0;
+  for (size_t j = 0; j < J; ++j) {
+    S[j].shape = ios[j].w;
+    S[j].ranks.assign(ios[j].d, 0);
+    S[j].cur = ios[j].H;
+    dmax = std::max(dmax, ios[j].d);
+  }
+  for (int n = 0; n <= dmax; ++n) {
+    for (size_t j = 0; j < J; ++j)
+      S[j].dst = (n == ios[j].d) ? ios[j].G : L.job[j].buf[which[j]];
     Arena ar;
     ar.base = ws;
     ar.top = L.phase_base;
     Program prog;
-    trunc_phase(io, L, n, shape, cur, dst, ranks, ar, prog);
+    trunc_phase(ios, L, n, S, ar, prog);
     prog.meta_region = align_up(ar.top, 256);
     if (prog.meta_region + align_up(prog.blob.size(), 256) + 256 > need)
       return fail(h, TSK_ERR_DEVICE, "truncation phase exceeds its planned workspace");
-    tsk_status st = run_program(h, prog, ws, s);
-    if (st != TSK_OK) return st;
-    if (n > 0) {
-      shape[n - 1] = ranks[n - 1];
-      cur = dst;
-      which ^= 1;
-    }
-    if (n < order) {
-      int32_t r = 0;
-      if (hipStreamSynchronize(s) != hipSuccess ||
-          hipMemcpy(&r, L.ranks + n, sizeof r, hipMemcpyDeviceToHost) != hipSuccess)
-        return fail(h, TSK_ERR_DEVICE, "reading the rank of mode %d failed", n);
-      if (r < 1 || r > shape[n]) return fail(h, TSK_ERR_DEVICE, "rank %d of mode %d out of range", r, n);
-      ranks[n] = r;
+    if (tsk_status st = run(prog); st != TSK_OK) return st;
+    for (size_t j = 0; j < J; ++j) {
+      if (n > 0 && n <= ios[j].d) {
+        S[j].shape[n - 1] = S[j].ranks[n - 1];
+        S[j].cur = S[j].dst;
+        which[j] ^= 1;
+      }
+      if (n < ios[j].d) {
+        const int32_t r = rank_of(j, n);
+        if (r < 1 || r > S[j].shape[n])
+          return fail(h, TSK_ERR_DEVICE, "rank %d of mode %d of job %zu out of range", r, n, j);
+        S[j].ranks[n] = r;
+      }
     }
   }
-  for (int k = 0; k < order; ++k) ranks_out[k] = ranks[k];
+  ranks.resize(J);
+  for (size_t j = 0; j < J; ++j) ranks[j] = S[j].ranks;
   return TSK_OK;
+}
+
+// The launches of a batch of truncations; ranks_out[j]: host [d_j].  One
+// stream synchronisation per mode reads every job's rank of that mode.
+static tsk_status truncate_run(tsk_handle h, const std::vector<TruncIO>& ios, char* ws,
+                               size_t need, hipStream_t s, int32_t* const* ranks_out) {
+  Arena fixed;
+  fixed.base = ws;
+  TruncLayout L;
+  trunc_layout(ios, fixed, L);
+  std::vector<int32_t> host(kMaxOrder * ios.size(), 0);
+  int last_read = -1;
+  auto run = [&](Program& prog) { return run_program(h, prog, ws, s); };
+  auto rank_of = [&](size_t j, int n) -> int32_t {
+    if (last_read != n) {
+      if (hipStreamSynchronize(s) != hipSuccess ||
+          hipMemcpy(host.data(), L.ranks, sizeof(int32_t) * host.size(), hipMemcpyDeviceToHost) !=
+              hipSuccess)
+        return 0;
+      last_read = n;
+    }
+    return host[j * kMaxOrder + n];
+  };
+  std::vector<std::vector<int32_t>> ranks;
+  if (tsk_status st = trunc_drive(h, ios, L, ws, need, run, rank_of, ranks); st != TSK_OK)
+    return st;
+  for (size_t j = 0; j < ios.size(); ++j)
+    for (int k = 0; k < ios[j].d; ++k) ranks_out[j][k] = ranks[j][k];
+  return TSK_OK;
+}
+
+static tsk_status truncate_run(tsk_handle h, const TruncIO& io, char* ws, size_t need,
+                               hipStream_t s, int32_t* ranks_out) {
+  int32_t* const outs[1] = {ranks_out};
+  return truncate_run(h, std::vector<TruncIO>{io}, ws, need, s, outs);
 }
 
 // ------------------------------------------------------------------ deterministic baseline
@@ -2095,113 +2190,146 @@ static tsk_status plan_det_sized(tsk_handle h, const Problem& P, char* ws, Progr
 // 1 x 1 GEMM per term); V_n assembled by copies scaled on the device;
 // V_n^T V_n (one GEMM per mode); the eigenvalues (Jacobi in LDS for
 // sum_i r_n^(i) <= 96, tridiagonal reduction and bisection above).
+// A batch of sums runs each of these launches once for all of its sums.
 struct SubrankOut {
-  int32_t* ranks = nullptr;  // device [d]
+  int32_t* ranks = nullptr;  // device [sums * kMaxOrder]
 };
 
-static void plan_subranks(const Problem& P, double eps, Arena& ar, Program& prog, SubrankOut& out) {
-  const int d = P.d, s = P.s;
-  out.ranks = (int32_t*)ar.take(sizeof(int32_t) * 64);
-  double* theta = (double*)ar.take(sizeof(double) * kMaxOrder);
+static void plan_subranks(const std::vector<Problem>& Ps, double eps, Arena& ar, Program& prog,
+                          SubrankOut& out) {
+  const size_t J = Ps.size();
+  out.ranks = (int32_t*)ar.take(sizeof(int32_t) * kMaxOrder * J);
+  double* theta = (double*)ar.take(sizeof(double) * kMaxOrder * J);
   // inputs in FP64
   std::vector<CopyJob> conv;
-  std::vector<const double*> G(s), U((size_t)s * d);
-  for (int i = 0; i < s; ++i) {
-    int64_t cs = 1;
-    for (int k = 0; k < d; ++k) cs *= P.r(i, k);
-    if (P.in_f64) {
-      G[i] = (const double*)P.cores[i];
-    } else {
-      double* p = (double*)ar.take(cs * 8);
-      conv.push_back(CopyJob{p, P.cores[i], cs, 1, cs, cs, 1, 0});
-      G[i] = p;
-    }
-    for (int k = 0; k < d; ++k) {
-      const size_t idx = (size_t)i * d + k;
+  std::vector<std::vector<const double*>> G(J), U(J);
+  for (size_t j = 0; j < J; ++j) {
+    const Problem& P = Ps[j];
+    const int d = P.d, s = P.s;
+    G[j].resize(s);
+    U[j].resize((size_t)s * d);
+    for (int i = 0; i < s; ++i) {
+      int64_t cs = 1;
+      for (int k = 0; k < d; ++k) cs *= P.r(i, k);
       if (P.in_f64) {
-        U[idx] = (const double*)P.factors[idx];
+        G[j][i] = (const double*)P.cores[i];
       } else {
-        double* p = (double*)ar.take(P.dims[k] * P.r(i, k) * 8);
-        conv.push_back(CopyJob{p, P.factors[idx], P.dims[k], P.r(i, k), P.dims[k], P.dims[k], 1, 0});
-        U[idx] = p;
+        double* p = (double*)ar.take(cs * 8);
+        conv.push_back(CopyJob{p, P.cores[i], cs, 1, cs, cs, 1, 0});
+        G[j][i] = p;
+      }
+      for (int k = 0; k < d; ++k) {
+        const size_t idx = (size_t)i * d + k;
+        if (P.in_f64) {
+          U[j][idx] = (const double*)P.factors[idx];
+        } else {
+          double* p = (double*)ar.take(P.dims[k] * P.r(i, k) * 8);
+          conv.push_back(
+              CopyJob{p, P.factors[idx], P.dims[k], P.r(i, k), P.dims[k], P.dims[k], 1, 0});
+          U[j][idx] = p;
+        }
       }
     }
   }
   emit_copies(prog, conv);
-  // squared Frobenius norms of the cores
-  double* norm2 = (double*)ar.take(sizeof(double) * s);
+  // squared Frobenius norms of the cores (one 1 x 1 product per term)
+  std::vector<double*> norm2(J);
   {
     GemmBatch gb(P_FP64, R_OTHER, &ar);
-    int64_t kt = 0;
-    for (int i = 0; i < s; ++i) {
-      int64_t cs = 1;
-      for (int k = 0; k < d; ++k) cs *= P.r(i, k);
-      kt = std::max<int64_t>(kt, ceil_div(cs, 16));
+    int64_t kt = 0, terms = 0;
+    for (size_t j = 0; j < J; ++j) {
+      const Problem& P = Ps[j];
+      terms += P.s;
+      for (int i = 0; i < P.s; ++i) {
+        int64_t cs = 1;
+        for (int k = 0; k < P.d; ++k) cs *= P.r(i, k);
+        kt = std::max<int64_t>(kt, ceil_div(cs, 16));
+      }
     }
-    const int splits = choose_splits(s, kt);
-    for (int i = 0; i < s; ++i) {
-      int64_t cs = 1;
-      for (int k = 0; k < d; ++k) cs *= P.r(i, k);
-      gb.add(norm2 + i, true, 1, 0, 1, 1, 1, 0, {seg(G[i], 1, 1, 0, G[i], 1, 1, 0, cs)},
-             (int)std::min<int64_t>(splits, std::max<int64_t>(1, ceil_div(cs, 16) / 2)));
+    const int splits = choose_splits(terms, kt);
+    for (size_t j = 0; j < J; ++j) {
+      const Problem& P = Ps[j];
+      norm2[j] = (double*)ar.take(sizeof(double) * P.s);
+      for (int i = 0; i < P.s; ++i) {
+        int64_t cs = 1;
+        for (int k = 0; k < P.d; ++k) cs *= P.r(i, k);
+        gb.add(norm2[j] + i, true, 1, 0, 1, 1, 1, 0,
+               {seg(G[j][i], 1, 1, 0, G[j][i], 1, 1, 0, cs)},
+               (int)std::min<int64_t>(splits, std::max<int64_t>(1, ceil_div(cs, 16) / 2)));
+      }
     }
     emit_gemm(prog, gb);
   }
-  // V_n, then V_n^T V_n, per mode
+  // V_n, then V_n^T V_n, per sum and mode
   std::vector<CopyJob> scaled;
-  std::vector<double*> V(d), B(d), lam(d), scratch(d);
-  std::vector<int64_t> Wn(d);
-  for (int n = 0; n < d; ++n) {
-    int64_t W = 0;
-    for (int i = 0; i < s; ++i) W += P.r(i, n);
-    Wn[n] = W;
-    V[n] = (double*)ar.take(P.dims[n] * W * 8);
-    B[n] = (double*)ar.take(W * W * 8);
-    lam[n] = (double*)ar.take(W * 8);
-    scratch[n] = (double*)ar.take(W * W * 8);
-    int64_t col = 0;
-    for (int i = 0; i < s; ++i) {
-      CopyJob J{V[n] + P.dims[n] * col, U[(size_t)i * d + n], P.dims[n], P.r(i, n), P.dims[n],
-                P.dims[n], 1, 1};
-      J.norm2 = norm2 + i;
-      J.mul = std::fabs(P.coeffs[i]);
-      scaled.push_back(J);
-      col += P.r(i, n);
+  struct ModeMem {
+    double *V, *B, *lam, *scratch;
+    int64_t W, n;
+  };
+  std::vector<std::vector<ModeMem>> mm(J);
+  int64_t gram_tiles = 0;
+  for (size_t j = 0; j < J; ++j) {
+    const Problem& P = Ps[j];
+    mm[j].resize(P.d);
+    for (int n = 0; n < P.d; ++n) {
+      int64_t W = 0;
+      for (int i = 0; i < P.s; ++i) W += P.r(i, n);
+      ModeMem& M = mm[j][n];
+      M.W = W;
+      M.n = P.dims[n];
+      M.V = (double*)ar.take(P.dims[n] * W * 8);
+      M.B = (double*)ar.take(W * W * 8);
+      M.lam = (double*)ar.take(W * 8);
+      M.scratch = (double*)ar.take(W * W * 8);
+      gram_tiles += ceil_div(W, 64) * ceil_div(W, 64);
+      int64_t col = 0;
+      for (int i = 0; i < P.s; ++i) {
+        CopyJob C{M.V + P.dims[n] * col, U[j][(size_t)i * P.d + n], P.dims[n], P.r(i, n), P.dims[n],
+                  P.dims[n], 1, 1};
+        C.norm2 = norm2[j] + i;
+        C.mul = std::fabs(P.coeffs[i]);
+        scaled.push_back(C);
+        col += P.r(i, n);
+      }
     }
   }
   emit_copies(prog, scaled);
   {
     GemmBatch gb(P_FP64, R_OTHER, &ar);
-    for (int n = 0; n < d; ++n) {
-      const int64_t W = Wn[n], nn = P.dims[n];
-      const int splits = choose_splits(ceil_div(W, 64) * ceil_div(W, 64) * d, ceil_div(nn, 16));
-      gb.add(B[n], true, W, 0, (int)W, (int)W, 1, 0, {seg(V[n], nn, 1, 0, V[n], nn, 1, 0, nn)},
-             splits);
-    }
+    for (size_t j = 0; j < J; ++j)
+      for (const ModeMem& M : mm[j]) {
+        const int splits = choose_splits(gram_tiles, ceil_div(M.n, 16));
+        gb.add(M.B, true, M.W, 0, (int)M.W, (int)M.W, 1, 0,
+               {seg(M.V, M.n, 1, 0, M.V, M.n, 1, 0, M.n)}, splits);
+      }
     emit_gemm(prog, gb);
   }
   std::vector<EigJob> small, large;
   int wsmall = 0, wlarge = 0;
-  for (int n = 0; n < d; ++n) {
-    EigJob J{};
-    J.C = B[n];
-    J.V = scratch[n];
-    J.lam = lam[n];
-    J.theta = theta + n;
-    J.rank = out.ranks + n;
-    J.ldc = Wn[n];
-    J.ldv = Wn[n];
-    J.tol = 1e-15;
-    J.theta_scale = eps * eps / d;
-    J.W = (int32_t)Wn[n];
-    J.set_theta = 1;
-    J.clip = 1;
-    if (Wn[n] <= kEigMaxW) {
-      small.push_back(J);
-      wsmall = std::max<int>(wsmall, (int)Wn[n]);
-    } else {
-      large.push_back(J);
-      wlarge = std::max<int>(wlarge, (int)Wn[n]);
+  for (size_t j = 0; j < J; ++j) {
+    const Problem& P = Ps[j];
+    for (int n = 0; n < P.d; ++n) {
+      const ModeMem& M = mm[j][n];
+      EigJob E{};
+      E.C = M.B;
+      E.V = M.scratch;
+      E.lam = M.lam;
+      E.theta = theta + j * kMaxOrder + n;
+      E.rank = out.ranks + j * kMaxOrder + n;
+      E.ldc = M.W;
+      E.ldv = M.W;
+      E.tol = 1e-15;
+      E.theta_scale = eps * eps / P.d;
+      E.W = (int32_t)M.W;
+      E.set_theta = 1;
+      E.clip = 1;
+      if (M.W <= kEigMaxW) {
+        small.push_back(E);
+        wsmall = std::max<int>(wsmall, (int)M.W);
+      } else {
+        large.push_back(E);
+        wlarge = std::max<int>(wlarge, (int)M.W);
+      }
     }
   }
   for (int which = 0; which < 2; ++which) {
@@ -2231,15 +2359,32 @@ static tsk_status validate_subranks(tsk_handle h, const tsk_tucker_sum* sum, dou
   return TSK_OK;
 }
 
-static tsk_status plan_subranks_sized(tsk_handle h, const Problem& P, double eps, char* ws,
-                                      Program& prog, SubrankOut& out, size_t* bytes) {
+static tsk_status validate_subranks_batch(tsk_handle h, int32_t batch, const tsk_tucker_sum* sums,
+                                          double eps, std::vector<Problem>& Ps) {
+  if (batch < 1 || sums == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "batch < 1 or sums is NULL");
+  Ps.assign(batch, Problem{});
+  for (int j = 0; j < batch; ++j)
+    if (tsk_status st = validate_subranks(h, sums + j, eps, Ps[j]); st != TSK_OK) {
+      h->err = "sum " + std::to_string(j) + ": " + h->err;
+      return st;
+    }
+  return TSK_OK;
+}
+
+static tsk_status plan_subranks_sized(tsk_handle h, const std::vector<Problem>& Ps, double eps,
+                                      char* ws, Program& prog, SubrankOut& out, size_t* bytes) {
   Arena ar;
   ar.base = ws;
-  plan_subranks(P, eps, ar, prog, out);
+  plan_subranks(Ps, eps, ar, prog, out);
   if (!ar.too_far.empty()) return fail(h, TSK_ERR_UNSUPPORTED, "%s", ar.too_far.c_str());
   prog.meta_region = align_up(ar.top, 256);
   *bytes = prog.meta_region + align_up(prog.blob.size(), 256) + 256;
   return TSK_OK;
+}
+
+static tsk_status plan_subranks_sized(tsk_handle h, const Problem& P, double eps, char* ws,
+                                      Program& prog, SubrankOut& out, size_t* bytes) {
+  return plan_subranks_sized(h, std::vector<Problem>{P}, eps, ws, prog, out, bytes);
 }
 
 // ------------------------------------------------------------------ plan self-check
@@ -2446,7 +2591,8 @@ void check_program(const Program& prog, Checker& ck) {
           ck.span(J.C, 0, (J.W - 1) * J.ldc + J.W - 1, 8, "eig C");
           ck.span(J.V, 0, (J.W - 1) * J.ldv + J.W - 1, 8, "eig V");
           ck.span(J.lam, 0, J.W - 1, 8, "eig lam");
-          if (st.pass == 0 && J.W > kEigMaxW) {
+          if (st.pass == 0 && st.wmax > kEigMaxW) {
+            // the global-memory form runs for every job of such a launch
             const int64_t Wp = J.W + (J.W & 1);
             ck.span(J.work, 0, 2 * Wp * Wp - 1, 8, "eig work");
           }
@@ -2765,21 +2911,25 @@ extern "C" int tsk_plan_selfcheck_project(const tsk_tucker_sum* sum, const int64
 // Every phase of a truncation planned with the given ranks (as the device
 // would report them), each launch checked against the workspace and the
 // caller's buffers.
-extern "C" int tsk_plan_selfcheck_truncate(int32_t order, const int64_t* dims,
-                                           const int64_t* widths, const int32_t* ranks,
-                                           char* msg, size_t msglen) {
+// Host-only bounds check of a batch of truncations of one order: job j has
+// dims[j*order..], widths[j*order..] and takes the ranks ranks[j*order..]
+// (as if the device had chosen them).
+extern "C" int tsk_plan_selfcheck_truncate_batched(int32_t batch, int32_t order,
+                                                   const int64_t* dims, const int64_t* widths,
+                                                   const int32_t* ranks, char* msg,
+                                                   size_t msglen) {
   auto say = [&](const std::string& s) {
     if (msg && msglen) {
       std::strncpy(msg, s.c_str(), msglen - 1);
       msg[msglen - 1] = 0;
     }
   };
-  tsk_handle_ scratch_handle;
-  TruncIO io;
-  if (tsk_status st = validate_trunc(&scratch_handle, order, dims, widths, 0.5, io); st != TSK_OK) {
-    say(scratch_handle.err);
-    return st;
+  if (batch < 1 || dims == nullptr || widths == nullptr || ranks == nullptr) {
+    say("bad batch or NULL arrays");
+    return TSK_ERR_INVALID_ARG;
   }
+  tsk_handle_ scratch_handle;
+  std::vector<TruncIO> ios(batch);
   Checker ck;
   uintptr_t next = (uintptr_t)1 << 44;
   auto fake = [&](size_t bytes, const char* name) {
@@ -2788,20 +2938,29 @@ extern "C" int tsk_plan_selfcheck_truncate(int32_t order, const int64_t* dims,
     next += align_up(bytes, (size_t)1 << 20) + ((size_t)1 << 30);
     return p;
   };
-  int64_t hs = 1;
-  for (int k = 0; k < order; ++k) {
-    if (ranks[k] < 1 || ranks[k] > widths[k]) {
-      say("rank outside [1, width]");
-      return TSK_ERR_INVALID_ARG;
+  for (int j = 0; j < batch; ++j) {
+    const int64_t* dj = dims + (size_t)j * order;
+    const int64_t* wj = widths + (size_t)j * order;
+    if (tsk_status st = validate_trunc(&scratch_handle, order, dj, wj, 0.5, ios[j]); st != TSK_OK) {
+      say(scratch_handle.err);
+      return st;
     }
-    io.Q.push_back((const double*)fake(dims[k] * widths[k] * 8, "Q"));
-    io.U.push_back((double*)fake(dims[k] * widths[k] * 8, "U"));
-    hs *= widths[k];
+    int64_t hs = 1;
+    for (int k = 0; k < order; ++k) {
+      const int32_t r = ranks[(size_t)j * order + k];
+      if (r < 1 || r > wj[k]) {
+        say("rank outside [1, width]");
+        return TSK_ERR_INVALID_ARG;
+      }
+      ios[j].Q.push_back((const double*)fake(dj[k] * wj[k] * 8, "Q"));
+      ios[j].U.push_back((double*)fake(dj[k] * wj[k] * 8, "U"));
+      hs *= wj[k];
+    }
+    ios[j].H = (const double*)fake(hs * 8, "H");
+    ios[j].G = (double*)fake(hs * 8, "G");
   }
-  io.H = (const double*)fake(hs * 8, "H");
-  io.G = (double*)fake(hs * 8, "G");
   bool far = false;
-  const size_t need = trunc_workspace(io, &far);
+  const size_t need = trunc_workspace(ios, &far);
   if (far) {
     say("stride beyond 31-bit offsets");
     return TSK_ERR_UNSUPPORTED;
@@ -2810,40 +2969,34 @@ extern "C" int tsk_plan_selfcheck_truncate(int32_t order, const int64_t* dims,
   Arena fixed;
   fixed.base = ws;
   TruncLayout L;
-  trunc_layout(io, fixed, L);
-  std::vector<int64_t> shape = io.w;
-  std::vector<int32_t> rk(order, 0);
-  const double* cur = io.H;
-  int which = 0;
-  for (int n = 0; n <= order; ++n) {
-    double* dst = (n == order) ? io.G : L.buf[which];
-    Arena ar;
-    ar.base = ws;
-    ar.top = L.phase_base;
-    Program prog;
-    trunc_phase(io, L, n, shape, cur, dst, rk, ar, prog);
-    prog.meta_region = align_up(ar.top, 256);
-    if (prog.meta_region + align_up(prog.blob.size(), 256) + 256 > need) {
-      say("phase exceeds the planned workspace");
-      return 99;
-    }
+  trunc_layout(ios, fixed, L);
+  auto run = [&](Program& prog) -> tsk_status {
     check_program(prog, ck);
-    if (!ck.ok) {
-      say(ck.err);
-      return 98;
-    }
-    if (n > 0) {
-      shape[n - 1] = rk[n - 1];
-      cur = dst;
-      which ^= 1;
-    }
-    if (n < order) rk[n] = ranks[n];
+    return ck.ok ? TSK_OK : TSK_ERR_DEVICE;
+  };
+  auto rank_of = [&](size_t j, int n) -> int32_t { return ranks[j * order + n]; };
+  std::vector<std::vector<int32_t>> out;
+  const tsk_status st = trunc_drive(&scratch_handle, ios, L, ws, need, run, rank_of, out);
+  if (!ck.ok) {
+    say(ck.err);
+    return 98;
+  }
+  if (st != TSK_OK) {
+    say(scratch_handle.err);
+    return 99;
   }
   say("ok");
   return 0;
 }
 
-extern "C" int tsk_plan_selfcheck_subranks(const tsk_tucker_sum* sum, char* msg, size_t msglen) {
+extern "C" int tsk_plan_selfcheck_truncate(int32_t order, const int64_t* dims,
+                                           const int64_t* widths, const int32_t* ranks,
+                                           char* msg, size_t msglen) {
+  return tsk_plan_selfcheck_truncate_batched(1, order, dims, widths, ranks, msg, msglen);
+}
+
+extern "C" int tsk_plan_selfcheck_subranks_batched(int32_t batch, const tsk_tucker_sum* sums,
+                                                   char* msg, size_t msglen) {
   auto say = [&](const std::string& s) {
     if (msg && msglen) {
       std::strncpy(msg, s.c_str(), msglen - 1);
@@ -2851,8 +3004,8 @@ extern "C" int tsk_plan_selfcheck_subranks(const tsk_tucker_sum* sum, char* msg,
     }
   };
   tsk_handle_ scratch_handle;
-  Problem P;
-  if (tsk_status st = validate_subranks(&scratch_handle, sum, 0.5, P); st != TSK_OK) {
+  std::vector<Problem> Ps;
+  if (tsk_status st = validate_subranks_batch(&scratch_handle, batch, sums, 0.5, Ps); st != TSK_OK) {
     say(scratch_handle.err);
     return st;
   }
@@ -2864,19 +3017,21 @@ extern "C" int tsk_plan_selfcheck_subranks(const tsk_tucker_sum* sum, char* msg,
     next += align_up(bytes, (size_t)1 << 20) + ((size_t)1 << 30);
     return q;
   };
-  const size_t ein = P.in_f64 ? 8 : 4;
-  for (int i = 0; i < P.s; ++i) {
-    int64_t cs = 1;
-    for (int k = 0; k < P.d; ++k) cs *= P.r(i, k);
-    P.cores[i] = fake(cs * ein, "core");
-    for (int k = 0; k < P.d; ++k)
-      P.factors[(size_t)i * P.d + k] = fake(P.dims[k] * P.r(i, k) * ein, "factor");
+  for (Problem& P : Ps) {
+    const size_t ein = P.in_f64 ? 8 : 4;
+    for (int i = 0; i < P.s; ++i) {
+      int64_t cs = 1;
+      for (int k = 0; k < P.d; ++k) cs *= P.r(i, k);
+      P.cores[i] = fake(cs * ein, "core");
+      for (int k = 0; k < P.d; ++k)
+        P.factors[(size_t)i * P.d + k] = fake(P.dims[k] * P.r(i, k) * ein, "factor");
+    }
   }
   tsk_handle_ fake_handle;
   Program p0;
   SubrankOut o0;
   size_t need = 0;
-  if (tsk_status st = plan_subranks_sized(&fake_handle, P, 0.5, nullptr, p0, o0, &need); st != TSK_OK) {
+  if (tsk_status st = plan_subranks_sized(&fake_handle, Ps, 0.5, nullptr, p0, o0, &need); st != TSK_OK) {
     say(fake_handle.err);
     return st;
   }
@@ -2884,7 +3039,7 @@ extern "C" int tsk_plan_selfcheck_subranks(const tsk_tucker_sum* sum, char* msg,
   Program prog;
   SubrankOut o1;
   size_t need2 = 0;
-  plan_subranks_sized(&fake_handle, P, 0.5, ws, prog, o1, &need2);
+  plan_subranks_sized(&fake_handle, Ps, 0.5, ws, prog, o1, &need2);
   if (need2 != need) {
     say("workspace size differs between the size query and the call");
     return 99;
@@ -2896,6 +3051,10 @@ extern "C" int tsk_plan_selfcheck_subranks(const tsk_tucker_sum* sum, char* msg,
   }
   say("ok");
   return 0;
+}
+
+extern "C" int tsk_plan_selfcheck_subranks(const tsk_tucker_sum* sum, char* msg, size_t msglen) {
+  return tsk_plan_selfcheck_subranks_batched(1, sum, msg, msglen);
 }
 
 extern "C" int tsk_plan_selfcheck_deterministic(const tsk_tucker_sum* sum, char* msg,
@@ -3383,6 +3542,115 @@ tsk_status tucker_sum_subranks(tsk_handle h, const tsk_tucker_sum* sum, double e
     return fail(h, TSK_ERR_DEVICE, "reading the effective subranks failed");
   for (int n = 0; n < P.d; ++n) ell_out[n] = r[n] + p[n];
   return TSK_OK;
+}
+
+tsk_status tucker_sum_subranks_batched_workspace_size(tsk_handle h, int32_t batch,
+                                                      const tsk_tucker_sum* sums, size_t* bytes) {
+  if (h == nullptr || bytes == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL handle or bytes");
+  h->err.clear();
+  std::vector<Problem> Ps;
+  tsk_status st = validate_subranks_batch(h, batch, sums, 0.5, Ps);
+  if (st != TSK_OK) return st;
+  Program prog;
+  SubrankOut out;
+  return plan_subranks_sized(h, Ps, 0.5, nullptr, prog, out, bytes);
+}
+
+tsk_status tucker_sum_subranks_batched(tsk_handle h, int32_t batch, const tsk_tucker_sum* sums,
+                                       double eps, const int32_t* p, int32_t* ell_out, void* ws,
+                                       size_t ws_bytes, void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  std::vector<Problem> Ps;
+  tsk_status st = validate_subranks_batch(h, batch, sums, eps, Ps);
+  if (st != TSK_OK) return st;
+  if (p == nullptr || ell_out == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "p or ell_out is NULL");
+  size_t total = 0;
+  for (const Problem& P : Ps) total += P.d;
+  for (size_t i = 0; i < total; ++i)
+    if (p[i] < 0) return fail(h, TSK_ERR_INVALID_ARG, "p[%zu] < 0", i);
+  if (ws == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  Program prog;
+  SubrankOut out;
+  size_t need = 0;
+  if ((st = plan_subranks_sized(h, Ps, eps, (char*)ws, prog, out, &need)) != TSK_OK) return st;
+  if (ws_bytes < need)
+    return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  if ((st = set_device(h)) != TSK_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = run_program(h, prog, (char*)ws, s)) != TSK_OK) return st;
+  std::vector<int32_t> r((size_t)kMaxOrder * batch);
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(r.data(), out.ranks, sizeof(int32_t) * r.size(), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(h, TSK_ERR_DEVICE, "reading the effective subranks failed");
+  size_t at = 0;
+  for (int j = 0; j < batch; ++j)
+    for (int n = 0; n < Ps[j].d; ++n, ++at) ell_out[at] = r[(size_t)j * kMaxOrder + n] + p[at];
+  return TSK_OK;
+}
+
+static tsk_status validate_trunc_batch(tsk_handle h, int32_t batch, const tsk_truncation* jobs,
+                                       bool need_ptrs, std::vector<TruncIO>& ios) {
+  if (batch < 1 || jobs == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "batch < 1 or jobs is NULL");
+  ios.assign(batch, TruncIO{});
+  for (int j = 0; j < batch; ++j) {
+    const tsk_truncation& T = jobs[j];
+    if (tsk_status st = validate_trunc(h, T.order, T.dims, T.widths, T.eps, ios[j]); st != TSK_OK) {
+      h->err = "job " + std::to_string(j) + ": " + h->err;
+      return st;
+    }
+    if (!need_ptrs) {
+      ios[j].Q.assign(T.order, nullptr);
+      ios[j].U.assign(T.order, nullptr);
+      continue;
+    }
+    if (T.Q == nullptr || T.H == nullptr || T.U_out == nullptr || T.G_out == nullptr ||
+        T.ranks_out == nullptr)
+      return fail(h, TSK_ERR_INVALID_ARG, "job %d: NULL Q, H, U_out, G_out or ranks_out", j);
+    for (int k = 0; k < T.order; ++k) {
+      if (T.Q[k] == nullptr || T.U_out[k] == nullptr)
+        return fail(h, TSK_ERR_INVALID_ARG, "job %d: Q[%d] or U_out[%d] is NULL", j, k, k);
+      ios[j].Q.push_back(T.Q[k]);
+      ios[j].U.push_back(T.U_out[k]);
+    }
+    ios[j].H = T.H;
+    ios[j].G = T.G_out;
+  }
+  return TSK_OK;
+}
+
+tsk_status tucker_truncate_batched_workspace_size(tsk_handle h, int32_t batch,
+                                                  const tsk_truncation* jobs, size_t* bytes) {
+  if (h == nullptr || bytes == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL handle or bytes");
+  h->err.clear();
+  std::vector<TruncIO> ios;
+  tsk_status st = validate_trunc_batch(h, batch, jobs, false, ios);
+  if (st != TSK_OK) return st;
+  bool far = false;
+  *bytes = trunc_workspace(ios, &far);
+  if (far) return fail(h, TSK_ERR_UNSUPPORTED, "an operand stride reaches past 2^31 bytes inside one tile");
+  return TSK_OK;
+}
+
+tsk_status tucker_truncate_batched(tsk_handle h, int32_t batch, const tsk_truncation* jobs,
+                                   void* ws, size_t ws_bytes, void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  std::vector<TruncIO> ios;
+  tsk_status st = validate_trunc_batch(h, batch, jobs, true, ios);
+  if (st != TSK_OK) return st;
+  if (ws == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  bool far = false;
+  const size_t need = trunc_workspace(ios, &far);
+  if (far) return fail(h, TSK_ERR_UNSUPPORTED, "an operand stride reaches past 2^31 bytes inside one tile");
+  if (ws_bytes < need)
+    return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  if ((st = set_device(h)) != TSK_OK) return st;
+  std::vector<int32_t*> outs(batch);
+  for (int j = 0; j < batch; ++j) outs[j] = jobs[j].ranks_out;
+  return truncate_run(h, ios, (char*)ws, need, (hipStream_t)stream, outs.data());
 }
 
 tsk_status tucker_sum_round_deterministic_workspace_size(tsk_handle h,

@@ -309,3 +309,62 @@ def test_deterministic_plan_in_bounds(dims, ranks):
         msg = ctypes.create_string_buffer(512)
         rc = fn(ctypes.byref(tsum), msg, 512)
         assert rc == 0, msg.value.decode()
+
+
+def test_truncate_batched_plan_in_bounds():
+    """The batched Stage-4 truncation over jobs of different widths (some
+    past the LDS eigensolver) and device ranks stays in bounds, including
+    the grouped eigensolver launches."""
+    from paper_2603_13532_amd import _lib
+    lib = _lib.load()
+    fn = lib.tsk_plan_selfcheck_truncate_batched
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                   ctypes.c_char_p, ctypes.c_size_t]
+    rng = np.random.default_rng(3)
+    for batch in (1, 2, 64):
+        dims, widths, ranks = [], [], []
+        for j in range(batch):
+            n = [int(x) for x in rng.integers(20, 200, 3)]
+            w = [int(min(x, rng.integers(1, 130))) for x in n]
+            r = [int(rng.integers(1, x + 1)) for x in w]
+            dims += n
+            widths += w
+            ranks += r
+        msg = ctypes.create_string_buffer(512)
+        rc = fn(batch, 3, (ctypes.c_int64 * len(dims))(*dims),
+                (ctypes.c_int64 * len(widths))(*widths), (ctypes.c_int32 * len(ranks))(*ranks),
+                msg, 512)
+        assert rc == 0, (batch, msg.value.decode())
+
+
+def test_subranks_batched_plan_in_bounds():
+    """Batched Stage 1 over sums of different shapes (one with a mode above
+    the LDS eigensolver's width) and both input dtypes."""
+    from paper_2603_13532_amd import _lib
+    lib = _lib.load()
+    fn = lib.tsk_plan_selfcheck_subranks_batched
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_int32, ctypes.POINTER(_lib.TuckerSum), ctypes.c_char_p,
+                   ctypes.c_size_t]
+    shapes = [((64, 64, 64), np.full((4, 3), 8)),
+              ((130, 70, 90), np.array([[70, 5, 33], [1, 66, 12], [40, 40, 40]])),
+              ((100, 100, 100), np.full((9, 3), 6)),
+              ((40, 30, 20, 25), np.array([[6, 5, 4, 7], [3, 8, 2, 5]]))]
+    keep = []
+    for in_f64 in (True, False):
+        sums = []
+        for dims, ranks in shapes:
+            s, d = ranks.shape
+            arrs = ((ctypes.c_int64 * d)(*dims),
+                    (ctypes.c_int32 * (s * d))(*[int(x) for x in ranks.ravel()]),
+                    (ctypes.c_void_p * s)(*([0x1000] * s)),
+                    (ctypes.c_void_p * (s * d))(*([0x1000] * (s * d))))
+            keep.append(arrs)
+            sums.append(_lib.TuckerSum(d, s, arrs[0], arrs[1], arrs[2], arrs[3], None,
+                                       0 if in_f64 else 1))
+        c_sums = (_lib.TuckerSum * len(sums))(*sums)
+        msg = ctypes.create_string_buffer(512)
+        rc = fn(len(sums), c_sums, msg, 512)
+        assert rc == 0, msg.value.decode()
