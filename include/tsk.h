@@ -332,7 +332,11 @@ tsk_status tucker_sum_recompress_batched(tsk_handle handle, int32_t batch,
  * the contractions run in spec->sketch_prec.  Intermediates (P, V, W) are
  * recomputed from the inputs and Omega (regenerated from the seed).
  * Returns TSK_ERR_UNSUPPORTED for the Kronecker sketch, oversketched modes or
- * widths above 96. */
+ * widths above 96.  The solve checks each R_n on the device: a mode with
+ * some |R_jj| <= 64 w_n u max_i |R_ii| (u = 2^-53; e.g. the Householder result
+ * of a rank-deficient Y_n) is counted, and the next tsk_qr_fallback_count
+ * returns TSK_ERR_RANK_DEFICIENT; that call's gradients are then not
+ * meaningful. */
 tsk_status tucker_sum_backward_workspace_size(tsk_handle handle, const tsk_tucker_sum* sum,
                                               const tsk_sketch_spec* spec, size_t* bytes);
 tsk_status tucker_sum_recompress_backward(tsk_handle handle, const tsk_tucker_sum* sum,
@@ -345,8 +349,9 @@ tsk_status tucker_sum_recompress_backward(tsk_handle handle, const tsk_tucker_su
 /* Number of mode QRs that took the Householder path since the handle was
  * created (Cholesky breakdown, or qr_policy 1).  Synchronises `stream`.
  * Returns TSK_ERR_RANK_DEFICIENT (count still written) if, since the last
- * call, a Cholesky QR broke down under qr_policy 2; the outputs of that call
- * are still the Householder result. */
+ * call, a Cholesky QR broke down under qr_policy 2 (the outputs of that call
+ * are still the Householder result) or a backward call met a numerically
+ * singular R_n.  Each condition is reported once. */
 tsk_status tsk_qr_fallback_count(tsk_handle handle, void* stream, int64_t* count);
 
 #ifdef __cplusplus

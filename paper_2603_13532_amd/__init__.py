@@ -25,7 +25,7 @@ __all__ = [
     "tucker_sum_recompress_backward", "recompress", "tucker_sum_recompress_noalloc",
     "tucker_sum_project", "tucker_truncate", "round_sum", "effective_subranks", "sketch_sum",
     "round_deterministic", "effective_subranks_batched", "tucker_truncate_batched",
-    "sketch_sum_batched",
+    "sketch_sum_batched", "carve_fortran",
 ]
 
 
@@ -50,6 +50,30 @@ def fortran(t: torch.Tensor) -> torch.Tensor:
 def empty_fortran(shape, dtype, device) -> torch.Tensor:
     rev = list(reversed(range(len(shape))))
     return torch.empty(tuple(reversed(tuple(shape))), dtype=dtype, device=device).permute(rev)
+
+
+def carve_fortran(shapes, dtype, device):
+    """Column-major tensors of the given shapes as views of ONE allocation
+    (each view 256-byte aligned): a batch's many small outputs without a
+    caching-allocator call per tensor."""
+    es = torch.empty((), dtype=dtype).element_size()
+    align = max(1, 256 // es)
+    offs, total = [], 0
+    for sh in shapes:
+        n = 1
+        for x in sh:
+            n *= int(x)
+        offs.append(total)
+        total += (n + align - 1) // align * align
+    buf = torch.empty(max(total, 1), dtype=dtype, device=device)
+    out = []
+    for sh, off in zip(shapes, offs):
+        strides, st = [], 1
+        for x in sh:
+            strides.append(st)
+            st *= int(x)
+        out.append(buf.as_strided(tuple(int(x) for x in sh), tuple(strides), off))
+    return out
 
 
 def _dtype_code(dt) -> int:
@@ -401,6 +425,15 @@ def tucker_truncate_batched(jobs, eps):
     dev = jobs[0][1].device
     h = Handle.get(dev)
     keep, structs, outs = [], [], []
+    shapes = []
+    for Q, H in jobs:
+        widths = [int(x) for x in H.shape]
+        total = 1
+        for w in widths:
+            total *= w
+        shapes += [(int(q.shape[0]), w) for q, w in zip(Q, widths)] + [(total,)]
+    bufs = carve_fortran(shapes, torch.float64, dev)
+    at = 0
     for Q, H in jobs:
         d = H.dim()
         Qf = [fortran(q.to(torch.float64)) for q in Q]
@@ -409,11 +442,8 @@ def tucker_truncate_batched(jobs, eps):
         widths = [int(x) for x in Hf.shape]
         if [int(q.shape[1]) for q in Qf] != widths:
             raise ValueError("Q_k must have as many columns as H has entries along mode k")
-        U = [empty_fortran((n, w), torch.float64, dev) for n, w in zip(dims, widths)]
-        total = 1
-        for w in widths:
-            total *= w
-        G = torch.empty(total, dtype=torch.float64, device=dev)
+        U, G = bufs[at:at + d], bufs[at + d]
+        at += d + 1
         arrs = ((c_int64 * d)(*dims), (c_int64 * d)(*widths),
                 (c_void_p * d)(*[q.data_ptr() for q in Qf]),
                 (c_void_p * d)(*[u.data_ptr() for u in U]), (c_int32 * d)())
@@ -578,11 +608,17 @@ class BatchRecompressor:
         self.c_sums = (_lib.TuckerSum * B)(*[m.sum for m in self.ms])
         self.c_specs = (_lib.SketchSpec * B)(*[m.spec for m in self.ms])
         self.Q, self.H, self._cq = [], [], []
+        bws = [m.widths()[1] for m in self.ms]
+        shapes = []
+        for m, bw in zip(self.ms, bws):
+            shapes += [(m.dims[n], bw[n]) for n in range(m.d)] + [tuple(bw)]
+        bufs = carve_fortran(shapes, self.out_dtype, m0.device)
+        at = 0
         for m in self.ms:
-            _, bw = m.widths()
-            qs = [empty_fortran((m.dims[n], bw[n]), self.out_dtype, m.device) for n in range(m.d)]
+            qs = bufs[at:at + m.d]
             self.Q.append(qs)
-            self.H.append(empty_fortran(tuple(bw), self.out_dtype, m.device))
+            self.H.append(bufs[at + m.d])
+            at += m.d + 1
             self._cq.append((c_void_p * m.d)(*[q.data_ptr() for q in qs]))
         self.c_q = (POINTER(c_void_p) * B)(*[ctypes.cast(a, POINTER(c_void_p)) for a in self._cq])
         self.c_h = (c_void_p * B)(*[h.data_ptr() for h in self.H])
@@ -692,6 +728,9 @@ class _RecompressFn(torch.autograd.Function):
                                                 meta["seed"], qs, rs, h_bar, q_bar,
                                                 coeffs=meta["coeffs"],
                                                 sketch_prec=meta["sketch_prec"])
+        # raises TskError (TSK_ERR_RANK_DEFICIENT) when some R_n was
+        # numerically singular, i.e. the forward's Y_n had deficient rank
+        qr_fallback_count(qs[0].device)
         return (None, *gb, *[u for us in ub for u in us])
 
 

@@ -102,6 +102,10 @@ struct TrsmJob {
   int64_t n, w;
   int64_t row0;         // first row of this job's chunk
   int32_t rows, pad_;
+  // counted once per mode (by the chunk at row 0) when some |R_jj| is at most
+  // 64 w u max_i |R_ii| (u = 2^-53): R is numerically singular and the
+  // solve meaningless
+  unsigned long long* singular;
 };
 
 // S = copyltu(M): lower triangle of M mirrored to the upper one.

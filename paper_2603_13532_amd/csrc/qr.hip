@@ -1,4 +1,4 @@
-// Thin QR of the sketches Y_n in FP64 (the "qr(Y_n, 'econ')" step of
+// Thin QR of the sketches Y_n in FP64 (the economy QR of Stage 2 of
 // Algorithms 4/5), with diag(R) >= 0.
 //
 // Default path: Cholesky QR2.  The Gram matrix Y^T Y is formed by the MFMA
@@ -1028,6 +1028,15 @@ __global__ __launch_bounds__(64) void trsm_rt_kernel(const TrsmJob* __restrict__
   __shared__ double sx[kTrsmMax][64];
   for (int e = t; e < w * w; e += 64) sR[e] = J.R[e];
   __syncthreads();
+  if (t == 0 && J.row0 == 0 && J.singular != nullptr) {
+    double dmax = 0.0, dmin = INFINITY;
+    for (int j = 0; j < w; ++j) {
+      const double a = fabs(sR[j + j * w]);
+      dmax = fmax(dmax, a);
+      dmin = fmin(dmin, a);
+    }
+    if (!(dmin > 64.0 * w * 0x1p-53 * dmax)) atomicAdd(J.singular, 1ull);
+  }
   const int64_t row = J.row0 + t;
   const bool active = t < J.rows && row < J.n;
   if (active) {

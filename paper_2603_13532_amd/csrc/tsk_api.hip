@@ -1057,6 +1057,7 @@ struct BackwardIO {
   bool out_f64 = true;              // dtype of Q, Hbar, Qbar
   std::vector<void*> core_bar;      // sum dtype
   std::vector<void*> factor_bar;    // sum dtype, [s*d]
+  unsigned long long* singular = nullptr;  // counter of singular R_n (or null)
 };
 
 // Reverse mode of the KRP recompression, in the order of the oracle's
@@ -1342,7 +1343,7 @@ void build_backward(const Problem& P, const BackwardIO& io, Arena& ar, Program& 
     for (int k = 0; k < d; ++k)
       for (int64_t r0 = 0; r0 < P.dims[k]; r0 += 64)
         tj.push_back(TrsmJob{Qb[k], io.R[k], Qb[k], P.dims[k], P.w[k], r0,
-                             (int32_t)std::min<int64_t>(64, P.dims[k] - r0), 0});
+                             (int32_t)std::min<int64_t>(64, P.dims[k] - r0), 0, io.singular});
     Step tr{};
     tr.kind = S_TRSM;
     tr.meta = prog.put(tj);
@@ -2553,6 +2554,7 @@ void check_program(const Program& prog, Checker& ck) {
           ck.span(J.R, 0, J.w * J.w - 1, 8, "trsm R");
           ck.span(J.Z, 0, J.n * J.w - 1, 8, "trsm Z");
           ck.span(J.X, 0, J.n * J.w - 1, 8, "trsm X");
+          if (J.singular) ck.span(J.singular, 0, 0, 8, "trsm flag");
         }
         break;
       }
@@ -2818,6 +2820,7 @@ extern "C" int tsk_plan_selfcheck_backward(const tsk_tucker_sum* sum, const tsk_
     hsize *= P.w[n];
   }
   io.Hbar = fake(hsize * eo, "Hbar");
+  io.singular = (unsigned long long*)fake(256, "counter");
   Program p0;
   size_t need = 0;
   if (plan_backward(P, io, nullptr, p0, &need) != TSK_OK) {
@@ -3910,6 +3913,7 @@ tsk_status tucker_sum_recompress_backward(tsk_handle h, const tsk_tucker_sum* su
   BackwardIO io;
   if ((st = backward_io(h, P, Q, R, H_bar, Q_bar, out_dtype, core_bar, factor_bar, io)) != TSK_OK)
     return st;
+  io.singular = (unsigned long long*)(h->d_counter + 2);
   if (ws == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "workspace is NULL");
   if (((uintptr_t)ws & 255) != 0) return fail(h, TSK_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   Program prog;
@@ -3928,10 +3932,19 @@ tsk_status tsk_qr_fallback_count(tsk_handle h, void* stream, int64_t* count) {
   if (st != TSK_OK) return st;
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
     return fail(h, TSK_ERR_DEVICE, "stream synchronisation failed");
-  int64_t c[2] = {0, 0};
+  int64_t c[3] = {0, 0, 0};
   if (hipMemcpy(c, h->d_counter, sizeof c, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(h, TSK_ERR_DEVICE, "counter read failed");
   *count = c[0];
+  if (c[2] != 0) {
+    // singular R_n met by a backward call: reported once, then cleared
+    if (hipMemset(h->d_counter + 2, 0, sizeof(int64_t)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
+      return fail(h, TSK_ERR_DEVICE, "counter reset failed");
+    return fail(h, TSK_ERR_RANK_DEFICIENT,
+                "%lld mode(s) of a backward call had a numerically singular R_n",
+                (long long)c[2]);
+  }
   if (c[1] != 0) {
     // breakdowns under qr_policy 2 are reported once, then cleared
     if (hipMemset(h->d_counter + 1, 0, sizeof(int64_t)) != hipSuccess ||

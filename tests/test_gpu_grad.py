@@ -72,6 +72,21 @@ def test_fp64_gradient_matches_oracle_small(tsk):
             assert rel(a, b) < 1e-9
 
 
+def test_backward_reports_singular_r(tsk):
+    """A sum whose sketches have lower rank than the sketch width takes the
+    Householder path, whose R is singular: the backward must report
+    TSK_ERR_RANK_DEFICIENT rather than return meaningless gradients, and
+    report it once (a following full-rank call is clean)."""
+    import torch
+    ts = synth.random_sum(4, (16, 18, 14), [[2, 2, 2]])
+    tg = synth.random_sum(5, (16, 18, 14), [[2, 2, 2]])
+    with pytest.raises(tsk.TskError) as err:
+        gpu_grads(tsk, ts, tg, 6, 3, torch.float64, "fp64")
+    assert err.value.name == "TSK_ERR_RANK_DEFICIENT"
+    ts, tg, m = small_problem()
+    gpu_grads(tsk, ts, tg, m, 3, torch.float64, "fp64")
+
+
 def test_fp64_gradient_against_finite_differences(tsk):
     """64 random entries of cores and factors: GPU adjoint vs central FD of
     the GPU FP64 forward (h = 1e-6)."""
