@@ -71,6 +71,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2603_13532_amd",
+                          "tune_gfx950.json")
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +88,12 @@ def parse():
                     help="bound on the oracle's CPU time for the baseline sample")
     ap.add_argument("--profile-only", default=None, metavar="FORM",
                     help="only replay the batch in FORM (for kernel traces and counters)")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE, metavar="JSON",
+                    help="autotuned launch parameters to load before timing ('' for none)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the batch's launch parameters live instead of loading a cache")
+    ap.add_argument("--tune-save", default="", metavar="JSON",
+                    help="with --autotune: write the tuned table here")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device to device (HBM counter calibration)")
     return ap.parse_args()
@@ -283,9 +293,49 @@ def batch_inputs(tsk, sums, form, dev):
              "kind": "krp", "sizes": [one["ell"][0]], "seed": one["omega_seed"]} for one in sums]
 
 
+def apply_tuning(tsk, args, sums, forms, dev):
+    """Autotuned launch parameters for the timed plans: tuned live on the
+    batch (--autotune, each form in turn), or loaded from the JSON cache.
+    Returns a description for the JSON line."""
+    if args.autotune:
+        import synth
+        singles = []
+        want = args.legs.split(",")
+        if "structured" in want:
+            singles.append((rounded_f32(synth.config_structured()), [74]))
+        if "precision" in want:
+            singles.append((rounded_f32(synth.config_precision()), [56]))
+        for form in forms:
+            _, sp, pp = FORMS[form]
+            tsk.autotune(batch_inputs(tsk, sums, form, dev), sp, pp, reps=3)
+            for ts, sizes in singles:
+                one = dict(ts, ell=[sizes[0]])
+                tsk.autotune(batch_inputs(tsk, [one], form, dev), sp, pp, reps=3)
+        if args.tune_save:
+            tsk.autotune_save(args.tune_save)
+        return {"source": "tuned live on the batch (3 timed runs per candidate)"}
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        tsk.autotune_load(args.tune_cache)
+        with open(args.tune_cache) as f:
+            n = len(json.load(f)["entries"])
+        return {"source": os.path.relpath(args.tune_cache, os.path.dirname(TUNE_CACHE) + "/.."),
+                "classes": n}
+    return {"source": "planner defaults"}
+
+
 def batch_leg(tsk, args, sums, refs, forms, dev):
     import torch
-    out = {}
+    # every form once with the planner's defaults, for the tuning's effect
+    tsk.autotune_clear()
+    untuned = {}
+    for form in forms:
+        _, sp, pp = FORMS[form]
+        br = tsk.BatchRecompressor(batch_inputs(tsk, sums, form, dev), sp, pp).capture()
+        untuned[form] = time_replays(br.replay, args.steps, args.warmup)
+        del br
+    tuning = apply_tuning(tsk, args, sums, forms, dev)
+    log(f"launch parameters: {tuning}")
+    out = {"_tuning": tuning}
     for form in forms:
         _, sp, pp = FORMS[form]
         br = tsk.BatchRecompressor(batch_inputs(tsk, sums, form, dev), sp, pp).capture()
@@ -297,8 +347,10 @@ def batch_leg(tsk, args, sums, refs, forms, dev):
         out[form] = {"ms_per_batch": ms, "recompressions_per_s": len(sums) * 1e3 / ms,
                      "max_rel_err": errs_sorted[-1], "median_rel_err": errs_sorted[len(errs) // 2],
                      "sums_above_1e-6": int(sum(e > ERR_BAR for e in errs)),
-                     "sketch_prec": sp, "project_prec": pp, "_br": br}
-        log(f"batch {form}: {ms:.3f} ms per {len(sums)} sums, worst err {errs_sorted[-1]:.2e}, "
+                     "sketch_prec": sp, "project_prec": pp, "_br": br,
+                     "untuned_ms_per_batch": untuned[form]}
+        log(f"batch {form}: {ms:.3f} ms per {len(sums)} sums (planner defaults "
+            f"{untuned[form]:.3f}), worst err {errs_sorted[-1]:.2e}, "
             f"{out[form]['sums_above_1e-6']} above 1e-6")
     return out
 
@@ -646,6 +698,8 @@ def main():
     if args.profile_only:
         form = args.profile_only
         _, sp, pp = FORMS[form]
+        if args.tune_cache and os.path.exists(args.tune_cache):
+            tsk.autotune_load(args.tune_cache)
         br = tsk.BatchRecompressor(batch_inputs(tsk, sums, form, dev), sp, pp).capture()
         for i in range(args.warmup + args.steps):
             br.replay()
@@ -660,6 +714,7 @@ def main():
     log(f"oracle for the batch: {time.perf_counter() - t0:.1f} s")
 
     batch = batch_leg(tsk, args, sums, refs, forms, dev)
+    tuning = batch.pop("_tuning")
     ok = [f for f in forms if batch[f]["max_rel_err"] <= ERR_BAR]
     best = min(ok, key=lambda f: batch[f]["ms_per_batch"]) if ok else "fp64"
     chosen = batch[best]
@@ -745,6 +800,7 @@ def main():
         "target_3x_at_1e-6_met": bool(fp64_rate and best != "fp64" and
                                       chosen["recompressions_per_s"] >= 3 * fp64_rate),
         "forms": forms_out,
+        "launch_parameters": tuning,
         "roofline": roof,
         "step_roofline": step_roof,
         "kernels": kernels,

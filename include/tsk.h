@@ -346,6 +346,32 @@ tsk_status tucker_sum_recompress_backward(tsk_handle handle, const tsk_tucker_su
                                           void* const* core_bar, void* const* factor_bar,
                                           void* ws, size_t ws_bytes, void* stream);
 
+/* Autotuning of the planner's launch parameters for the batched and
+ * single-sum calls (the autotuned tiles of the batching form): the K-split
+ * target of every grouped GEMM class (factor sketch, term expansion,
+ * projection W and final TTM) and of the Khatri-Rao core sketch, and how many
+ * waves may share one 32 x 32 output quadrant in the core sketch.  A class
+ * is (kernel, precision, log2 of the launch's output tiles before
+ * splitting, log2 of its K-tiles).  tsk_autotune plans and runs the batch
+ * (the arguments of tucker_sum_recompress_batched, which it overwrites)
+ * under every candidate value, times each launch with HIP events over
+ * `reps` runs after a warm-up, and keeps per class the value whose launches
+ * were fastest; it allocates and frees its own workspace and synchronises
+ * `stream`.  The table lives in the handle and shapes every plan made
+ * after it changes (workspace sizes included: query them again).  Results
+ * of tuned plans differ from untuned ones only in the order of
+ * floating-point summation.
+ * tsk_autotune_save writes the table as JSON ({"arch": ..., "entries":
+ * [{"kernel", "param", "prec", "tiles_log2", "ktiles_log2", "value",
+ * "us"}, ...]}); tsk_autotune_load replaces the table with a file's, and
+ * rejects a file written for another GPU architecture. */
+tsk_status tsk_autotune(tsk_handle handle, int32_t batch, const tsk_tucker_sum* sums,
+                        const tsk_sketch_spec* specs, void* const* const* Q_out,
+                        void* const* H_out, tsk_dtype out_dtype, int32_t reps, void* stream);
+tsk_status tsk_autotune_save(tsk_handle handle, const char* path);
+tsk_status tsk_autotune_load(tsk_handle handle, const char* path);
+tsk_status tsk_autotune_clear(tsk_handle handle);
+
 /* Number of mode QRs that took the Householder path since the handle was
  * created (Cholesky breakdown, or qr_policy 1).  Synchronises `stream`.
  * Returns TSK_ERR_RANK_DEFICIENT (count still written) if, since the last

@@ -56,6 +56,11 @@ int tsk_plan_selfcheck_truncate_batched(int32_t batch, int32_t order, const int6
                                         const int64_t* widths, const int32_t* ranks, char* msg,
                                         size_t msglen);
 
+/* Parses a tuning cache (the JSON of tsk_autotune_save) for GPU
+ * architecture `arch` and writes the table back as JSON to `out`, or the
+ * parse error; TSK_OK or TSK_ERR_INVALID_ARG. */
+int tsk_tune_json_check(const char* json, const char* arch, char* out, size_t outlen);
+
 /* Self-check of tucker_sum_subranks. */
 int tsk_plan_selfcheck_subranks(const tsk_tucker_sum* sum, char* msg, size_t msglen);
 

@@ -25,7 +25,8 @@ __all__ = [
     "tucker_sum_recompress_backward", "recompress", "tucker_sum_recompress_noalloc",
     "tucker_sum_project", "tucker_truncate", "round_sum", "effective_subranks", "sketch_sum",
     "round_deterministic", "effective_subranks_batched", "tucker_truncate_batched",
-    "sketch_sum_batched", "carve_fortran",
+    "sketch_sum_batched", "carve_fortran", "autotune", "autotune_save", "autotune_load",
+    "autotune_clear",
 ]
 
 
@@ -649,6 +650,36 @@ class BatchRecompressor:
     def replay(self):
         self.graph.replay()
         return self.Q, self.H
+
+
+def autotune(sums, sketch_prec="fp64", project_prec="fp64", out_dtype=None, qr_policy="auto",
+             reps=5):
+    """Measure the planner's launch parameters on this batch (the arguments
+    of tucker_sum_recompress_batched) and keep the fastest per launch class
+    in the device's handle; later plans use them.  Recompressors built
+    before the call keep their workspace size: build them again."""
+    br = BatchRecompressor(sums, sketch_prec, project_prec, out_dtype, qr_policy)
+    check(load().tsk_autotune(br.h.ptr, len(br.ms), br.c_sums, br.c_specs, br.c_q, br.c_h,
+                              _dtype_code(br.out_dtype), int(reps),
+                              c_void_p(_stream_ptr(br.ms[0].device))), br.h.ptr)
+
+
+def autotune_save(path, device=None):
+    """Write the handle's tuning table as JSON."""
+    h = Handle.get(device)
+    check(load().tsk_autotune_save(h.ptr, str(path).encode()), h.ptr)
+
+
+def autotune_load(path, device=None):
+    """Replace the handle's tuning table with a JSON cache's (rejected if it
+    was written for another GPU architecture)."""
+    h = Handle.get(device)
+    check(load().tsk_autotune_load(h.ptr, str(path).encode()), h.ptr)
+
+
+def autotune_clear(device=None):
+    h = Handle.get(device)
+    check(load().tsk_autotune_clear(h.ptr), h.ptr)
 
 
 def tucker_sum_recompress_batched(sums, sketch_prec="fp64", project_prec="fp64", out_dtype=None,

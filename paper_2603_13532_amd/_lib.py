@@ -127,6 +127,12 @@ PROTOTYPES = {
                                                POINTER(c_void_p), POINTER(c_void_p), c_void_p,
                                                POINTER(c_void_p), c_int, POINTER(c_void_p),
                                                POINTER(c_void_p), c_void_p, c_size_t, c_void_p]),
+    "tsk_autotune": (c_int, [c_void_p, c_int32, POINTER(TuckerSum), POINTER(SketchSpec),
+                             POINTER(POINTER(c_void_p)), POINTER(c_void_p), c_int, c_int32,
+                             c_void_p]),
+    "tsk_autotune_save": (c_int, [c_void_p, c_char_p]),
+    "tsk_autotune_load": (c_int, [c_void_p, c_char_p]),
+    "tsk_autotune_clear": (c_int, [c_void_p]),
     "tsk_profile_enable": (c_int, [c_void_p, c_int32]),
     "tsk_profile_report": (c_int, [c_void_p, c_char_p, c_size_t, POINTER(c_size_t)]),
 }

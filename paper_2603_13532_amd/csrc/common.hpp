@@ -71,7 +71,8 @@ struct KrpDesc {
   void* part;                    // splits > 1: per-tile partial blocks
   int32_t r[kMaxOrder];
   int32_t order, mode, m, splits;
-  int64_t strideSplit;           // unused (kept for layout stability)
+  int32_t kw_max;                // most waves that may share one 32x32 quadrant (1, 2 or 4)
+  int32_t pad_kw;
   int64_t Kc;                    // prod_{k != n} r_k
   int32_t tiles_m, tiles_n;
   int64_t tile_begin;

@@ -371,16 +371,18 @@ __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type
 // waves share them, kw = 4 or 2 waves per quadrant each taking every kw-th
 // step of the K-tile, so no SIMD idles; BF16 K-tiles are a single step, and
 // their waves outside the region skip the MFMAs (kw = 1, `active` false).
+// kw_max (a tuning choice of the launch) caps the sharing: below 4 a
+// one-quadrant tile, below 2 a two-quadrant tile, keeps kw = 1.
 struct WaveRole {
   int kw, wm, wn, phase;
   bool active;
 };
 template <int P>
-__device__ __forceinline__ WaveRole wave_role(int w, int mr, int nc) {
+__device__ __forceinline__ WaveRole wave_role(int w, int mr, int nc, int kw_max) {
   if constexpr (P == P_FP64 || P == P_FP32) {
     const int qm = mr > 32 ? 2 : 1, qn = nc > 32 ? 2 : 1;
-    if (qm * qn == 1) return WaveRole{4, 0, 0, w, true};
-    if (qm * qn == 2) {
+    if (qm * qn == 1 && kw_max >= 4) return WaveRole{4, 0, 0, w, true};
+    if (qm * qn == 2 && kw_max >= 2) {
       const int q = w & 1;
       return WaveRole{2, qm == 2 ? q : 0, qm == 2 ? 0 : q, w >> 1, true};
     }
@@ -747,7 +749,7 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
   const int rn = rk[n];
   const int64_t stn = st[n];
 
-  const WaveRole role = wave_role<P>(w, rn - m0, m - n0);
+  const WaveRole role = wave_role<P>(w, rn - m0, m - n0, D.kw_max);
   acc_t acc[2][2];
   acc_zero<P>(acc);
   // the block's 64 columns of every P_k (k != n) into LDS when they fit the

@@ -34,6 +34,15 @@ struct ProfRecord {
   std::string name;
   hipEvent_t begin, end;
   double flops, bytes;
+  int step = -1;  // index of the launch in its program
+};
+
+// One autotuned choice: the value of a launch parameter for a class of
+// launches, keyed by (kernel role, precision, log2 of the launch's tiles
+// before splitting, log2 of its K-tiles); `us` is the time it measured.
+struct TuneEntry {
+  int value;
+  double us;
 };
 
 struct tsk_handle_ {
@@ -52,6 +61,11 @@ struct tsk_handle_ {
   char* scratch_dev = nullptr;
   void* fixed_stage = nullptr;
   hipEvent_t fixed_stage_done = nullptr;
+  // autotuned launch parameters (split-K targets, KRP quadrant sharing);
+  // while tsk_autotune measures, force_* override every class
+  std::map<uint32_t, TuneEntry> tune;
+  int force_split = 0, force_kw = 0;
+  std::string arch;
 };
 
 // Device memory of tucker_sum_recompress_noalloc: one array per device,
@@ -233,6 +247,7 @@ struct Step {
   int wmax = 0;  // chol: widest Gram of the launch
   int hh_kernels = 3;  // householder: which of the two kernels have panels
   int krp_lds = 0;     // krp: LDS elements for the P slices (largest that fits)
+  std::vector<uint32_t> keys;  // autotuning classes whose choices shaped this launch
 };
 
 // LDS elements a KRP launch needs for its P slices: the largest slice set
@@ -297,6 +312,7 @@ struct GemmBatch {
   std::vector<ReduceJob> reduces;
   int64_t tiles = 0;
   double flops = 0, bytes = 0;
+  std::vector<uint32_t> keys;  // autotuning classes of its split decisions
   GemmBatch(int p, int r, Arena* a) : prec(p), role(r), ar(a) {}
   // Add one descriptor; `splits` > 1 writes partials to `part` and queues a
   // reduction into C.
@@ -397,10 +413,12 @@ void emit_gemm(Program& prog, GemmBatch& gb) {
   st.meta2 = prog.put(gb.segs);
   st.count = (int)gb.descs.size();
   st.tiles = gb.tiles;
+  st.keys = gb.keys;
   prog.steps.push_back(st);
   if (!gb.reduces.empty()) {
     Step r{};
     r.kind = S_TILE_REDUCE;
+    r.keys = gb.keys;  // the split choice also sets the reduction's work
     for (const ReduceJob& J : gb.reduces)
       r.bytes += (double)J.rows * J.cols * (J.parts + 1 + J.beta) * (J.out_f64 ? 8 : 4);
     r.meta = prog.put(gb.reduces);
@@ -434,6 +452,24 @@ int choose_splits(int64_t tiles_without_split, int64_t k_tiles, int64_t target =
   s = std::min<int64_t>(s, k_tiles / 2);
   s = std::min<int64_t>(s, 32);
   return (int)std::max<int64_t>(s, 1);
+}
+
+// Autotuning classes.  A key packs the launch parameter (split-K target of
+// a GEMM role or of the KRP core sketch, or the KRP quadrant sharing), the
+// precision and two log2 shape buckets: the output tiles the launch has
+// before splitting, and the K-tiles of its longest product.
+constexpr int kTuneKrpSplit = 16, kTuneKrpKw = 17;
+int lg2(int64_t x) {
+  int l = 0;
+  while (x > 1) {
+    x >>= 1;
+    ++l;
+  }
+  return l;
+}
+uint32_t tune_key(int cls, int prec, int64_t tiles, int64_t ktiles) {
+  return (uint32_t)(cls & 31) << 20 | (uint32_t)(prec & 15) << 16 |
+         (uint32_t)std::min(lg2(tiles), 255) << 8 | (uint32_t)std::min(lg2(ktiles), 255);
 }
 
 size_t esize(bool f64) { return f64 ? 8 : 4; }
@@ -475,14 +511,39 @@ struct Builder {
   std::vector<QrDesc> qr;
   bool any_chol = false;
   int64_t* d_counter = nullptr;
+  const tsk_handle_* th = nullptr;  // its tuning table, if any
+  std::vector<uint32_t> krp_keys;
   explicit Builder(Arena& a) : ar(a) {}
   GemmBatch& g(int stage, int prec, int role) {
     auto it = gemm.find(stage);
     if (it == gemm.end()) it = gemm.emplace(stage, GemmBatch(prec, role, &ar)).first;
     return it->second;
   }
-  int splits(int64_t tiles_without_split, int64_t k_tiles, int64_t target = 512) const {
-    return choose_splits(tiles_without_split * nsums, k_tiles, target);
+  // The tuned value of class `key`, the forced one while tuning, else dflt.
+  int tuned(uint32_t key, int force, int dflt) const {
+    if (th == nullptr) return dflt;
+    if (force > 0) return force;
+    auto it = th->tune.find(key);
+    return it == th->tune.end() ? dflt : it->second.value;
+  }
+  // K-splits of one sum's share of a grouped GEMM launch (the launch holds
+  // nsums such shares): the split target comes from the tuning table.
+  int splits(GemmBatch& gb, int64_t tiles_without_split, int64_t k_tiles, int64_t target = 512) {
+    const int64_t tiles = tiles_without_split * nsums;
+    const uint32_t key = tune_key(gb.role, gb.prec, tiles, k_tiles);
+    if (std::find(gb.keys.begin(), gb.keys.end(), key) == gb.keys.end()) gb.keys.push_back(key);
+    return choose_splits(tiles, k_tiles, tuned(key, th ? th->force_split : 0, (int)target));
+  }
+  int krp_splits(int prec, int64_t tiles_without_split, int64_t k_tiles) {
+    const int64_t tiles = tiles_without_split * nsums;
+    const uint32_t key = tune_key(kTuneKrpSplit, prec, tiles, k_tiles);
+    if (std::find(krp_keys.begin(), krp_keys.end(), key) == krp_keys.end()) krp_keys.push_back(key);
+    return choose_splits(tiles, k_tiles, tuned(key, th ? th->force_split : 0, 1024));
+  }
+  int krp_kw(int prec, int64_t tiles_without_split, int64_t k_tiles) {
+    const uint32_t key = tune_key(kTuneKrpKw, prec, tiles_without_split * nsums, k_tiles);
+    if (std::find(krp_keys.begin(), krp_keys.end(), key) == krp_keys.end()) krp_keys.push_back(key);
+    return tuned(key, th ? th->force_kw : 0, 4);
   }
   void emit(Program& prog);
 };
@@ -610,7 +671,7 @@ void build_projection(const Problem& P, const std::vector<const void*>& Q, bool 
         tiles0 += ceil_div(P.w[k], 64) * ceil_div(P.r(i, k), 64);
         kt = std::max<int64_t>(kt, ceil_div(P.dims[k], tp64 ? 16 : 32));
       }
-    const int splits = B.splits(tiles0, kt);
+    const int splits = B.splits(gb, tiles0, kt);
     for (int i = 0; i < s; ++i)
       for (int k = 0; k < d; ++k) {
         const int64_t n = P.dims[k], r = P.r(i, k), w = P.w[k];
@@ -669,7 +730,7 @@ void build_projection(const Problem& P, const std::vector<const void*>& Q, bool 
     }
     int64_t kt = 0;
     for (int i = 0; i < s; ++i) kt += ceil_div(shape[i][d - 1], tp64 ? 16 : 32);
-    const int splits = B.splits(ceil_div(L, 64) * ceil_div(w, 64), kt);
+    const int splits = B.splits(gb, ceil_div(L, 64) * ceil_div(w, 64), kt);
     gb.add(H, out_f64, L, 0, (int)L, (int)w, 1, 0, sg, splits);
   }
 }
@@ -738,7 +799,7 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
         tiles0 += ceil_div(P.r(i, k), 64) * ceil_div(P.ow[k], 64);
         kt = std::max<int64_t>(kt, ceil_div(P.dims[k], ts64 ? 16 : 32));
       }
-    const int splits = B.splits(tiles0, kt);
+    const int splits = B.splits(gb, tiles0, kt);
     for (int i = 0; i < s; ++i)
       for (int k = 0; k < d; ++k) {
         const int64_t n = P.dims[k], r = P.r(i, k), m = P.ow[k];
@@ -766,7 +827,8 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
       }
     // the Khatri-Rao expansion makes a KRP K-tile costly, so several rounds
     // of short workgroups beat one round of long ones
-    const int splits = B.splits(tiles0, ktmax, 1024);
+    const int splits = B.krp_splits(P.ps, tiles0, ktmax);
+    const int kw_max = B.krp_kw(P.ps, tiles0, ktmax);
     int64_t& tiles = B.krp_tiles;
     const size_t kd_first = kd.size();
     for (int i = 0; i < s; ++i)
@@ -792,7 +854,7 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
         const int sp = (int)std::min<int64_t>(splits, std::max<int64_t>(1, ceil_div(Kc, ts64 ? 16 : 32) / 2));
         D.splits = sp;
         D.V = v;
-        D.strideSplit = 0;
+        D.kw_max = kw_max;
         D.part = nullptr;
             if (sp > 1) {
           const int64_t ntiles = (int64_t)D.tiles_m * D.tiles_n;
@@ -919,7 +981,7 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
       for (int i = 0; i < s; ++i) ktn += ceil_div(P.r(i, n), bk);
       kt = std::max(kt, ktn);
     }
-    const int splits = B.splits(tiles0, kt);
+    const int splits = B.splits(gb, tiles0, kt);
     for (int n = 0; n < d; ++n) {
       const int64_t nn = P.dims[n];
       std::vector<GemmSeg> sg;
@@ -990,10 +1052,12 @@ void Builder::emit(Program& prog) {
     st.count = (int)krp.size();
     st.tiles = krp_tiles;
     st.krp_lds = krp_lds_elems(krp.data(), krp.size());
+    st.keys = krp_keys;
     prog.steps.push_back(st);
     if (!krp_red.empty()) {
       Step r{};
       r.kind = S_TILE_REDUCE;
+      r.keys = krp_keys;
       for (const ReduceJob& J : krp_red)
         r.bytes += (double)J.rows * J.cols * (J.parts + 1) * (J.out_f64 ? 8 : 4);
       r.meta = prog.put(krp_red);
@@ -1183,6 +1247,7 @@ void build_backward(const Problem& P, const BackwardIO& io, Arena& ar, Program& 
     D.tiles_m = (int)ceil_div(P.r(i, mode), 64);
     D.tiles_n = (int)ceil_div(m, 64);
     D.splits = 1;
+    D.kw_max = 4;
     D.V = out;
     D.tile_begin = tiles;
     tiles += (int64_t)D.tiles_m * D.tiles_n;
@@ -1636,7 +1701,8 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
     if (e != hipSuccess) return fail(h, TSK_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     if (ev1 != nullptr) {
       if (hipEventRecord(ev1, stream) != hipSuccess) return fail(h, TSK_ERR_DEVICE, "hipEventRecord failed");
-      h->prof_records.push_back(ProfRecord{step_name(st), ev0, ev1, st.flops, st.bytes});
+      h->prof_records.push_back(
+          ProfRecord{step_name(st), ev0, ev1, st.flops, st.bytes, (int)(&st - prog.steps.data())});
     }
   }
   return TSK_OK;
@@ -1652,6 +1718,7 @@ tsk_status plan_many(tsk_handle h, const std::vector<Problem>& Ps, const std::ve
     Program p0;
     Builder B0(a0);
     B0.nsums = (int)Ps.size();
+    B0.th = h;
     for (size_t j = 0; j < Ps.size(); ++j) build_sum(Ps[j], outs[j], B0);
     nctr = a0.ctr_used;
     if (!a0.too_far.empty()) return fail(h, TSK_ERR_UNSUPPORTED, "%s", a0.too_far.c_str());
@@ -1662,6 +1729,7 @@ tsk_status plan_many(tsk_handle h, const std::vector<Problem>& Ps, const std::ve
   Builder B(ar);
   B.nsums = (int)Ps.size();
   B.d_counter = h ? h->d_counter : nullptr;
+  B.th = h;
   for (size_t j = 0; j < Ps.size(); ++j) build_sum(Ps[j], outs[j], B);
   B.emit(prog);
   prog.meta_region = align_up(ar.top, 256);
@@ -1683,6 +1751,7 @@ tsk_status plan_project(tsk_handle h, const Problem& P, const std::vector<const 
   ar.ctr_base = (int32_t*)ar.take(256);
   Builder B(ar);
   B.d_counter = h ? h->d_counter : nullptr;
+  B.th = h;
   build_projection(P, Q, q_f64, P.cores, P.factors, P.in_f64, H, out_f64, B);
   if (!ar.too_far.empty()) return fail(h, TSK_ERR_UNSUPPORTED, "%s", ar.too_far.c_str());
   B.emit(prog);
@@ -3148,6 +3217,13 @@ tsk_status tsk_create(tsk_handle* handle, int device) {
   tsk_handle h = new (std::nothrow) tsk_handle_();
   if (h == nullptr) return TSK_ERR_OUT_OF_MEMORY;
   h->device = device;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+      h->arch = prop.gcnArchName;
+      h->arch = h->arch.substr(0, h->arch.find(':'));
+    }
+  }
   if (hipSetDevice(device) != hipSuccess || hipMalloc((void**)&h->d_counter, 256) != hipSuccess) {
     delete h;
     return TSK_ERR_DEVICE;
@@ -3838,6 +3914,373 @@ tsk_status tucker_sum_recompress_batched(tsk_handle h, int32_t batch, const tsk_
     return fail(h, TSK_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu needed", ws_bytes, need);
   if ((st = set_device(h)) != TSK_OK) return st;
   return run_program(h, prog, (char*)ws, (hipStream_t)stream);
+}
+
+// ---- autotuning: measured choices of the planner's launch parameters
+static const char* prec_name(int p) {
+  switch (p) {
+    case P_FP64: return "fp64";
+    case P_FP32: return "fp32";
+    case P_BF16X1: return "bf16x1";
+    case P_BF16X3: return "bf16x3";
+    case P_BF16X6: return "bf16x6";
+  }
+  return "?";
+}
+
+static const char* tune_kernel_name(int cls) {
+  return (cls == kTuneKrpSplit || cls == kTuneKrpKw) ? "krp_core_sketch" : role_name(cls);
+}
+
+static const char* tune_param_name(int cls) {
+  return cls == kTuneKrpKw ? "waves_per_quadrant" : "split_target";
+}
+
+static std::string tune_dump(const std::map<uint32_t, TuneEntry>& t, const std::string& arch) {
+  std::string js = "{\n  \"arch\": \"" + arch + "\",\n  \"entries\": [";
+  bool first = true;
+  for (const auto& kv : t) {
+    const uint32_t k = kv.first;
+    const int cls = (k >> 20) & 31, prec = (k >> 16) & 15, tl = (k >> 8) & 255, kl = k & 255;
+    char line[512];
+    snprintf(line, sizeof line,
+             "%s\n    {\"kernel\": \"%s\", \"param\": \"%s\", \"prec\": \"%s\", \"tiles_log2\": %d, "
+             "\"ktiles_log2\": %d, \"value\": %d, \"us\": %.3f}",
+             first ? "" : ",", tune_kernel_name(cls), tune_param_name(cls), prec_name(prec), tl, kl,
+             kv.second.value, kv.second.us);
+    js += line;
+    first = false;
+  }
+  js += "\n  ]\n}\n";
+  return js;
+}
+
+// Reads the text tune_dump writes (keys in any order, any whitespace).
+// Fails, leaving `out` untouched, on malformed input, an unknown kernel,
+// parameter or precision, a value outside its range, or another arch.
+static bool tune_parse(const std::string& text, const std::string& arch,
+                std::map<uint32_t, TuneEntry>& out, std::string& err) {
+  size_t i = 0;
+  const size_t n = text.size();
+  auto ws = [&]() {
+    while (i < n && (text[i] == ' ' || text[i] == '\n' || text[i] == '\t' || text[i] == '\r')) ++i;
+  };
+  auto expect = [&](char c) {
+    ws();
+    if (i < n && text[i] == c) {
+      ++i;
+      return true;
+    }
+    err = std::string("expected '") + c + "' at offset " + std::to_string(i);
+    return false;
+  };
+  auto str = [&](std::string& v) {
+    if (!expect('"')) return false;
+    const size_t b = i;
+    while (i < n && text[i] != '"') ++i;
+    if (i >= n) {
+      err = "unterminated string";
+      return false;
+    }
+    v = text.substr(b, i - b);
+    ++i;
+    return true;
+  };
+  auto num = [&](double& v) {
+    ws();
+    const char* b = text.c_str() + i;
+    char* e = nullptr;
+    v = std::strtod(b, &e);
+    if (e == b) {
+      err = "expected a number at offset " + std::to_string(i);
+      return false;
+    }
+    i += (size_t)(e - b);
+    return true;
+  };
+  std::map<uint32_t, TuneEntry> table;
+  std::string file_arch;
+  bool have_entries = false;
+  if (!expect('{')) return false;
+  for (;;) {
+    std::string key;
+    if (!str(key) || !expect(':')) return false;
+    if (key == "arch") {
+      if (!str(file_arch)) return false;
+    } else if (key == "entries") {
+      have_entries = true;
+      if (!expect('[')) return false;
+      ws();
+      if (i < n && text[i] == ']') {
+        ++i;
+      } else {
+        for (;;) {
+          if (!expect('{')) return false;
+          std::string kernel, param, prec;
+          double tl = -1, kl = -1, value = -1, us = 0;
+          for (;;) {
+            std::string f;
+            if (!str(f) || !expect(':')) return false;
+            bool ok = true;
+            if (f == "kernel") ok = str(kernel);
+            else if (f == "param") ok = str(param);
+            else if (f == "prec") ok = str(prec);
+            else if (f == "tiles_log2") ok = num(tl);
+            else if (f == "ktiles_log2") ok = num(kl);
+            else if (f == "value") ok = num(value);
+            else if (f == "us") ok = num(us);
+            else {
+              err = "unknown field " + f;
+              return false;
+            }
+            if (!ok) return false;
+            ws();
+            if (i < n && text[i] == ',') {
+              ++i;
+              continue;
+            }
+            if (!expect('}')) return false;
+            break;
+          }
+          int cls = -1;
+          if (kernel == "krp_core_sketch")
+            cls = param == "split_target" ? kTuneKrpSplit
+                  : param == "waves_per_quadrant" ? kTuneKrpKw : -1;
+          else if (param == "split_target")
+            for (int r = 0; r < R_OTHER; ++r)
+              if (kernel == role_name(r)) cls = r;
+          int pc = -1;
+          for (int q = 0; q <= P_BF16X6; ++q)
+            if (prec == prec_name(q)) pc = q;
+          if (cls < 0 || pc < 0) {
+            err = "unknown kernel, parameter or precision: " + kernel + " " + param + " " + prec;
+            return false;
+          }
+          const bool kw = cls == kTuneKrpKw;
+          if (tl < 0 || tl > 62 || kl < 0 || kl > 62 || tl != (int)tl || kl != (int)kl ||
+              (kw ? !(value == 1 || value == 2 || value == 4) : !(value >= 1 && value <= 65536)) ||
+              value != (int)value) {
+            err = "entry for " + kernel + " out of range";
+            return false;
+          }
+          const uint32_t k = (uint32_t)cls << 20 | (uint32_t)pc << 16 | (uint32_t)tl << 8 | (uint32_t)kl;
+          table[k] = TuneEntry{(int)value, us};
+          ws();
+          if (i < n && text[i] == ',') {
+            ++i;
+            continue;
+          }
+          if (!expect(']')) return false;
+          break;
+        }
+      }
+    } else {
+      err = "unknown key " + key;
+      return false;
+    }
+    ws();
+    if (i < n && text[i] == ',') {
+      ++i;
+      continue;
+    }
+    if (!expect('}')) return false;
+    break;
+  }
+  if (!have_entries) {
+    err = "no entries";
+    return false;
+  }
+  if (file_arch != arch) {
+    err = "cache is for '" + file_arch + "', the device is '" + arch + "'";
+    return false;
+  }
+  out = table;
+  return true;
+}
+
+// Median time (ms) of every launch of `prog` over `reps` runs after one
+// warm-up run.
+static tsk_status time_steps(tsk_handle h, Program& prog, char* ws, hipStream_t s, int reps,
+                             std::vector<double>& med) {
+  const bool was = h->prof;
+  std::vector<std::vector<double>> samples(prog.steps.size());
+  auto recycle = [&]() {
+    for (auto& r : h->prof_records) {
+      h->event_pool.push_back(r.begin);
+      h->event_pool.push_back(r.end);
+    }
+    h->prof_records.clear();
+  };
+  recycle();
+  h->prof = true;
+  tsk_status st = TSK_OK;
+  for (int r = 0; r <= reps && st == TSK_OK; ++r) {
+    st = run_program(h, prog, ws, s);
+    if (st == TSK_OK && hipStreamSynchronize(s) != hipSuccess)
+      st = fail(h, TSK_ERR_DEVICE, "stream synchronisation failed");
+    if (st == TSK_OK && r > 0)
+      for (auto& rec : h->prof_records) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, rec.begin, rec.end) != hipSuccess) {
+          st = fail(h, TSK_ERR_DEVICE, "hipEventElapsedTime failed");
+          break;
+        }
+        if (rec.step >= 0 && rec.step < (int)samples.size()) samples[rec.step].push_back(ms);
+      }
+    recycle();
+  }
+  h->prof = was;
+  if (st != TSK_OK) return st;
+  med.assign(prog.steps.size(), 0.0);
+  for (size_t j = 0; j < samples.size(); ++j) {
+    auto& v = samples[j];
+    if (v.empty()) continue;
+    std::sort(v.begin(), v.end());
+    med[j] = v[v.size() / 2];
+  }
+  return TSK_OK;
+}
+
+// One tuning pass: every candidate value forced on every class of the pass
+// at once (the launches of different classes do not share their choices),
+// each class then keeping the value under which its launches were fastest.
+static tsk_status tune_pass(tsk_handle h, const std::vector<Problem>& Ps,
+                            const std::vector<Outputs>& outs, hipStream_t s, int reps, bool kw_pass,
+                            char*& ws, size_t& cap, std::map<uint32_t, TuneEntry>& best) {
+  static const int kSplitTargets[] = {128, 256, 512, 1024, 2048, 4096};
+  static const int kKw[] = {1, 4};
+  const int* cand = kw_pass ? kKw : kSplitTargets;
+  const int ncand = kw_pass ? 2 : 6;
+  tsk_status st = TSK_OK;
+  for (int c = 0; c < ncand && st == TSK_OK; ++c) {
+    h->force_split = kw_pass ? 0 : cand[c];
+    h->force_kw = kw_pass ? cand[c] : 0;
+    Program p0, prog;
+    size_t need = 0;
+    if ((st = plan_many(h, Ps, outs, nullptr, p0, &need)) != TSK_OK) break;
+    if (need > cap) {
+      if (ws != nullptr && hipFree(ws) != hipSuccess) {
+        st = fail(h, TSK_ERR_DEVICE, "hipFree failed");
+        break;
+      }
+      ws = nullptr;
+      cap = 0;
+      if (hipMalloc((void**)&ws, need) != hipSuccess) {
+        st = fail(h, TSK_ERR_OUT_OF_MEMORY, "tuning workspace of %zu bytes", need);
+        break;
+      }
+      cap = need;
+    }
+    if ((st = plan_many(h, Ps, outs, ws, prog, &need)) != TSK_OK) break;
+    std::vector<double> med;
+    if ((st = time_steps(h, prog, ws, s, reps, med)) != TSK_OK) break;
+    std::map<uint32_t, double> cost;
+    for (size_t j = 0; j < prog.steps.size(); ++j)
+      for (uint32_t k : prog.steps[j].keys)
+        if ((((k >> 20) & 31) == kTuneKrpKw) == kw_pass) cost[k] += med[j];
+    for (const auto& kv : cost) {
+      auto it = best.find(kv.first);
+      const double us = kv.second * 1e3;
+      if (it == best.end() || us < it->second.us) best[kv.first] = TuneEntry{cand[c], us};
+    }
+  }
+  h->force_split = 0;
+  h->force_kw = 0;
+  return st;
+}
+
+tsk_status tsk_autotune(tsk_handle h, int32_t batch, const tsk_tucker_sum* sums,
+                        const tsk_sketch_spec* specs, void* const* const* Q_out,
+                        void* const* H_out, tsk_dtype out_dtype, int32_t reps, void* stream) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->err.clear();
+  if (reps < 1 || reps > 100) return fail(h, TSK_ERR_INVALID_ARG, "reps must be in [1, 100]");
+  std::vector<Problem> Ps;
+  tsk_status st = validate_batch(h, batch, sums, specs, Ps);
+  if (st != TSK_OK) return st;
+  if (Q_out == nullptr || H_out == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "Q_out or H_out is NULL");
+  if (out_dtype != TSK_F64 && out_dtype != TSK_F32) return fail(h, TSK_ERR_INVALID_ARG, "bad out_dtype");
+  std::vector<Outputs> outs(batch);
+  for (int b = 0; b < batch; ++b) {
+    outs[b].recompress = true;
+    outs[b].out_f64 = out_dtype == TSK_F64;
+    if (Q_out[b] == nullptr || H_out[b] == nullptr)
+      return fail(h, TSK_ERR_INVALID_ARG, "Q_out[%d] or H_out[%d] is NULL", b, b);
+    outs[b].H = H_out[b];
+    for (int n = 0; n < Ps[b].d; ++n) {
+      if (Q_out[b][n] == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "Q_out[%d][%d] is NULL", b, n);
+      outs[b].Q.push_back(Q_out[b][n]);
+    }
+  }
+  if ((st = set_device(h)) != TSK_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = nullptr;
+  size_t cap = 0;
+  std::map<uint32_t, TuneEntry> split_best, kw_best;
+  // the measured classes start from the planner's defaults, so that the
+  // split pass sees the default quadrant sharing and vice versa
+  std::map<uint32_t, TuneEntry> saved = h->tune;
+  st = tune_pass(h, Ps, outs, s, reps, false, ws, cap, split_best);
+  if (st == TSK_OK) {
+    for (const auto& kv : split_best) h->tune[kv.first] = kv.second;
+    st = tune_pass(h, Ps, outs, s, reps, true, ws, cap, kw_best);
+  }
+  if (st == TSK_OK)
+    for (const auto& kv : kw_best) h->tune[kv.first] = kv.second;
+  else
+    h->tune = saved;
+  if (hipStreamSynchronize(s) != hipSuccess && st == TSK_OK)
+    st = fail(h, TSK_ERR_DEVICE, "stream synchronisation failed");
+  if (ws != nullptr && hipFree(ws) != hipSuccess && st == TSK_OK)
+    st = fail(h, TSK_ERR_DEVICE, "hipFree failed");
+  return st;
+}
+
+// Host-only check of the tuning cache format (tests; not part of the ABI
+// header): parse `json` for `arch` and write the table back as text.
+int tsk_tune_json_check(const char* json, const char* arch, char* out, size_t outlen) {
+  if (json == nullptr || arch == nullptr || out == nullptr || outlen == 0) return TSK_ERR_INVALID_ARG;
+  std::map<uint32_t, TuneEntry> table;
+  std::string err;
+  const bool ok = tune_parse(json, arch, table, err);
+  const std::string text = ok ? tune_dump(table, arch) : err;
+  std::strncpy(out, text.c_str(), outlen - 1);
+  out[outlen - 1] = 0;
+  return ok ? TSK_OK : TSK_ERR_INVALID_ARG;
+}
+
+tsk_status tsk_autotune_clear(tsk_handle h) {
+  if (h == nullptr) return TSK_ERR_INVALID_ARG;
+  h->tune.clear();
+  return TSK_OK;
+}
+
+tsk_status tsk_autotune_save(tsk_handle h, const char* path) {
+  if (h == nullptr || path == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL handle or path");
+  h->err.clear();
+  const std::string js = tune_dump(h->tune, h->arch);
+  FILE* f = std::fopen(path, "w");
+  if (f == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "cannot open %s for writing", path);
+  const bool ok = std::fwrite(js.data(), 1, js.size(), f) == js.size();
+  if (std::fclose(f) != 0 || !ok) return fail(h, TSK_ERR_INVALID_ARG, "writing %s failed", path);
+  return TSK_OK;
+}
+
+tsk_status tsk_autotune_load(tsk_handle h, const char* path) {
+  if (h == nullptr || path == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "NULL handle or path");
+  h->err.clear();
+  FILE* f = std::fopen(path, "r");
+  if (f == nullptr) return fail(h, TSK_ERR_INVALID_ARG, "cannot open %s", path);
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  std::map<uint32_t, TuneEntry> table;
+  std::string err;
+  if (!tune_parse(text, h->arch, table, err)) return fail(h, TSK_ERR_INVALID_ARG, "%s: %s", path, err.c_str());
+  h->tune = table;
+  return TSK_OK;
 }
 
 static tsk_status backward_io(tsk_handle h, const Problem& P, const void* const* Q,
