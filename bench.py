@@ -194,13 +194,17 @@ def profile_report(lib, _lib, h, fn, steps):
 
 
 def csrc_digest():
-    """Digest of the kernel sources: HBM counters taken on other sources no
-    longer describe the kernels."""
+    """Digest of the kernel sources and of the launch-parameter cache: HBM
+    counters taken on other kernels or other plans no longer describe the
+    launches."""
     d = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_13532_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         with open(os.path.join(csrc, f), "rb") as fh:
             d.update(f.encode() + fh.read())
+    if os.path.exists(TUNE_CACHE):
+        with open(TUNE_CACHE, "rb") as fh:
+            d.update(b"tune" + fh.read())
     return d.hexdigest()[:16]
 
 
