@@ -11,10 +11,16 @@
 // the rotations (one lane per pair, Golub and Van Loan's symmetric 2 x 2
 // Schur form), then every 2 x 2 block (row pair, column pair) of A is
 // replaced by J1^T A J2 and every row of V by its row times J, in one pass.
-// A pair is left alone once |a_pq| <= tol sqrt(|a_pp a_qq|); the
-// decomposition has converged when a sweep rotates no pair (for a positive
-// semidefinite matrix this threshold gives the small eigenvalues relative
-// accuracy).  Eigenvalues are then sorted in decreasing order (rank of each
+// A pair is left alone once |a_pq| <= tol sqrt(|a_pp a_qq|), or once both
+// of its diagonal entries and a_pq are at the rounding level of the largest
+// diagonal entry d (|a_pq| <= tol d and a_pp, a_qq <= 64 tol d); the
+// decomposition has converged when a sweep rotates no pair.  The relative
+// test gives a positive semidefinite matrix's small eigenvalues (and their
+// eigenvectors) relative accuracy; the second test stops the rotations
+// inside a rank-deficient Gram's near-null block, whose entries are the
+// rounding noise of the Gram's formation and would otherwise keep sweeps
+// going, while every pair with a diagonal entry above that level (a kept
+// direction) is still rotated.  Eigenvalues are then sorted in decreasing order (rank of each
 // by counting), with their eigenvectors, and the rank rule is applied:
 // r = the smallest r >= 1 whose discarded eigenvalue sum is <= theta.
 #include <hip/hip_runtime.h>
@@ -52,12 +58,22 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigJob* _
   int* pr = (int*)(cs + 2 * half);  // p, q per pair
   __shared__ int s_rotated;
 
+  __shared__ double s_dmax[kEigThreads / 64];
   for (int e = t; e < Wp * Wp; e += kEigThreads) {
     const int i = e % Wp, j = e / Wp;
     A[e] = (i < W && j < W) ? J.C[i + (int64_t)J.ldc * j] : 0.0;
     V[e] = i == j ? 1.0 : 0.0;
   }
+  // the largest diagonal entry (>= every |a_pq| of a positive semidefinite
+  // matrix), the scale of the Gram's rounding noise
+  double dm = 0.0;
+  for (int i = t; i < W; i += kEigThreads) dm = fmax(dm, fabs(J.C[i + (int64_t)J.ldc * i]));
+  for (int off = 32; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off));
+  if ((t & 63) == 0) s_dmax[t >> 6] = dm;
   __syncthreads();
+  double floor_apq = 0.0;
+  for (int w = 0; w < kEigThreads / 64; ++w) floor_apq = fmax(floor_apq, s_dmax[w]);
+  floor_apq *= J.tol;
 
   for (int sweep = 0; sweep < kEigMaxSweeps; ++sweep) {
     if (t == 0) s_rotated = 0;
@@ -73,7 +89,9 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigJob* _
         double c = 1.0, s = 0.0;
         if (q < W) {
           const double app = A[p + Wp * p], aqq = A[q + Wp * q], apq = A[p + Wp * q];
-          if (fabs(apq) > J.tol * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
+          if (fabs(apq) > J.tol * sqrt(fabs(app * aqq)) &&
+              (fabs(apq) > floor_apq || fmax(fabs(app), fabs(aqq)) > 64.0 * floor_apq) &&
+              fabs(apq) > 1e-300) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
