@@ -1711,18 +1711,11 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
 // Plan into a null-based arena to size the workspace, then rebase.
 tsk_status plan_many(tsk_handle h, const std::vector<Problem>& Ps, const std::vector<Outputs>& outs,
                      char* ws, Program& prog, size_t* bytes) {
-  // first pass counts the zero-initialised words, the second places them first
+  // the per-mode QR flag words come first: one per mode of every sum whose
+  // QR is planned
   int64_t nctr = 0;
-  {
-    Arena a0;
-    Program p0;
-    Builder B0(a0);
-    B0.nsums = (int)Ps.size();
-    B0.th = h;
-    for (size_t j = 0; j < Ps.size(); ++j) build_sum(Ps[j], outs[j], B0);
-    nctr = a0.ctr_used;
-    if (!a0.too_far.empty()) return fail(h, TSK_ERR_UNSUPPORTED, "%s", a0.too_far.c_str());
-  }
+  for (size_t j = 0; j < Ps.size(); ++j)
+    if (outs[j].recompress) nctr += Ps[j].d;
   Arena ar;
   ar.base = ws;
   ar.ctr_base = (int32_t*)ar.take(sizeof(int32_t) * std::max<int64_t>(nctr, 1));
@@ -1731,6 +1724,9 @@ tsk_status plan_many(tsk_handle h, const std::vector<Problem>& Ps, const std::ve
   B.d_counter = h ? h->d_counter : nullptr;
   B.th = h;
   for (size_t j = 0; j < Ps.size(); ++j) build_sum(Ps[j], outs[j], B);
+  if (!ar.too_far.empty()) return fail(h, TSK_ERR_UNSUPPORTED, "%s", ar.too_far.c_str());
+  if (ar.ctr_used != nctr) return fail(h, TSK_ERR_DEVICE, "QR flag words planned %lld, placed %lld",
+                                      (long long)ar.ctr_used, (long long)nctr);
   B.emit(prog);
   prog.meta_region = align_up(ar.top, 256);
   *bytes = prog.meta_region + align_up(prog.blob.size(), 256) + 256;

@@ -9,8 +9,8 @@ and `scales` maps each velocity-factor name to a device vector over the
 xi_x grid (xi+ = max(xi_x, 0), xi- = min(xi_x, 0) for upwind fluxes).  A
 term is the source node's Tucker tensor with its first factor's rows
 multiplied by that vector (diag(scale) U_1), which is a Tucker tensor of
-the same ranks; it is formed once per (node, factor) and shared by every sum
-that uses it.  The sums of a step are independent, so each stage of the
+the same ranks; every node's scaled first factor comes from one scaling of
+all first factors side by side, and is shared by every sum that uses it.  The sums of a step are independent, so each stage of the
 sketched sum (Stage 1 sizes, Stages 2-3, Stage 4) runs as one batched
 launch sequence over all nodes.
 """
@@ -23,7 +23,15 @@ def euler_sums(states, terms, scales):
     """The per-node update sums of one step as dicts of cores, factors and
     coefficients (the input of sketch_sum_batched).  `states[a]` is the
     (core, [U_1, U_2, U_3]) of node a, float64 on the device."""
-    scaled = {}
+    # every node's first factor side by side (one column-major matrix), then
+    # one scaling per velocity factor; each node's scaled factor is a view
+    u1s = [fortran(us[0]) for _, us in states]
+    cols = [0]
+    for u in u1s:
+        cols.append(cols[-1] + u.shape[1])
+    stacked = torch.cat([u.t() for u in u1s], dim=0).t()
+    scaled_all = {kind: stacked * v.unsqueeze(1) for kind, v in scales.items()}
+    views = {}
     sums = []
     for tl in terms:
         cores, facs, coeffs = [], [], []
@@ -33,9 +41,9 @@ def euler_sums(states, terms, scales):
                 u1 = us[0]
             else:
                 key = (src, kind)
-                if key not in scaled:
-                    scaled[key] = fortran(scales[kind].unsqueeze(1) * us[0])
-                u1 = scaled[key]
+                if key not in views:
+                    views[key] = scaled_all[kind][:, cols[src]:cols[src + 1]]
+                u1 = views[key]
             cores.append(g)
             facs.append([u1] + list(us[1:]))
             coeffs.append(float(c))
