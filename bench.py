@@ -623,9 +623,9 @@ def torch_f64():
 
 
 def cpu_baseline(sums, seconds):
-    """The oracle on the host cores: as many sums of the batch (in order) as
-    fit in `seconds`, with the BLAS thread pool at its default, then again
-    single-threaded."""
+    """The oracle on the host cores: sums of the batch in order (passing over
+    the batch again when it runs out) until `seconds` of CPU time are spent,
+    with the BLAS thread pool at its default, then again single-threaded."""
     from oracle import recompress as RC
     try:
         from threadpoolctl import threadpool_info, threadpool_limits
@@ -634,8 +634,8 @@ def cpu_baseline(sums, seconds):
 
     def run(limit):
         done, t_tot = 0, 0.0
-        while t_tot < seconds and done < len(sums):
-            one = sums[done]
+        while t_tot < seconds:
+            one = sums[done % len(sums)]
             t0 = time.perf_counter()
             RC.recompress(one, "krp", [one["ell"][0]], one["omega_seed"])
             t_tot += time.perf_counter() - t0
@@ -650,7 +650,7 @@ def cpu_baseline(sums, seconds):
         with threadpool_limits(limits=1):
             d1, t1 = run(1)
         single = {"value": d1 / t1, "unit": "recompressions/s", "cores": 1,
-                  "sample": f"first {d1} sums of the batch, {t1:.1f} s"}
+                  "sample": f"{d1} sums of the batch in order, {t1:.1f} s"}
     cpu_model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -661,8 +661,9 @@ def cpu_baseline(sums, seconds):
     except OSError:
         pass
     return {"value": done / t, "unit": "recompressions/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {done} of the 256 sums of the batch workload (FP64 NumPy oracle, "
-                      f"structured path), {t:.1f} s of CPU time",
+            "sample": f"{done} sums of the 256-sum batch workload in order, passing over it "
+                      f"{done / len(sums):.1f} times (FP64 NumPy oracle, structured path), "
+                      f"{t:.1f} s of CPU time",
             "cpu_model": cpu_model, "nproc": os.cpu_count(), "single_thread": single}
 
 

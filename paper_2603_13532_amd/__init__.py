@@ -422,36 +422,50 @@ def _subranks_batched(ms, eps, p):
 def tucker_truncate_batched(jobs, eps):
     """Stage 4 for many cores at once: `jobs` is a list of (Q list, H) pairs
     (FP64, as tucker_truncate takes them).  Returns a list of (G, [U..],
-    ranks)."""
+    ranks).  The outputs of all jobs share one allocation; the ctypes
+    arguments are flat arrays with one entry per (job, mode)."""
     dev = jobs[0][1].device
     h = Handle.get(dev)
-    keep, structs, outs = [], [], []
-    shapes = []
+    Qs, Hs, ds = [], [], []
     for Q, H in jobs:
-        widths = [int(x) for x in H.shape]
-        total = 1
-        for w in widths:
-            total *= w
-        shapes += [(int(q.shape[0]), w) for q, w in zip(Q, widths)] + [(total,)]
-    bufs = carve_fortran(shapes, torch.float64, dev)
-    at = 0
-    for Q, H in jobs:
-        d = H.dim()
-        Qf = [fortran(q.to(torch.float64)) for q in Q]
-        Hf = fortran(H.to(torch.float64))
-        dims = [int(q.shape[0]) for q in Qf]
-        widths = [int(x) for x in Hf.shape]
-        if [int(q.shape[1]) for q in Qf] != widths:
-            raise ValueError("Q_k must have as many columns as H has entries along mode k")
-        U, G = bufs[at:at + d], bufs[at + d]
-        at += d + 1
-        arrs = ((c_int64 * d)(*dims), (c_int64 * d)(*widths),
-                (c_void_p * d)(*[q.data_ptr() for q in Qf]),
-                (c_void_p * d)(*[u.data_ptr() for u in U]), (c_int32 * d)())
-        keep.append((Qf, Hf, arrs))
-        structs.append(_lib.Truncation(d, arrs[0], arrs[1], arrs[2], Hf.data_ptr(), float(eps),
-                                       arrs[3], G.data_ptr(), arrs[4]))
-        outs.append((G, U, arrs[4]))
+        Qs.append([fortran(q if q.dtype == torch.float64 else q.to(torch.float64)) for q in Q])
+        Hs.append(fortran(H if H.dtype == torch.float64 else H.to(torch.float64)))
+        ds.append(H.dim())
+    tot = sum(ds)
+    dims = [int(q.shape[0]) for qs in Qs for q in qs]
+    widths = [int(x) for hh in Hs for x in hh.shape]
+    if [int(q.shape[1]) for qs in Qs for q in qs] != widths:
+        raise ValueError("Q_k must have as many columns as H has entries along mode k")
+    # element offsets of every U_k (n_k x w_k) and G (prod w_k), 256-byte aligned
+    offs, top, at = [], 0, 0
+    for d in ds:
+        o = []
+        size = 1
+        for k in range(d):
+            o.append(top)
+            top += (dims[at + k] * widths[at + k] + 31) // 32 * 32
+            size *= widths[at + k]
+        o.append(top)
+        top += (size + 31) // 32 * 32
+        offs.append(o)
+        at += d
+    buf = torch.empty(max(top, 1), dtype=torch.float64, device=dev)
+    base = buf.data_ptr()
+    c_dims = (c_int64 * tot)(*dims)
+    c_w = (c_int64 * tot)(*widths)
+    c_q = (c_void_p * tot)(*[q.data_ptr() for qs in Qs for q in qs])
+    c_u = (c_void_p * tot)(*[base + 8 * x for o, d in zip(offs, ds) for x in o[:d]])
+    c_r = (c_int32 * tot)()
+    P64, PV, P32 = POINTER(c_int64), POINTER(c_void_p), POINTER(c_int32)
+    a_dims, a_w = ctypes.addressof(c_dims), ctypes.addressof(c_w)
+    a_q, a_u, a_r = ctypes.addressof(c_q), ctypes.addressof(c_u), ctypes.addressof(c_r)
+    structs, at = [], 0
+    for d, hh, o in zip(ds, Hs, offs):
+        structs.append(_lib.Truncation(
+            d, ctypes.cast(a_dims + 8 * at, P64), ctypes.cast(a_w + 8 * at, P64),
+            ctypes.cast(a_q + 8 * at, PV), hh.data_ptr(), float(eps), ctypes.cast(a_u + 8 * at, PV),
+            base + 8 * o[d], ctypes.cast(a_r + 4 * at, P32)))
+        at += d
     B = len(structs)
     c_jobs = (_lib.Truncation * B)(*structs)
     nbytes = c_size_t()
@@ -459,10 +473,18 @@ def tucker_truncate_batched(jobs, eps):
     ws = h.workspace(nbytes.value)
     check(load().tucker_truncate_batched(h.ptr, B, c_jobs, c_void_p(ws.data_ptr()), ws.numel(),
                                          c_void_p(_stream_ptr(dev))), h.ptr)
-    res = []
-    for G, U, cr in outs:
-        r = list(cr)
-        res.append((_core_view(G, r), [u[:, :rk] for u, rk in zip(U, r)], r))
+    ranks = list(c_r)
+    res, at = [], 0
+    for d, o in zip(ds, offs):
+        r = ranks[at:at + d]
+        us = [buf.as_strided((dims[at + k], r[k]), (1, dims[at + k]), o[k]) for k in range(d)]
+        strides, st = [], 1
+        for x in r:
+            strides.append(st)
+            st *= x
+        res.append((buf.as_strided(tuple(r), tuple(strides), o[d]), us, r))
+        at += d
+    del Qs, Hs  # kept alive until the call above returned
     return res
 
 

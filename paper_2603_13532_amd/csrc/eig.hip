@@ -44,8 +44,10 @@ __device__ __forceinline__ int rr_index(int i, int r, int Wp) {
 // GLOBAL: the matrix and its eigenvectors live in the job's workspace (A at
 // J.work, Wp x Wp each) instead of LDS, for widths above kEigMaxW; the
 // rotation parameters stay in LDS.
-template <bool GLOBAL>
-__global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigJob* __restrict__ jobs) {
+// NT threads (64 for widths up to 16, whose rounds hold at most 64 block
+// updates: one wave, so the barriers cost nothing; else 512).
+template <bool GLOBAL, int NT>
+__global__ __launch_bounds__(NT) void jacobi_eig_kernel(const EigJob* __restrict__ jobs) {
   const EigJob J = jobs[blockIdx.x];
   const int W = J.W;
   const int Wp = W + (W & 1);
@@ -58,21 +60,21 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigJob* _
   int* pr = (int*)(cs + 2 * half);  // p, q per pair
   __shared__ int s_rotated;
 
-  __shared__ double s_dmax[kEigThreads / 64];
-  for (int e = t; e < Wp * Wp; e += kEigThreads) {
+  __shared__ double s_dmax[NT / 64];
+  for (int e = t; e < Wp * Wp; e += NT) {
     const int i = e % Wp, j = e / Wp;
     A[e] = (i < W && j < W) ? J.C[i + (int64_t)J.ldc * j] : 0.0;
-    V[e] = i == j ? 1.0 : 0.0;
+    if (!J.values_only) V[e] = i == j ? 1.0 : 0.0;
   }
   // the largest diagonal entry (>= every |a_pq| of a positive semidefinite
   // matrix), the scale of the Gram's rounding noise
   double dm = 0.0;
-  for (int i = t; i < W; i += kEigThreads) dm = fmax(dm, fabs(J.C[i + (int64_t)J.ldc * i]));
+  for (int i = t; i < W; i += NT) dm = fmax(dm, fabs(J.C[i + (int64_t)J.ldc * i]));
   for (int off = 32; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off));
   if ((t & 63) == 0) s_dmax[t >> 6] = dm;
   __syncthreads();
   double floor_apq = 0.0;
-  for (int w = 0; w < kEigThreads / 64; ++w) floor_apq = fmax(floor_apq, s_dmax[w]);
+  for (int w = 0; w < NT / 64; ++w) floor_apq = fmax(floor_apq, s_dmax[w]);
   floor_apq *= J.tol;
 
   for (int sweep = 0; sweep < kEigMaxSweeps; ++sweep) {
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigJob* _
       }
       __syncthreads();
       // A <- J^T A J, one 2 x 2 block (row pair k1, column pair k2) per item
-      for (int e = t; e < half * half; e += kEigThreads) {
+      for (int e = t; e < half * half; e += NT) {
         const int k1 = e % half, k2 = e / half;
         const int p1 = pr[2 * k1], q1 = pr[2 * k1 + 1], p2 = pr[2 * k2], q2 = pr[2 * k2 + 1];
         const double c1 = cs[2 * k1], s1 = cs[2 * k1 + 1], c2 = cs[2 * k2], s2 = cs[2 * k2 + 1];
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigJob* _
         A[q1 + Wp * q2] = s2 * rc + c2 * rd;
       }
       // V <- V J: row i, pair k
-      for (int e = t; e < Wp * half; e += kEigThreads) {
+      for (int e = t; e < (J.values_only ? 0 : Wp * half); e += NT) {
         const int i = e % Wp, k = e / Wp;
         const int p = pr[2 * k], q = pr[2 * k + 1];
         const double c = cs[2 * k], s = cs[2 * k + 1];
@@ -138,26 +140,24 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(const EigJob* _
     __syncthreads();
   }
 
-  // eigenvalues (clipped at zero when asked), their order, and the rank rule
-  double lam = 0.0;
-  int pos = 0;
-  if (t < W) {
-    lam = A[t + Wp * t];
+  // eigenvalues (clipped at zero when asked), their order, and the rank
+  // rule; sorted eigenvalues go to the (now free) rotation scratch (Wp
+  // doubles), every thread handling the eigenvalues t, t + NT, ...
+  double* sorted = cs;
+  __syncthreads();
+  for (int i = t; i < W; i += NT) {
+    double lam = A[i + Wp * i];
     if (J.clip) lam = fmax(lam, 0.0);
+    int pos = 0;
     for (int j = 0; j < W; ++j) {
       double lj = A[j + Wp * j];
       if (J.clip) lj = fmax(lj, 0.0);
-      pos += (lj > lam || (lj == lam && j < t)) ? 1 : 0;
+      pos += (lj > lam || (lj == lam && j < i)) ? 1 : 0;
     }
-  }
-  __syncthreads();
-  // sorted eigenvalues into the (now free) rotation scratch: Wp doubles
-  double* sorted = cs;
-  if (t < W) {
     sorted[pos] = lam;
     J.lam[pos] = lam;
   }
-  for (int e = t; e < W * W; e += kEigThreads) {
+  for (int e = t; e < (J.values_only ? 0 : W * W); e += NT) {
     const int i = e % W, j = e / W;  // row i of eigenvector j
     int pj = 0;
     double lj = A[j + Wp * j];
@@ -401,19 +401,23 @@ hipError_t launch_jacobi_eig(const EigJob* jobs, int count, int wmax, hipStream_
   if (wmax > kEigMaxW) {
     const int Wp = wmax + (wmax & 1);
     const size_t lds = (size_t)Wp * sizeof(double) + (size_t)Wp * sizeof(int);
-    jacobi_eig_kernel<true><<<dim3((unsigned)count), dim3(kEigThreads), lds, stream>>>(jobs);
+    jacobi_eig_kernel<true, kEigThreads><<<dim3((unsigned)count), dim3(kEigThreads), lds, stream>>>(jobs);
+    return hipGetLastError();
+  }
+  const size_t lds = jacobi_eig_lds(wmax);
+  if (wmax <= 16) {
+    jacobi_eig_kernel<false, 64><<<dim3((unsigned)count), dim3(64), lds, stream>>>(jobs);
     return hipGetLastError();
   }
   static bool attr_set = false;
   if (!attr_set) {
-    const hipError_t e = hipFuncSetAttribute((const void*)jacobi_eig_kernel<false>,
+    const hipError_t e = hipFuncSetAttribute((const void*)jacobi_eig_kernel<false, kEigThreads>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              (int)jacobi_eig_lds(kEigMaxW));
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  const size_t lds = jacobi_eig_lds(wmax);
-  jacobi_eig_kernel<false><<<dim3((unsigned)count), dim3(kEigThreads), lds, stream>>>(jobs);
+  jacobi_eig_kernel<false, kEigThreads><<<dim3((unsigned)count), dim3(kEigThreads), lds, stream>>>(jobs);
   return hipGetLastError();
 }
 

@@ -127,7 +127,8 @@ struct EigJob {
   double* work;
   int64_t ldc, ldv;
   double tol, theta_scale;
-  int32_t W, set_theta, clip, pad_;
+  int32_t W, set_theta, clip;
+  int32_t values_only;  // Jacobi: skip the eigenvectors (V neither formed nor written)
 };
 hipError_t launch_jacobi_eig(const EigJob* jobs, int count, int wmax, hipStream_t stream);
 // Eigenvalues only (lam, decreasing; no eigenvectors) of larger matrices,

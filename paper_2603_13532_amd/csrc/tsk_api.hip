@@ -2389,6 +2389,7 @@ static void plan_subranks(const std::vector<Problem>& Ps, double eps, Arena& ar,
       E.W = (int32_t)M.W;
       E.set_theta = 1;
       E.clip = 1;
+      E.values_only = 1;  // Stage 1 needs the eigenvalues only
       if (M.W <= kEigMaxW) {
         small.push_back(E);
         wsmall = std::max<int>(wsmall, (int)M.W);
