@@ -558,8 +558,8 @@ def ndg_leg(tsk, dev, steps):
     dt = 0.1 h / ((2k+1) Xi), from the rank-6 initial condition.  Every step
     recompresses the 64 node sums (9 Tucker terms each) with the batched
     sketched sum (KRP and Kronecker: batched Stage 1, Stages 2-3, Stage 4)
-    and, for comparison, with the deterministic baseline node by node, all
-    on the GPU.  Wall time per step (host included: sizes and ranks come back
+    and, for comparison, with the KRP sketched sum and with the
+    deterministic baseline node by node, all on the GPU.  Wall time per step (host included: sizes and ranks come back
     to the host), and the final states of the sketched runs against the
     deterministic one."""
     import torch
@@ -599,6 +599,17 @@ def ndg_leg(tsk, dev, steps):
         out[f"{kind}_final_sizes_max"] = [int(max(s_[k] for s_ in sizes))
                                           for k in range(len(sizes[0]))]
 
+    def per_node(x):
+        # the same sketched sums, one sum at a time (no batching across nodes)
+        new = []
+        for sm in gndg.euler_sums(x, terms, scales):
+            g, us, _, _ = tsk.sketch_sum(sm["cores"], sm["factors"], "krp", eps, p, 5,
+                                         coeffs=sm["coeffs"])
+            new.append((g, us))
+        return new, None
+    _, t, _ = run(per_node)
+    out["krp_node_by_node_ms_per_step"] = float(np.median(t))
+
     def det(x):
         new, ranks = gndg.euler_step_deterministic(x, terms, scales, eps)
         return new, ranks
@@ -612,7 +623,9 @@ def ndg_leg(tsk, dev, steps):
         out[f"{kind}_final_vs_deterministic_max"] = max(
             xhat_rel_diff(ga, ua, gb, ub) for (ga, ua), (gb, ub) in zip(finals[kind], states))
     log(f"NDG {nsteps} steps: krp {out['krp_ms_per_step']:.2f} ms/step, kron "
-        f"{out['kron_ms_per_step']:.2f}, deterministic {out['deterministic_ms_per_step']:.2f}; "
+        f"{out['kron_ms_per_step']:.2f}, krp node by node "
+        f"{out['krp_node_by_node_ms_per_step']:.2f}, deterministic node by node "
+        f"{out['deterministic_ms_per_step']:.2f}; "
         f"final krp vs deterministic {out['krp_final_vs_deterministic_max']:.1e}")
     return out
 

@@ -113,3 +113,26 @@ def test_truncate_fast_decay(tsk, eps):
     ranks = stage_alone(tsk, ts, "krp", [40], 9, eps)
     if eps >= 1e-4:
         assert max(ranks) < 40
+
+
+def test_truncate_width_above_the_thread_count(tsk):
+    """A mode wider than the eigensolver's 512 threads (global-memory Jacobi,
+    width 520): every eigenvalue enters the sort and the rank rule.  H is
+    520 x 4 x 3 with its first 508 mode-1 slices zero, so its mode-1 Gram has
+    rank 12 and its nonzero eigenvalues sit at diagonal positions 508..519,
+    past the first 512."""
+    import torch
+    rng = np.random.default_rng(31)
+    qs = [np.linalg.qr(rng.standard_normal((n, w)))[0] for n, w in ((600, 520), (10, 4), (9, 3))]
+    h = rng.standard_normal((520, 4, 3)) * (10.0 ** (-0.4 * np.arange(3)))[None, None, :]
+    h[:508] = 0.0
+    eps = 1e-3
+    g_ref, v_ref = RC.st_hosvd(h, eps)
+    u_ref = [q @ v for q, v in zip(qs, v_ref)]
+    qd = [torch.from_numpy(np.asfortranarray(q)).to(DEV) for q in qs]
+    hd = tsk.fortran(torch.from_numpy(np.asfortranarray(h)).to(DEV))
+    g, us, ranks = tsk.tucker_truncate(qd, hd, eps)
+    torch.cuda.synchronize()
+    assert tuple(ranks) == g_ref.shape, (ranks, g_ref.shape)
+    diff = tucker_rel_diff(np_of(g), [np_of(u) for u in us], g_ref, u_ref)
+    assert diff <= max(1e-12, condition_bound(h, ranks)), diff
