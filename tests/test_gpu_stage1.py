@@ -88,3 +88,26 @@ def test_sketch_sum_end_to_end(tsk, kind):
     x_err = RC.rel_err_tucker(np_of(g), [np_of(u) for u in us], ts)
     print(f"{kind}: sizes {sizes}, ranks {ranks}, error vs the sum {x_err:.2e}")
     assert x_err < 10 * eps
+
+
+def test_batched_subranks_match_oracle(tsk):
+    """tucker_sum_subranks_batched over sums of different shapes and orders of
+    magnitude in one launch sequence (widths below and above 96, so the LDS
+    Jacobi and the tridiagonal path share a call), FP64 and FP32 inputs."""
+    import torch
+    sums = [CASES[k]() for k in ("tiny", "ragged", "low_rank", "structured")] + \
+        synth.config_batch(count=24)[::3]
+    for one in sums:
+        one.setdefault("coeffs", np.ones(len(one["cores"])))
+    for dtype in (torch.float64, torch.float32):
+        batch = []
+        for one in sums:
+            cores, factors = to_torch(one, DEV, dtype)
+            batch.append({"cores": cores, "factors": factors, "coeffs": one["coeffs"]})
+        got = tsk.effective_subranks_batched(batch, 1e-3, 2)
+        for one, g in zip(sums, got):
+            ref = one if dtype == torch.float64 else {
+                **one, "cores": [c.astype(np.float32).astype(np.float64) for c in one["cores"]],
+                "factors": [[u.astype(np.float32).astype(np.float64) for u in us]
+                            for us in one["factors"]]}
+            assert g == RC.effective_subranks(ref, 1e-3, 2), (one["dims"], g)

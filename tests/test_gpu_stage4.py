@@ -136,3 +136,33 @@ def test_truncate_width_above_the_thread_count(tsk):
     assert tuple(ranks) == g_ref.shape, (ranks, g_ref.shape)
     diff = tucker_rel_diff(np_of(g), [np_of(u) for u in us], g_ref, u_ref)
     assert diff <= max(1e-12, condition_bound(h, ranks)), diff
+
+
+def test_truncate_batched_matches_oracle(tsk):
+    """tucker_truncate_batched over cores of different orders and widths in
+    one call (widths 7 to 120: LDS and global-memory Jacobi in the same
+    phases), each against the oracle's st_hosvd of that core alone."""
+    import torch
+    rng = np.random.default_rng(41)
+    shapes = [((60, 50, 40), (30, 20, 10)), ((200, 150, 130), (120, 40, 9)),
+              ((40, 30, 20, 25), (11, 11, 11, 7)), ((64, 64, 64), (25, 25, 25))]
+    jobs, refs = [], []
+    for dims, widths in shapes:
+        qs = [np.linalg.qr(rng.standard_normal((n, w)))[0] for n, w in zip(dims, widths)]
+        h = rng.standard_normal(widths)
+        for k, w in enumerate(widths):  # decaying spectra in every mode
+            sh = [1] * len(widths)
+            sh[k] = w
+            h = h * (10.0 ** (-0.15 * np.arange(w))).reshape(sh)
+        jobs.append(([torch.from_numpy(np.asfortranarray(q)).to(DEV) for q in qs],
+                     tsk.fortran(torch.from_numpy(np.asfortranarray(h)).to(DEV))))
+        refs.append((qs, h))
+    for eps in (1e-2, 1e-6):
+        out = tsk.tucker_truncate_batched(jobs, eps)
+        torch.cuda.synchronize()
+        for (qs, h), (g, us, ranks) in zip(refs, out):
+            g_ref, v_ref = RC.st_hosvd(h, eps)
+            assert tuple(ranks) == g_ref.shape, (ranks, g_ref.shape)
+            diff = tucker_rel_diff(np_of(g), [np_of(u) for u in us], g_ref,
+                                   [q @ v for q, v in zip(qs, v_ref)])
+            assert diff <= max(1e-12, condition_bound(h, ranks)), (eps, h.shape, diff)
