@@ -684,8 +684,10 @@ def cpu_baseline(sums, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): every GPU box "
-              "here has one GPU, and the path has no multi-GPU part to time", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the path is built "
+              "and timed on a single GPU; independent sums or the terms of one sum would be "
+              "sharded across GPUs as the design notes describe, and no multi-GPU figure is "
+              "measured", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
