@@ -1018,8 +1018,12 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
   if (!out.out_f64)
     for (int n = 0; n < d; ++n)
       cq.push_back(CopyJob{out.Q[n], Qd[n], P.dims[n], P.w[n], P.dims[n], P.dims[n], 0, 1});
-  std::vector<const void*> Qc(Qd.begin(), Qd.end());
-  build_projection(P, Qc, true, core_s, fac_s, ts64, out.H, out.out_f64, B);
+  // an FP32-class projection reads the FP32 output bases (written by the
+  // same copy launch, before it) instead of converting Q a second time
+  const bool q_out32 = !out.out_f64 && !is_fp64(P.pp);
+  std::vector<const void*> Qc = q_out32 ? std::vector<const void*>(out.Q.begin(), out.Q.end())
+                                        : std::vector<const void*>(Qd.begin(), Qd.end());
+  build_projection(P, Qc, !q_out32, core_s, fac_s, ts64, out.H, out.out_f64, B);
 }
 
 void Builder::emit(Program& prog) {
