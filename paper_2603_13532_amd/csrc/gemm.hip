@@ -191,9 +191,12 @@ constexpr int kSegCache = 32;  // small enough for four FP64 workgroups per CU
 typedef __attribute__((address_space(3))) GemmSeg lds_seg_t;
 typedef __attribute__((address_space(3))) uint64_t lds_u64_t;
 
-template <int P>
+// A32: the A operands are stored in FP32 while the product runs in P (FP64):
+// they are converted as they are loaded, so no FP64 copy is made.
+template <int P, bool A32 = false>
 struct SegCursor {
   typedef typename PT<P>::in_t in_t;
+  typedef typename std::conditional<A32, float, in_t>::type a_src_t;
   static constexpr int BK = PT<P>::BK;
   static constexpr int PER = Stage<P>::PER_THREAD;
   const GemmSeg* segs;  // global table, from the descriptor's first segment
@@ -226,14 +229,14 @@ struct SegCursor {
   __device__ __forceinline__ void load() {
     if (si - c0 >= kSegCache) fill(si);
     lds_seg_t& S = cache[si - c0];
-    constexpr int64_t es = sizeof(in_t);
+    constexpr int64_t es = sizeof(in_t), ea = sizeof(a_src_t);
     const char* sA = uni((const char*)S.A);
     const char* sB = uni((const char*)S.B);
     const int64_t a_sx = uni((int64_t)S.a_sx), a_sk = uni((int64_t)S.a_sk);
     const int64_t b_sx = uni((int64_t)S.b_sx), b_sk = uni((int64_t)S.b_sk);
-    A = sA + (b * uni((int64_t)S.strideA) + (int64_t)m0 * a_sx) * es;
+    A = sA + (b * uni((int64_t)S.strideA) + (int64_t)m0 * a_sx) * ea;
     B = sB + (b * uni((int64_t)S.strideB) + (int64_t)n0 * b_sx) * es;
-    a_step = (int64_t)BK * a_sk * es;
+    a_step = (int64_t)BK * a_sk * ea;
     b_step = (int64_t)BK * b_sk * es;
     K = uni((int)S.K);
     nkt = (K + BK - 1) / BK;
@@ -244,7 +247,7 @@ struct SegCursor {
     for (int j = 0; j < PER; ++j) {
       int x, k;
       PanelMap<P>::xk(a_xc, t, j, x, k);
-      offA[j] = m0 + x < M ? (uint32_t)(((int64_t)x * a_sx + (int64_t)k * a_sk) * es) : kOob;
+      offA[j] = m0 + x < M ? (uint32_t)(((int64_t)x * a_sx + (int64_t)k * a_sk) * ea) : kOob;
       kA[j] = k;
       PanelMap<P>::xk(b_xc, t, j, x, k);
       offB[j] = n0 + x < N ? (uint32_t)(((int64_t)x * b_sx + (int64_t)k * b_sk) * es) : kOob;
@@ -273,7 +276,7 @@ struct SegCursor {
     const rsrc_t rB = make_rsrc(B + (int64_t)kt * b_step);
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-      ra[j] = bload<in_t>(rA, kA[j] < left ? offA[j] : kOob);
+      ra[j] = (in_t)bload<a_src_t>(rA, kA[j] < left ? offA[j] : kOob);
       rb[j] = bload<in_t>(rB, kB[j] < left ? offB[j] : kOob);
     }
   }
@@ -417,7 +420,7 @@ __device__ __forceinline__ void kloop_role(Cur& cur, bool have, typename Lds<P>:
 // kernel traces separate them); the code is the same for every role.
 // At least four waves per SIMD (<= 128 VGPRs): with the LDS of one
 // workgroup under 40 KB, four workgroups share a CU.
-template <int P, int ROLE>
+template <int P, int ROLE, bool A32 = false>
 __global__ __launch_bounds__(NTHREADS, 4) void gemm_kernel(const GemmDesc* __restrict__ descs,
                                                         int ndesc,
                                                         const GemmSeg* __restrict__ segs) {
@@ -429,7 +432,7 @@ __global__ __launch_bounds__(NTHREADS, 4) void gemm_kernel(const GemmDesc* __res
   int seg_begin, seg_count;
   const int di = find_gemm_desc(descs, ndesc, tile, seg_begin, seg_count);
   __shared__ GemmSeg sseg[kSegCache];
-  SegCursor<P> cur;
+  SegCursor<P, A32> cur;
   cur.segs = segs + seg_begin;
   cur.cache = (lds_seg_t*)sseg;
   cur.seg_end = seg_count;
@@ -504,13 +507,14 @@ __global__ __launch_bounds__(NTHREADS, 4) void gemm_kernel(const GemmDesc* __res
 typedef __attribute__((address_space(3))) const float lds_cf32;
 typedef __attribute__((address_space(3))) const double lds_cf64;
 
-template <int P, bool LDS_P>
+template <int P, bool LDS_P, bool G32 = false>
 struct KrpCursor {
   typedef typename PT<P>::in_t in_t;
+  typedef typename std::conditional<G32, float, in_t>::type g_src_t;  // core elements
   typedef typename std::conditional<P == P_FP64, lds_cf64, lds_cf32>::type lds_in_t;
   static constexpr int BK = PT<P>::BK;
   static constexpr int PER = Stage<P>::PER_THREAD;
-  const in_t* G;
+  const void* G;  // core, g_src_t elements
   in_t alpha;
   const in_t* Pk[kMaxOrder];
   lds_in_t* sP;
@@ -531,7 +535,7 @@ struct KrpCursor {
     else return Pk[k][dg + (int64_t)(n0 + x) * rk[k]];
   }
   __device__ __forceinline__ void fetch(in_t (&ra)[PER], in_t (&rb)[PER], bool live) const {
-    constexpr int64_t es = sizeof(in_t);
+    constexpr int64_t es = sizeof(g_src_t);
     const rsrc_t rG = make_rsrc(G);
     const int64_t Kc = live ? this->Kc : 0;
     if constexpr (P != P_FP64 && P != P_FP32) {
@@ -556,7 +560,7 @@ struct KrpCursor {
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
         const bool valid = c0 + j < Kc;
-        ra[j] = bload<in_t>(rG, (valid && a < rn) ? (uint32_t)(((int64_t)a * stn + offg) * es) : kOob);
+        ra[j] = (in_t)bload<g_src_t>(rG, (valid && a < rn) ? (uint32_t)(((int64_t)a * stn + offg) * es) : kOob);
         in_t prod = (in_t)1;
 #pragma unroll
         for (int k = 0; k < kMaxOrder; ++k)
@@ -595,7 +599,7 @@ struct KrpCursor {
       for (int j = 0; j < PER; ++j) {
         const int x = t / BK + (NTHREADS / BK) * j;
         const int a = m0 + x, tt = n0 + x;
-        ra[j] = bload<in_t>(rG, (valid && a < rn) ? (uint32_t)(((int64_t)a * stn + offg) * es) : kOob);
+        ra[j] = (in_t)bload<g_src_t>(rG, (valid && a < rn) ? (uint32_t)(((int64_t)a * stn + offg) * es) : kOob);
         in_t prod = (in_t)1;
 #pragma unroll
         for (int k = 0; k < kMaxOrder; ++k)
@@ -614,15 +618,16 @@ struct KrpCursor {
 // is NO LDS reads with no branch, so the whole K-loop iteration stays one
 // basic block.  Digits past the end of K wrap and stay inside their ranges;
 // those depths read zeros.
-template <int P, int NO>
+template <int P, int NO, bool G32 = false>
 struct KrpFixed {
   typedef typename PT<P>::in_t in_t;
+  typedef typename std::conditional<G32, float, in_t>::type g_src_t;  // core elements
   typedef typename std::conditional<P == P_FP64, lds_cf64, lds_cf32>::type lds_in_t;
   static constexpr int BK = PT<P>::BK;
   static constexpr int PER = Stage<P>::PER_THREAD;
   static constexpr bool FPK = (P == P_FP64 || P == P_FP32);  // one depth, PER rows per thread
   static constexpr int NX = FPK ? PER : 1;                   // rows (and columns) per thread
-  const in_t* G;
+  const void* G;  // core, g_src_t elements
   in_t alpha;
   lds_in_t* sP;
   int rk[NO], inc[NO];  // radices of the other modes and the digits of one tile step
@@ -657,7 +662,7 @@ struct KrpFixed {
     return kt < nkt;
   }
   __device__ __forceinline__ void fetch(in_t (&ra)[PER], in_t (&rb)[PER], bool live) const {
-    constexpr uint32_t es = sizeof(in_t);
+    constexpr uint32_t es = sizeof(g_src_t);
     const rsrc_t rG = make_rsrc(G);
     if constexpr (FPK) {
       const bool valid = live && c < Kc;
@@ -666,7 +671,7 @@ struct KrpFixed {
       for (int j = 0; j < NO; ++j) offg += (uint32_t)(dg[j] * st[j]) * es;
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
-        ra[i] = bload<in_t>(rG, (valid && rowoff[i] != kOob) ? rowoff[i] + offg : kOob);
+        ra[i] = (in_t)bload<g_src_t>(rG, (valid && rowoff[i] != kOob) ? rowoff[i] + offg : kOob);
         in_t prod = sP[pb[i][0] + dg[0]];
 #pragma unroll
         for (int j = 1; j < NO; ++j) prod *= sP[pb[i][j] + dg[j]];
@@ -683,7 +688,7 @@ struct KrpFixed {
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const bool valid = live && c + i < Kc;
-        ra[i] = bload<in_t>(rG, (valid && rowoff[0] != kOob) ? rowoff[0] + offg : kOob);
+        ra[i] = (in_t)bload<g_src_t>(rG, (valid && rowoff[0] != kOob) ? rowoff[0] + offg : kOob);
         in_t prod = sP[pb[0][0] + d[0]];
 #pragma unroll
         for (int j = 1; j < NO; ++j) prod *= sP[pb[0][j] + d[j]];
@@ -705,7 +710,7 @@ struct KrpFixed {
 
 // KRP core sketch: rows a of G_(n) against Khatri-Rao columns t, K = c over
 // the other modes, first remaining mode fastest (unfolding index equation).
-template <int P>
+template <int P, bool G32 = false>
 __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict__ descs,
                                                        int ndesc, int lds_cap) {
   typedef typename PT<P>::in_t in_t;
@@ -727,7 +732,7 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
   // the wave index goes through readfirstlane so that the compiler sees it as
   // uniform: branches on it stay scalar and the accumulators stay in place
   const int t = threadIdx.x, lane = t & 63, w = uni(t >> 6), wm = w & 1, wn = w >> 1;
-  const in_t* __restrict__ G = (const in_t*)D.G;
+  const void* G = D.G;  // FP32 elements when G32
   const in_t alpha = (in_t)D.alpha;
   void* part_base = D.part;
   void* Vout = D.V;
@@ -831,7 +836,9 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
 #pragma unroll
     for (int i = 0; i < Cur::NX; ++i) {
       const int x = Cur::FPK ? t / BK + (NTHREADS / BK) * i : (t & (TILE - 1));
-      cur.rowoff[i] = m0 + x < rn ? (uint32_t)((int64_t)(m0 + x) * stn * (int64_t)sizeof(in_t)) : kOob;
+      cur.rowoff[i] = m0 + x < rn ? (uint32_t)((int64_t)(m0 + x) * stn *
+                                               (int64_t)sizeof(typename Cur::g_src_t))
+                                  : kOob;
       cur.tok[i] = n0 + x < m;
     }
     cur.Kc = Kc;
@@ -844,18 +851,18 @@ __global__ __launch_bounds__(NTHREADS) void krp_kernel(const KrpDesc* __restrict
     kloop_role<P>(cur, cur.kt < cur.nkt, s, acc, t, lane, role);
   };
   if (lds_p && order == 3) {
-    KrpFixed<P, 2> cur;
+    KrpFixed<P, 2, G32> cur;
     fixed(cur, std::integral_constant<int, 2>());
   } else if (lds_p && order == 4) {
-    KrpFixed<P, 3> cur;
+    KrpFixed<P, 3, G32> cur;
     fixed(cur, std::integral_constant<int, 3>());
   } else if (lds_p) {
-    KrpCursor<P, true> cur;
+    KrpCursor<P, true, G32> cur;
     TSK_KRP_CURSOR(cur)
-    cur.sP = (typename KrpCursor<P, true>::lds_in_t*)sP;
+    cur.sP = (typename KrpCursor<P, true, G32>::lds_in_t*)sP;
     kloop_role<P>(cur, cur.kt < cur.nkt, s, acc, t, lane, role);
   } else {
-    KrpCursor<P, false> cur;
+    KrpCursor<P, false, G32> cur;
     TSK_KRP_CURSOR(cur)
     cur.sP = nullptr;
     kloop_role<P>(cur, cur.kt < cur.nkt, s, acc, t, lane, role);
@@ -1203,9 +1210,20 @@ hipError_t launch_gemm_p(int role, dim3 grid, const GemmDesc* descs, int ndesc,
 }
 
 hipError_t launch_gemm(int prec, int role, const GemmDesc* descs, int ndesc, const GemmSeg* segs,
-                       int64_t total_tiles, hipStream_t stream) {
+                       int64_t total_tiles, hipStream_t stream, bool a32) {
   if (ndesc <= 0 || total_tiles <= 0) return hipSuccess;
   const dim3 grid((unsigned)total_tiles), block(NTHREADS);
+  if (a32) {
+    // FP32 A operands in an FP64 product: the sketch of FP32-stored inputs
+    if (prec != P_FP64) return hipErrorInvalidValue;
+    if (role == R_FACTOR_SKETCH)
+      gemm_kernel<P_FP64, R_FACTOR_SKETCH, true><<<grid, block, 0, stream>>>(descs, ndesc, segs);
+    else if (role == R_TERM_EXPAND)
+      gemm_kernel<P_FP64, R_TERM_EXPAND, true><<<grid, block, 0, stream>>>(descs, ndesc, segs);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   switch (prec) {
     case P_FP64:
       // the QR products are FP64 only
@@ -1227,9 +1245,17 @@ hipError_t launch_gemm(int prec, int role, const GemmDesc* descs, int ndesc, con
 }
 
 hipError_t launch_krp(int prec, const KrpDesc* descs, int ndesc, int64_t total_tiles,
-                      int lds_elems, hipStream_t stream) {
+                      int lds_elems, hipStream_t stream, bool g32) {
   if (ndesc <= 0 || total_tiles <= 0) return hipSuccess;
   if (lds_elems < 0 || lds_elems > kKrpLds) return hipErrorInvalidValue;
+  if (g32) {
+    // FP32 cores in an FP64 core sketch
+    if (prec != P_FP64) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)total_tiles), block(NTHREADS);
+    const size_t dyn = (size_t)lds_elems * sizeof(double);
+    krp_kernel<P_FP64, true><<<grid, block, dyn, stream>>>(descs, ndesc, lds_elems);
+    return hipGetLastError();
+  }
   const dim3 grid((unsigned)total_tiles), block(NTHREADS);
   const size_t dyn = (size_t)lds_elems * (prec == P_FP64 ? sizeof(double) : sizeof(float));
   switch (prec) {

@@ -23,16 +23,19 @@ hipError_t launch_omega_jobs(const OmegaJobDev* jobs, int count, int64_t max_cou
                              hipStream_t stream);
 
 // Grouped GEMM over `ndesc` device descriptors covering `total_tiles` tiles.
+// a32: the A operands are FP32 in an FP64 product (factor sketch and term
+// expansion only).
 hipError_t launch_gemm(int prec, int role, const GemmDesc* descs, int ndesc, const GemmSeg* segs,
-                       int64_t total_tiles, hipStream_t stream);
+                       int64_t total_tiles, hipStream_t stream, bool a32 = false);
 
 // KRP core sketches over `ndesc` device descriptors covering `total_tiles` tiles.
 // Elements of P slices a KRP workgroup may keep in LDS (the block's 64
 // columns of every P_k, k != n); launches size their LDS by the largest
 // such slice set among their descriptors (`lds_elems`, <= kKrpLds).
 constexpr int kKrpLds = 6144;
+// g32: FP32 cores in an FP64 core sketch.
 hipError_t launch_krp(int prec, const KrpDesc* descs, int ndesc, int64_t total_tiles,
-                      int lds_elems, hipStream_t stream);
+                      int lds_elems, hipStream_t stream, bool g32 = false);
 
 // Core adjoint of the KRP sketch (core-shaped outputs).
 hipError_t launch_krp_adj(int prec, const KrpAdjDesc* descs, int ndesc, int64_t total_tiles,

@@ -248,6 +248,7 @@ struct Step {
   int hh_kernels = 3;  // householder: which of the two kernels have panels
   int krp_lds = 0;     // krp: LDS elements for the P slices (largest that fits)
   std::vector<uint32_t> keys;  // autotuning classes whose choices shaped this launch
+  bool a32 = false;  // FP64 GEMM / core sketch whose A operands (cores) are stored in FP32
 };
 
 // LDS elements a KRP launch needs for its P slices: the largest slice set
@@ -313,6 +314,7 @@ struct GemmBatch {
   int64_t tiles = 0;
   double flops = 0, bytes = 0;
   std::vector<uint32_t> keys;  // autotuning classes of its split decisions
+  bool a32 = false;            // every A operand stored in FP32 (prec FP64)
   GemmBatch(int p, int r, Arena* a) : prec(p), role(r), ar(a) {}
   // Add one descriptor; `splits` > 1 writes partials to `part` and queues a
   // reduction into C.
@@ -414,6 +416,7 @@ void emit_gemm(Program& prog, GemmBatch& gb) {
   st.count = (int)gb.descs.size();
   st.tiles = gb.tiles;
   st.keys = gb.keys;
+  st.a32 = gb.a32;
   prog.steps.push_back(st);
   if (!gb.reduces.empty()) {
     Step r{};
@@ -513,6 +516,10 @@ struct Builder {
   int64_t* d_counter = nullptr;
   const tsk_handle_* th = nullptr;  // its tuning table, if any
   std::vector<uint32_t> krp_keys;
+  // FP64 sketch of FP32-stored inputs (every sum of the plan, KRP): the
+  // factor sketch, core sketch and term expansion read the FP32 cores and
+  // factors directly instead of FP64 copies
+  bool direct32 = false;
   explicit Builder(Arena& a) : ar(a) {}
   GemmBatch& g(int stage, int prec, int role) {
     auto it = gemm.find(stage);
@@ -751,7 +758,7 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
   for (int i = 0; i < s; ++i) {
     int64_t csize = 1;
     for (int k = 0; k < d; ++k) csize *= P.r(i, k);
-    if (P.in_f64 == ts64) {
+    if (P.in_f64 == ts64 || B.direct32) {
       core_s[i] = P.cores[i];
     } else {
       void* p = ar.take(csize * es);
@@ -761,7 +768,7 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
     for (int k = 0; k < d; ++k) {
       const int64_t n = P.dims[k], r = P.r(i, k);
       const void* u = P.factors[(size_t)i * d + k];
-      if (P.in_f64 == ts64) {
+      if (P.in_f64 == ts64 || B.direct32) {
         fac_s[(size_t)i * d + k] = u;
       } else {
         void* p = ar.take(n * r * es);
@@ -793,6 +800,7 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
   std::vector<void*> Pf((size_t)s * d);
   {
     GemmBatch& gb = B.g(ST_FACTOR, P.ps, R_FACTOR_SKETCH);
+    gb.a32 = B.direct32;
     int64_t tiles0 = 0, kt = 0;
     for (int i = 0; i < s; ++i)
       for (int k = 0; k < d; ++k) {
@@ -965,6 +973,7 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
     Y[n] = out.recompress ? (double*)ar.take(P.dims[n] * P.W[n] * 8) : out.Y[n];
   {
     GemmBatch& gb = B.g(ST_EXPAND, P.ps, R_TERM_EXPAND);
+    gb.a32 = B.direct32;
     // K-split over the term concatenation when the output tiles alone cannot fill the GPU
     int64_t tiles0 = 0, kt = 0;
     const int bk = ts64 ? 16 : 32;
@@ -1023,7 +1032,7 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
   const bool q_out32 = !out.out_f64 && !is_fp64(P.pp);
   std::vector<const void*> Qc = q_out32 ? std::vector<const void*>(out.Q.begin(), out.Q.end())
                                         : std::vector<const void*>(Qd.begin(), Qd.end());
-  build_projection(P, Qc, !q_out32, core_s, fac_s, ts64, out.H, out.out_f64, B);
+  build_projection(P, Qc, !q_out32, core_s, fac_s, ts64 && !B.direct32, out.H, out.out_f64, B);
 }
 
 void Builder::emit(Program& prog) {
@@ -1057,6 +1066,7 @@ void Builder::emit(Program& prog) {
     st.tiles = krp_tiles;
     st.krp_lds = krp_lds_elems(krp.data(), krp.size());
     st.keys = krp_keys;
+    st.a32 = direct32;
     prog.steps.push_back(st);
     if (!krp_red.empty()) {
       Step r{};
@@ -1672,11 +1682,11 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
       case S_OMEGA: e = launch_omega_jobs((const OmegaJobDev*)(meta + st.meta), st.count, st.rows, stream); break;
       case S_GEMM:
         e = launch_gemm(st.prec, st.role, (const GemmDesc*)(meta + st.meta), st.count,
-                        (const GemmSeg*)(meta + st.meta2), st.tiles, stream);
+                        (const GemmSeg*)(meta + st.meta2), st.tiles, stream, st.a32);
         break;
       case S_KRP:
         e = launch_krp(st.prec, (const KrpDesc*)(meta + st.meta), st.count, st.tiles, st.krp_lds,
-                       stream);
+                       stream, st.a32);
         break;
       case S_REDUCE: e = launch_reduce((const ReduceJob*)(meta + st.meta), st.count, stream); break;
       case S_TILE_REDUCE: e = launch_tile_reduce((const ReduceJob*)(meta + st.meta), st.count, stream); break;
@@ -1727,6 +1737,9 @@ tsk_status plan_many(tsk_handle h, const std::vector<Problem>& Ps, const std::ve
   B.nsums = (int)Ps.size();
   B.d_counter = h ? h->d_counter : nullptr;
   B.th = h;
+  B.direct32 = !Ps.empty();
+  for (const Problem& P : Ps)
+    if (P.kind != TSK_SKETCH_KRP || P.in_f64 || !is_fp64(P.ps)) B.direct32 = false;
   for (size_t j = 0; j < Ps.size(); ++j) build_sum(Ps[j], outs[j], B);
   if (!ar.too_far.empty()) return fail(h, TSK_ERR_UNSUPPORTED, "%s", ar.too_far.c_str());
   if (ar.ctr_used != nctr) return fail(h, TSK_ERR_DEVICE, "QR flag words planned %lld, placed %lld",
@@ -2522,7 +2535,8 @@ void check_program(const Program& prog, Checker& ck) {
             if (S.a_sx != 1 && S.a_sk != 1) { ck.ok = false; ck.err = "gemm A has no unit stride"; return; }
             if (S.b_sx != 1 && S.b_sk != 1) { ck.ok = false; ck.err = "gemm B has no unit stride"; return; }
             if (S.K == 0) continue;
-            ck.span(S.A, 0, (D.batch - 1) * S.strideA + max_off({{D.M, S.a_sx}, {S.K, S.a_sk}}), ein, "gemm A");
+            ck.span(S.A, 0, (D.batch - 1) * S.strideA + max_off({{D.M, S.a_sx}, {S.K, S.a_sk}}),
+                    st.a32 ? 4 : ein, "gemm A");
             ck.span(S.B, 0, (D.batch - 1) * S.strideB + max_off({{D.N, S.b_sx}, {S.K, S.b_sk}}), ein, "gemm B");
           }
           ck.span(D.C, 0, (D.batch - 1) * D.strideC + max_off({{D.M, 1}, {D.N, D.ldc}}),
@@ -2553,7 +2567,7 @@ void check_program(const Program& prog, Checker& ck) {
           }
           if (Kc != D.Kc) { ck.ok = false; ck.err = "krp Kc mismatch"; return; }
           if (st.krp_lds < 0 || st.krp_lds > kKrpLds) { ck.ok = false; ck.err = "krp LDS size"; return; }
-          ck.span(D.G, 0, cs - 1, e, "krp G");
+          ck.span(D.G, 0, cs - 1, st.a32 ? 4 : e, "krp G");
           ck.span(D.V, 0, (int64_t)D.r[D.mode] * D.m - 1, e, "krp V");
           if (D.splits > 1) {
             const int64_t nt = (int64_t)D.tiles_m * D.tiles_n;
