@@ -11,6 +11,7 @@ the componentwise envelope tol * |terms| (the same chain evaluated on the
 absolute values of its inputs), which catches a wrong block anywhere,
 including the small trailing slices of a decaying H that a normwise check
 cannot see."""
+import numpy as np
 import pytest
 
 import ladder
@@ -80,3 +81,27 @@ def test_ladder_ragged(tsk, refs, name, form):
 @pytest.mark.parametrize("name", ladder.LARGE)
 def test_ladder_workloads(tsk, refs, name, form):
     check(ladder.measure(tsk, name, form, refs))
+
+
+@pytest.mark.parametrize("name", ladder.SMALL)
+def test_fp64_on_fp32_storage(tsk, name):
+    """FP64 arithmetic on FP32-stored inputs (the Khatri-Rao sketch then reads
+    the FP32 cores and factors directly, the projection from FP64 copies):
+    the FP64 form's bounds, against the oracle on the same FP32 values."""
+    import torch
+    ts, kind, sizes, seed = ladder.case(name)
+    tsx = ladder.rounded_to_f32(ts)
+    ref = ladder.RC.recompress(tsx, kind, sizes, seed)
+    cores, factors = ladder.to_torch(tsx, ladder.DEV, torch.float32)
+    ys = tsk.tucker_sum_sketch(cores, factors, kind, sizes, seed, coeffs=tsx["coeffs"],
+                               sketch_prec="fp64")
+    qs, h = tsk.tucker_sum_recompress(cores, factors, kind, sizes, seed, coeffs=tsx["coeffs"],
+                                      sketch_prec="fp64", project_prec="fp64",
+                                      out_dtype=torch.float64)
+    torch.cuda.synchronize()
+    y_rel = max(ladder.rel(ladder.np_of(a), b) for a, b in zip(ys, ref["Y"]))
+    qs = [ladder.np_of(q) for q in qs]
+    x_rel = ladder.tucker_rel_diff(ladder.np_of(h), qs, ref["H"], ref["Q"], device=ladder.DEV)
+    orth = max(float(np.linalg.norm(q.T @ q - np.eye(q.shape[1]))) for q in qs)
+    print(f"{name} ({kind}): Y {y_rel:.1e}, X {x_rel:.1e}, orth {orth:.1e}")
+    assert y_rel <= BOUNDS["fp64"]["y"] and x_rel <= BOUNDS["fp64"]["x"] and orth <= 1e-12
