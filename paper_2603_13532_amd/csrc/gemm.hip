@@ -20,9 +20,46 @@ namespace tsk {
 
 namespace {
 
-// GEMM descriptor lookup that also returns the descriptor's segment range,
-// read in the same pass, so that the segment table can be fetched while the
-// descriptor itself is still in flight.
+// Index of the last of n entries whose begin(i) <= key (begin(0) = 0 <=
+// key, and begin never decreases), for a 256-thread block in uniform
+// control flow.  Up to 256 entries every thread tests one and the block
+// counts; up to 65536, a coarse pass over every stride-th entry finds the
+// block of `stride` entries that holds the key and a second pass counts
+// within it: two memory round trips instead of a binary search's chain of
+// dependent loads.
+template <typename F>
+__device__ __forceinline__ int find_last_le(int n, int64_t key, F begin) {
+  const int t = threadIdx.x;
+  if (n <= NTHREADS) {
+    const bool le = t < n && begin(t) <= key;
+    return uni(__syncthreads_count(le) - 1);
+  }
+  if (n <= NTHREADS * NTHREADS) {
+    const int stride = (n + NTHREADS - 1) / NTHREADS;
+    const int i1 = t * stride;
+    const bool le1 = i1 < n && begin(i1) <= key;
+    const int base = uni(__syncthreads_count(le1) - 1) * stride;
+    const int i2 = base + t;
+    const bool le2 = t < stride && i2 < n && begin(i2) <= key;
+    return base + uni(__syncthreads_count(le2) - 1);
+  }
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin(mid) <= key) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Descriptor of a linear tile id: the last one whose tile_begin <= tile.
+template <typename D>
+__device__ __forceinline__ int find_desc(const D* __restrict__ descs, int ndesc, int64_t tile) {
+  return find_last_le(ndesc, tile, [&](int i) { return (int64_t)descs[i].tile_begin; });
+}
+
+// GEMM descriptor lookup that also returns the descriptor's segment range
+// (read in the same pass for up to 256 descriptors, so that the segment
+// table can be fetched while the descriptor itself is still in flight).
 __device__ __forceinline__ int find_gemm_desc(const GemmDesc* __restrict__ descs, int ndesc,
                                               int64_t tile, int& seg_begin, int& seg_count) {
   __shared__ int s_sb[NTHREADS], s_sc[NTHREADS];
@@ -39,32 +76,10 @@ __device__ __forceinline__ int find_gemm_desc(const GemmDesc* __restrict__ descs
     seg_count = uni(s_sc[di]);
     return di;
   }
-  int lo = 0, hi = ndesc - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
-  }
-  seg_begin = descs[lo].seg_begin;
-  seg_count = descs[lo].seg_count;
-  return lo;
-}
-
-// Descriptor of a linear tile id: the last one whose tile_begin <= tile.
-// Up to 256 descriptors every thread tests one and the block counts (one
-// memory round trip); beyond that, a binary search.
-template <typename D>
-__device__ __forceinline__ int find_desc(const D* __restrict__ descs, int ndesc, int64_t tile) {
-  if (ndesc <= NTHREADS) {
-    const int t = threadIdx.x;
-    const bool le = t < ndesc && descs[t].tile_begin <= tile;
-    return uni(__syncthreads_count(le) - 1);
-  }
-  int lo = 0, hi = ndesc - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
-  }
-  return lo;
+  const int di = find_desc(descs, ndesc, tile);
+  seg_begin = descs[di].seg_begin;
+  seg_count = descs[di].seg_count;
+  return di;
 }
 
 // Accumulator element type of a precision form.
@@ -1140,12 +1155,7 @@ __device__ __forceinline__ void copy_chunk(const S* __restrict__ src, D* __restr
 // is found by binary search over the jobs' first chunks.
 __global__ __launch_bounds__(256) void copy_kernel(const CopyJob* __restrict__ jobs, int count) {
   const int64_t chunk = blockIdx.x;
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].chunk_begin <= chunk) lo = mid;
-    else hi = mid - 1;
-  }
+  const int lo = find_last_le(count, chunk, [&](int i) { return (int64_t)jobs[i].chunk_begin; });
   const CopyJob& J = jobs[lo];
   const int64_t n = J.rows * J.cols;
   const int64_t base = (chunk - J.chunk_begin) * kCopyChunk;
@@ -1162,12 +1172,7 @@ __global__ __launch_bounds__(256) void copy_kernel(const CopyJob* __restrict__ j
 __global__ __launch_bounds__(256) void block_scatter_kernel(const BlockJob* __restrict__ jobs,
                                                             int count) {
   const int64_t chunk = blockIdx.x;
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].chunk_begin <= chunk) lo = mid;
-    else hi = mid - 1;
-  }
+  const int lo = find_last_le(count, chunk, [&](int i) { return (int64_t)jobs[i].chunk_begin; });
   const BlockJob& J = jobs[lo];
   const int64_t base = (chunk - J.chunk_begin) * kCopyChunk;
   for (int k = 0; k < kCopyChunk / 256; ++k) {
