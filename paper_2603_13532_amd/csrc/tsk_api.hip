@@ -1566,7 +1566,7 @@ const char* role_name(int role) {
 }
 
 // Name of the kernel symbol a step launches (template arguments as a kernel
-// trace prints them), followed by the step's role.
+// trace prints them, defaulted ones left out), followed by the step's role.
 std::string step_name(const Step& st) {
   char buf[96];
   switch (st.kind) {
@@ -1575,10 +1575,14 @@ std::string step_name(const Step& st) {
       int role = st.role;
       if (role > R_OTHER || role < 0) role = R_OTHER;
       if ((role == R_QR_GRAM || role == R_QR_BASIS) && st.prec != P_FP64) role = R_OTHER;
-      snprintf(buf, sizeof buf, "gemm_kernel<%d, %d> %s", st.prec, role, role_name(role));
+      // the FP32-source variant carries its template flag, as a trace prints it
+      snprintf(buf, sizeof buf, "gemm_kernel<%d, %d%s> %s", st.prec, role, st.a32 ? ", true" : "",
+               role_name(role));
       return buf;
     }
-    case S_KRP: snprintf(buf, sizeof buf, "krp_kernel<%d> core_sketch", st.prec); return buf;
+    case S_KRP:
+      snprintf(buf, sizeof buf, "krp_kernel<%d%s> core_sketch", st.prec, st.a32 ? ", true" : "");
+      return buf;
     case S_REDUCE: return "reduce_kernel";
     case S_TILE_REDUCE: return "tile_reduce_kernel";
     case S_COPY: return "copy_kernel";
