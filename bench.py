@@ -96,6 +96,9 @@ def parse():
                     help="with --autotune: write the tuned table here")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device to device (HBM counter calibration)")
+    ap.add_argument("--ndg-phases", type=int, default=0, metavar="STEPS",
+                    help="only run STEPS batched NDG steps (KRP) and print each step's "
+                         "wall time per phase (for kernel traces)")
     return ap.parse_args()
 
 
@@ -630,6 +633,29 @@ def ndg_leg(tsk, dev, steps):
     return out
 
 
+def ndg_phases(dev, steps):
+    """The NDG run of ndg_leg (KRP, batched over the 64 nodes) for `steps`
+    steps from the initial condition, each step's wall milliseconds per
+    phase (forming the sums, marshalling, Stage 1, planning, Stages 2-3,
+    Stage 4; the device synchronised between phases) printed on a line."""
+    import torch
+    from synth import ndg
+    from paper_2603_13532_amd import ndg as gndg
+    st = ndg.setup(nx=32, k=1, nxi=100, xi_max=12.0)
+    nsteps = int(np.ceil(0.005 / st["dt"] - 1e-9))
+    st["dt"] = 0.005 / nsteps
+    terms = ndg.euler_terms(st)
+    states = gndg.to_device(ndg.initial_state(st), dev)
+    scales = {k: torch.from_numpy(v).to(dev) for k, v in st["scale"].items()}
+    names = ("sums", "marshal", "stage1", "plan", "recompress", "truncate")
+    for _ in range(steps):
+        tm = {}
+        states, _, _ = gndg.euler_step(states, terms, scales, 1e-6, 5, kind="krp", seed=5,
+                                       timings=tm)
+        print(" ".join(f"{k} {tm[k]:.2f}" for k in names) +
+              f" total {sum(tm[k] for k in names):.2f}", flush=True)
+
+
 def torch_f64():
     import torch
     return torch.float64
@@ -708,6 +734,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": n, "launches": 3}))
+        return
+
+    if args.ndg_phases:
+        ndg_phases(dev, args.ndg_phases)
         return
 
     forms = [f for f in args.forms.split(",") if f]

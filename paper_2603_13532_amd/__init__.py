@@ -488,26 +488,56 @@ def tucker_truncate_batched(jobs, eps):
     return res
 
 
-def sketch_sum_batched(sums, kind, eps, p, seed, sketch_prec="fp64", project_prec="fp64"):
+def sketch_sum_batched(sums, kind, eps, p, seed, sketch_prec="fp64", project_prec="fp64",
+                       timings=None):
     """Algorithm 5 (kind "krp") or 4 ("kron") for many independent sums,
     each stage one launch sequence over all of them: Stage 1 sizes from eps
     and p, the sketch widths, Stages 2-3 (tucker_sum_recompress_batched,
     FP64 outputs) and the Stage 4 truncation with eps.  `sums`: list of dicts
     with cores, factors and optionally coeffs; `seed`: an int shared by every
-    sum or a list.  Returns a list of (G, [U..], ranks, sizes)."""
+    sum or a list.  Returns a list of (G, [U..], ranks, sizes).
+
+    With `timings` (a dict, for profiling), the device is synchronised after
+    every phase and the phase's wall milliseconds are added under "marshal",
+    "stage1", "plan" (sketch sizes and the batched plan), "recompress"
+    (Stages 2-3) and "truncate" (Stage 4)."""
+    mark = _phase_clock(timings, sums[0]["cores"][0].device if sums else None)
     seen = {}
     ms = [_Marshal(x["cores"], x["factors"], x.get("coeffs"), "krp", [1], 0, None, sketch_prec,
                    project_prec, "auto", seen) for x in sums]
+    mark("marshal")
     ells = _subranks_batched(ms, eps, p)
+    mark("stage1")
     seeds = seed if hasattr(seed, "__len__") else [seed] * len(sums)
     sizes = []
     for m, ell, sd in zip(ms, ells, seeds):
         sz = [krp_width(ell)] if kind == "krp" else kron_sizes(ell)
         sizes.append(sz)
         m.set_spec(kind, sz, sd, sketch_prec, project_prec)
-    q, h = BatchRecompressor(None, sketch_prec, project_prec, torch.float64, _marshals=ms)()
+    br = BatchRecompressor(None, sketch_prec, project_prec, torch.float64, _marshals=ms)
+    mark("plan")
+    q, h = br()
+    mark("recompress")
     tr = tucker_truncate_batched(list(zip(q, h)), eps)
+    mark("truncate")
     return [(g, us, r, sz) for (g, us, r), sz in zip(tr, sizes)]
+
+
+def _phase_clock(timings, device):
+    """A marker that adds the wall milliseconds since the previous mark to
+    timings[name] after synchronising `device` (a no-op without timings)."""
+    if timings is None or device is None:
+        return lambda name: None
+    import time
+    torch.cuda.synchronize(device)
+    last = [time.perf_counter()]
+
+    def mark(name):
+        torch.cuda.synchronize(device)
+        now = time.perf_counter()
+        timings[name] = timings.get(name, 0.0) + 1e3 * (now - last[0])
+        last[0] = now
+    return mark
 
 
 def round_deterministic(cores, factors, tau, coeffs=None):

@@ -51,11 +51,21 @@ def euler_sums(states, terms, scales):
     return sums
 
 
-def euler_step(states, terms, scales, eps, p, kind="krp", seed=0):
+def euler_step(states, terms, scales, eps, p, kind="krp", seed=0, timings=None):
     """One forward-Euler step with the sketched sum (Algorithm 5 for kind
     "krp", 4 for "kron") at tolerance eps and oversampling p.  Returns the
-    new states, the ranks and the sketch sizes of every node."""
-    out = sketch_sum_batched(euler_sums(states, terms, scales), kind, eps, p, seed)
+    new states, the ranks and the sketch sizes of every node.  `timings`: as
+    for sketch_sum_batched, plus "sums" (forming the node sums)."""
+    t0 = None
+    if timings is not None:
+        import time
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+    sums = euler_sums(states, terms, scales)
+    if timings is not None:
+        torch.cuda.synchronize()
+        timings["sums"] = timings.get("sums", 0.0) + 1e3 * (time.perf_counter() - t0)
+    out = sketch_sum_batched(sums, kind, eps, p, seed, timings=timings)
     return [(g, us) for g, us, _, _ in out], [r for _, _, r, _ in out], [s for _, _, _, s in out]
 
 
