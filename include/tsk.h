@@ -101,12 +101,19 @@ typedef struct {
   tsk_precision sketch_prec;   /* factor sketch, core sketch, term expansion        */
   tsk_precision project_prec;  /* Q^T U and the multi-TTM of the core projection    */
   int32_t qr_policy;           /* 0: Cholesky QR2, Householder on breakdown (device
-                                  side); 1: Householder always; 2: Cholesky QR2,
-                                  breakdown reported as TSK_ERR_RANK_DEFICIENT      */
+                                  side), and directly for a mode whose total rank
+                                  sum_i r_n^(i) is below its sketch width (Y_n is
+                                  then rank deficient); 1: Householder always;
+                                  2: Cholesky QR2, breakdown reported as
+                                  TSK_ERR_RANK_DEFICIENT                            */
 } tsk_sketch_spec;
 
 /* Handle on HIP device `device`.  Allocates the handle's counter block and
- * nothing else on the device. */
+ * nothing else on the device, and creates a second stream of default
+ * priority: a call forks independent launches onto it from the caller's
+ * stream and joins them back before it returns (the caller's stream waits
+ * for them, so stream order is kept and a captured graph holds both
+ * branches). */
 tsk_status tsk_create(tsk_handle* handle, int device);
 tsk_status tsk_destroy(tsk_handle handle);
 const char* tsk_status_string(tsk_status status);
@@ -373,7 +380,8 @@ tsk_status tsk_autotune_load(tsk_handle handle, const char* path);
 tsk_status tsk_autotune_clear(tsk_handle handle);
 
 /* Number of mode QRs that took the Householder path since the handle was
- * created (Cholesky breakdown, or qr_policy 1).  Synchronises `stream`.
+ * created (Cholesky breakdown, a total rank below the sketch width under
+ * qr_policy 0, or qr_policy 1).  Synchronises `stream`.
  * Returns TSK_ERR_RANK_DEFICIENT (count still written) if, since the last
  * call, a Cholesky QR broke down under qr_policy 2 (the outputs of that call
  * are still the Householder result) or a backward call met a numerically

@@ -103,13 +103,16 @@ hipError_t launch_chol(const QrDesc* qr, int count, int pass, double tol, int wm
                        hipStream_t stream);
 // max_elems: largest (n+1)*W + 2W among the descriptors (sizes the in-LDS panel).
 // Panels the eight-wave register kernel takes (the others go to the
-// general Householder kernel); `kernels` says which of the two to launch
-// (bit 0: register kernel, bit 1: general kernel), from the panel shapes.
+// general Householder kernel).  A launch factors the modes `sel` names (bit
+// 0: planned for Householder directly, or all under `force`; bit 1: broken
+// down in the first Cholesky pass), workgroup b taking the b-th such mode of
+// its kernel's kind; grid[0] / grid[1] workgroups of the register / general
+// kernel (at least the number of such modes; 0 skips that kernel).
 constexpr int kHhWideCols = 64;
 constexpr int kHhWideRows = 384;
 __host__ __device__ inline bool hh_wide_panel(int64_t n, int64_t W) { return W <= kHhWideCols && n <= kHhWideRows; }
 hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* fallback_counter,
-                              int64_t max_elems, int kernels, hipStream_t stream);
+                              int64_t max_elems, int sel, const int* grid, hipStream_t stream);
 
 // Symmetric eigendecomposition of a W x W matrix (W <= kEigMaxW) by one
 // workgroup: eigenvalues in decreasing order into lam[0..W), their

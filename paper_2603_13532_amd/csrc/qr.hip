@@ -894,10 +894,14 @@ __device__ __forceinline__ void hh_wide(const QrDesc& D, lds_f64* park, lds_f64*
 }
 
 // Whether descriptor D needs the Householder path of the given kind (the
-// eight-wave register kernel when `wide`, the general kernel otherwise).
-__device__ __forceinline__ bool hh_needed(const QrDesc& D, int force, bool wide) {
+// eight-wave register kernel when `wide`, the general kernel otherwise) in
+// a launch that takes the modes `sel` names: bit 0 the modes planned for
+// Householder directly (or every mode under `force`), bit 1 the modes whose
+// Cholesky pass broke down.
+__device__ __forceinline__ bool hh_needed(const QrDesc& D, int force, bool wide, int sel) {
   if (hh_wide_panel(D.n, D.W) != wide) return false;
-  return force || D.hh_direct || *D.flag != 0;  // flag written by the first chol pass
+  if (force || D.hh_direct) return (sel & 1) != 0;
+  return (sel & 2) != 0 && *D.flag != 0;  // flag written by the first chol pass
 }
 
 // Index of the b-th descriptor (in descriptor order) that needs this
@@ -908,7 +912,7 @@ __device__ __forceinline__ bool hh_needed(const QrDesc& D, int force, bool wide)
 // descriptors fall.  Block-wide: every thread returns the same index.
 template <int T>
 __device__ int hh_nth_job(const QrDesc* __restrict__ qrs, int count, int force, bool wide,
-                          int b) {
+                          int sel, int b) {
   constexpr int NWV = T / 64;
   __shared__ int s_cnt[NWV];
   __shared__ int s_found;
@@ -917,7 +921,7 @@ __device__ int hh_nth_job(const QrDesc* __restrict__ qrs, int count, int force, 
   int base = 0;
   for (int c0 = 0; c0 < count; c0 += T) {
     const int i = c0 + t;
-    const bool need = i < count && hh_needed(qrs[i], force, wide);
+    const bool need = i < count && hh_needed(qrs[i], force, wide, sel);
     const unsigned long long m = __ballot(need);
     if (lane == 0) s_cnt[wv] = __popcll(m);
     __syncthreads();
@@ -940,8 +944,8 @@ __device__ int hh_nth_job(const QrDesc* __restrict__ qrs, int count, int force, 
 // Panels with W <= kWideCols and n <= kWideRows go here (one workgroup of
 // kWideWaves waves each); householder_kernel takes the others.
 __global__ __launch_bounds__(kWideWaves * 64) void householder_wide_kernel(
-    const QrDesc* __restrict__ qrs, int count, int force, unsigned long long* counter) {
-  const int job = hh_nth_job<kWideWaves * 64>(qrs, count, force, true, blockIdx.x);
+    const QrDesc* __restrict__ qrs, int count, int force, int sel, unsigned long long* counter) {
+  const int job = hh_nth_job<kWideWaves * 64>(qrs, count, force, true, sel, blockIdx.x);
   if (job < 0) return;
   const QrDesc& D = qrs[job];
   const bool broke = !D.hh_direct && *D.flag != 0;
@@ -974,11 +978,11 @@ __global__ __launch_bounds__(kWideWaves * 64) void householder_wide_kernel(
 static_assert(kWideRows <= 48 * kWideWaves, "register window of the wide Householder path");
 
 __global__ __launch_bounds__(256) void householder_kernel(const QrDesc* __restrict__ qrs,
-                                                          int count, int force,
+                                                          int count, int force, int sel,
                                                           unsigned long long* counter,
                                                           int64_t lds_elems) {
   extern __shared__ __align__(16) double hsm[];
-  const int job = hh_nth_job<256>(qrs, count, force, false, blockIdx.x);
+  const int job = hh_nth_job<256>(qrs, count, force, false, sel, blockIdx.x);
   if (job < 0) return;
   const QrDesc& D = qrs[job];
   const bool broke = !D.hh_direct && *D.flag != 0;
@@ -1081,7 +1085,7 @@ hipError_t launch_chol(const QrDesc* qr, int count, int pass, double tol, int wm
 }
 
 hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* fallback_counter,
-                              int64_t max_elems, int kernels, hipStream_t stream) {
+                              int64_t max_elems, int sel, const int* grid, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
   // LDS for the largest panel (plus tau, signs and reduction slots), capped
   int64_t elems = max_elems < kHhLdsMax ? max_elems : kHhLdsMax;
@@ -1094,15 +1098,15 @@ hipError_t launch_householder(const QrDesc* qr, int count, int force, int64_t* f
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  if (kernels & 1) {
-    householder_wide_kernel<<<dim3((unsigned)count), dim3(kWideWaves * 64), 0, stream>>>(
-        qr, count, force, (unsigned long long*)fallback_counter);
+  if (grid[0] > 0) {
+    householder_wide_kernel<<<dim3((unsigned)grid[0]), dim3(kWideWaves * 64), 0, stream>>>(
+        qr, count, force, sel, (unsigned long long*)fallback_counter);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (kernels & 2) {
-    householder_kernel<<<dim3((unsigned)count), dim3(256), (size_t)elems * sizeof(double), stream>>>(
-        qr, count, force, (unsigned long long*)fallback_counter, elems);
+  if (grid[1] > 0) {
+    householder_kernel<<<dim3((unsigned)grid[1]), dim3(256), (size_t)elems * sizeof(double), stream>>>(
+        qr, count, force, sel, (unsigned long long*)fallback_counter, elems);
     return hipGetLastError();
   }
   return hipSuccess;

@@ -66,6 +66,10 @@ struct tsk_handle_ {
   std::map<uint32_t, TuneEntry> tune;
   int force_split = 0, force_kw = 0;
   std::string arch;
+  // second stream (default priority, non-blocking) and the events that fork
+  // work onto it and join it back
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 };
 
 // Device memory of tucker_sum_recompress_noalloc: one array per device,
@@ -225,8 +229,11 @@ tsk_status validate_spec(tsk_handle h, const tsk_sketch_spec* spec, Problem& P) 
 }
 
 // ------------------------------------------------------------------ program
+// S_FORK makes the handle's second stream wait for the work enqueued so
+// far; steps marked `side` then run on that stream, and S_JOIN makes the
+// caller's stream wait for them (in a captured graph: two branches).
 enum StepKind { S_OMEGA, S_GEMM, S_KRP, S_REDUCE, S_TILE_REDUCE, S_COPY, S_FILL, S_CHOL, S_HOUSE,
-                S_KRP_ADJ, S_SYM, S_TRSM, S_EIG, S_SCATTER };
+                S_KRP_ADJ, S_SYM, S_TRSM, S_EIG, S_SCATTER, S_FORK, S_JOIN };
 
 struct Step {
   StepKind kind;
@@ -245,7 +252,9 @@ struct Step {
   int32_t value = 0;
   double tol = 0;
   int wmax = 0;  // chol: widest Gram of the launch
-  int hh_kernels = 3;  // householder: which of the two kernels have panels
+  int hh_sel = 3;             // householder: modes taken (bit 0 direct, bit 1 broken down)
+  int hh_grid[2] = {0, 0};    // householder: workgroups of the register / general kernel
+  bool side = false;          // runs on the handle's second stream (between S_FORK and S_JOIN)
   int krp_lds = 0;     // krp: LDS elements for the P slices (largest that fits)
   std::vector<uint32_t> keys;  // autotuning classes whose choices shaped this launch
   bool a32 = false;  // FP64 GEMM / core sketch whose A operands (cores) are stored in FP32
@@ -559,10 +568,13 @@ struct Builder {
 // (n_k x min(n_k, W_k)) and, when R is not empty, R[k] (min(n_k, W_k) x
 // W_k): Cholesky QR2 where W_k <= 96 <= ... fits (W_k <= min(96, n_k) and
 // policy != 1), with a device-side Householder fallback on breakdown, and
-// Householder directly otherwise.
+// Householder directly otherwise.  `rank_bound` (optional): an upper bound
+// on rank(Y[k]); under policy 0 a mode whose bound is below W_k has a
+// singular Gram, so it skips the Cholesky attempt that would break down.
 void plan_qr(Builder& B, const std::vector<int64_t>& dims, const std::vector<int64_t>& Wd,
              const std::vector<const double*>& Y, const std::vector<double*>& Q,
-             const std::vector<double*>& R, int qr_policy) {
+             const std::vector<double*>& R, int qr_policy,
+             const std::vector<int64_t>& rank_bound = {}) {
   Arena& ar = B.ar;
   const int d = (int)dims.size();
   std::vector<QrDesc> qd(d);
@@ -579,7 +591,8 @@ void plan_qr(Builder& B, const std::vector<int64_t>& dims, const std::vector<int
     q.flag = flags + n;
     q.hh = (double*)ar.take((nn * W + W) * 8);  // panel, then the R-diagonal signs
     q.tau = (double*)ar.take(W * 8);
-    const bool chol = qr_policy != 1 && W <= 96 && W <= nn;
+    const bool deficient = qr_policy == 0 && !rank_bound.empty() && rank_bound[n] < W;
+    const bool chol = qr_policy != 1 && W <= 96 && W <= nn && !deficient;
     q.hh_direct = chol ? 0 : 1;
     q.report_only = qr_policy == 2 ? 1 : 0;
     if (chol) {
@@ -1020,7 +1033,13 @@ void build_sum(const Problem& P, const Outputs& out, Builder& B) {
   std::vector<double*> Qd(d);
   for (int n = 0; n < d; ++n)
     Qd[n] = out.out_f64 ? (double*)out.Q[n] : (double*)ar.take(P.dims[n] * P.w[n] * 8);
-  plan_qr(B, P.dims, P.W, std::vector<const double*>(Y.begin(), Y.end()), Qd, out.R, P.qr_policy);
+  // Y_n = X_(n) S_n lies in the span of the terms' mode-n factors, so its
+  // rank is at most the sum's total mode-n rank
+  std::vector<int64_t> total_rank(d, 0);
+  for (int n = 0; n < d; ++n)
+    for (int i = 0; i < s; ++i) total_rank[n] += P.r(i, n);
+  plan_qr(B, P.dims, P.W, std::vector<const double*>(Y.begin(), Y.end()), Qd, out.R, P.qr_policy,
+          total_rank);
 
   // ---- core projection (Section 3.3)
   std::vector<CopyJob>& cq = B.copies[ST_QCOPY];
@@ -1083,6 +1102,37 @@ void Builder::emit(Program& prog) {
   emit_gemm_stage(ST_EXPAND);
   if (!qr.empty()) {
     const size_t qmeta = prog.put(qr);
+    // modes planned for Householder directly and modes that try Cholesky QR
+    // first, per kernel kind (register kernel, general kernel)
+    int direct[2] = {0, 0}, tried[2] = {0, 0};
+    int64_t general_elems = 0;
+    for (const QrDesc& q : qr) {
+      const int k = hh_wide_panel(q.n, q.W) ? 0 : 1;
+      (q.hh_direct ? direct : tried)[k] += 1;
+      if (k == 1) general_elems = std::max<int64_t>(general_elems, (q.n + 1) * q.W + 2 * q.W);
+    }
+    auto house = [&](int sel, int grid_reg, int grid_gen, bool side) {
+      Step hh{};
+      hh.kind = S_HOUSE;
+      hh.meta = qmeta;
+      hh.count = (int)qr.size();
+      hh.ptr = d_counter;
+      hh.hh_sel = sel;
+      hh.hh_grid[0] = grid_reg;
+      hh.hh_grid[1] = grid_gen;
+      hh.rows = general_elems;
+      hh.side = side;
+      prog.steps.push_back(hh);
+    };
+    // the direct modes need nothing from the Cholesky passes: they run on the
+    // second stream, beside the passes of the other modes
+    const bool fork = any_chol && direct[0] + direct[1] > 0;
+    if (fork) {
+      Step f{};
+      f.kind = S_FORK;
+      prog.steps.push_back(f);
+      house(1, direct[0], direct[1], true);
+    }
     if (any_chol) {
       for (int pass = 1; pass <= 2; ++pass) {
         emit_gemm_stage(pass == 1 ? ST_GRAM1 : ST_GRAM2);
@@ -1103,21 +1153,15 @@ void Builder::emit(Program& prog) {
         emit_gemm_stage(pass == 1 ? ST_BASIS1 : ST_BASIS2);
       }
     }
-    Step hh{};
-    hh.kind = S_HOUSE;
-    hh.meta = qmeta;
-    hh.count = (int)qr.size();
-    hh.ptr = d_counter;
-    hh.hh_kernels = 0;
-    for (const QrDesc& q : qr) {
-      if (hh_wide_panel(q.n, q.W)) {
-        hh.hh_kernels |= 1;
-      } else {
-        hh.hh_kernels |= 2;
-        hh.rows = std::max<int64_t>(hh.rows, (q.n + 1) * q.W + 2 * q.W);
-      }
+    if (fork)
+      house(2, tried[0], tried[1], false);
+    else
+      house(3, direct[0] + tried[0], direct[1] + tried[1], false);
+    if (fork) {
+      Step j{};
+      j.kind = S_JOIN;
+      prog.steps.push_back(j);
     }
-    prog.steps.push_back(hh);
   }
   emit_copy_stage(ST_QCOPY);
   emit_gemm_stage(ST_PROJW);
@@ -1597,6 +1641,8 @@ std::string step_name(const Step& st) {
     case S_TRSM: return "trsm_rt_kernel";
     case S_EIG: return st.pass == 1 ? "tridiag_eig_kernel" : "jacobi_eig_kernel";
     case S_SCATTER: return "block_scatter_kernel";
+    case S_FORK: return "fork";
+    case S_JOIN: return "join";
   }
   return "unknown";
 }
@@ -1670,6 +1716,16 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
   }
   for (const Step& st : prog.steps) {
     hipError_t e = hipSuccess;
+    if (st.kind == S_FORK || st.kind == S_JOIN) {
+      hipEvent_t ev = st.kind == S_FORK ? h->fork_ev : h->join_ev;
+      hipStream_t from = st.kind == S_FORK ? stream : h->side;
+      hipStream_t to = st.kind == S_FORK ? h->side : stream;
+      if (hipEventRecord(ev, from) != hipSuccess || hipStreamWaitEvent(to, ev, 0) != hipSuccess)
+        return fail(h, TSK_ERR_DEVICE, "stream %s failed", st.kind == S_FORK ? "fork" : "join");
+      continue;
+    }
+    const hipStream_t caller = stream;
+    hipStream_t stream = st.side ? h->side : caller;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (prof) {
       for (hipEvent_t* ev : {&ev0, &ev1}) {
@@ -1711,9 +1767,11 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
         e = st.pass == 1 ? launch_tridiag_eig((const EigJob*)(meta + st.meta), st.count, st.wmax, stream)
                          : launch_jacobi_eig((const EigJob*)(meta + st.meta), st.count, st.wmax, stream);
         break;
+      case S_FORK:
+      case S_JOIN: break;  // handled above
       case S_HOUSE:
         e = launch_householder((const QrDesc*)(meta + st.meta), st.count, st.force, (int64_t*)st.ptr,
-                               st.rows, st.hh_kernels, stream);
+                               st.rows, st.hh_sel, st.hh_grid, stream);
         break;
     }
     if (e != hipSuccess) return fail(h, TSK_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -2516,8 +2574,18 @@ int64_t max_off(std::initializer_list<std::pair<int64_t, int64_t>> terms) {
 
 void check_program(const Program& prog, Checker& ck) {
   const char* blob = prog.blob.data();
+  bool forked = false;  // between S_FORK and S_JOIN
   for (const Step& st : prog.steps) {
+    if (st.side && !forked) { ck.ok = false; ck.err = "second-stream launch outside a fork"; return; }
     switch (st.kind) {
+      case S_FORK:
+        if (forked) { ck.ok = false; ck.err = "fork inside a fork"; return; }
+        forked = true;
+        break;
+      case S_JOIN:
+        if (!forked) { ck.ok = false; ck.err = "join without a fork"; return; }
+        forked = false;
+        break;
       case S_OMEGA: {
         const OmegaJob* js = (const OmegaJob*)(blob + st.meta);
         for (int i = 0; i < st.count; ++i) ck.span(js[i].out, 0, js[i].count - 1, js[i].f64 ? 8 : 4, "omega");
@@ -2696,6 +2764,7 @@ void check_program(const Program& prog, Checker& ck) {
       case S_CHOL:
       case S_HOUSE: {
         const QrDesc* qs = (const QrDesc*)(blob + st.meta);
+        int hh_take[2] = {0, 0};
         for (int i = 0; i < st.count; ++i) {
           const QrDesc& q = qs[i];
           ck.span(q.Y, 0, q.n * q.W - 1, 8, "qr Y");
@@ -2704,10 +2773,10 @@ void check_program(const Program& prog, Checker& ck) {
           ck.span(q.tau, 0, q.W - 1, 8, "qr tau");
           ck.span(q.flag, 0, 0, 4, "qr flag");
           if (q.R) ck.span(q.R, 0, q.w * q.W - 1, 8, "qr R");
-          if (st.kind == S_HOUSE && !(st.hh_kernels & (hh_wide_panel(q.n, q.W) ? 1 : 2))) {
-            ck.ok = false;
-            ck.err = "householder panel whose kernel is not launched";
-            return;
+          if (st.kind == S_HOUSE) {
+            // every mode the launch may take has a workgroup of its kernel
+            const bool takes = (q.hh_direct || st.force) ? (st.hh_sel & 1) : (st.hh_sel & 2);
+            if (takes) ++hh_take[hh_wide_panel(q.n, q.W) ? 0 : 1];
           }
           if (st.kind == S_CHOL && q.gram_part && q.W <= 96 && q.W <= q.n) {
             if (q.W > st.wmax) { ck.ok = false; ck.err = "chol LDS sized below a Gram width"; return; }
@@ -2717,11 +2786,16 @@ void check_program(const Program& prog, Checker& ck) {
             ck.span(q.q1, 0, q.n * q.W - 1, 8, "qr q1");
           }
         }
+        if (st.kind == S_HOUSE && (hh_take[0] > st.hh_grid[0] || hh_take[1] > st.hh_grid[1])) {
+          ck.ok = false;
+          ck.err = "householder launch with fewer workgroups than modes";
+        }
         break;
       }
     }
     if (!ck.ok) return;
   }
+  if (forked) { ck.ok = false; ck.err = "fork without a join"; }
 }
 
 // One line per launch of a checked plan: kernel, descriptors, workgroups,
@@ -2743,8 +2817,10 @@ static std::string describe_program(const Program& prog) {
     } else if (st.kind == S_KRP) {
       const KrpDesc* ds = (const KrpDesc*)(blob + st.meta);
       for (int i = 0; i < st.count; ++i) max_split = std::max(max_split, (int)ds[i].splits);
-    } else if (st.kind == S_CHOL || st.kind == S_HOUSE) {
+    } else if (st.kind == S_CHOL) {
       blocks = st.count;
+    } else if (st.kind == S_HOUSE) {
+      blocks = st.hh_grid[0] + st.hh_grid[1];
     }
     snprintf(line, sizeof line, "%-40s descs=%d blocks=%lld max_split=%d max_seg=%d flops=%.3g\n",
              step_name(st).c_str(), st.count, (long long)blocks, max_split, max_seg, st.flops);
@@ -3272,9 +3348,14 @@ tsk_status tsk_create(tsk_handle* handle, int device) {
   }
   if (hipHostMalloc(&h->fixed_stage, kFixedStageBytes, hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&h->fixed_stage_done, hipEventDisableTiming) != hipSuccess ||
-      hipEventRecord(h->fixed_stage_done, nullptr) != hipSuccess) {
+      hipEventRecord(h->fixed_stage_done, nullptr) != hipSuccess ||
+      hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming) != hipSuccess) {
     if (h->fixed_stage) hipHostFree(h->fixed_stage);
     if (h->fixed_stage_done) hipEventDestroy(h->fixed_stage_done);
+    if (h->side) hipStreamDestroy(h->side);
+    if (h->fork_ev) hipEventDestroy(h->fork_ev);
     hipFree(h->d_counter);
     delete h;
     return TSK_ERR_OUT_OF_MEMORY;
@@ -3294,6 +3375,9 @@ tsk_status tsk_destroy(tsk_handle h) {
   for (void* p : h->pinned_keep) hipHostFree(p);
   if (h->fixed_stage_done) hipEventDestroy(h->fixed_stage_done);
   if (h->fixed_stage) hipHostFree(h->fixed_stage);
+  if (h->fork_ev) hipEventDestroy(h->fork_ev);
+  if (h->join_ev) hipEventDestroy(h->join_ev);
+  if (h->side) hipStreamDestroy(h->side);
   for (auto& r : h->prof_records) {
     hipEventDestroy(r.begin);
     hipEventDestroy(r.end);

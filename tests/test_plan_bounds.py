@@ -94,8 +94,9 @@ def test_long_modes_beyond_31_bit_tile_offsets_are_rejected(n, prec, ok):
     offsets from its origin, and offsets of 2^31 and up read as zero.  The
     Gram product of the QR reads the FP64 Y_n with stride n across a tile
     (in every precision form), so a mode of 5M rows must be refused as
-    unsupported instead of silently computing with zeros."""
-    rc, msg = selfcheck((n, 6), [[2, 2]], "krp", [4], prec, prec, prec == "fp64", prec == "fp64")
+    unsupported instead of silently computing with zeros.  (Rank 4 at width
+    4, so that the mode's QR is planned as Cholesky QR.)"""
+    rc, msg = selfcheck((n, 6), [[4, 4]], "krp", [4], prec, prec, prec == "fp64", prec == "fp64")
     if ok:
         assert rc == 0, msg
     else:
@@ -368,3 +369,57 @@ def test_subranks_batched_plan_in_bounds():
         msg = ctypes.create_string_buffer(512)
         rc = fn(len(sums), c_sums, msg, 512)
         assert rc == 0, msg.value.decode()
+
+
+def describe(dims, ranks, kind, sizes):
+    """The planner's launch list of one sum (tsk_plan_describe), one kernel
+    name per launch."""
+    from paper_2603_13532_amd import _lib
+    lib = _lib.load()
+    fn = lib.tsk_plan_describe
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_int32, ctypes.POINTER(_lib.TuckerSum), ctypes.POINTER(_lib.SketchSpec),
+                   ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
+    ranks = np.asarray(ranks)
+    s, d = ranks.shape
+    c_dims = (ctypes.c_int64 * d)(*dims)
+    c_ranks = (ctypes.c_int32 * (s * d))(*[int(x) for x in ranks.ravel()])
+    c_cores = (ctypes.c_void_p * s)(*([0x1000] * s))
+    c_fac = (ctypes.c_void_p * (s * d))(*([0x1000] * (s * d)))
+    c_sizes = (ctypes.c_int32 * len(sizes))(*sizes)
+    tsum = _lib.TuckerSum(d, s, c_dims, c_ranks, c_cores, c_fac, None, 0)
+    spec = _lib.SketchSpec(_lib.KINDS[kind], c_sizes, 5, None, _lib.PRECISIONS["fp64"],
+                           _lib.PRECISIONS["fp64"], 0)
+    msg = ctypes.create_string_buffer(1 << 14)
+    rc = fn(1, ctypes.byref(tsum), ctypes.byref(spec), 0, msg, 1 << 14)
+    assert rc == 0, msg.value.decode()
+    lines = msg.value.decode().splitlines()[:-1]
+    return [ln.split()[0] for ln in lines], lines
+
+
+def test_rank_deficient_mode_skips_cholesky_and_overlaps_it():
+    """A mode whose total rank (sum over terms of r_n) is below its sketch
+    width has a rank-deficient Y_n, so its Gram is singular and Cholesky QR
+    would break down: the plan sends it to Householder directly, in a launch
+    forked onto the second stream before the other modes' Cholesky passes
+    and joined before the projection."""
+    # mode 0: total rank 6 < 10 (deficient); modes 1, 2: 30 >= 10
+    names, lines = describe((200, 100, 100), [[3, 15, 15], [3, 15, 15]], "krp", [10])
+    assert names.count("fork") == 1 and names.count("join") == 1
+    f, j = names.index("fork"), names.index("join")
+    assert names[f + 1] == "householder_kernel"
+    assert int(lines[f + 1].split("blocks=")[1].split()[0]) == 1  # the one deficient mode
+    chol = [i for i, n in enumerate(names) if n == "chol_kernel"]
+    assert len(chol) == 2 and all(f + 1 < i < j for i in chol)
+    # the breakdown launch for the Cholesky modes comes after both passes
+    hh = [i for i, n in enumerate(names) if n == "householder_kernel"]
+    assert len(hh) == 2 and chol[-1] < hh[1] < j
+    assert int(lines[hh[1]].split("blocks=")[1].split()[0]) == 2
+    assert all(i > j for i, n in enumerate(names) if n.startswith("gemm_kernel")
+               and ("proj_w" in lines[i] or "proj_final" in lines[i]))
+    # full rank in every mode: no fork, one Householder launch after the passes
+    names, _ = describe((200, 100, 100), [[6, 15, 15], [6, 15, 15]], "krp", [10])
+    assert "fork" not in names and "join" not in names
+    assert names.count("householder_kernel") == 1
+    assert names.index("householder_kernel") > max(i for i, n in enumerate(names)
+                                                   if n == "chol_kernel")
