@@ -317,7 +317,7 @@ template <int P> struct Depth { static constexpr int value = 2; };
 // outside the output tile: it fetches and stages its share and meets every
 // barrier, but issues no MFMAs (the choice is made once, outside the loop,
 // so the loop body stays one basic block).
-template <int P, int D, bool MMA, class Cur, int KW = 1>
+template <int P, int D, bool MMA, class Cur, int KW = 1, int MB = 2>
 __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type (&s)[2],
                                       typename PT<P>::acc_t (&acc)[2][2], int t, int lane, int wm,
                                       int wn, int phase = 0) {
@@ -364,7 +364,7 @@ __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type
       cur.fetch(ra[d], rb[d], have);
       const bool fa = cur.a_xc, fb = cur.b_xc;
       const in_t fal = cur.alpha;
-      if constexpr (MMA) mma_tile<P, KW>(s[buf], acc, lane, wm, wn, phase);
+      if constexpr (MMA) mma_tile<P, KW, MB>(s[buf], acc, lane, wm, wn, phase);
       const int nx = (d + 1) % D;
       stage<P>(s[buf ^ 1], map, ax[nx], bx[nx], t, ra[nx], rb[nx], al[nx]);
       --inflight;
@@ -390,23 +390,28 @@ __device__ __forceinline__ void kloop(Cur& cur, bool have, typename Lds<P>::type
 // step of the K-tile, so no SIMD idles; BF16 K-tiles are a single step, and
 // their waves outside the region skip the MFMAs (kw = 1, `active` false).
 // kw_max (a tuning choice of the launch) caps the sharing: below 4 a
-// one-quadrant tile, below 2 a two-quadrant tile, keeps kw = 1.
+// one-quadrant tile, below 2 a two-quadrant tile, keeps kw = 1.  mb: the
+// 16-row blocks of the wave's quadrant that hold valid rows (FP64/FP32: 1
+// when they all lie in the first block, whose MFMAs are then the only ones
+// issued; otherwise 2).
 struct WaveRole {
   int kw, wm, wn, phase;
   bool active;
+  int mb;
 };
 template <int P>
 __device__ __forceinline__ WaveRole wave_role(int w, int mr, int nc, int kw_max) {
+  auto blocks = [&](int wm) { return (P == P_FP64 || P == P_FP32) && mr - 32 * wm <= 16 ? 1 : 2; };
   if constexpr (P == P_FP64 || P == P_FP32) {
     const int qm = mr > 32 ? 2 : 1, qn = nc > 32 ? 2 : 1;
-    if (qm * qn == 1 && kw_max >= 4) return WaveRole{4, 0, 0, w, true};
+    if (qm * qn == 1 && kw_max >= 4) return WaveRole{4, 0, 0, w, true, blocks(0)};
     if (qm * qn == 2 && kw_max >= 2) {
-      const int q = w & 1;
-      return WaveRole{2, qm == 2 ? q : 0, qm == 2 ? 0 : q, w >> 1, true};
+      const int q = w & 1, wm = qm == 2 ? q : 0;
+      return WaveRole{2, wm, qm == 2 ? 0 : q, w >> 1, true, blocks(wm)};
     }
   }
   const int wm = w & 1, wn = w >> 1;
-  return WaveRole{1, wm, wn, 0, wm * 32 < mr && wn * 32 < nc};
+  return WaveRole{1, wm, wn, 0, wm * 32 < mr && wn * 32 < nc, blocks(wm)};
 }
 
 // K-loop with the wave role chosen per tile (one branch, outside the loop).
@@ -417,11 +422,17 @@ __device__ __forceinline__ void kloop_role(Cur& cur, bool have, typename Lds<P>:
   constexpr int D = Depth<P>::value;
   if constexpr (P == P_FP64 || P == P_FP32) {
     if (role.kw == 4) {
-      kloop<P, D, true, Cur, 4>(cur, have, s, acc, t, lane, role.wm, role.wn, role.phase);
+      if (role.mb == 1) kloop<P, D, true, Cur, 4, 1>(cur, have, s, acc, t, lane, role.wm, role.wn, role.phase);
+      else kloop<P, D, true, Cur, 4>(cur, have, s, acc, t, lane, role.wm, role.wn, role.phase);
       return;
     }
     if (role.kw == 2) {
-      kloop<P, D, true, Cur, 2>(cur, have, s, acc, t, lane, role.wm, role.wn, role.phase);
+      if (role.mb == 1) kloop<P, D, true, Cur, 2, 1>(cur, have, s, acc, t, lane, role.wm, role.wn, role.phase);
+      else kloop<P, D, true, Cur, 2>(cur, have, s, acc, t, lane, role.wm, role.wn, role.phase);
+      return;
+    }
+    if (role.active && role.mb == 1) {
+      kloop<P, D, true, Cur, 1, 1>(cur, have, s, acc, t, lane, role.wm, role.wn);
       return;
     }
   }
@@ -490,7 +501,7 @@ __global__ __launch_bounds__(NTHREADS, 4) void gemm_kernel(const GemmDesc* __res
   // one quadrant per wave here: the shared-quadrant variants of the K-loop
   // push this kernel past its 128-register budget (it spills), and at two
   // workgroups per CU the lost occupancy costs what the shared quadrants save
-  const WaveRole role{1, w & 1, w >> 1, 0, (w & 1) * 32 < M - m0 && (w >> 1) * 32 < N - n0};
+  const WaveRole role{1, w & 1, w >> 1, 0, (w & 1) * 32 < M - m0 && (w >> 1) * 32 < N - n0, 2};
   if (have) {
     if (role.active) kloop<P, Depth<P>::value, true>(cur, have, s, acc, t, lane, role.wm, role.wn);
     else kloop<P, Depth<P>::value, false>(cur, have, s, acc, t, lane, role.wm, role.wn);

@@ -129,11 +129,16 @@ __device__ __forceinline__ void lds_put(typename Lds<P>::type& s, int which, int
 // takes the 4-deep steps p, p + KW, ... of each K-tile, so a tile whose
 // valid region covers fewer than four quadrants still keeps every wave's
 // MFMA pipe busy; the partial accumulators are summed in the epilogue.
-template <int P, int KW = 1>
+//
+// MB = 1 (FP64/FP32 only): the quadrant's valid rows all lie in its first
+// 16-row block, so only that block row is computed (the second one's
+// accumulators stay zero); chosen per wave outside the K-loop.
+template <int P, int KW = 1, int MB = 2>
 __device__ __forceinline__ void mma_tile(const typename Lds<P>::type& s,
                                          typename PT<P>::acc_t (&acc)[2][2], int lane, int wm,
                                          int wn, int phase = 0) {
   const int r = lane & 15, kq = lane >> 4;
+  static_assert(MB == 2 || P == P_FP64 || P == P_FP32, "row-block skipping is FP64/FP32 only");
   if constexpr (P == P_FP64 || P == P_FP32) {
     // Fragments of the whole K-tile are read up front; every 16 x 16 block
     // is computed (MFMAs under per-block branches also make the compiler
@@ -147,14 +152,14 @@ __device__ __forceinline__ void mma_tile(const typename Lds<P>::type& s,
       const int q = (KW == 1) ? qq : phase + KW * qq;
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        a[qq][i] = s.a[4 * q + kq][wm * 32 + 16 * i + r];
+        if (i < MB) a[qq][i] = s.a[4 * q + kq][wm * 32 + 16 * i + r];
         b[qq][i] = s.b[4 * q + kq][wn * 32 + 16 * i + r];
       }
     }
 #pragma unroll
     for (int qq = 0; qq < NQ; ++qq)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < MB; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = mma(a[qq][i], b[qq][j], acc[i][j]);
   } else {

@@ -410,8 +410,42 @@ GemmSeg seg(const void* A, int64_t a_sx, int64_t a_sk, int64_t sA, const void* B
   return g;
 }
 
+int64_t tiles_of(const GemmDesc& d) { return (int64_t)d.tiles_m * d.tiles_n * d.batch * d.splits; }
+int64_t tiles_of(const KrpDesc& d) { return (int64_t)d.tiles_m * d.tiles_n * d.splits; }
+
+// Workgroups are dispatched in tile order, so a descriptor's place in its
+// launch decides when its tiles start.  Descriptors go longest tile first
+// (K per split, descending; equal ones keep their order) so that no long
+// tile starts last and runs alone at the end of the launch, and tile_begin
+// is renumbered.  Each tile's arithmetic does not depend on the order.
+template <typename D, typename KofD>
+void longest_first(std::vector<D>& ds, KofD k_of) {
+  std::vector<size_t> idx(ds.size());
+  std::vector<int64_t> key(ds.size());
+  for (size_t i = 0; i < ds.size(); ++i) {
+    idx[i] = i;
+    key[i] = ceil_div(k_of(ds[i]), (int64_t)std::max<int32_t>(ds[i].splits, 1));
+  }
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return key[a] > key[b]; });
+  std::vector<D> out;
+  out.reserve(ds.size());
+  int64_t tiles = 0;
+  for (size_t i : idx) {
+    D d = ds[i];
+    d.tile_begin = tiles;
+    tiles += tiles_of(d);
+    out.push_back(d);
+  }
+  ds.swap(out);
+}
+
 void emit_gemm(Program& prog, GemmBatch& gb) {
   if (gb.descs.empty()) return;
+  longest_first(gb.descs, [&](const GemmDesc& d) {
+    int64_t K = 0;
+    for (int j = 0; j < d.seg_count; ++j) K += gb.segs[d.seg_begin + j].K;
+    return K;
+  });
   Step st{};
   st.kind = S_GEMM;
   st.prec = gb.prec;
@@ -1080,6 +1114,7 @@ void Builder::emit(Program& prog) {
     st.prec = krp_prec;
     st.flops = krp_flops;
     st.bytes = krp_bytes;
+    longest_first(krp, [](const KrpDesc& d) { return d.Kc; });
     st.meta = prog.put(krp);
     st.count = (int)krp.size();
     st.tiles = krp_tiles;
