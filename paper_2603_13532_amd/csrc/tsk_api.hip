@@ -54,7 +54,7 @@ struct tsk_handle_ {
   int64_t* d_counter = nullptr;
   std::vector<Staging> ring;
   size_t ring_next = 0;
-  std::vector<void*> pinned_keep;  // staging owned by captured graphs
+  std::vector<void*> device_keep;  // descriptor copies owned by captured graphs
   // tucker_sum_recompress_noalloc: the device address of this device's
   // static scratch array, and pinned staging for its descriptor upload,
   // both set up by tsk_create
@@ -1682,17 +1682,7 @@ std::string step_name(const Step& st) {
   return "unknown";
 }
 
-tsk_status acquire_staging(tsk_handle h, size_t bytes, bool capturing, void** host,
-                           hipEvent_t* ev) {
-  if (capturing) {
-    void* p = nullptr;
-    if (hipHostMalloc(&p, std::max<size_t>(bytes, 64), hipHostMallocDefault) != hipSuccess)
-      return fail(h, TSK_ERR_OUT_OF_MEMORY, "pinned staging allocation failed");
-    h->pinned_keep.push_back(p);
-    *host = p;
-    *ev = nullptr;
-    return TSK_OK;
-  }
+tsk_status acquire_staging(tsk_handle h, size_t bytes, void** host, hipEvent_t* ev) {
   if (h->ring.empty()) h->ring.resize(8);
   Staging& sl = h->ring[h->ring_next];
   h->ring_next = (h->ring_next + 1) % h->ring.size();
@@ -1739,13 +1729,31 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
         return fail(h, TSK_ERR_DEVICE, "waiting for the previous descriptor upload failed");
       host = h->fixed_stage;
       ev = h->fixed_stage_done;
+    } else if (capturing) {
+      // A captured call keeps its descriptors in device memory of the
+      // handle's (until tsk_destroy), filled once here through the handle's
+      // idle second stream; the graph copies them into the workspace on the
+      // device, so a replay neither reads host memory over the bus nor relies
+      // on the workspace keeping them between replays.
+      void* dev = nullptr;
+      if (hipMalloc(&dev, prog.blob.size()) != hipSuccess)
+        return fail(h, TSK_ERR_OUT_OF_MEMORY, "descriptor copy allocation failed");
+      h->device_keep.push_back(dev);
+      if (hipMemcpyAsync(dev, prog.blob.data(), prog.blob.size(), hipMemcpyHostToDevice,
+                         h->side) != hipSuccess ||
+          hipStreamSynchronize(h->side) != hipSuccess)
+        return fail(h, TSK_ERR_DEVICE, "descriptor copy failed");
+      if (hipMemcpyAsync(meta, dev, prog.blob.size(), hipMemcpyDeviceToDevice, stream) != hipSuccess)
+        return fail(h, TSK_ERR_DEVICE, "descriptor upload failed");
     } else {
-      tsk_status st = acquire_staging(h, prog.blob.size(), capturing, &host, &ev);
+      tsk_status st = acquire_staging(h, prog.blob.size(), &host, &ev);
       if (st != TSK_OK) return st;
     }
-    std::memcpy(host, prog.blob.data(), prog.blob.size());
-    if (hipMemcpyAsync(meta, host, prog.blob.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
-      return fail(h, TSK_ERR_DEVICE, "descriptor upload failed");
+    if (host != nullptr) {
+      std::memcpy(host, prog.blob.data(), prog.blob.size());
+      if (hipMemcpyAsync(meta, host, prog.blob.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
+        return fail(h, TSK_ERR_DEVICE, "descriptor upload failed");
+    }
     if (ev != nullptr && hipEventRecord(ev, stream) != hipSuccess)
       return fail(h, TSK_ERR_DEVICE, "hipEventRecord failed");
   }
@@ -3407,7 +3415,7 @@ tsk_status tsk_destroy(tsk_handle h) {
     if (sl.done) hipEventDestroy(sl.done);
     if (sl.host) hipHostFree(sl.host);
   }
-  for (void* p : h->pinned_keep) hipHostFree(p);
+  for (void* p : h->device_keep) hipFree(p);
   if (h->fixed_stage_done) hipEventDestroy(h->fixed_stage_done);
   if (h->fixed_stage) hipHostFree(h->fixed_stage);
   if (h->fork_ev) hipEventDestroy(h->fork_ev);

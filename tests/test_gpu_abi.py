@@ -149,3 +149,59 @@ def test_graph_replay_matches_eager(env):
     q2, h2 = eager()
     torch.cuda.synchronize()
     assert torch.equal(h, h2)
+
+
+def test_replay_refreshes_descriptors_after_workspace_reuse(env):
+    """A captured call copies its launch descriptors into the workspace on
+    every replay (from a device copy the handle keeps), so another call that
+    reuses the same workspace between replays, overwriting them and every
+    intermediate, does not change what the replay computes."""
+    import torch
+    tsk, _lib, lib = env
+    h = tsk.Handle.get(DEV)
+
+    def setup(ts, sizes):
+        m = marshal(tsk, ts, "krp", sizes)
+        need = ctypes.c_size_t()
+        assert lib.tucker_sum_workspace_size(h.ptr, ctypes.byref(m.sum), ctypes.byref(m.spec),
+                                             ctypes.byref(need)) == 0
+        w = sizes[0]
+        qs = [tsk.empty_fortran((n, min(n, w)), torch.float64, DEV) for n in m.dims]
+        hh = tsk.empty_fortran(tuple(min(n, w) for n in m.dims), torch.float64, DEV)
+        cq = (ctypes.c_void_p * len(qs))(*[q.data_ptr() for q in qs])
+        return m, need.value, qs, hh, cq
+
+    def call(m, qs, hh, cq, ws, nbytes, stream):
+        st = lib.tucker_sum_recompress(h.ptr, ctypes.byref(m.sum), ctypes.byref(m.spec), cq,
+                                       ctypes.c_void_p(hh.data_ptr()), 0, None,
+                                       ctypes.c_void_p(ws.data_ptr()), nbytes,
+                                       ctypes.c_void_p(stream))
+        assert st == 0, lib.tsk_last_error_detail(h.ptr)
+
+    a = setup(synth.random_sum(11, (80, 72, 64), [[9, 7, 8], [6, 10, 5]]), (14,))
+    b = setup(synth.random_sum(12, (96, 88, 70), [[12, 11, 10], [8, 9, 7], [5, 5, 5]]), (20,))
+    ws = torch.empty(max(a[1], b[1]), dtype=torch.uint8, device=DEV)
+    cur = torch.cuda.current_stream(DEV)
+    call(a[0], a[2], a[3], a[4], ws, ws.numel(), cur.cuda_stream)
+    torch.cuda.synchronize()
+    want_h = a[3].clone()
+    want_q = [q.clone() for q in a[2]]
+
+    gs = torch.cuda.Stream(DEV)
+    graph = torch.cuda.CUDAGraph()
+    gs.wait_stream(cur)
+    with torch.cuda.graph(graph, stream=gs, capture_error_mode="relaxed"):
+        call(a[0], a[2], a[3], a[4], ws, ws.numel(), gs.cuda_stream)
+    cur.wait_stream(gs)
+    for rep in range(3):
+        # the other sum through the same workspace: its descriptors and
+        # intermediates overwrite the captured call's
+        call(b[0], b[2], b[3], b[4], ws, ws.numel(), cur.cuda_stream)
+        a[3].fill_(float("nan"))
+        for q in a[2]:
+            q.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(a[3], want_h), rep
+        for q, wq in zip(a[2], want_q):
+            assert torch.equal(q, wq), rep
