@@ -113,7 +113,14 @@ typedef struct {
  * priority: a call forks independent launches onto it from the caller's
  * stream and joins them back before it returns (the caller's stream waits
  * for them, so stream order is kept and a captured graph holds both
- * branches). */
+ * branches).
+ *
+ * Graph capture: a call made while `stream` is being captured (relaxed
+ * mode) allocates a device copy of its launch descriptors, which the handle
+ * holds until tsk_destroy, and records a device-to-device copy of them into
+ * the workspace; every replay therefore rewrites what it needs, and other
+ * calls may use the same workspace between replays.  The capture itself
+ * waits on the handle's second stream while filling that copy. */
 tsk_status tsk_create(tsk_handle* handle, int device);
 tsk_status tsk_destroy(tsk_handle handle);
 const char* tsk_status_string(tsk_status status);
