@@ -52,7 +52,9 @@ static_assert(sizeof(GemmSeg) % 8 == 0, "segments are copied as 8-byte words");
 struct GemmDesc {
   void* C;
   void* part;          // splits > 1: per-tile partial blocks (64 x 64, accumulator type)
-  int64_t ldc, strideC, strideSplit;
+  int64_t ldc, strideC;
+  int32_t bpw;         // batch elements per workgroup (one-tile elements, splits == 1)
+  int32_t pad_;
   int32_t M, N, batch, splits;
   int32_t seg_begin, seg_count;
   int32_t tiles_m, tiles_n;

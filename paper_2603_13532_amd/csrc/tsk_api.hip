@@ -345,7 +345,7 @@ struct GemmBatch {
     D.C = C;
     D.ldc = ldc;
     D.strideC = strideC;
-    D.strideSplit = 0;
+    D.bpw = 1;
     D.beta = beta;
     D.part = nullptr;
     if (splits > 1) {
@@ -410,7 +410,9 @@ GemmSeg seg(const void* A, int64_t a_sx, int64_t a_sk, int64_t sA, const void* B
   return g;
 }
 
-int64_t tiles_of(const GemmDesc& d) { return (int64_t)d.tiles_m * d.tiles_n * d.batch * d.splits; }
+int64_t tiles_of(const GemmDesc& d) {
+  return (int64_t)d.tiles_m * d.tiles_n * ceil_div(d.batch, std::max<int32_t>(d.bpw, 1)) * d.splits;
+}
 int64_t tiles_of(const KrpDesc& d) { return (int64_t)d.tiles_m * d.tiles_n * d.splits; }
 
 // Workgroups are dispatched in tile order, so a descriptor's place in its
@@ -419,7 +421,7 @@ int64_t tiles_of(const KrpDesc& d) { return (int64_t)d.tiles_m * d.tiles_n * d.s
 // tile starts last and runs alone at the end of the launch, and tile_begin
 // is renumbered.  Each tile's arithmetic does not depend on the order.
 template <typename D, typename KofD>
-void longest_first(std::vector<D>& ds, KofD k_of) {
+int64_t longest_first(std::vector<D>& ds, KofD k_of) {
   std::vector<size_t> idx(ds.size());
   std::vector<int64_t> key(ds.size());
   for (size_t i = 0; i < ds.size(); ++i) {
@@ -437,14 +439,34 @@ void longest_first(std::vector<D>& ds, KofD k_of) {
     out.push_back(d);
   }
   ds.swap(out);
+  return tiles;
+}
+
+// Launches of many one-tile batch elements (the TTMs of the projection's
+// later modes, one per trailing index) give each workgroup bpw consecutive
+// elements, so that a tile's descriptor search and segment load are paid
+// once per group; bpw grows with the launch's element count (one per
+// kBpwElems elements, at most kMaxBpw), keeping several rounds of workgroups.
+constexpr int64_t kBpwElems = 8192;
+constexpr int kMaxBpw = 8;
+bool groupable(const GemmDesc& d) { return d.tiles_m == 1 && d.tiles_n == 1 && d.splits == 1 && d.batch > 1; }
+void group_batches(std::vector<GemmDesc>& ds) {
+  int64_t elems = 0;
+  for (const GemmDesc& d : ds)
+    if (groupable(d)) elems += d.batch;
+  const int bpw = (int)std::min<int64_t>(kMaxBpw, std::max<int64_t>(1, elems / kBpwElems));
+  if (bpw < 2) return;
+  for (GemmDesc& d : ds)
+    if (groupable(d)) d.bpw = bpw;
 }
 
 void emit_gemm(Program& prog, GemmBatch& gb) {
   if (gb.descs.empty()) return;
-  longest_first(gb.descs, [&](const GemmDesc& d) {
+  group_batches(gb.descs);
+  gb.tiles = longest_first(gb.descs, [&](const GemmDesc& d) {
     int64_t K = 0;
     for (int j = 0; j < d.seg_count; ++j) K += gb.segs[d.seg_begin + j].K;
-    return K;
+    return K * std::min<int64_t>(std::max<int32_t>(d.bpw, 1), d.batch);
   });
   Step st{};
   st.kind = S_GEMM;
@@ -2643,7 +2665,12 @@ void check_program(const Program& prog, Checker& ck) {
         for (int i = 0; i < st.count; ++i) {
           const GemmDesc& D = ds[i];
           if (D.tile_begin != tiles) { ck.ok = false; ck.err = "gemm tile prefix mismatch"; return; }
-          tiles += (int64_t)D.tiles_m * D.tiles_n * D.batch * D.splits;
+          if (D.bpw > 1 && (D.splits != 1 || D.tiles_m != 1 || D.tiles_n != 1)) {
+            ck.ok = false;
+            ck.err = "batch elements grouped on a tile that is split or not alone";
+            return;
+          }
+          tiles += tiles_of(D);
           if (D.tiles_m * 64 < D.M || D.tiles_n * 64 < D.N) { ck.ok = false; ck.err = "gemm tiles too few"; return; }
           for (int j = 0; j < D.seg_count; ++j) {
             const GemmSeg& S = sg[D.seg_begin + j];

@@ -423,3 +423,53 @@ def test_rank_deficient_mode_skips_cholesky_and_overlaps_it():
     assert names.count("householder_kernel") == 1
     assert names.index("householder_kernel") > max(i for i, n in enumerate(names)
                                                    if n == "chol_kernel")
+
+
+def describe_batched(sums, m_of, prec="fp64", project="fp32"):
+    """tsk_plan_describe of a KRP batch (FP32-stored inputs): one line per launch."""
+    from paper_2603_13532_amd import _lib
+    lib = _lib.load()
+    fn = lib.tsk_plan_describe
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_int32, ctypes.POINTER(_lib.TuckerSum), ctypes.POINTER(_lib.SketchSpec),
+                   ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
+    keep = []
+    ts = (_lib.TuckerSum * len(sums))()
+    sp = (_lib.SketchSpec * len(sums))()
+    for b, one in enumerate(sums):
+        ranks = np.asarray(one["ranks"])
+        s, d = ranks.shape
+        c_dims = (ctypes.c_int64 * d)(*one["dims"])
+        c_ranks = (ctypes.c_int32 * (s * d))(*[int(x) for x in ranks.ravel()])
+        c_cores = (ctypes.c_void_p * s)(*([0x1000] * s))
+        c_fac = (ctypes.c_void_p * (s * d))(*([0x1000] * (s * d)))
+        c_sizes = (ctypes.c_int32 * 1)(m_of(one))
+        keep += [c_dims, c_ranks, c_cores, c_fac, c_sizes]
+        ts[b] = _lib.TuckerSum(d, s, c_dims, c_ranks, c_cores, c_fac, None, 1)
+        sp[b] = _lib.SketchSpec(_lib.KINDS["krp"], c_sizes, 7 + b, None, _lib.PRECISIONS[prec],
+                                _lib.PRECISIONS[project], 0)
+    msg = ctypes.create_string_buffer(1 << 16)
+    rc = fn(len(sums), ts, sp, 1, msg, 1 << 16)
+    assert rc == 0, msg.value.decode()
+    return msg.value.decode().splitlines()[:-1]
+
+
+def test_one_tile_batch_elements_are_grouped_per_workgroup():
+    """The projection's mode-2 TTM is one 64 x 64 tile per trailing index
+    (r_3 of each term).  With 8192 or more such elements in a launch, each
+    workgroup takes bpw = min(8, elements // 8192) consecutive ones; fewer,
+    and every element keeps its own workgroup.  Every output width here is
+    at most 56, so every element is a single tile."""
+    def blocks(line):
+        return int(line.split("blocks=")[1].split()[0])
+    big = synth.config_batch(count=256)
+    ttm = [ln for ln in describe_batched(big, lambda one: one["ell"][0]) if "proj_ttm" in ln]
+    assert len(ttm) == 2
+    r3 = [int(r[2]) for one in big for r in np.asarray(one["ranks"])]
+    bpw = min(8, sum(r3) // 8192)
+    assert bpw >= 2
+    assert blocks(ttm[1]) == sum(-(-x // bpw) for x in r3)
+    small = big[:16]
+    ttm = [ln for ln in describe_batched(small, lambda one: one["ell"][0]) if "proj_ttm" in ln]
+    r3 = [int(r[2]) for one in small for r in np.asarray(one["ranks"])]
+    assert sum(r3) < 8192 and blocks(ttm[1]) == sum(r3)
