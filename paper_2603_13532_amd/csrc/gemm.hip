@@ -473,29 +473,75 @@ __global__ __launch_bounds__(NTHREADS, 4) void gemm_kernel(const GemmDesc* __res
   const int tm = (int)(local % D.tiles_m);
   local /= D.tiles_m;
   const int tn = (int)(local % D.tiles_n);
-  // a workgroup takes bpw consecutive batch elements (one tile each, no
-  // K-split) or one tile of one element
-  const int bpw = D.bpw > 1 ? D.bpw : 1;
-  const int64_t b0 = (local / D.tiles_n) * bpw;
-  const int nb = (int)min((int64_t)bpw, (int64_t)D.batch - b0);
-  const int M = D.M, N = D.N;
-  const int m0 = tm * TILE, n0 = tn * TILE;
-  // the wave index goes through readfirstlane so that the compiler sees it as
-  // uniform: branches on it stay scalar and the accumulators stay in place
-  const int t = threadIdx.x, lane = t & 63, w = uni(t >> 6);
-  // one quadrant per wave here: the shared-quadrant variants of the K-loop
-  // push this kernel past its 128-register budget (it spills), and at two
-  // workgroups per CU the lost occupancy costs what the shared quadrants save
-  const WaveRole role{1, w & 1, w >> 1, 0, (w & 1) * 32 < M - m0 && (w >> 1) * 32 < N - n0, 2};
+  if constexpr (ROLE == R_PROJ_TTM) {
+    // a workgroup takes bpw consecutive batch elements (one tile each, no
+    // K-split) or one tile of one element
+    const int bpw = D.bpw > 1 ? D.bpw : 1;
+    const int64_t b0 = (local / D.tiles_n) * bpw;
+    const int nb = (int)min((int64_t)bpw, (int64_t)D.batch - b0);
+    const int M = D.M, N = D.N;
+    const int m0 = tm * TILE, n0 = tn * TILE;
+    // the wave index goes through readfirstlane so that the compiler sees it as
+    // uniform: branches on it stay scalar and the accumulators stay in place
+    const int t = threadIdx.x, lane = t & 63, w = uni(t >> 6);
+    // one quadrant per wave here: the shared-quadrant variants of the K-loop
+    // push this kernel past its 128-register budget (it spills), and at two
+    // workgroups per CU the lost occupancy costs what the shared quadrants save
+    const WaveRole role{1, w & 1, w >> 1, 0, (w & 1) * 32 < M - m0 && (w >> 1) * 32 < N - n0, 2};
 
-  for (int e = 0; e < nb; ++e) {
-    const int64_t b = b0 + e;
-    if (e > 0) {
-      // the previous element's epilogue reads its tile from the K-loop's
-      // LDS buffers, which this element's first staging overwrites
-      __syncthreads();
-      if (cur.c0 != 0) cur.fill(0);
+    for (int e = 0; e < nb; ++e) {
+      const int64_t b = b0 + e;
+      if (e > 0) {
+        // the previous element's epilogue reads its tile from the K-loop's
+        // LDS buffers, which this element's first staging overwrites
+        __syncthreads();
+        if (cur.c0 != 0) cur.fill(0);
+      }
+      acc_t acc[2][2];
+      acc_zero<P>(acc);
+
+      cur.si = 0;
+      cur.kt = 0;
+      cur.nkt = 0;
+      cur.b = b;
+      cur.m0 = m0;
+      cur.n0 = n0;
+      cur.M = M;
+      cur.N = N;
+      cur.t = t;
+      cur.step = splits;
+      bool have = false;
+      if (seg_count > 0) {
+        cur.load();
+        have = cur.skip(split);
+      }
+      if (have) {
+        if (role.active) kloop<P, Depth<P>::value, true>(cur, have, s, acc, t, lane, role.wm, role.wn);
+        else kloop<P, Depth<P>::value, false>(cur, have, s, acc, t, lane, role.wm, role.wn);
+      }
+
+      const int64_t off = b * D.strideC;
+      if (splits == 1) {
+        if (D.c_f64)
+          store_tile<P, double>(acc, (double*)D.C + off, D.ldc, M, N, m0, n0, D.beta != 0, lane,
+                                role.wm, role.wn, s, t, role.phase, role.kw);
+        else
+          store_tile<P, float>(acc, (float*)D.C + off, D.ldc, M, N, m0, n0, D.beta != 0, lane,
+                               role.wm, role.wn, s, t, role.phase, role.kw);
+      } else {
+        typedef typename AccElem<P>::type ae;
+        store_partial<P>(acc, (ae*)D.part + (tile_ns * splits + split) * (TILE * TILE), lane,
+                         role.wm, role.wn, s, t, role.phase, role.kw);
+      }
     }
+  } else {
+    const int64_t b = local / D.tiles_n;
+    const int M = D.M, N = D.N;
+    const int m0 = tm * TILE, n0 = tn * TILE;
+    // the wave index goes through readfirstlane so that the compiler sees it as
+    // uniform: branches on it stay scalar and the accumulators stay in place
+    const int t = threadIdx.x, lane = t & 63, w = uni(t >> 6);
+
     acc_t acc[2][2];
     acc_zero<P>(acc);
 
@@ -514,6 +560,10 @@ __global__ __launch_bounds__(NTHREADS, 4) void gemm_kernel(const GemmDesc* __res
       cur.load();
       have = cur.skip(split);
     }
+    // one quadrant per wave here: the shared-quadrant variants of the K-loop
+    // push this kernel past its 128-register budget (it spills), and at two
+    // workgroups per CU the lost occupancy costs what the shared quadrants save
+    const WaveRole role{1, w & 1, w >> 1, 0, (w & 1) * 32 < M - m0 && (w >> 1) * 32 < N - n0, 2};
     if (have) {
       if (role.active) kloop<P, Depth<P>::value, true>(cur, have, s, acc, t, lane, role.wm, role.wn);
       else kloop<P, Depth<P>::value, false>(cur, have, s, acc, t, lane, role.wm, role.wn);

@@ -442,8 +442,9 @@ int64_t longest_first(std::vector<D>& ds, KofD k_of) {
   return tiles;
 }
 
-// Launches of many one-tile batch elements (the TTMs of the projection's
-// later modes, one per trailing index) give each workgroup bpw consecutive
+// Projection TTM launches of many one-tile batch elements (the later modes,
+// one element per trailing index; the kernel of that role alone carries the
+// loop, so that the other roles' code is unchanged) give each workgroup bpw consecutive
 // elements, so that a tile's descriptor search and segment load are paid
 // once per group; bpw grows with the launch's element count (one per
 // kBpwElems elements, at most kMaxBpw), keeping several rounds of workgroups.
@@ -462,7 +463,7 @@ void group_batches(std::vector<GemmDesc>& ds) {
 
 void emit_gemm(Program& prog, GemmBatch& gb) {
   if (gb.descs.empty()) return;
-  group_batches(gb.descs);
+  if (gb.role == R_PROJ_TTM) group_batches(gb.descs);  // the only kernel built with the loop
   gb.tiles = longest_first(gb.descs, [&](const GemmDesc& d) {
     int64_t K = 0;
     for (int j = 0; j < d.seg_count; ++j) K += gb.segs[d.seg_begin + j].K;
@@ -2665,7 +2666,8 @@ void check_program(const Program& prog, Checker& ck) {
         for (int i = 0; i < st.count; ++i) {
           const GemmDesc& D = ds[i];
           if (D.tile_begin != tiles) { ck.ok = false; ck.err = "gemm tile prefix mismatch"; return; }
-          if (D.bpw > 1 && (D.splits != 1 || D.tiles_m != 1 || D.tiles_n != 1)) {
+          if (D.bpw > 1 && (D.splits != 1 || D.tiles_m != 1 || D.tiles_n != 1 ||
+                            st.role != R_PROJ_TTM)) {
             ck.ok = false;
             ck.err = "batch elements grouped on a tile that is split or not alone";
             return;
