@@ -446,7 +446,10 @@ __device__ __forceinline__ void kloop_role(Cur& cur, bool have, typename Lds<P>:
 // kernel traces separate them); the code is the same for every role.
 // At least four waves per SIMD (<= 128 VGPRs): with the LDS of one
 // workgroup under 40 KB, four workgroups share a CU.
-template <int P, int ROLE, bool A32 = false>
+// GROUPED: the variant whose workgroups take several consecutive one-tile
+// batch elements (the descriptors' bpw); launched only for launches that
+// group, so that every other launch runs the one-tile body alone.
+template <int P, int ROLE, bool A32 = false, bool GROUPED = false>
 __global__ __launch_bounds__(NTHREADS, 4) void gemm_kernel(const GemmDesc* __restrict__ descs,
                                                         int ndesc,
                                                         const GemmSeg* __restrict__ segs) {
@@ -473,7 +476,7 @@ __global__ __launch_bounds__(NTHREADS, 4) void gemm_kernel(const GemmDesc* __res
   const int tm = (int)(local % D.tiles_m);
   local /= D.tiles_m;
   const int tn = (int)(local % D.tiles_n);
-  if constexpr (ROLE == R_PROJ_TTM) {
+  if constexpr (GROUPED) {
     // a workgroup takes bpw consecutive batch elements (one tile each, no
     // K-split) or one tile of one element
     const int bpw = D.bpw > 1 ? D.bpw : 1;
@@ -1274,8 +1277,13 @@ __global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* p, int64_t count
 
 template <int P>
 hipError_t launch_gemm_p(int role, dim3 grid, const GemmDesc* descs, int ndesc,
-                         const GemmSeg* segs, hipStream_t stream) {
+                         const GemmSeg* segs, hipStream_t stream, bool grouped) {
   const dim3 block(NTHREADS);
+  if (grouped) {
+    if (role != R_PROJ_TTM) return hipErrorInvalidValue;
+    gemm_kernel<P, R_PROJ_TTM, false, true><<<grid, block, 0, stream>>>(descs, ndesc, segs);
+    return hipGetLastError();
+  }
   switch (role) {
     case R_FACTOR_SKETCH: gemm_kernel<P, R_FACTOR_SKETCH><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
     case R_KRON_TTM: gemm_kernel<P, R_KRON_TTM><<<grid, block, 0, stream>>>(descs, ndesc, segs); break;
@@ -1289,9 +1297,10 @@ hipError_t launch_gemm_p(int role, dim3 grid, const GemmDesc* descs, int ndesc,
 }
 
 hipError_t launch_gemm(int prec, int role, const GemmDesc* descs, int ndesc, const GemmSeg* segs,
-                       int64_t total_tiles, hipStream_t stream, bool a32) {
+                       int64_t total_tiles, hipStream_t stream, bool a32, bool grouped) {
   if (ndesc <= 0 || total_tiles <= 0) return hipSuccess;
   const dim3 grid((unsigned)total_tiles), block(NTHREADS);
+  if (grouped && (a32 || role != R_PROJ_TTM)) return hipErrorInvalidValue;
   if (a32) {
     // FP32 A operands in an FP64 product: the sketch of FP32-stored inputs
     if (prec != P_FP64) return hipErrorInvalidValue;
@@ -1314,11 +1323,11 @@ hipError_t launch_gemm(int prec, int role, const GemmDesc* descs, int ndesc, con
         gemm_kernel<P_FP64, R_QR_BASIS><<<grid, block, 0, stream>>>(descs, ndesc, segs);
         return hipGetLastError();
       }
-      return launch_gemm_p<P_FP64>(role, grid, descs, ndesc, segs, stream);
-    case P_FP32: return launch_gemm_p<P_FP32>(role, grid, descs, ndesc, segs, stream);
-    case P_BF16X1: return launch_gemm_p<P_BF16X1>(role, grid, descs, ndesc, segs, stream);
-    case P_BF16X3: return launch_gemm_p<P_BF16X3>(role, grid, descs, ndesc, segs, stream);
-    case P_BF16X6: return launch_gemm_p<P_BF16X6>(role, grid, descs, ndesc, segs, stream);
+      return launch_gemm_p<P_FP64>(role, grid, descs, ndesc, segs, stream, grouped);
+    case P_FP32: return launch_gemm_p<P_FP32>(role, grid, descs, ndesc, segs, stream, grouped);
+    case P_BF16X1: return launch_gemm_p<P_BF16X1>(role, grid, descs, ndesc, segs, stream, grouped);
+    case P_BF16X3: return launch_gemm_p<P_BF16X3>(role, grid, descs, ndesc, segs, stream, grouped);
+    case P_BF16X6: return launch_gemm_p<P_BF16X6>(role, grid, descs, ndesc, segs, stream, grouped);
     default: return hipErrorInvalidValue;
   }
 }

@@ -24,9 +24,11 @@ hipError_t launch_omega_jobs(const OmegaJobDev* jobs, int count, int64_t max_cou
 
 // Grouped GEMM over `ndesc` device descriptors covering `total_tiles` tiles.
 // a32: the A operands are FP32 in an FP64 product (factor sketch and term
-// expansion only).
+// expansion only).  grouped: some descriptors give a workgroup several
+// one-tile batch elements (bpw > 1; projection TTMs only).
 hipError_t launch_gemm(int prec, int role, const GemmDesc* descs, int ndesc, const GemmSeg* segs,
-                       int64_t total_tiles, hipStream_t stream, bool a32 = false);
+                       int64_t total_tiles, hipStream_t stream, bool a32 = false,
+                       bool grouped = false);
 
 // KRP core sketches over `ndesc` device descriptors covering `total_tiles` tiles.
 // Elements of P slices a KRP workgroup may keep in LDS (the block's 64

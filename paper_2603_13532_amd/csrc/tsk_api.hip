@@ -258,6 +258,7 @@ struct Step {
   int krp_lds = 0;     // krp: LDS elements for the P slices (largest that fits)
   std::vector<uint32_t> keys;  // autotuning classes whose choices shaped this launch
   bool a32 = false;  // FP64 GEMM / core sketch whose A operands (cores) are stored in FP32
+  bool grouped = false;  // GEMM: some descriptors group one-tile batch elements (bpw > 1)
 };
 
 // LDS elements a KRP launch needs for its P slices: the largest slice set
@@ -443,9 +444,9 @@ int64_t longest_first(std::vector<D>& ds, KofD k_of) {
 }
 
 // Projection TTM launches of many one-tile batch elements (the later modes,
-// one element per trailing index; the kernel of that role alone carries the
-// loop, so that the other roles' code is unchanged) give each workgroup bpw consecutive
-// elements, so that a tile's descriptor search and segment load are paid
+// one element per trailing index; such a launch runs a separate grouped
+// kernel, so every other launch keeps the one-tile body) give each
+// workgroup bpw consecutive elements, so that a tile's descriptor search and segment load are paid
 // once per group; bpw grows with the launch's element count (one per
 // kBpwElems elements, at most kMaxBpw), keeping several rounds of workgroups.
 constexpr int64_t kBpwElems = 8192;
@@ -463,7 +464,7 @@ void group_batches(std::vector<GemmDesc>& ds) {
 
 void emit_gemm(Program& prog, GemmBatch& gb) {
   if (gb.descs.empty()) return;
-  if (gb.role == R_PROJ_TTM) group_batches(gb.descs);  // the only kernel built with the loop
+  if (gb.role == R_PROJ_TTM) group_batches(gb.descs);  // the only role with a grouped kernel
   gb.tiles = longest_first(gb.descs, [&](const GemmDesc& d) {
     int64_t K = 0;
     for (int j = 0; j < d.seg_count; ++j) K += gb.segs[d.seg_begin + j].K;
@@ -483,6 +484,7 @@ void emit_gemm(Program& prog, GemmBatch& gb) {
   st.tiles = gb.tiles;
   st.keys = gb.keys;
   st.a32 = gb.a32;
+  for (const GemmDesc& d : gb.descs) st.grouped = st.grouped || d.bpw > 1;
   prog.steps.push_back(st);
   if (!gb.reduces.empty()) {
     Step r{};
@@ -1677,9 +1679,10 @@ std::string step_name(const Step& st) {
       int role = st.role;
       if (role > R_OTHER || role < 0) role = R_OTHER;
       if ((role == R_QR_GRAM || role == R_QR_BASIS) && st.prec != P_FP64) role = R_OTHER;
-      // the FP32-source variant carries its template flag, as a trace prints it
-      snprintf(buf, sizeof buf, "gemm_kernel<%d, %d%s> %s", st.prec, role, st.a32 ? ", true" : "",
-               role_name(role));
+      // the FP32-source and grouped variants carry their template flags, as a
+      // trace prints them
+      snprintf(buf, sizeof buf, "gemm_kernel<%d, %d%s> %s", st.prec, role,
+               st.grouped ? ", false, true" : (st.a32 ? ", true" : ""), role_name(role));
       return buf;
     }
     case S_KRP:
@@ -1808,7 +1811,7 @@ tsk_status run_program(tsk_handle h, Program& prog, char* ws, hipStream_t stream
       case S_OMEGA: e = launch_omega_jobs((const OmegaJobDev*)(meta + st.meta), st.count, st.rows, stream); break;
       case S_GEMM:
         e = launch_gemm(st.prec, st.role, (const GemmDesc*)(meta + st.meta), st.count,
-                        (const GemmSeg*)(meta + st.meta2), st.tiles, stream, st.a32);
+                        (const GemmSeg*)(meta + st.meta2), st.tiles, stream, st.a32, st.grouped);
         break;
       case S_KRP:
         e = launch_krp(st.prec, (const KrpDesc*)(meta + st.meta), st.count, st.tiles, st.krp_lds,
