@@ -170,3 +170,46 @@ def test_batched_rejects_mixed_order(tsk):
     with pytest.raises(tsk.TskError) as ei:
         tsk.BatchRecompressor(ins)
     assert ei.value.name == "TSK_ERR_INVALID_ARG"
+
+
+def test_graph_replay_with_deficient_modes(tsk):
+    """Sums whose total rank is below the sketch width send their modes to
+    Householder on the handle's second stream (a forked branch of the
+    captured graph, joined before the projection), beside the Cholesky
+    passes of the full-rank sums.  Replays, with outputs poisoned and eager
+    work in between, match the eager batch bit for bit, and every sum
+    matches the oracle."""
+    import torch
+    shapes = [((96, 80, 72), [[3, 4, 5], [2, 2, 2]]),        # total ranks 5, 6, 7 < 14
+              ((96, 80, 72), [[10, 12, 9], [11, 7, 13]]),    # 21, 19, 22 >= 14
+              ((128, 64, 70), [[4, 3, 2]]),                   # all modes deficient
+              ((128, 64, 70), [[12, 3, 3], [9, 2, 14]])]      # 21, 5, 17: mode 2 deficient
+    sums = []
+    for i, (dims, ranks) in enumerate(shapes):
+        one = synth.random_sum(300 + i, dims, ranks)
+        one.update(ell=(14, 14, 14), omega_seed=40 + i)
+        sums.append(one)
+    ins = batch_inputs(tsk, sums, torch.float64)
+    before = tsk.qr_fallback_count()
+    qe, he = tsk.BatchRecompressor(ins)()
+    torch.cuda.synchronize()
+    assert tsk.qr_fallback_count() - before >= 3 + 3 + 1  # every deficient mode took Householder
+    qe = [[q.clone() for q in qs] for qs in qe]
+    he = [h.clone() for h in he]
+    br = tsk.BatchRecompressor(ins).capture()
+    for rep in range(3):
+        for h in br.H:
+            h.fill_(float("nan"))
+        for qs in br.Q:
+            for q in qs:
+                q.fill_(float("nan"))
+        q, h = br.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(h, he):
+            assert torch.equal(a, b), rep
+        for qa, qb in zip(q, qe):
+            for a, b in zip(qa, qb):
+                assert torch.equal(a, b), rep
+        _ = (torch.randn(4096, device=DEV) * 3).sum().item()
+    for one, q, h in zip(sums, qe, he):
+        compare(one, "krp", [14], one["omega_seed"], q, h, 1e-10, 1e-11)
