@@ -741,6 +741,16 @@ void build_projection(const Problem& P, const std::vector<const void*>& Q, bool 
       }
     }
   }
+  // The last mode is contracted over all terms at once: its W blocks (each
+  // scaled by its term's coefficient) sit side by side in one w x sum_i r
+  // matrix, and the last TTM writes every term's result side by side in one
+  // L x sum_i r matrix, so that the final product is one dense K range.
+  std::vector<int64_t> koff(s + 1, 0);
+  for (int i = 0; i < s; ++i) koff[i + 1] = koff[i] + P.r(i, d - 1);
+  int64_t Lfin = 1;
+  for (int k = 0; k < d - 1; ++k) Lfin *= P.w[k];
+  char* Wlast = (char*)ar.take(P.w[d - 1] * koff[s] * ep);
+  char* Ucat = (char*)ar.take(Lfin * koff[s] * ep);
   std::vector<void*> Wm((size_t)s * d);
   {
     GemmBatch& gb = B.g(ST_PROJW, P.pp, R_PROJ_W);
@@ -754,10 +764,12 @@ void build_projection(const Problem& P, const std::vector<const void*>& Q, bool 
     for (int i = 0; i < s; ++i)
       for (int k = 0; k < d; ++k) {
         const int64_t n = P.dims[k], r = P.r(i, k), w = P.w[k];
-        void* p = ar.take(w * r * ep);
+        const bool last = k == d - 1;
+        void* p = last ? (void*)(Wlast + (size_t)(w * koff[i]) * ep) : ar.take(w * r * ep);
         Wm[(size_t)i * d + k] = p;
         gb.add(p, tp64, w, 0, (int)w, (int)r, 1, 0,
-               {seg(Qp[k], n, 1, 0, fac_p[(size_t)i * d + k], n, 1, 0, n)}, splits);
+               {seg(Qp[k], n, 1, 0, fac_p[(size_t)i * d + k], n, 1, 0, n,
+                    last ? P.coeffs[i] : 1.0)}, splits);
       }
   }
   // multi-TTM, modes 0..d-2 per term, then the last mode K-concatenated over terms
@@ -766,16 +778,18 @@ void build_projection(const Problem& P, const std::vector<const void*>& Q, bool 
   std::vector<void*> buf0(s), buf1(s);
   for (int i = 0; i < s; ++i) {
     for (int k = 0; k < d; ++k) shape[i].push_back(P.r(i, k));
-    int64_t mx = 1;
+    // outputs of the TTMs before the last (which writes into Ucat), in two
+    // alternating buffers
+    int64_t mx = 0;
     std::vector<int64_t> sh = shape[i];
-    for (int k = 0; k < d - 1; ++k) {
+    for (int k = 0; k < d - 2; ++k) {
       sh[k] = P.w[k];
       int64_t sz = 1;
       for (auto x : sh) sz *= x;
       mx = std::max(mx, sz);
     }
-    buf0[i] = ar.take(mx * ep);
-    buf1[i] = ar.take(mx * ep);
+    buf0[i] = d > 2 ? ar.take(mx * ep) : nullptr;
+    buf1[i] = d > 3 ? ar.take(mx * ep) : nullptr;
     cur[i] = core_p[i];
   }
   for (int k = 0; k < d - 1; ++k) {
@@ -783,7 +797,8 @@ void build_projection(const Problem& P, const std::vector<const void*>& Q, bool 
     for (int i = 0; i < s; ++i) {
       const int64_t rk = shape[i][k], w = P.w[k];
       const void* Wk = Wm[(size_t)i * d + k];  // w x r_k
-      void* outp = (k % 2 == 0) ? buf0[i] : buf1[i];
+      void* outp = (k == d - 2) ? (void*)(Ucat + (size_t)(Lfin * koff[i]) * ep)
+                                : ((k % 2 == 0) ? buf0[i] : buf1[i]);
       int64_t L = 1, Rr = 1;
       for (int j = 0; j < k; ++j) L *= shape[i][j];
       for (int j = k + 1; j < d; ++j) Rr *= shape[i][j];
@@ -799,18 +814,11 @@ void build_projection(const Problem& P, const std::vector<const void*>& Q, bool 
   }
   {
     GemmBatch& gb = B.g(ST_FINAL, P.pp, R_PROJ_FINAL);
-    int64_t L = 1;
-    for (int k = 0; k < d - 1; ++k) L *= P.w[k];
-    const int64_t w = P.w[d - 1];
-    std::vector<GemmSeg> sg;
-    for (int i = 0; i < s; ++i) {
-      const int64_t rl = shape[i][d - 1];
-      sg.push_back(seg(cur[i], 1, L, 0, Wm[(size_t)i * d + d - 1], 1, w, 0, rl, P.coeffs[i]));
-    }
-    int64_t kt = 0;
-    for (int i = 0; i < s; ++i) kt += ceil_div(shape[i][d - 1], tp64 ? 16 : 32);
+    const int64_t L = Lfin, w = P.w[d - 1];
+    const int64_t kt = ceil_div(koff[s], tp64 ? 16 : 32);
     const int splits = B.splits(gb, ceil_div(L, 64) * ceil_div(w, 64), kt);
-    gb.add(H, out_f64, L, 0, (int)L, (int)w, 1, 0, sg, splits);
+    gb.add(H, out_f64, L, 0, (int)L, (int)w, 1, 0, {seg(Ucat, 1, L, 0, Wlast, 1, w, 0, koff[s])},
+           splits);
   }
 }
 
