@@ -300,7 +300,12 @@ tsk_status tucker_sum_round_deterministic(tsk_handle handle, const tsk_tucker_su
  * contents: calls whose executions overlap on one device (different streams,
  * threads or handles) race and must be serialised by the caller.  Before
  * reusing the staging the call waits for the previous no-allocation call's
- * descriptor upload on the same handle. */
+ * descriptor upload on the same handle.  Under graph capture the recorded
+ * upload reads the handle's staging again on every replay, so a replay
+ * uploads the descriptors of the last no-allocation call made on that
+ * handle: while such a graph is in use, its handle must make no other
+ * no-allocation call (give each captured no-allocation call a handle of its
+ * own; handles are cheap, and the scratch array is shared by all of them). */
 #define TSK_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 #define TSK_NOALLOC_DESCRIPTOR_BYTES ((size_t)1 << 20)
 tsk_status tucker_sum_recompress_noalloc(tsk_handle handle, const tsk_tucker_sum* sum,
