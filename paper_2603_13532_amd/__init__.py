@@ -139,6 +139,23 @@ class Handle:
             pass
 
 
+def _with_workspace(h, call, size):
+    """call(ws) -> status through the handle's growable workspace.  A call
+    given too small a workspace is refused before anything is enqueued, so
+    then size() -> bytes is queried and the call made again on a grown one
+    (with some headroom): a sequence of similar calls plans each once
+    instead of twice."""
+    ws = h.ws if h.ws is not None else h.workspace(1 << 20)
+    st = call(ws)
+    if st == _WORKSPACE_TOO_SMALL:
+        ws = h.workspace(int(size() * 1.25))
+        st = call(ws)
+    check(st, h.ptr)
+
+
+_WORKSPACE_TOO_SMALL = 4
+
+
 # ---------------------------------------------------------------- marshalling
 def _tensor_info(t, seen):
     """(tensor, column-major tensor, dtype, device, shape, pointer) of t,
@@ -404,14 +421,17 @@ def _subranks_batched(ms, eps, p):
     for m in ms:
         pv += [int(x) for x in (p if hasattr(p, "__len__") else [p] * m.d)]
     total = len(pv)
-    nbytes = c_size_t()
-    check(load().tucker_sum_subranks_batched_workspace_size(h.ptr, B, c_sums, byref(nbytes)),
-          h.ptr)
-    ws = h.workspace(nbytes.value)
     out = (c_int32 * total)()
-    check(load().tucker_sum_subranks_batched(h.ptr, B, c_sums, float(eps), (c_int32 * total)(*pv),
-                                             out, c_void_p(ws.data_ptr()), ws.numel(),
-                                             c_void_p(_stream_ptr(ms[0].device))), h.ptr)
+    c_p = (c_int32 * total)(*pv)
+    stream = c_void_p(_stream_ptr(ms[0].device))
+
+    def size():
+        nbytes = c_size_t()
+        check(load().tucker_sum_subranks_batched_workspace_size(h.ptr, B, c_sums, byref(nbytes)),
+              h.ptr)
+        return nbytes.value
+    _with_workspace(h, lambda ws: load().tucker_sum_subranks_batched(
+        h.ptr, B, c_sums, float(eps), c_p, out, c_void_p(ws.data_ptr()), ws.numel(), stream), size)
     res, at = [], 0
     for m in ms:
         res.append(list(out[at:at + m.d]))
@@ -514,7 +534,8 @@ def sketch_sum_batched(sums, kind, eps, p, seed, sketch_prec="fp64", project_pre
         sz = [krp_width(ell)] if kind == "krp" else kron_sizes(ell)
         sizes.append(sz)
         m.set_spec(kind, sz, sd, sketch_prec, project_prec)
-    br = BatchRecompressor(None, sketch_prec, project_prec, torch.float64, _marshals=ms)
+    br = BatchRecompressor(None, sketch_prec, project_prec, torch.float64, _marshals=ms,
+                           _shared_ws=True)
     mark("plan")
     q, h = br()
     mark("recompress")
@@ -649,7 +670,7 @@ class BatchRecompressor:
     kind and precisions."""
 
     def __init__(self, sums, sketch_prec="fp64", project_prec="fp64", out_dtype=None,
-                 qr_policy="auto", _marshals=None):
+                 qr_policy="auto", _marshals=None, _shared_ws=False):
         seen = {}
         self.ms = _marshals if _marshals is not None else [
             _Marshal(x["cores"], x["factors"], x.get("coeffs"), x["kind"], x["sizes"], x["seed"],
@@ -675,20 +696,34 @@ class BatchRecompressor:
             self._cq.append((c_void_p * m.d)(*[q.data_ptr() for q in qs]))
         self.c_q = (POINTER(c_void_p) * B)(*[ctypes.cast(a, POINTER(c_void_p)) for a in self._cq])
         self.c_h = (c_void_p * B)(*[h.data_ptr() for h in self.H])
+        # a one-shot call (_shared_ws) runs in the handle's workspace and plans
+        # once; otherwise the call owns a workspace, which graph capture needs
+        self.ws = None if _shared_ws else torch.empty(max(self._size(), 256), dtype=torch.uint8,
+                                                      device=m0.device)
+
+    def _size(self):
         nbytes = c_size_t()
-        check(load().tucker_sum_batched_workspace_size(self.h.ptr, B, self.c_sums, self.c_specs,
-                                                       byref(nbytes)), self.h.ptr)
-        self.ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=m0.device)
+        check(load().tucker_sum_batched_workspace_size(self.h.ptr, len(self.ms), self.c_sums,
+                                                       self.c_specs, byref(nbytes)), self.h.ptr)
+        return nbytes.value
 
     def __call__(self, stream=None):
         st = _stream_ptr(self.ms[0].device) if stream is None else stream
-        check(load().tucker_sum_recompress_batched(
-            self.h.ptr, len(self.ms), self.c_sums, self.c_specs, self.c_q, self.c_h,
-            _dtype_code(self.out_dtype), c_void_p(self.ws.data_ptr()), self.ws.numel(),
-            c_void_p(st)), self.h.ptr)
+
+        def call(ws):
+            return load().tucker_sum_recompress_batched(
+                self.h.ptr, len(self.ms), self.c_sums, self.c_specs, self.c_q, self.c_h,
+                _dtype_code(self.out_dtype), c_void_p(ws.data_ptr()), ws.numel(), c_void_p(st))
+        if self.ws is None:
+            _with_workspace(self.h, call, self._size)
+        else:
+            check(call(self.ws), self.h.ptr)
         return self.Q, self.H
 
     def capture(self):
+        if self.ws is None:
+            # the handle's workspace may be reallocated by a later call
+            raise RuntimeError("a recompressor on the handle's shared workspace cannot be captured")
         dev = self.ms[0].device
         self.graph_stream = torch.cuda.Stream(dev)
         self.graph = torch.cuda.CUDAGraph()
