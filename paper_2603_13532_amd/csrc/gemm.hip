@@ -599,6 +599,17 @@ __global__ __launch_bounds__(NTHREADS, 4) void gemm_kernel(const GemmDesc* __res
 typedef __attribute__((address_space(3))) const float lds_cf32;
 typedef __attribute__((address_space(3))) const double lds_cf64;
 
+// The Khatri-Rao entry is computed for every depth and column and then
+// selected (zero past K or past the sketch width): its LDS reads stay in
+// range because the digits wrap, and the select discards what lies past the
+// loaded columns.  Pinning the product in a register keeps the compiler from
+// sinking its reads and products under a per-element divergent branch.
+template <typename T>
+__device__ __forceinline__ T krp_select(bool keep, T prod) {
+  asm volatile("" : "+v"(prod));
+  return keep ? prod : (T)0;
+}
+
 template <int P, bool LDS_P, bool G32 = false>
 struct KrpCursor {
   typedef typename PT<P>::in_t in_t;
@@ -657,7 +668,7 @@ struct KrpCursor {
 #pragma unroll
         for (int k = 0; k < kMaxOrder; ++k)
           if (k < order && k != n) prod *= pval(k, x, dg[k]);
-        rb[j] = (valid && tt < m) ? prod : (in_t)0;
+        rb[j] = krp_select(valid && tt < m, prod);
         // next depth: add one to the mixed-radix digits, branch-free
         bool carry = true;
 #pragma unroll
@@ -696,7 +707,7 @@ struct KrpCursor {
 #pragma unroll
         for (int k = 0; k < kMaxOrder; ++k)
           if (k < order && k != n) prod *= pval(k, x, dig[k]);
-        rb[j] = (valid && tt < m) ? prod : (in_t)0;
+        rb[j] = krp_select(valid && tt < m, prod);
       }
     }
   }
@@ -767,7 +778,7 @@ struct KrpFixed {
         in_t prod = sP[pb[i][0] + dg[0]];
 #pragma unroll
         for (int j = 1; j < NO; ++j) prod *= sP[pb[i][j] + dg[j]];
-        rb[i] = (valid && tok[i]) ? prod : (in_t)0;
+        rb[i] = krp_select(valid && tok[i], prod);
       }
     } else {
       int d[NO];
@@ -784,7 +795,7 @@ struct KrpFixed {
         in_t prod = sP[pb[0][0] + d[0]];
 #pragma unroll
         for (int j = 1; j < NO; ++j) prod *= sP[pb[0][j] + d[j]];
-        rb[i] = (valid && tok[0]) ? prod : (in_t)0;
+        rb[i] = krp_select(valid && tok[0], prod);
         // next depth: add one to the digits, branch-free
         bool carry = true;
 #pragma unroll
