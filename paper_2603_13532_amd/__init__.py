@@ -214,6 +214,88 @@ class _Marshal:
             self.c_omega = (c_void_p * d)(*[o.data_ptr() for o in self.omega])
         self.set_spec(kind, sizes, seed, sketch_prec, project_prec, qr_policy)
 
+    @classmethod
+    def many(cls, sums, sketch_prec="fp64", project_prec="fp64"):
+        """One marshal per sum (dicts with cores, factors and optionally
+        coeffs; spec "krp", sizes [1], seed 0 until set_spec), with the same
+        checks as the constructor but the ctypes arrays of all sums laid out
+        flat, one array per field, each sum's TuckerSum pointing at its
+        stretch: the per-sum cost of a batch is a few list operations instead
+        of five ctypes arrays."""
+        seen = {}
+        dims_all, ranks_all, cores_all, facs_all, coefs_all, layout = [], [], [], [], [], []
+        first = []
+
+        def info(t):
+            # a tensor's dtype and device are checked once, when it is first seen
+            got = _tensor_info(t, seen)
+            if not first:
+                first.append(got)
+            elif got[2] is not first[0][2] or got[3] != first[0][3]:
+                raise ValueError("all cores and factors must share dtype and device")
+            return got
+
+        get = seen.get
+        add_rank, add_core, add_fac = ranks_all.extend, cores_all.append, facs_all.append
+        for x in sums:
+            cores, factors, coeffs = x["cores"], x["factors"], x.get("coeffs")
+            s, d = len(cores), len(factors[0])
+            if len(factors) != s:
+                raise ValueError("every term needs one core and one list of factors")
+            dims = None
+            for g, us in zip(cores, factors):
+                gi = get(id(g)) or info(g)
+                rk = gi[4]
+                if len(rk) != d or len(us) != d:
+                    raise ValueError("every core must have one dimension per factor")
+                add_rank(rk)
+                add_core(gi[5])
+                col = []
+                for k in range(d):
+                    u = us[k]
+                    ui = get(id(u)) or info(u)
+                    sh = ui[4]
+                    if len(sh) != 2 or sh[1] != rk[k]:
+                        raise ValueError(f"factor {k} shape {sh} does not match core")
+                    col.append(sh[0])
+                    add_fac(ui[5])
+                if dims is None:
+                    dims = col
+                elif col != dims:
+                    raise ValueError("all terms must share the mode sizes")
+            layout.append((d, s, dims, None if coeffs is None else len(coefs_all)))
+            dims_all += dims
+            if coeffs is not None:
+                coefs_all += [float(c) for c in coeffs]
+        c_dims = (c_int64 * max(len(dims_all), 1))(*dims_all)
+        c_ranks = (c_int32 * max(len(ranks_all), 1))(*ranks_all)
+        c_cores = (c_void_p * max(len(cores_all), 1))(*cores_all)
+        c_facs = (c_void_p * max(len(facs_all), 1))(*facs_all)
+        c_coefs = (c_double * max(len(coefs_all), 1))(*coefs_all)
+        a_dims, a_ranks = ctypes.addressof(c_dims), ctypes.addressof(c_ranks)
+        a_cores, a_facs = ctypes.addressof(c_cores), ctypes.addressof(c_facs)
+        a_coefs = ctypes.addressof(c_coefs)
+        P64, P32, PV, PD = POINTER(c_int64), POINTER(c_int32), POINTER(c_void_p), POINTER(c_double)
+        shared = (c_dims, c_ranks, c_cores, c_facs, c_coefs, seen)
+        dt, dev = (first[0][2], first[0][6]) if first else (None, None)
+        code = _dtype_code(dt) if dt is not None else 0
+        out, at_d, at_t, at_r = [], 0, 0, 0
+        for d, s, dims, at_c in layout:
+            m = cls.__new__(cls)
+            m.d, m.s, m.dtype, m.device, m.dims = d, s, dt, dev, dims
+            m._shared = shared
+            m.omega = m.c_omega = None
+            m.sum = _lib.TuckerSum(
+                d, s, ctypes.cast(a_dims + 8 * at_d, P64), ctypes.cast(a_ranks + 4 * at_r, P32),
+                ctypes.cast(a_cores + 8 * at_t, PV), ctypes.cast(a_facs + 8 * at_r, PV),
+                None if at_c is None else ctypes.cast(a_coefs + 8 * at_c, PD), code)
+            m.set_spec("krp", [1], 0, sketch_prec, project_prec)
+            out.append(m)
+            at_d += d
+            at_t += s
+            at_r += s * d
+        return out
+
     def set_spec(self, kind, sizes, seed, sketch_prec="fp64", project_prec="fp64",
                  qr_policy="auto"):
         sizes = [int(x) for x in sizes]
@@ -407,10 +489,7 @@ def effective_subranks_batched(sums, eps, p):
     `sums`: list of dicts with keys cores, factors and optionally coeffs; p:
     an int or a per-mode list shared by every sum.  Returns a list of ell
     lists."""
-    seen = {}
-    ms = [_Marshal(x["cores"], x["factors"], x.get("coeffs"), "krp", [1], 0, None, "fp64",
-                   "fp64", "auto", seen) for x in sums]
-    return _subranks_batched(ms, eps, p)
+    return _subranks_batched(_Marshal.many(sums), eps, p)
 
 
 def _subranks_batched(ms, eps, p):
@@ -522,9 +601,7 @@ def sketch_sum_batched(sums, kind, eps, p, seed, sketch_prec="fp64", project_pre
     "stage1", "plan" (sketch sizes and the batched plan), "recompress"
     (Stages 2-3) and "truncate" (Stage 4)."""
     mark = _phase_clock(timings, sums[0]["cores"][0].device if sums else None)
-    seen = {}
-    ms = [_Marshal(x["cores"], x["factors"], x.get("coeffs"), "krp", [1], 0, None, sketch_prec,
-                   project_prec, "auto", seen) for x in sums]
+    ms = _Marshal.many(sums, sketch_prec, project_prec)
     mark("marshal")
     ells = _subranks_batched(ms, eps, p)
     mark("stage1")
@@ -671,10 +748,11 @@ class BatchRecompressor:
 
     def __init__(self, sums, sketch_prec="fp64", project_prec="fp64", out_dtype=None,
                  qr_policy="auto", _marshals=None, _shared_ws=False):
-        seen = {}
-        self.ms = _marshals if _marshals is not None else [
-            _Marshal(x["cores"], x["factors"], x.get("coeffs"), x["kind"], x["sizes"], x["seed"],
-                     None, sketch_prec, project_prec, qr_policy, seen) for x in sums]
+        if _marshals is None:
+            _marshals = _Marshal.many(sums, sketch_prec, project_prec)
+            for m, x in zip(_marshals, sums):
+                m.set_spec(x["kind"], x["sizes"], x["seed"], sketch_prec, project_prec, qr_policy)
+        self.ms = _marshals
         m0 = self.ms[0]
         self.h = Handle.get(m0.device)
         self.out_dtype = m0.dtype if out_dtype is None else out_dtype
