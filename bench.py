@@ -662,34 +662,43 @@ def torch_f64():
 
 
 def cpu_baseline(sums, seconds):
-    """The oracle on the host cores: sums of the batch in order (passing over
-    the batch again when it runs out) until `seconds` of CPU time are spent,
-    with the BLAS thread pool at its default, then again single-threaded."""
+    """The oracle on the host cores: three runs over the batch's sums in
+    order from the first (passing over the batch again when it runs out),
+    each until a third of `seconds` of CPU time is spent, the median rate
+    reported; with the BLAS thread pool at its default, then again
+    single-threaded."""
     from oracle import recompress as RC
     try:
         from threadpoolctl import threadpool_info, threadpool_limits
     except Exception:
         threadpool_info = threadpool_limits = None
 
-    def run(limit):
+    def run(budget):
         done, t_tot = 0, 0.0
-        while t_tot < seconds:
+        while t_tot < budget:
             one = sums[done % len(sums)]
             t0 = time.perf_counter()
             RC.recompress(one, "krp", [one["ell"][0]], one["omega_seed"])
             t_tot += time.perf_counter() - t0
             done += 1
         return done, t_tot
+
+    def median_of_three():
+        runs = [run(seconds / 3) for _ in range(3)]
+        rates = sorted(d / t for d, t in runs)
+        return rates[1], rates, sum(d for d, _ in runs), sum(t for _, t in runs)
     threads = os.cpu_count()
     if threadpool_info is not None:
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    done, t = run(None)
+    rate, rates, done, t = median_of_three()
     single = None
     if threadpool_limits is not None:
         with threadpool_limits(limits=1):
-            d1, t1 = run(1)
-        single = {"value": d1 / t1, "unit": "recompressions/s", "cores": 1,
-                  "sample": f"{d1} sums of the batch in order, {t1:.1f} s"}
+            rate1, rates1, d1, t1 = median_of_three()
+        single = {"value": rate1, "unit": "recompressions/s", "cores": 1,
+                  "runs": [round(x, 2) for x in rates1],
+                  "sample": f"median of 3 runs over the batch's sums in order from the first, "
+                            f"{d1} sums in {t1:.1f} s in all"}
     cpu_model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -699,10 +708,11 @@ def cpu_baseline(sums, seconds):
                     break
     except OSError:
         pass
-    return {"value": done / t, "unit": "recompressions/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} sums of the 256-sum batch workload in order, passing over it "
-                      f"{done / len(sums):.1f} times (FP64 NumPy oracle, structured path), "
-                      f"{t:.1f} s of CPU time",
+    return {"value": rate, "unit": "recompressions/s", "cores": int(threads), "kind": "oracle",
+            "runs": [round(x, 2) for x in rates],
+            "sample": f"median of 3 runs, each over the 256-sum batch workload's sums in order "
+                      f"from the first for {seconds / 3:.1f} s of CPU time (FP64 NumPy oracle, "
+                      f"structured path); {done} sums in {t:.1f} s in all",
             "cpu_model": cpu_model, "nproc": os.cpu_count(), "single_thread": single}
 
 
