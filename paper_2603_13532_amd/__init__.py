@@ -59,22 +59,18 @@ def carve_fortran(shapes, dtype, device):
     caching-allocator call per tensor."""
     es = torch.empty((), dtype=dtype).element_size()
     align = max(1, 256 // es)
-    offs, total = [], 0
+    views, total = [], 0
     for sh in shapes:
-        n = 1
+        sh = tuple(int(x) for x in sh)
+        strides, n = [], 1
         for x in sh:
-            n *= int(x)
-        offs.append(total)
+            strides.append(n)
+            n *= x
+        views.append((sh, tuple(strides), total))
         total += (n + align - 1) // align * align
     buf = torch.empty(max(total, 1), dtype=dtype, device=device)
-    out = []
-    for sh, off in zip(shapes, offs):
-        strides, st = [], 1
-        for x in sh:
-            strides.append(st)
-            st *= int(x)
-        out.append(buf.as_strided(tuple(int(x) for x in sh), tuple(strides), off))
-    return out
+    view = buf.as_strided
+    return [view(sh, st, off) for sh, st, off in views]
 
 
 def _dtype_code(dt) -> int:
